@@ -1,0 +1,99 @@
+"""Closed-form solutions used to pin the oracle -- TEST INFRASTRUCTURE.
+
+All formulas are written from the mathematics of the Pennes equation (Eq 1)
+and of the explicit Euler step (Eq 6), not from the oracle's code.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def slab_discrete(theta0, src, alpha, m, h, dt, n_steps, rho_c):
+    """Explicit-Euler solution of the 7-point / 3-point slab scheme.
+
+    1-D grid x_j = j h, j = 0..M, theta_0 = theta_M = 0, with theta = T - T_a
+    (= T - T_Gamma).  Interior nodes obey
+        theta_j^{k+1} = theta_j^k + dt [alpha (theta_{j-1} - 2 theta_j
+                        + theta_{j+1}) / h^2 - m theta_j + s_j / rho_c]
+    The sine vectors sin(n pi j / M) diagonalise it with
+        mu_n = 4 alpha / h^2 sin^2(n pi / (2 M)) + m,
+    so each mode evolves as g^k b_n + (1 - g^k) s_n / (rho_c mu_n),
+    g = 1 - dt mu_n.  theta0 and src hold the M-1 interior values.
+    """
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    src = np.asarray(src, dtype=np.float64)
+    Mc = len(theta0) + 1
+    j = np.arange(1, Mc)
+    n = np.arange(1, Mc)
+    S = np.sin(np.pi * np.outer(n, j) / Mc)          # S S^T = (M/2) I
+    b = S @ theta0 * (2.0 / Mc)
+    s = S @ src * (2.0 / Mc)
+    mu = 4.0 * alpha / h**2 * np.sin(n * np.pi / (2 * Mc)) ** 2 + m
+    g = 1.0 - dt * mu
+    coef = g**n_steps * b + (1.0 - g**n_steps) * s / (rho_c * mu)
+    return coef @ S
+
+
+def slab_series(x, t, L, alpha, m, rho_c, theta0_fn, src_fn, n_terms=400,
+                n_quad=4000):
+    """Continuous Pennes slab: theta(0)=theta(L)=0, constant properties.
+
+    rho_c theta_t = k theta_xx - w_b c_b theta + Q(x), alpha = k / rho_c,
+    m = w_b c_b / rho_c.  With sine coefficients b_n of theta(x,0) and q_n of
+    Q(x), lambda_n = alpha (n pi / L)^2 + m:
+        theta = sum_n [b_n e^{-lambda_n t}
+                       + q_n / (rho_c lambda_n) (1 - e^{-lambda_n t})]
+                      sin(n pi x / L)
+    Coefficients come from a midpoint rule with n_quad points.
+    """
+    xq = (np.arange(n_quad) + 0.5) * L / n_quad
+    n = np.arange(1, n_terms + 1)
+    Sq = np.sin(np.outer(n, xq) * np.pi / L)
+    b = Sq @ theta0_fn(xq) * (2.0 / n_quad)
+    q = Sq @ src_fn(xq) * (2.0 / n_quad)
+    lam = alpha * (n * np.pi / L) ** 2 + m
+    e = np.exp(-lam * t)
+    coef = b * e + q / (rho_c * lam) * (1.0 - e)
+    return np.sin(np.outer(np.asarray(x), n) * np.pi / L) @ coef
+
+
+def uniform_perfusion(theta0, dt, m, n):
+    """Uniform field, no conduction: theta^n = theta0 (1 - dt m)^n."""
+    return theta0 * (1.0 - dt * m) ** n
+
+
+def uniform_metabolic_ti(T0, dt, Qm, rho_c, n):
+    """Uniform field, constant properties, metabolic heat only."""
+    return T0 + n * dt * Qm / rho_c
+
+
+def uniform_metabolic_td(T0, dt, Qm, rho_c_fn, n):
+    """Scalar explicit recurrence T <- T + dt Qm / (rho(T) c(T))."""
+    T = float(T0)
+    for _ in range(n):
+        T = T + dt * Qm / rho_c_fn(T)
+    return T
+
+
+def kuhn_cube_lambda(n_cubes, h):
+    """Largest eigenvalue of -Laplacian (7-point) on an n^3-cube grid with
+    Dirichlet boundary: 12 / h^2 sin^2((n-1) pi / (2n))."""
+    return 12.0 / h**2 * np.sin((n_cubes - 1) * np.pi / (2 * n_cubes)) ** 2
+
+
+def kirchhoff_slab(x, L, T_left, T_right, k0, beta, T_r):
+    """Steady 1-D conduction with k = k0 (1 + beta (T - T_r)).
+
+    U(T) = k0 [(T - T_r) + beta (T - T_r)^2 / 2] satisfies U'' = 0, so U is
+    linear in x between its boundary values; invert the quadratic for T.
+    """
+    def U(T):
+        d = T - T_r
+        return k0 * (d + beta * d * d / 2.0)
+    u = U(T_left) + (U(T_right) - U(T_left)) * np.asarray(x) / L
+    return T_r + (-1.0 + np.sqrt(1.0 + 2.0 * beta * u / k0)) / beta
+
+
+def gaussian_total_power(Q0, sigma):
+    """Integral of Q0 exp(-r^2 / (2 sigma^2)) over R^3."""
+    return Q0 * (2.0 * np.pi) ** 1.5 * sigma**3
