@@ -1,0 +1,245 @@
+/*
+ * fedfem.h -- C ABI of the MI355X (gfx950) FED-FEM bio-heat library.
+ *
+ * The library advances the Pennes bio-heat equation (Zhang & Chauhan,
+ * arXiv 1909.05098, Eq 1-2) on a mesh of four-node linear tetrahedra with
+ * the fast explicit dynamics finite element algorithm (Algorithm 1):
+ * pre-computed element matrices A = V_tet B^T B (Eq 15-16), element-level
+ * thermal loads F_e = k(T) A T_e with k averaged over the element's nodes
+ * (Eq 13, 17), assembly at the nodes (Eq 11) and the explicit nodal update
+ * with lumped capacity and perfusion (Eq 19).
+ *
+ * Conventions shared by every entry point:
+ *   - All host values are double precision, SI units, temperatures in degC.
+ *   - Node and element ids are 0-based and refer to the caller's numbering;
+ *     the library may renumber internally but never exposes that order.
+ *   - Every function returns FEDFEM_OK (0) or a negative FEDFEM_E_* code.
+ *     No C++ exception crosses the ABI.  A handle is not thread-safe.
+ *   - Host pointers passed in are only read during the call (the library
+ *     deep-copies what it keeps); the caller keeps ownership.
+ *   - After FEDFEM_E_HIP a handle is unusable except for fedfem_destroy.
+ */
+#ifndef FEDFEM_H
+#define FEDFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define FEDFEM_OK 0
+#define FEDFEM_E_INVALID (-1)         /* bad argument; see fedfem_last_error */
+#define FEDFEM_E_DEGENERATE (-2)      /* |det J| <= 1e-12 (longest edge)^3   */
+#define FEDFEM_E_NOT_PRECOMPUTED (-3) /* call fedfem_precompute first        */
+#define FEDFEM_E_UNSTABLE (-4)        /* dt >= critical dt (Eq 9)            */
+#define FEDFEM_E_DIVERGED (-5)        /* non-finite or |T| > 1e4 degC seen   */
+#define FEDFEM_E_HIP (-6)             /* HIP runtime failure (sticky)        */
+#define FEDFEM_E_NOMEM (-7)           /* host or device allocation failed    */
+#define FEDFEM_E_STATE (-8)           /* call not valid in the current state */
+
+/* ---- precision of the time-stepping kernels ----------------------------- */
+#define FEDFEM_FP64 0  /* element loop and nodal state in double             */
+#define FEDFEM_FP32C 1 /* element loop in float; nodal T carried as a        */
+                       /* compensated float pair hi + lo                      */
+
+/* ---- how a Gaussian source density becomes nodal heat flows ------------ */
+#define FEDFEM_SOURCE_NODAL 0      /* Q_i = Q_r(x_i) V_i (lumped volume)     */
+#define FEDFEM_SOURCE_CONSISTENT 1 /* Q_i = integral of Q_r N_i dV           */
+
+/* Mesh (Sec 2.3.3): xyz is [n_nodes][3] metres, tets is [n_tets][4]. */
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;
+    int64_t n_tets;
+    const int32_t *tets;
+} fedfem_mesh;
+
+/*
+ * Tissue and blood properties (Eq 1-2).  Each tissue property follows
+ *   p(T) = p0 + dp_dT * (clamp(T, T_lo, T_hi) - T_ref),
+ * i.e. linear interpolation of tabulated data with constant extension
+ * outside [T_lo, T_hi] (Sec 3.1.6).  w_b is the perfusion mass rate
+ * [kg/(m^3 s)], c_b the blood heat capacity, T_a the arterial temperature,
+ * Q_m the metabolic heat density [W/m^3].  rho(T) c(T) and k(T) must stay
+ * positive on the window.
+ */
+typedef struct {
+    double rho0, c0, k0;
+    double drho_dT, dc_dT, dk_dT;
+    double T_ref, T_lo, T_hi;
+    double w_b, c_b, T_a, Q_m;
+    int32_t precision; /* FEDFEM_FP64 or FEDFEM_FP32C */
+} fedfem_materials;
+
+/*
+ * Initial and essential boundary conditions (Eq 3; Algorithm 1,
+ * initialisation).  Dirichlet nodes are held at dir_T from the initial state
+ * on.  dt > 0 fixes the step; -1 < dt < 0 asks for |dt| times the critical
+ * step found by fedfem_precompute (Eq 9).
+ */
+typedef struct {
+    double T0;
+    int64_t n_dir;
+    const int32_t *dir_nodes;
+    const double *dir_T;
+    double dt;
+} fedfem_bc;
+
+/*
+ * Layout options, read by fedfem_precompute.  reorder = 1 renumbers nodes
+ * and elements along a Morton (Z-order) curve of their coordinates, 0 keeps
+ * the caller's order.  tile_elems (64..8192, multiple of 64, 0 = default
+ * 1024) is the number of consecutive elements whose loads are gathered in
+ * on-chip memory before assembly.  threads is the workgroup size of the
+ * element kernel (64..1024, multiple of 64, 0 = default 256).
+ */
+typedef struct {
+    int32_t reorder;
+    int32_t tile_elems;
+    int32_t threads;
+    int32_t reserved[5];
+} fedfem_options;
+
+/* Sizes of the pre-computed layout, for reporting. */
+typedef struct {
+    int64_t n_nodes, n_tets, n_dirichlet;
+    int64_t n_tiles, n_partials, max_tile_nodes;
+    int32_t precision, tile_elems, threads, reorder;
+    int64_t device_bytes;     /* device memory owned by the handle */
+    double lambda_geometry;   /* top eigenvalue of (sum A_e, diag V) */
+    int32_t lanczos_iterations;
+    int32_t reserved[7];
+} fedfem_info;
+
+typedef struct fedfem_handle fedfem_handle;
+
+/*
+ * Create a handle: validates the mesh (counts, node ids, finite
+ * coordinates), materials (positive properties on the window) and boundary
+ * conditions (ids in range, no duplicates, finite values), deep-copies all
+ * inputs, and creates the handle's HIP stream on the current device.  No
+ * device memory is allocated until fedfem_precompute.
+ */
+int fedfem_create(const fedfem_mesh *mesh, const fedfem_materials *mat,
+                  const fedfem_bc *bc, fedfem_handle **out);
+
+/* Set layout options (before fedfem_precompute; FEDFEM_E_STATE after). */
+int fedfem_set_options(fedfem_handle *h, const fedfem_options *opt);
+
+/*
+ * Pre-computation (Algorithm 1, pre-computation block; Sec 2.3.5), on the
+ * GPU in double precision: Jacobians, volumes, gradients and element
+ * matrices (Eq 15-16), lumped nodal volumes (Sec 2.3.4), the critical step
+ * (Eq 9) by Lanczos iteration on (sum_e A_e, diag V) over the free nodes
+ * bounded over the property window, and the initial state.  Returns
+ * FEDFEM_E_DEGENERATE naming the first bad element in fedfem_last_error,
+ * FEDFEM_E_UNSTABLE if a fixed dt is not below the critical step.
+ */
+int fedfem_precompute(fedfem_handle *h);
+
+/*
+ * Advance n_steps explicit steps (Algorithm 1, time-stepping block;
+ * Eq 13, 17, 11, 19).  source is a nodal heat flow Q_r [W] per node
+ * (length n_nodes, caller's numbering); when non-NULL it replaces the active
+ * source before stepping, when NULL the active source (zero initially) is
+ * kept.  The n steps run as captured HIP graphs on the handle's stream; the
+ * call returns after they finish.  Returns FEDFEM_E_DIVERGED if any node
+ * went non-finite or beyond 1e4 degC (the state is then the post-step
+ * state).
+ */
+int fedfem_step(fedfem_handle *h, int64_t n_steps, const double *source);
+
+/* Replace the active nodal source [W] (NULL = zero). */
+int fedfem_set_source(fedfem_handle *h, const double *source);
+
+/*
+ * Set the active source from n_src Gaussian densities
+ * Q_r(x) = Q0 exp(-|x - c|^2 / (2 sigma^2)) [W/m^3], params = n_src rows
+ * of (cx, cy, cz, sigma, Q0).  mode FEDFEM_SOURCE_NODAL samples the density
+ * at the nodes times the lumped nodal volume; FEDFEM_SOURCE_CONSISTENT
+ * integrates Q_r N_i over each element with a 256-point composite rule (two
+ * regular refinements, 4-point degree-2 rule per child, corners in
+ * lexicographic coordinate order; elements whose bounding sphere lies beyond
+ * 8 sigma get nothing).  Computed on the GPU in double precision.
+ */
+int fedfem_set_gaussian_sources(fedfem_handle *h, int32_t n_src,
+                                const double *params, int32_t mode);
+
+/* Copy the active nodal source [W] to host memory (length n_nodes). */
+int fedfem_read_source(fedfem_handle *h, double *out);
+
+/* Blocking copy of the nodal temperatures (hi + lo in double) to host. */
+int fedfem_read_T(fedfem_handle *h, double *T_out);
+
+/* Same into device memory d_out (n_nodes doubles); synchronises. */
+int fedfem_read_T_device(fedfem_handle *h, double *d_out);
+
+/* Current step, critical step (Eq 9) and simulated time. */
+int fedfem_get_dt(const fedfem_handle *h, double *dt, double *dt_cr);
+int fedfem_get_time(const fedfem_handle *h, double *t, int64_t *steps);
+
+/* Change the step; FEDFEM_E_UNSTABLE unless 0 < dt < dt_cr. */
+int fedfem_set_dt(fedfem_handle *h, double dt);
+
+/*
+ * Use a caller-owned HIP stream (e.g. a torch stream, passed as its
+ * hipStream_t); NULL returns to the handle's own stream.  The stream must
+ * outlive its use by the handle.
+ */
+int fedfem_set_stream(fedfem_handle *h, void *stream);
+
+/*
+ * Raw state for checkpoints.  fedfem_state_bytes gives the size of the
+ * state buffer: FP32C stores hi[n] then lo[n] (float), FP64 stores T[n]
+ * (double), in the caller's node order.  Reading then writing the same
+ * buffer restores the state bit for bit.
+ */
+int fedfem_state_bytes(const fedfem_handle *h, size_t *bytes);
+int fedfem_read_state(fedfem_handle *h, void *buf, double *t, int64_t *steps);
+int fedfem_write_state(fedfem_handle *h, const void *buf, double t,
+                       int64_t steps);
+
+/* Layout sizes and estimator results (after fedfem_precompute). */
+int fedfem_get_info(const fedfem_handle *h, fedfem_info *info);
+
+/*
+ * Profiling aid: advance n_steps exactly as fedfem_step does, but launch
+ * each kernel separately with HIP events around it, and return the mean
+ * duration [ms] of the element-load kernel and of the node-update kernel.
+ */
+int fedfem_time_kernels(fedfem_handle *h, int64_t n_steps, double *elem_ms,
+                        double *node_ms);
+
+/* Release all host and device resources of h (NULL is accepted). */
+int fedfem_destroy(fedfem_handle *h);
+
+/* Text for a return code, and the handle's last error message. */
+const char *fedfem_strerror(int code);
+int fedfem_last_error(const fedfem_handle *h, char *buf, size_t len);
+
+/* ---- batched execution ------------------------------------------------- */
+/*
+ * Many independent scenarios (Algorithm 1 applied to each) advanced by one
+ * graph-captured launch sequence.  The handles must be precomputed, share
+ * one precision, and stay alive while the batch exists.  A batch copies
+ * their pre-computed layouts once; each run takes every handle's current
+ * state and active source, advances scenario j by n_steps[j] steps, and
+ * writes the states back to the handles (read them with fedfem_read_T).
+ */
+typedef struct fedfem_batch fedfem_batch;
+
+int fedfem_batch_create(fedfem_handle *const *handles, int32_t n,
+                        fedfem_batch **out);
+int fedfem_batch_run(fedfem_batch *b, const int64_t *n_steps);
+/* Mean device time [ms] of the last fedfem_batch_run's launch sequence. */
+int fedfem_batch_last_ms(const fedfem_batch *b, double *ms);
+int fedfem_batch_destroy(fedfem_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEDFEM_H */

@@ -1,0 +1,869 @@
+// C ABI of the FED-FEM gfx950 library: handle lifecycle, pre-computation,
+// graph-captured time stepping, sources, read-back and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <utility>
+#include <vector>
+
+#include "../../include/fedfem.h"
+#include "handle.h"
+#include "internal.h"
+
+using namespace fedfem;
+
+namespace {
+
+int set_err(fedfem_handle* h, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    return code;
+}
+
+int hip_fail(fedfem_handle* h, hipError_t e, const char* where) {
+    if (h) h->broken = true;
+    return set_err(h, FEDFEM_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIPCHK(h, expr)                                            \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return hip_fail((h), e_, #expr);     \
+    } while (0)
+
+bool finite_all(const double* p, int64_t n) {
+    for (int64_t i = 0; i < n; i++)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Property window bounds of the clamped linear laws (rho c may be quadratic
+// in T; its extremum may lie inside the window).
+void window_bounds(const fedfem_materials& m, double* kmin, double* kmax, double* rcmin,
+                   double* rcmax) {
+    std::vector<double> ts = {m.T_lo, m.T_hi};
+    const double a = m.drho_dT * m.dc_dT;
+    if (a != 0.0) {
+        const double b = m.rho0 * m.dc_dT + m.c0 * m.drho_dT;
+        const double tv = m.T_ref - b / (2.0 * a);
+        if (tv > m.T_lo && tv < m.T_hi) ts.push_back(tv);
+    }
+    *kmin = 1e300;
+    *kmax = -1e300;
+    *rcmin = 1e300;
+    *rcmax = -1e300;
+    for (double T : ts) {
+        const double d = T - m.T_ref;
+        const double k = m.k0 + m.dk_dT * d;
+        const double rc = (m.rho0 + m.drho_dT * d) * (m.c0 + m.dc_dT * d);
+        *kmin = std::min(*kmin, k);
+        *kmax = std::max(*kmax, k);
+        *rcmin = std::min(*rcmin, rc);
+        *rcmax = std::max(*rcmax, rc);
+    }
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (a[0..k), b[1..k))
+// by Sturm-sequence bisection, and the last component of its unit
+// eigenvector by shifted inverse iteration.
+void tridiag_top(const std::vector<double>& a, const std::vector<double>& b, int k,
+                 double* theta, double* last) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; i++) {
+        const double r = (i > 0 ? std::fabs(b[i]) : 0.0) + (i + 1 < k ? std::fabs(b[i + 1]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto count_below = [&](double x) {
+        int c = 0;
+        double q = a[0] - x;
+        if (q < 0) c++;
+        for (int i = 1; i < k; i++) {
+            if (q == 0.0) q = 1e-300;
+            q = (a[i] - x) - b[i] * b[i] / q;
+            if (q < 0) c++;
+        }
+        return c;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(hi), 1e-300); it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= k)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    *theta = hi;
+    // inverse iteration with a shift just above theta: (T - s I) y = x
+    const double s = hi + 1e-9 * std::max(std::fabs(hi), 1e-300);
+    std::vector<double> y(k, 1.0), c(k), d(k);
+    for (int rep = 0; rep < 3; rep++) {
+        // Thomas algorithm on the (negative definite) shifted matrix
+        d[0] = a[0] - s;
+        std::vector<double> r = y;
+        for (int i = 1; i < k; i++) {
+            c[i] = b[i] / d[i - 1];
+            d[i] = (a[i] - s) - c[i] * b[i];
+            r[i] -= c[i] * r[i - 1];
+        }
+        y[k - 1] = r[k - 1] / d[k - 1];
+        for (int i = k - 2; i >= 0; i--) y[i] = (r[i] - b[i + 1] * y[i + 1]) / d[i];
+        double nrm = 0.0;
+        for (double v : y) nrm += v * v;
+        nrm = std::sqrt(nrm);
+        for (double& v : y) v /= nrm;
+    }
+    *last = y[k - 1];
+}
+
+// Quadrature points of the composite source rule: two regular (Bey)
+// refinements of the reference tetrahedron, then the symmetric 4-point
+// degree-2 rule on each of the 64 children, in barycentric coordinates.
+void make_quadrature(std::vector<double>& pts) {
+    struct Tet {
+        double v[4][4];
+    };
+    std::vector<Tet> level(1);
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) level[0].v[i][j] = (i == j) ? 1.0 : 0.0;
+    // child corner lists over {v0..v3, m01, m02, m03, m12, m13, m23}
+    static const int kids[8][4] = {{0, 4, 5, 6}, {4, 1, 7, 8}, {5, 7, 2, 9}, {6, 8, 9, 3},
+                                   {4, 5, 6, 8}, {4, 5, 7, 8}, {5, 6, 8, 9}, {5, 7, 8, 9}};
+    static const int mids[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int lv = 0; lv < 2; lv++) {
+        std::vector<Tet> next;
+        for (const Tet& t : level) {
+            double P[10][4];
+            for (int i = 0; i < 4; i++) std::memcpy(P[i], t.v[i], sizeof(P[i]));
+            for (int m = 0; m < 6; m++)
+                for (int c = 0; c < 4; c++)
+                    P[4 + m][c] = 0.5 * (t.v[mids[m][0]][c] + t.v[mids[m][1]][c]);
+            for (int k = 0; k < 8; k++) {
+                Tet ch;
+                for (int i = 0; i < 4; i++) std::memcpy(ch.v[i], P[kids[k][i]], sizeof(ch.v[i]));
+                next.push_back(ch);
+            }
+        }
+        level.swap(next);
+    }
+    const double wa = (5.0 + 3.0 * std::sqrt(5.0)) / 20.0;
+    const double wb = (5.0 - std::sqrt(5.0)) / 20.0;
+    pts.clear();
+    for (const Tet& t : level)
+        for (int q = 0; q < 4; q++)
+            for (int c = 0; c < 4; c++) {
+                double s = 0.0;
+                for (int k = 0; k < 4; k++) s += (k == q ? wa : wb) * t.v[k][c];
+                pts.push_back(s);
+            }
+}
+
+template <typename T>
+int dalloc(fedfem_handle* h, T** p, size_t count) {
+    void* q = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(h, FEDFEM_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    h->allocs.push_back(q);
+    h->dev_bytes += (int64_t)bytes;
+    *p = static_cast<T*>(q);
+    return FEDFEM_OK;
+}
+
+void dfree(fedfem_handle* h, void* p) {
+    if (!p) return;
+    auto it = std::find(h->allocs.begin(), h->allocs.end(), p);
+    if (it != h->allocs.end()) {
+        h->allocs.erase(it);
+        (void)hipFree(p);
+    }
+}
+
+template <typename T>
+int upload(fedfem_handle* h, T** dst, const std::vector<T>& src) {
+    int rc = dalloc(h, dst, src.size());
+    if (rc) return rc;
+    HIPCHK(h, hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice,
+                             h->own_stream));
+    return FEDFEM_OK;
+}
+
+void drop_graphs(fedfem_handle* h) {
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+}
+
+Props<float> props_f(const fedfem_handle* h) {
+    const fedfem_materials& m = h->mat;
+    Props<float> p;
+    p.k0 = (float)m.k0;
+    p.dk = (float)m.dk_dT;
+    p.rho0 = (float)m.rho0;
+    p.drho = (float)m.drho_dT;
+    p.c0 = (float)m.c0;
+    p.dc = (float)m.dc_dT;
+    p.Tref = (float)m.T_ref;
+    p.Tlo = (float)m.T_lo;
+    p.Thi = (float)m.T_hi;
+    p.wbcb = (float)(m.w_b * m.c_b);
+    p.Ta = (float)m.T_a;
+    p.Qm = (float)m.Q_m;
+    p.dt = (float)h->dt;
+    return p;
+}
+
+Props<double> props_d(const fedfem_handle* h) {
+    const fedfem_materials& m = h->mat;
+    Props<double> p;
+    p.k0 = m.k0;
+    p.dk = m.dk_dT;
+    p.rho0 = m.rho0;
+    p.drho = m.drho_dT;
+    p.c0 = m.c0;
+    p.dc = m.dc_dT;
+    p.Tref = m.T_ref;
+    p.Tlo = m.T_lo;
+    p.Thi = m.T_hi;
+    p.wbcb = m.w_b * m.c_b;
+    p.Ta = m.T_a;
+    p.Qm = m.Q_m;
+    p.dt = h->dt;
+    return p;
+}
+
+hipError_t launch_one_step(fedfem_handle* h, int cur, hipStream_t s) {
+    const bool td = h->mat.dk_dT != 0.0;
+    if (h->fp32c) return launch_step_f32c(h->d, cur, props_f(h), td, h->d_flag, s);
+    return launch_step_f64(h->d, cur, props_d(h), td, h->d_flag, s);
+}
+
+int get_graph(fedfem_handle* h, int64_t n, int cur, hipGraphExec_t* out) {
+    auto key = std::make_pair(n, cur);
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        *out = it->second;
+        return FEDFEM_OK;
+    }
+    if (h->graphs.size() >= 8) drop_graphs(h);
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int c = cur;
+    for (int64_t k = 0; k < n; k++) {
+        hipError_t e = launch_one_step(h, c, h->cap_stream);
+        if (e != hipSuccess) {
+            hipGraph_t g;
+            (void)hipStreamEndCapture(h->cap_stream, &g);
+            return hip_fail(h, e, "kernel launch during capture");
+        }
+        c ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(h, hipStreamEndCapture(h->cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
+    h->graphs[key] = ex;
+    *out = ex;
+    return FEDFEM_OK;
+}
+
+int check_handle(fedfem_handle* h, bool need_pre) {
+    if (!h) return FEDFEM_E_INVALID;
+    if (h->broken) return set_err(h, FEDFEM_E_HIP, "handle unusable after a HIP failure");
+    if (need_pre && !h->precomputed)
+        return set_err(h, FEDFEM_E_NOT_PRECOMPUTED, "fedfem_precompute has not run");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    return FEDFEM_OK;
+}
+
+int lanczos(fedfem_handle* h, const double* coef64) {
+    const int64_t N = h->N;
+    const int maxit = h->lz_max_iter;
+    double *sc, *v, *vprev, *w, *xs, *partial, *bsum, *alpha, *beta, *scal;
+    int rc = 0;
+    const int64_t nb = (N + 255) / 256;
+    if ((rc = dalloc(h, &sc, N)) || (rc = dalloc(h, &v, N)) || (rc = dalloc(h, &vprev, N)) ||
+        (rc = dalloc(h, &w, N)) || (rc = dalloc(h, &xs, N)) ||
+        (rc = dalloc(h, &partial, h->d.P)) || (rc = dalloc(h, &bsum, nb)) ||
+        (rc = dalloc(h, &alpha, maxit + 1)) || (rc = dalloc(h, &beta, maxit + 2)) ||
+        (rc = dalloc(h, &scal, 4)))
+        return rc;
+    HIPCHK(h, hipMemsetAsync(beta, 0, sizeof(double) * (maxit + 2), h->own_stream));
+    HIPCHK(h, launch_lanczos_start(N, h->d_Vi, h->d_isdir, sc, v, vprev, xs, bsum, scal,
+                                   h->own_stream));
+    std::vector<double> a(maxit + 1), b(maxit + 2);
+    double theta = 0.0, prev = -1.0, last = 0.0;
+    int k = 0;
+    for (int j = 0; j < maxit; j++) {
+        HIPCHK(h, launch_lanczos_iter(h->d, coef64, j, sc, v, vprev, w, xs, partial, bsum,
+                                      alpha, beta, h->own_stream));
+        k = j + 1;
+        if (k < 16 || k % 16 == 0 || k == maxit) {
+            HIPCHK(h, hipMemcpyAsync(a.data(), alpha, sizeof(double) * k,
+                                     hipMemcpyDeviceToHost, h->own_stream));
+            HIPCHK(h, hipMemcpyAsync(b.data(), beta, sizeof(double) * (k + 1),
+                                     hipMemcpyDeviceToHost, h->own_stream));
+            HIPCHK(h, hipStreamSynchronize(h->own_stream));
+            tridiag_top(a, b, k, &theta, &last);
+            const bool breakdown = b[k] <= 1e-13 * std::max(theta, 1e-300);
+            if (breakdown || std::fabs(theta - prev) <= 1e-11 * theta) break;
+            prev = theta;
+        }
+    }
+    h->lz_iters = k;
+    h->lam_ritz = theta;
+    h->lam_geo = theta + std::fabs(b[k] * last);
+    for (void* p : {(void*)sc, (void*)v, (void*)vprev, (void*)w, (void*)xs, (void*)partial,
+                    (void*)bsum, (void*)alpha, (void*)beta, (void*)scal})
+        dfree(h, p);
+    return FEDFEM_OK;
+}
+
+int release_device(fedfem_handle* h) {
+    drop_graphs(h);
+    for (void* p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+    h->dev_bytes = 0;
+    h->d = DevLayout();
+    return FEDFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fedfem_strerror(int code) {
+    switch (code) {
+        case FEDFEM_OK: return "ok";
+        case FEDFEM_E_INVALID: return "invalid argument";
+        case FEDFEM_E_DEGENERATE: return "degenerate element";
+        case FEDFEM_E_NOT_PRECOMPUTED: return "not precomputed";
+        case FEDFEM_E_UNSTABLE: return "time step not below the critical step";
+        case FEDFEM_E_DIVERGED: return "solution diverged";
+        case FEDFEM_E_HIP: return "HIP runtime failure";
+        case FEDFEM_E_NOMEM: return "out of memory";
+        case FEDFEM_E_STATE: return "call not valid in this state";
+        default: return "unknown error";
+    }
+}
+
+int fedfem_last_error(const fedfem_handle* h, char* buf, size_t len) {
+    if (!h || !buf || len == 0) return FEDFEM_E_INVALID;
+    std::snprintf(buf, len, "%s", h->err.c_str());
+    return FEDFEM_OK;
+}
+
+int fedfem_create(const fedfem_mesh* mesh, const fedfem_materials* mat, const fedfem_bc* bc,
+                  fedfem_handle** out) {
+    if (!out) return FEDFEM_E_INVALID;
+    *out = nullptr;
+    if (!mesh || !mat || !bc) return FEDFEM_E_INVALID;
+    const int64_t N = mesh->n_nodes, E = mesh->n_tets;
+    if (N < 4 || E < 1 || !mesh->xyz || !mesh->tets || N > INT32_MAX || 4 * E > INT32_MAX)
+        return FEDFEM_E_INVALID;
+    if (!finite_all(mesh->xyz, 3 * N)) return FEDFEM_E_INVALID;
+    fedfem_handle* h = new (std::nothrow) fedfem_handle();
+    if (!h) return FEDFEM_E_NOMEM;
+    auto fail = [&](int code) {
+        delete h;
+        return code;
+    };
+    try {
+        h->N = N;
+        h->E = E;
+        h->xyz.assign(mesh->xyz, mesh->xyz + 3 * N);
+        h->tets.assign(mesh->tets, mesh->tets + 4 * E);
+        std::vector<uint8_t> used(N, 0);
+        for (int64_t s = 0; s < 4 * E; s++) {
+            const int32_t n = h->tets[s];
+            if (n < 0 || n >= N) return fail(FEDFEM_E_INVALID);
+            used[n] = 1;
+        }
+        for (int64_t i = 0; i < N; i++)
+            if (!used[i]) return fail(FEDFEM_E_INVALID);
+        const fedfem_materials& m = *mat;
+        const double vals[] = {m.rho0, m.c0, m.k0, m.drho_dT, m.dc_dT, m.dk_dT, m.T_ref,
+                               m.T_lo, m.T_hi, m.w_b, m.c_b, m.T_a, m.Q_m};
+        if (!finite_all(vals, 13)) return fail(FEDFEM_E_INVALID);
+        if (!(m.T_lo < m.T_hi) || m.w_b < 0 || m.c_b < 0) return fail(FEDFEM_E_INVALID);
+        if (m.precision != FEDFEM_FP64 && m.precision != FEDFEM_FP32C)
+            return fail(FEDFEM_E_INVALID);
+        double kmin, kmax, rcmin, rcmax;
+        window_bounds(m, &kmin, &kmax, &rcmin, &rcmax);
+        if (!(kmin > 0) || !(rcmin > 0)) return fail(FEDFEM_E_INVALID);
+        h->mat = m;
+        h->fp32c = (m.precision == FEDFEM_FP32C);
+        if (!std::isfinite(bc->T0) || !std::isfinite(bc->dt) || bc->dt == 0.0 ||
+            bc->dt <= -1.0 || bc->n_dir < 0 || bc->n_dir > N)
+            return fail(FEDFEM_E_INVALID);
+        if (bc->n_dir > 0 && (!bc->dir_nodes || !bc->dir_T)) return fail(FEDFEM_E_INVALID);
+        h->T0 = bc->T0;
+        h->dt_spec = bc->dt;
+        std::vector<uint8_t> seen(N, 0);
+        for (int64_t k = 0; k < bc->n_dir; k++) {
+            const int32_t n = bc->dir_nodes[k];
+            if (n < 0 || n >= N || seen[n] || !std::isfinite(bc->dir_T[k]))
+                return fail(FEDFEM_E_INVALID);
+            seen[n] = 1;
+        }
+        h->dir_nodes.assign(bc->dir_nodes, bc->dir_nodes + bc->n_dir);
+        h->dir_T.assign(bc->dir_T, bc->dir_T + bc->n_dir);
+    } catch (const std::bad_alloc&) {
+        return fail(FEDFEM_E_NOMEM);
+    }
+    if (hipGetDevice(&h->device) != hipSuccess) return fail(FEDFEM_E_HIP);
+    if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(FEDFEM_E_HIP);
+    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(h->own_stream);
+        return fail(FEDFEM_E_HIP);
+    }
+    h->stream = h->own_stream;
+    h->opt.reorder = 1;
+    h->opt.tile_elems = 1024;
+    h->opt.threads = 256;
+    *out = h;
+    return FEDFEM_OK;
+}
+
+int fedfem_set_options(fedfem_handle* h, const fedfem_options* o) {
+    if (!h || !o) return FEDFEM_E_INVALID;
+    if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "options are fixed after precompute");
+    const int te = o->tile_elems ? o->tile_elems : 1024;
+    const int th = o->threads ? o->threads : 256;
+    if (te < 64 || te > 8192 || te % 64 || th < 64 || th > 1024 || th % 64 ||
+        (o->reorder != 0 && o->reorder != 1))
+        return set_err(h, FEDFEM_E_INVALID, "invalid options");
+    h->opt = *o;
+    h->opt.tile_elems = te;
+    h->opt.threads = th;
+    return FEDFEM_OK;
+}
+
+int fedfem_precompute(fedfem_handle* h) {
+    int rc = check_handle(h, false);
+    if (rc) return rc;
+    if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "already precomputed");
+    release_device(h);
+    const int64_t N = h->N, E = h->E;
+    hipDeviceProp_t prop;
+    HIPCHK(h, hipGetDeviceProperties(&prop, h->device));
+    const size_t lds_limit = prop.sharedMemPerBlock;
+    Layout& L = h->L;
+    std::string err;
+    int TE = h->opt.tile_elems;
+    try {
+        if (!build_layout(h->xyz.data(), h->tets.data(), N, E, h->opt.reorder, TE, L, err))
+            return set_err(h, FEDFEM_E_INVALID, "%s", err.c_str());
+        // shrink tiles until the widest kernel (FP64 loads) fits in LDS
+        while (tile_lds_bytes(L.tile_elems, L.max_tile_nodes, 8, false, true) > lds_limit) {
+            if (L.tile_elems <= 64)
+                return set_err(h, FEDFEM_E_INVALID, "tile does not fit in LDS");
+            if (!build_tiles(L, std::max(64, L.tile_elems / 128 * 64), err))
+                return set_err(h, FEDFEM_E_INVALID, "%s", err.c_str());
+        }
+    } catch (const std::bad_alloc&) {
+        return set_err(h, FEDFEM_E_NOMEM, "host allocation failed");
+    }
+    hipStream_t s = h->own_stream;
+    DevLayout& d = h->d;
+    d.N = N;
+    d.E = E;
+    d.T = L.T;
+    d.P = L.P;
+    d.tile_elems = L.tile_elems;
+    d.max_tile_nodes = L.max_tile_nodes;
+    d.threads = std::min(h->opt.threads, L.tile_elems);
+    // topology
+    if ((rc = upload(h, &d.tile_node_off, L.tile_node_off)) ||
+        (rc = upload(h, &d.tile_nodes, L.tile_nodes)) ||
+        (rc = upload(h, &d.seg_start, L.seg_start)) || (rc = upload(h, &d.slots, L.slots)) ||
+        (rc = upload(h, &d.part_off, L.part_off)) || (rc = upload(h, &d.part_idx, L.part_idx)) ||
+        (rc = upload(h, &h->d_ec_off, L.ec_off)) || (rc = upload(h, &h->d_ec, L.ec)) ||
+        (rc = upload(h, &h->d_conn, L.conn)) || (rc = upload(h, &h->d_xyz, L.xyz)) ||
+        (rc = upload(h, &h->d_nperm, L.nperm)))
+        return rc;
+    {
+        std::vector<int32_t> isd(N, 0);
+        std::vector<double> dT(N, 0.0);
+        for (size_t k = 0; k < h->dir_nodes.size(); k++) {
+            isd[L.ninv[h->dir_nodes[k]]] = 1;
+            dT[L.ninv[h->dir_nodes[k]]] = h->dir_T[k];
+        }
+        h->n_dir = (int64_t)h->dir_nodes.size();
+        if ((rc = upload(h, &h->d_isdir, isd)) || (rc = upload(h, &h->d_dirT, dT))) return rc;
+        h->host_isdir.swap(isd);
+    }
+    // geometry (Eq 15-16)
+    double* coef64 = nullptr;
+    int32_t* bad = nullptr;
+    int32_t* d_eperm = nullptr;
+    if ((rc = upload(h, &d_eperm, L.eperm))) return rc;
+    if ((rc = dalloc(h, &coef64, 6 * E)) || (rc = dalloc(h, &h->d_vol, E)) ||
+        (rc = dalloc(h, &bad, 1)) || (rc = dalloc(h, &h->d_Vi, N)) ||
+        (rc = dalloc(h, &h->d_flag, 4)) || (rc = dalloc(h, &h->d_stage, N)))
+        return rc;
+    HIPCHK(h, launch_fill_i32(bad, 1, INT32_MAX, s));
+    HIPCHK(h, launch_geometry(E, h->d_xyz, h->d_conn, d_eperm, coef64, h->d_vol, bad, s));
+    int32_t hbad = 0;
+    HIPCHK(h, hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(h, bad);
+    dfree(h, d_eperm);
+    if (hbad != INT32_MAX) {
+        release_device(h);
+        return set_err(h, FEDFEM_E_DEGENERATE, "degenerate tetrahedron %d", hbad);
+    }
+    HIPCHK(h, launch_lump(N, h->d_ec_off, h->d_ec, h->d_vol, h->d_Vi, s));
+    // time-stepping arrays in the chosen precision
+    const size_t rb = h->fp32c ? sizeof(float) : sizeof(double);
+    auto dalloc_bytes = [&](void** p, size_t count) -> int {
+        if (rb == 4) {
+            float* f;
+            int r = dalloc(h, &f, count);
+            *p = f;
+            return r;
+        }
+        double* g;
+        int r = dalloc(h, &g, count);
+        *p = g;
+        return r;
+    };
+    if (h->fp32c) {
+        if ((rc = dalloc_bytes(&d.coef, 6 * E))) return rc;
+        HIPCHK(h, launch_cast_coef(6 * E, coef64, static_cast<float*>(d.coef), s));
+    } else {
+        d.coef = coef64;
+    }
+    if ((rc = dalloc_bytes(&d.u, N)) || (rc = dalloc_bytes(&d.q, N)) ||
+        (rc = dalloc_bytes(&d.Thi[0], N)) || (rc = dalloc_bytes(&d.Thi[1], N)) ||
+        (rc = dalloc_bytes(&d.partial, d.P)))
+        return rc;
+    if (h->fp32c && ((rc = dalloc_bytes(&d.Tlo[0], N)) || (rc = dalloc_bytes(&d.Tlo[1], N))))
+        return rc;
+    HIPCHK(h, launch_node_init(N, h->d_Vi, h->d_isdir, h->d_dirT, h->T0, h->fp32c, d.u,
+                               d.Thi[0], d.Tlo[0], d.Thi[1], d.Tlo[1], s));
+    HIPCHK(h, launch_set_source(N, nullptr, nullptr, h->fp32c, d.q, s));
+    // critical step (Eq 9): top eigenvalue of the geometry pencil on free
+    // nodes, bounded over the property window
+    if (h->n_dir < N) {
+        rc = lanczos(h, coef64);
+        if (rc) return rc;
+    } else {
+        h->lam_geo = h->lam_ritz = 0.0;
+        h->lz_iters = 0;
+    }
+    if (h->fp32c) dfree(h, coef64);
+    double kmin, kmax, rcmin, rcmax;
+    window_bounds(h->mat, &kmin, &kmax, &rcmin, &rcmax);
+    const double lam = h->lam_geo * kmax / rcmin + h->mat.w_b * h->mat.c_b / rcmin;
+    h->dt_cr = lam > 0 ? 2.0 / lam : INFINITY;
+    {
+        std::vector<double> q;
+        make_quadrature(q);
+        if ((rc = upload(h, &h->d_qpts, q))) return rc;
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (h->dt_spec > 0) {
+        if (!(h->dt_spec < h->dt_cr)) {
+            h->dt = 0.0;
+            h->precomputed = true;
+            return set_err(h, FEDFEM_E_UNSTABLE, "dt %.9g is not below dt_cr %.9g", h->dt_spec,
+                           h->dt_cr);
+        }
+        h->dt = h->dt_spec;
+    } else {
+        if (!std::isfinite(h->dt_cr)) {
+            h->precomputed = true;
+            return set_err(h, FEDFEM_E_INVALID, "no finite critical step: give dt > 0");
+        }
+        h->dt = -h->dt_spec * h->dt_cr;
+    }
+    h->t = 0.0;
+    h->steps = 0;
+    h->cur = 0;
+    h->precomputed = true;
+    // host copies of the big arrays are no longer needed
+    std::vector<double>().swap(L.xyz);
+    std::vector<int32_t>().swap(L.conn);
+    std::vector<uint16_t>().swap(L.slots);
+    std::vector<int32_t>().swap(L.ec);
+    return FEDFEM_OK;
+}
+
+int fedfem_set_source(fedfem_handle* h, const double* source) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    hipStream_t s = h->stream;
+    if (source) {
+        if (!finite_all(source, h->N)) return set_err(h, FEDFEM_E_INVALID, "non-finite source");
+        HIPCHK(h, hipMemcpyAsync(h->d_stage, source, sizeof(double) * h->N,
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(h, launch_set_source(h->N, h->d_stage, h->d_nperm, h->fp32c, h->d.q, s));
+    } else {
+        HIPCHK(h, launch_set_source(h->N, nullptr, nullptr, h->fp32c, h->d.q, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    return FEDFEM_OK;
+}
+
+int fedfem_set_gaussian_sources(fedfem_handle* h, int32_t n_src, const double* params,
+                                int32_t mode) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (n_src < 0 || n_src > 4096 || (n_src > 0 && !params) ||
+        (mode != FEDFEM_SOURCE_NODAL && mode != FEDFEM_SOURCE_CONSISTENT))
+        return set_err(h, FEDFEM_E_INVALID, "bad source arguments");
+    for (int k = 0; k < n_src; k++) {
+        if (!finite_all(params + 5 * k, 5) || !(params[5 * k + 3] > 0))
+            return set_err(h, FEDFEM_E_INVALID, "bad Gaussian source %d", k);
+    }
+    hipStream_t s = h->stream;
+    if (n_src == 0) return fedfem_set_source(h, nullptr);
+    double* dsrc = nullptr;
+    if ((rc = dalloc(h, &dsrc, 5 * (size_t)n_src))) return rc;
+    HIPCHK(h, hipMemcpyAsync(dsrc, params, sizeof(double) * 5 * n_src, hipMemcpyHostToDevice, s));
+    if (mode == FEDFEM_SOURCE_NODAL) {
+        HIPCHK(h, launch_source_nodal(h->N, h->d_xyz, h->d_Vi, n_src, dsrc, h->d_stage, s));
+    } else {
+        double* slot = nullptr;
+        if ((rc = dalloc(h, &slot, 4 * (size_t)h->E))) {
+            dfree(h, dsrc);
+            return rc;
+        }
+        HIPCHK(h, launch_source_consistent(h->N, h->E, h->d_xyz, h->d_conn, h->d_vol,
+                                           h->d_ec_off, h->d_ec, n_src, dsrc, h->d_qpts, slot,
+                                           h->d_stage, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        dfree(h, slot);
+    }
+    HIPCHK(h, launch_set_source(h->N, h->d_stage, nullptr, h->fp32c, h->d.q, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(h, dsrc);
+    return FEDFEM_OK;
+}
+
+int fedfem_read_source(fedfem_handle* h, double* out) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!out) return FEDFEM_E_INVALID;
+    hipStream_t s = h->stream;
+    HIPCHK(h, launch_get_source(h->N, h->d.q, h->d_nperm, h->fp32c, h->d_stage, s));
+    HIPCHK(h, hipMemcpyAsync(out, h->d_stage, sizeof(double) * h->N, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return FEDFEM_OK;
+}
+
+int fedfem_step(fedfem_handle* h, int64_t n_steps, const double* source) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (n_steps < 0) return set_err(h, FEDFEM_E_INVALID, "negative step count");
+    if (!(h->dt > 0)) return set_err(h, FEDFEM_E_UNSTABLE, "no valid time step");
+    if (source && (rc = fedfem_set_source(h, source))) return rc;
+    if (n_steps == 0) return FEDFEM_OK;
+    hipStream_t s = h->stream;
+    HIPCHK(h, launch_fill_i32(h->d_flag, 1, 0, s));
+    int64_t left = n_steps;
+    while (left > 0) {
+        const int64_t chunk = std::min<int64_t>(left, 512);
+        hipGraphExec_t ex;
+        if ((rc = get_graph(h, chunk, h->cur, &ex))) return rc;
+        HIPCHK(h, hipGraphLaunch(ex, s));
+        if (chunk & 1) h->cur ^= 1;
+        left -= chunk;
+    }
+    int32_t flag = 0;
+    HIPCHK(h, hipMemcpyAsync(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->steps += n_steps;
+    h->t += (double)n_steps * h->dt;
+    if (flag) return set_err(h, FEDFEM_E_DIVERGED, "temperature left [-1e4, 1e4] degC or NaN");
+    return FEDFEM_OK;
+}
+
+int fedfem_time_kernels(fedfem_handle* h, int64_t n_steps, double* elem_ms, double* node_ms) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (n_steps <= 0 || n_steps > 10000 || !elem_ms || !node_ms)
+        return set_err(h, FEDFEM_E_INVALID, "bad arguments");
+    if (!(h->dt > 0)) return set_err(h, FEDFEM_E_UNSTABLE, "no valid time step");
+    hipStream_t s = h->stream;
+    std::vector<hipEvent_t> ev(2 * n_steps + 1);
+    for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
+    const bool td = h->mat.dk_dT != 0.0;
+    HIPCHK(h, launch_fill_i32(h->d_flag, 1, 0, s));
+    HIPCHK(h, hipEventRecord(ev[0], s));
+    for (int64_t k = 0; k < n_steps; k++) {
+        if (h->fp32c) {
+            HIPCHK(h, launch_elem_f32c(h->d, h->cur, props_f(h), td, s));
+            HIPCHK(h, hipEventRecord(ev[2 * k + 1], s));
+            HIPCHK(h, launch_node_f32c(h->d, h->cur, props_f(h), h->d_flag, s));
+        } else {
+            HIPCHK(h, launch_elem_f64(h->d, h->cur, props_d(h), td, s));
+            HIPCHK(h, hipEventRecord(ev[2 * k + 1], s));
+            HIPCHK(h, launch_node_f64(h->d, h->cur, props_d(h), h->d_flag, s));
+        }
+        HIPCHK(h, hipEventRecord(ev[2 * k + 2], s));
+        h->cur ^= 1;
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    double te = 0, tn = 0;
+    for (int64_t k = 0; k < n_steps; k++) {
+        float a = 0, b = 0;
+        HIPCHK(h, hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]));
+        HIPCHK(h, hipEventElapsedTime(&b, ev[2 * k + 1], ev[2 * k + 2]));
+        te += a;
+        tn += b;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    *elem_ms = te / n_steps;
+    *node_ms = tn / n_steps;
+    int32_t flag = 0;
+    HIPCHK(h, hipMemcpy(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+    h->steps += n_steps;
+    h->t += (double)n_steps * h->dt;
+    if (flag) return set_err(h, FEDFEM_E_DIVERGED, "temperature left [-1e4, 1e4] degC or NaN");
+    return FEDFEM_OK;
+}
+
+int fedfem_read_T(fedfem_handle* h, double* T_out) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!T_out) return FEDFEM_E_INVALID;
+    hipStream_t s = h->stream;
+    HIPCHK(h, launch_read_T(h->N, h->d.Thi[h->cur], h->d.Tlo[h->cur], h->d_nperm, h->fp32c,
+                            h->d_stage, s));
+    HIPCHK(h, hipMemcpyAsync(T_out, h->d_stage, sizeof(double) * h->N, hipMemcpyDeviceToHost,
+                             s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return FEDFEM_OK;
+}
+
+int fedfem_read_T_device(fedfem_handle* h, double* d_out) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!d_out) return FEDFEM_E_INVALID;
+    hipStream_t s = h->stream;
+    HIPCHK(h, launch_read_T(h->N, h->d.Thi[h->cur], h->d.Tlo[h->cur], h->d_nperm, h->fp32c,
+                            d_out, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return FEDFEM_OK;
+}
+
+int fedfem_get_dt(const fedfem_handle* h, double* dt, double* dt_cr) {
+    if (!h) return FEDFEM_E_INVALID;
+    if (!h->precomputed) return FEDFEM_E_NOT_PRECOMPUTED;
+    if (dt) *dt = h->dt;
+    if (dt_cr) *dt_cr = h->dt_cr;
+    return FEDFEM_OK;
+}
+
+int fedfem_get_time(const fedfem_handle* h, double* t, int64_t* steps) {
+    if (!h) return FEDFEM_E_INVALID;
+    if (t) *t = h->t;
+    if (steps) *steps = h->steps;
+    return FEDFEM_OK;
+}
+
+int fedfem_set_dt(fedfem_handle* h, double dt) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!(dt > 0) || !(dt < h->dt_cr))
+        return set_err(h, FEDFEM_E_UNSTABLE, "dt %.9g outside (0, %.9g)", dt, h->dt_cr);
+    if (dt != h->dt) drop_graphs(h);
+    h->dt = dt;
+    return FEDFEM_OK;
+}
+
+int fedfem_set_stream(fedfem_handle* h, void* stream) {
+    if (!h) return FEDFEM_E_INVALID;
+    h->stream = stream ? static_cast<hipStream_t>(stream) : h->own_stream;
+    return FEDFEM_OK;
+}
+
+int fedfem_state_bytes(const fedfem_handle* h, size_t* bytes) {
+    if (!h || !bytes) return FEDFEM_E_INVALID;
+    *bytes = (size_t)h->N * (h->fp32c ? 2 * sizeof(float) : sizeof(double));
+    return FEDFEM_OK;
+}
+
+int fedfem_read_state(fedfem_handle* h, void* buf, double* t, int64_t* steps) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!buf) return FEDFEM_E_INVALID;
+    size_t bytes = 0;
+    fedfem_state_bytes(h, &bytes);
+    hipStream_t s = h->stream;
+    HIPCHK(h, launch_state_io(h->N, h->d.Thi[h->cur], h->d.Tlo[h->cur], h->d_nperm, h->fp32c,
+                              h->d_stage, 1, s));
+    HIPCHK(h, hipMemcpyAsync(buf, h->d_stage, bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (t) *t = h->t;
+    if (steps) *steps = h->steps;
+    return FEDFEM_OK;
+}
+
+int fedfem_write_state(fedfem_handle* h, const void* buf, double t, int64_t steps) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!buf || !std::isfinite(t) || steps < 0) return FEDFEM_E_INVALID;
+    size_t bytes = 0;
+    fedfem_state_bytes(h, &bytes);
+    hipStream_t s = h->stream;
+    HIPCHK(h, hipMemcpyAsync(h->d_stage, buf, bytes, hipMemcpyHostToDevice, s));
+    for (int b = 0; b < 2; b++)
+        HIPCHK(h, launch_state_io(h->N, h->d.Thi[b], h->d.Tlo[b], h->d_nperm, h->fp32c,
+                                  h->d_stage, 0, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->t = t;
+    h->steps = steps;
+    return FEDFEM_OK;
+}
+
+int fedfem_get_info(const fedfem_handle* h, fedfem_info* info) {
+    if (!h || !info) return FEDFEM_E_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    info->n_nodes = h->N;
+    info->n_tets = h->E;
+    info->n_dirichlet = (int64_t)h->dir_nodes.size();
+    info->precision = h->mat.precision;
+    info->reorder = h->opt.reorder;
+    if (!h->precomputed) return FEDFEM_E_NOT_PRECOMPUTED;
+    info->n_tiles = h->d.T;
+    info->n_partials = h->d.P;
+    info->max_tile_nodes = h->d.max_tile_nodes;
+    info->tile_elems = h->d.tile_elems;
+    info->threads = h->d.threads;
+    info->device_bytes = h->dev_bytes;
+    info->lambda_geometry = h->lam_geo;
+    info->lanczos_iterations = h->lz_iters;
+    return FEDFEM_OK;
+}
+
+int fedfem_destroy(fedfem_handle* h) {
+    if (!h) return FEDFEM_OK;
+    (void)hipSetDevice(h->device);
+    if (h->own_stream) (void)hipStreamSynchronize(h->own_stream);
+    release_device(h);
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+    return FEDFEM_OK;
+}
+
+}  // extern "C"

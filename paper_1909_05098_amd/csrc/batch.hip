@@ -1,0 +1,408 @@
+// Batched execution of many independent scenarios (Algorithm 1 applied to
+// each) as one captured HIP graph.  The pre-computed layouts of all handles
+// are concatenated once; element tiles keep their per-scenario size, node
+// ranges are padded to whole 256-node blocks so a node block never mixes
+// scenarios.  At run time scenarios are ordered by step count, longest
+// first, so the scenarios still running at global step k are a prefix of the
+// tile and block lists and every launch covers exactly the active work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/fedfem.h"
+#include "handle.h"
+#include "internal.h"
+
+using namespace fedfem;
+
+struct fedfem_batch {
+    std::vector<fedfem_handle*> hs;
+    int S = 0;
+    bool fp32c = true;
+    int device = 0;
+    hipStream_t stream = nullptr, cap = nullptr;
+    DevLayout d;
+    std::vector<int64_t> node_off, elem_off, tile_off, pbase;
+    std::vector<int32_t> tile_count, block_count;
+    int32_t *tile_list = nullptr, *tile_elem_off = nullptr, *tile_scen = nullptr;
+    int32_t *block_list = nullptr, *block_scen = nullptr, *flags = nullptr;
+    void* props = nullptr;
+    std::vector<void*> allocs;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0.0;
+};
+
+namespace {
+
+template <typename T>
+hipError_t balloc(fedfem_batch* b, T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(16, count * sizeof(T)));
+    if (e != hipSuccess) return e;
+    b->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t bupload(fedfem_batch* b, T** p, const std::vector<T>& v) {
+    hipError_t e = balloc(b, p, v.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, b->stream);
+}
+
+void destroy_batch(fedfem_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (void* p : b->allocs) (void)hipFree(p);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+template <typename Real>
+Props<Real> props_of(const fedfem_handle* h) {
+    const fedfem_materials& m = h->mat;
+    Props<Real> p;
+    p.k0 = (Real)m.k0;
+    p.dk = (Real)m.dk_dT;
+    p.rho0 = (Real)m.rho0;
+    p.drho = (Real)m.drho_dT;
+    p.c0 = (Real)m.c0;
+    p.dc = (Real)m.dc_dT;
+    p.Tref = (Real)m.T_ref;
+    p.Tlo = (Real)m.T_lo;
+    p.Thi = (Real)m.T_hi;
+    p.wbcb = (Real)(m.w_b * m.c_b);
+    p.Ta = (Real)m.T_a;
+    p.Qm = (Real)m.Q_m;
+    p.dt = (Real)h->dt;
+    return p;
+}
+
+#define BCHK(expr)                                       \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) {                          \
+            destroy_batch(b);                            \
+            return FEDFEM_E_HIP;                         \
+        }                                                \
+    } while (0)
+
+#define RCHK(expr)                                       \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return FEDFEM_E_HIP;       \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch** out) {
+    if (!out || !handles || n <= 0) return FEDFEM_E_INVALID;
+    *out = nullptr;
+    for (int j = 0; j < n; j++) {
+        const fedfem_handle* h = handles[j];
+        if (!h || h->broken) return FEDFEM_E_INVALID;
+        if (!h->precomputed || !(h->dt > 0)) return FEDFEM_E_NOT_PRECOMPUTED;
+        if (h->fp32c != handles[0]->fp32c || h->device != handles[0]->device)
+            return FEDFEM_E_INVALID;
+        for (int k = 0; k < j; k++)
+            if (handles[k] == h) return FEDFEM_E_INVALID;
+    }
+    fedfem_batch* b = new (std::nothrow) fedfem_batch();
+    if (!b) return FEDFEM_E_NOMEM;
+    b->hs.assign(handles, handles + n);
+    b->S = n;
+    b->fp32c = handles[0]->fp32c;
+    b->device = handles[0]->device;
+    BCHK(hipSetDevice(b->device));
+    BCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    BCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    BCHK(hipEventCreate(&b->ev0));
+    BCHK(hipEventCreate(&b->ev1));
+    // offsets
+    int64_t Nt = 0, Et = 0, Tt = 0, Pt = 0;
+    int maxte = 0, maxn = 0;
+    b->node_off.resize(n + 1);
+    b->elem_off.resize(n + 1);
+    b->tile_off.resize(n + 1);
+    b->pbase.resize(n + 1);
+    for (int j = 0; j < n; j++) {
+        const fedfem_handle* h = handles[j];
+        b->node_off[j] = Nt;
+        b->elem_off[j] = Et;
+        b->tile_off[j] = Tt;
+        b->pbase[j] = Pt;
+        Nt += (h->N + 255) / 256 * 256;
+        Et += h->E;
+        Tt += h->d.T;
+        Pt += h->d.P;
+        maxte = std::max(maxte, h->d.tile_elems);
+        maxn = std::max(maxn, h->d.max_tile_nodes);
+    }
+    b->node_off[n] = Nt;
+    b->elem_off[n] = Et;
+    b->tile_off[n] = Tt;
+    b->pbase[n] = Pt;
+    if (Nt > INT32_MAX || 4 * Et > INT32_MAX || Pt > INT32_MAX) {
+        destroy_batch(b);
+        return FEDFEM_E_INVALID;
+    }
+    hipDeviceProp_t prop;
+    BCHK(hipGetDeviceProperties(&prop, b->device));
+    if (tile_lds_bytes(maxte, maxn, b->fp32c ? 4 : 8, b->fp32c, true) > prop.sharedMemPerBlock) {
+        destroy_batch(b);
+        return FEDFEM_E_INVALID;
+    }
+    DevLayout& d = b->d;
+    d.N = Nt;
+    d.E = Et;
+    d.T = Tt;
+    d.P = Pt;
+    d.tile_elems = maxte;
+    d.max_tile_nodes = maxn;
+    d.threads = 256;
+    // integer tables on the host
+    std::vector<int32_t> tno(Tt + 1), tnodes(Pt), poff(Nt + 1, 0), pidx(Pt), teo(Tt + 1),
+        tsc(Tt), bsc(Nt / 256);
+    std::vector<uint16_t> seg(Pt);
+    for (int j = 0; j < n; j++) {
+        const fedfem_handle* h = handles[j];
+        const Layout& L = h->L;
+        const int64_t no = b->node_off[j], to = b->tile_off[j], pb = b->pbase[j],
+                      eo = b->elem_off[j];
+        for (int64_t t = 0; t < h->d.T; t++) {
+            tno[to + t] = (int32_t)(L.tile_node_off[t] + pb);
+            teo[to + t] = (int32_t)(eo + t * h->d.tile_elems);
+            tsc[to + t] = j;
+        }
+        for (int64_t p = 0; p < h->d.P; p++) {
+            tnodes[pb + p] = (int32_t)(L.tile_nodes[p] + no);
+            seg[pb + p] = L.seg_start[p];
+            pidx[pb + p] = (int32_t)(L.part_idx[p] + pb);
+        }
+        const int64_t npad = b->node_off[j + 1] - no;
+        for (int64_t i = 0; i < npad; i++)
+            poff[no + i] = (int32_t)((i < h->N ? L.part_off[i] : L.part_off[h->N]) + pb);
+        for (int64_t k = no / 256; k < b->node_off[j + 1] / 256; k++) bsc[k] = j;
+    }
+    tno[Tt] = (int32_t)Pt;
+    teo[Tt] = (int32_t)Et;
+    poff[Nt] = (int32_t)Pt;
+    BCHK(bupload(b, &d.tile_node_off, tno));
+    BCHK(bupload(b, &d.tile_nodes, tnodes));
+    BCHK(bupload(b, &d.seg_start, seg));
+    BCHK(bupload(b, &d.part_off, poff));
+    BCHK(bupload(b, &d.part_idx, pidx));
+    BCHK(bupload(b, &b->tile_elem_off, teo));
+    BCHK(bupload(b, &b->tile_scen, tsc));
+    BCHK(bupload(b, &b->block_scen, bsc));
+    BCHK(balloc(b, &b->tile_list, Tt));
+    BCHK(balloc(b, &b->block_list, Nt / 256));
+    BCHK(balloc(b, &b->flags, n));
+    // numeric arrays
+    const size_t rb = b->fp32c ? 4 : 8;
+    auto ralloc = [&](void** p, size_t count) {
+        unsigned char* q = nullptr;
+        hipError_t e = balloc(b, &q, count * rb);
+        *p = q;
+        return e;
+    };
+    BCHK(balloc(b, &d.slots, 4 * Et));
+    BCHK(ralloc(&d.coef, 6 * Et));
+    BCHK(ralloc(&d.u, Nt));
+    BCHK(ralloc(&d.q, Nt));
+    BCHK(ralloc(&d.partial, Pt));
+    BCHK(ralloc(&b->props, n * (b->fp32c ? sizeof(Props<float>) : sizeof(Props<double>)) / rb + 1));
+    for (int k = 0; k < 2; k++) {
+        BCHK(ralloc(&d.Thi[k], Nt));
+        if (b->fp32c) BCHK(ralloc(&d.Tlo[k], Nt));
+    }
+    // padding nodes: u = -1 (never updated); copy each scenario's data
+    {
+        std::vector<unsigned char> neg(Nt * rb);
+        if (b->fp32c) {
+            std::vector<float> v(Nt, -1.0f);
+            std::memcpy(neg.data(), v.data(), Nt * rb);
+        } else {
+            std::vector<double> v(Nt, -1.0);
+            std::memcpy(neg.data(), v.data(), Nt * rb);
+        }
+        BCHK(hipMemcpyAsync(d.u, neg.data(), Nt * rb, hipMemcpyHostToDevice, b->stream));
+        BCHK(hipStreamSynchronize(b->stream));
+    }
+    for (int j = 0; j < n; j++) {
+        const fedfem_handle* h = handles[j];
+        const int64_t no = b->node_off[j], eo = b->elem_off[j];
+        BCHK(hipMemcpyAsync(d.slots + 4 * eo, h->d.slots, 4 * h->E * sizeof(uint16_t),
+                            hipMemcpyDeviceToDevice, b->stream));
+        for (int k = 0; k < 6; k++)
+            BCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.coef) + (k * Et + eo) * rb,
+                                static_cast<const unsigned char*>(h->d.coef) + k * h->E * rb,
+                                h->E * rb, hipMemcpyDeviceToDevice, b->stream));
+        BCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.u) + no * rb, h->d.u, h->N * rb,
+                            hipMemcpyDeviceToDevice, b->stream));
+    }
+    BCHK(hipStreamSynchronize(b->stream));
+    *out = b;
+    return FEDFEM_OK;
+}
+
+int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps) {
+    if (!b || !n_steps) return FEDFEM_E_INVALID;
+    const int S = b->S;
+    for (int j = 0; j < S; j++) {
+        if (n_steps[j] < 0 || n_steps[j] > 100000000) return FEDFEM_E_INVALID;
+        const fedfem_handle* h = b->hs[j];
+        if (h->broken || !h->precomputed || !(h->dt > 0)) return FEDFEM_E_STATE;
+    }
+    RCHK(hipSetDevice(b->device));
+    DevLayout& d = b->d;
+    const size_t rb = b->fp32c ? 4 : 8;
+    // longest first: active scenarios form a prefix
+    std::vector<int> ord(S);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int x, int y) { return n_steps[x] > n_steps[y]; });
+    std::vector<int32_t> tl, bl;
+    std::vector<int64_t> tcum(S + 1, 0), bcum(S + 1, 0);
+    for (int r = 0; r < S; r++) {
+        const int j = ord[r];
+        for (int64_t t = b->tile_off[j]; t < b->tile_off[j + 1]; t++) tl.push_back((int32_t)t);
+        for (int64_t k = b->node_off[j] / 256; k < b->node_off[j + 1] / 256; k++)
+            bl.push_back((int32_t)k);
+        tcum[r + 1] = (int64_t)tl.size();
+        bcum[r + 1] = (int64_t)bl.size();
+    }
+    RCHK(hipMemcpyAsync(b->tile_list, tl.data(), tl.size() * 4, hipMemcpyHostToDevice,
+                        b->stream));
+    RCHK(hipMemcpyAsync(b->block_list, bl.data(), bl.size() * 4, hipMemcpyHostToDevice,
+                        b->stream));
+    // per-scenario parameters (dt may have changed since creation)
+    if (b->fp32c) {
+        std::vector<Props<float>> p(S);
+        for (int j = 0; j < S; j++) p[j] = props_of<float>(b->hs[j]);
+        RCHK(hipMemcpyAsync(b->props, p.data(), S * sizeof(p[0]), hipMemcpyHostToDevice,
+                            b->stream));
+    } else {
+        std::vector<Props<double>> p(S);
+        for (int j = 0; j < S; j++) p[j] = props_of<double>(b->hs[j]);
+        RCHK(hipMemcpyAsync(b->props, p.data(), S * sizeof(p[0]), hipMemcpyHostToDevice,
+                            b->stream));
+    }
+    // copy-in of each scenario's state (both buffers) and source
+    for (int j = 0; j < S; j++) {
+        fedfem_handle* h = b->hs[j];
+        const int64_t no = b->node_off[j];
+        for (int k = 0; k < 2; k++) {
+            RCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.Thi[k]) + no * rb,
+                                h->d.Thi[h->cur], h->N * rb, hipMemcpyDeviceToDevice,
+                                b->stream));
+            if (b->fp32c)
+                RCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.Tlo[k]) + no * rb,
+                                    h->d.Tlo[h->cur], h->N * rb, hipMemcpyDeviceToDevice,
+                                    b->stream));
+        }
+        RCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.q) + no * rb, h->d.q, h->N * rb,
+                            hipMemcpyDeviceToDevice, b->stream));
+    }
+    RCHK(launch_fill_i32(b->flags, S, 0, b->stream));
+    // graph of the whole run
+    std::vector<int64_t> key(n_steps, n_steps + S);
+    const int64_t nmax = S ? n_steps[ord[0]] : 0;
+    hipGraphExec_t ex = nullptr;
+    auto it = b->graphs.find(key);
+    if (it != b->graphs.end()) {
+        ex = it->second;
+    } else if (nmax > 0) {
+        if (b->graphs.size() >= 4) {
+            for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+            b->graphs.clear();
+        }
+        BatchTables tb;
+        tb.tile_list = b->tile_list;
+        tb.tile_elem_off = b->tile_elem_off;
+        tb.tile_scen = b->tile_scen;
+        tb.block_list = b->block_list;
+        tb.block_scen = b->block_scen;
+        tb.props = b->props;
+        RCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        int r = S;  // number of active scenarios (prefix of ord)
+        hipError_t err = hipSuccess;
+        for (int64_t k = 0; k < nmax && err == hipSuccess; k++) {
+            while (r > 0 && n_steps[ord[r - 1]] <= k) r--;
+            const int cur = (int)(k & 1);
+            err = launch_elem_batch(d, tb, cur, (int)tcum[r], b->fp32c, b->cap);
+            if (err == hipSuccess)
+                err = launch_node_batch(d, tb, cur, (int)bcum[r], b->fp32c, b->flags, b->cap);
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return FEDFEM_E_HIP;
+        }
+        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        RCHK(e3);
+        b->graphs[key] = ex;
+    }
+    RCHK(hipEventRecord(b->ev0, b->stream));
+    if (ex) RCHK(hipGraphLaunch(ex, b->stream));
+    RCHK(hipEventRecord(b->ev1, b->stream));
+    // copy-out into each handle's current buffer
+    for (int j = 0; j < S; j++) {
+        fedfem_handle* h = b->hs[j];
+        const int64_t no = b->node_off[j];
+        const int fin = (int)(n_steps[j] & 1);
+        RCHK(hipMemcpyAsync(h->d.Thi[h->cur], static_cast<unsigned char*>(d.Thi[fin]) + no * rb,
+                            h->N * rb, hipMemcpyDeviceToDevice, b->stream));
+        if (b->fp32c)
+            RCHK(hipMemcpyAsync(h->d.Tlo[h->cur],
+                                static_cast<unsigned char*>(d.Tlo[fin]) + no * rb, h->N * rb,
+                                hipMemcpyDeviceToDevice, b->stream));
+    }
+    std::vector<int32_t> fl(S);
+    RCHK(hipMemcpyAsync(fl.data(), b->flags, S * 4, hipMemcpyDeviceToHost, b->stream));
+    RCHK(hipStreamSynchronize(b->stream));
+    float ms = 0.0f;
+    RCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    b->last_ms = ms;
+    int rc = FEDFEM_OK;
+    for (int j = 0; j < S; j++) {
+        fedfem_handle* h = b->hs[j];
+        h->steps += n_steps[j];
+        h->t += (double)n_steps[j] * h->dt;
+        if (fl[j]) {
+            h->err = "temperature left [-1e4, 1e4] degC or NaN in a batched run";
+            rc = FEDFEM_E_DIVERGED;
+        }
+    }
+    return rc;
+}
+
+int fedfem_batch_last_ms(const fedfem_batch* b, double* ms) {
+    if (!b || !ms) return FEDFEM_E_INVALID;
+    *ms = b->last_ms;
+    return FEDFEM_OK;
+}
+
+int fedfem_batch_destroy(fedfem_batch* b) {
+    destroy_batch(b);
+    return FEDFEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,488 @@
+// Pre-computation kernels for gfx950, double precision (Algorithm 1,
+// pre-computation block; Eq 15-16; Sec 2.3.4-2.3.5), plus the small
+// gather/scatter kernels that move nodal data between the caller's node
+// order and the internal one.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace fedfem {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(int64_t n, int bs = kBlock) {
+    return (unsigned)((n + bs - 1) / bs);
+}
+
+// Element geometry.  With edge vectors e_k = x_k - x_0 (the Jacobian's
+// columns), the rows of J^-1 are (e2 x e3, e3 x e1, e1 x e2) / det J, which
+// are the gradients of N_1..N_3; grad N_0 = -(sum of the others).  The
+// element matrix A = V_tet B^T B (Eq 15-16) has zero row sums, so its six
+// off-diagonal entries a_ab = V grad N_a . grad N_b define it.
+__global__ void k_geometry(int64_t E, const double* __restrict__ xyz,
+                           const int32_t* __restrict__ conn, const int32_t* __restrict__ eperm,
+                           double* __restrict__ coef, double* __restrict__ vol,
+                           int32_t* __restrict__ bad) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double p[4][3];
+    for (int c = 0; c < 4; c++) {
+        const int64_t n = conn[4 * e + c];
+        p[c][0] = xyz[3 * n];
+        p[c][1] = xyz[3 * n + 1];
+        p[c][2] = xyz[3 * n + 2];
+    }
+    double ed[3][3];
+    for (int k = 0; k < 3; k++)
+        for (int a = 0; a < 3; a++) ed[k][a] = p[k + 1][a] - p[0][a];
+    auto cross = [](const double* u, const double* v, double* w) {
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    double g[4][3];
+    cross(ed[1], ed[2], g[1]);
+    cross(ed[2], ed[0], g[2]);
+    cross(ed[0], ed[1], g[3]);
+    const double det = ed[0][0] * g[1][0] + ed[0][1] * g[1][1] + ed[0][2] * g[1][2];
+    double l2max = 0.0;
+    for (int a = 0; a < 4; a++)
+        for (int b = a + 1; b < 4; b++) {
+            const double dx = p[a][0] - p[b][0], dy = p[a][1] - p[b][1],
+                         dz = p[a][2] - p[b][2];
+            l2max = fmax(l2max, dx * dx + dy * dy + dz * dz);
+        }
+    const double lmax = sqrt(l2max);
+    if (!(fabs(det) > 1e-12 * lmax * lmax * lmax)) {
+        atomicMin(bad, eperm[e]);  // smallest caller element id
+        for (int k = 0; k < 6; k++) coef[k * E + e] = 0.0;
+        vol[e] = 0.0;
+        return;
+    }
+    const double inv = 1.0 / det;
+    for (int k = 1; k < 4; k++)
+        for (int a = 0; a < 3; a++) g[k][a] *= inv;
+    for (int a = 0; a < 3; a++) g[0][a] = -(g[1][a] + g[2][a] + g[3][a]);
+    const double V = fabs(det) / 6.0;
+    vol[e] = V;
+    const int pa[6] = {0, 0, 0, 1, 1, 2};
+    const int pb[6] = {1, 2, 3, 2, 3, 3};
+    for (int k = 0; k < 6; k++) {
+        const double* u = g[pa[k]];
+        const double* v = g[pb[k]];
+        coef[k * E + e] = V * (u[0] * v[0] + u[1] * v[1] + u[2] * v[2]);
+    }
+}
+
+// Lumped nodal volume: each element gives a quarter of its volume to each
+// of its nodes (Sec 2.3.4), summed in ascending element order.
+__global__ void k_lump(int64_t N, const int32_t* __restrict__ off,
+                       const int32_t* __restrict__ ec, const double* __restrict__ vol,
+                       double* __restrict__ Vi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int k = off[i]; k < off[i + 1]; k++) s += 0.25 * vol[ec[k] >> 2];
+    Vi[i] = s;
+}
+
+__device__ inline double gauss_at(const double* x, const double* g) {
+    const double dx = x[0] - g[0], dy = x[1] - g[1], dz = x[2] - g[2];
+    return g[4] * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * g[3] * g[3]));
+}
+
+__global__ void k_source_nodal(int64_t N, const double* __restrict__ xyz,
+                               const double* __restrict__ Vi, int n_src,
+                               const double* __restrict__ src, double* __restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int k = 0; k < n_src; k++) s += gauss_at(xyz + 3 * i, src + 5 * k);
+    q[i] = s * Vi[i];
+}
+
+// Consistent nodal heat flow: per element, the 256-point composite rule in
+// barycentric coordinates of the element with its corners taken in
+// lexicographic coordinate order; N_c at a point is its c-th barycentric
+// coordinate.  Elements whose bounding sphere is beyond 8 sigma of a source
+// get nothing from it.
+__global__ void k_source_elem(int64_t E, const double* __restrict__ xyz,
+                              const int32_t* __restrict__ conn,
+                              const double* __restrict__ vol, int n_src,
+                              const double* __restrict__ src,
+                              const double* __restrict__ qpts, double* __restrict__ slot) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double p[4][3];
+    int ord[4];
+    for (int c = 0; c < 4; c++) {
+        const int64_t n = conn[4 * e + c];
+        p[c][0] = xyz[3 * n];
+        p[c][1] = xyz[3 * n + 1];
+        p[c][2] = xyz[3 * n + 2];
+        ord[c] = c;
+    }
+    // rank corners by (x, y, z)
+    for (int i = 0; i < 4; i++)
+        for (int j = i + 1; j < 4; j++) {
+            const double* u = p[ord[i]];
+            const double* v = p[ord[j]];
+            const bool later = u[0] > v[0] || (u[0] == v[0] && (u[1] > v[1] ||
+                                                (u[1] == v[1] && u[2] > v[2])));
+            if (later) {
+                const int t = ord[i];
+                ord[i] = ord[j];
+                ord[j] = t;
+            }
+        }
+    double cen[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 4; c++)
+        for (int a = 0; a < 3; a++) cen[a] += 0.25 * p[c][a];
+    double r2 = 0.0;
+    for (int c = 0; c < 4; c++) {
+        const double dx = p[c][0] - cen[0], dy = p[c][1] - cen[1], dz = p[c][2] - cen[2];
+        r2 = fmax(r2, dx * dx + dy * dy + dz * dz);
+    }
+    const double rad = sqrt(r2);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < n_src; k++) {
+        const double* g = src + 5 * k;
+        const double dx = cen[0] - g[0], dy = cen[1] - g[1], dz = cen[2] - g[2];
+        if (sqrt(dx * dx + dy * dy + dz * dz) - rad > 8.0 * g[3]) continue;
+        for (int qi = 0; qi < 256; qi++) {
+            const double* b = qpts + 4 * qi;
+            double x[3];
+            for (int a = 0; a < 3; a++)
+                x[a] = b[0] * p[ord[0]][a] + b[1] * p[ord[1]][a] + b[2] * p[ord[2]][a] +
+                       b[3] * p[ord[3]][a];
+            const double f = gauss_at(x, g);
+            for (int r = 0; r < 4; r++) acc[r] += f * b[r];
+        }
+    }
+    for (int r = 0; r < 4; r++) slot[4 * e + ord[r]] = acc[r] * vol[e] / 256.0;
+}
+
+__global__ void k_gather_slots(int64_t N, const int32_t* __restrict__ off,
+                               const int32_t* __restrict__ ec,
+                               const double* __restrict__ slot, double* __restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int k = off[i]; k < off[i + 1]; k++) s += slot[ec[k]];
+    q[i] = s;
+}
+
+__global__ void k_cast(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+template <typename Real>
+__global__ void k_node_init(int64_t N, const double* __restrict__ Vi,
+                            const int32_t* __restrict__ is_dir,
+                            const double* __restrict__ dirT, double T0, Real* __restrict__ u,
+                            Real* __restrict__ h0, Real* __restrict__ l0,
+                            Real* __restrict__ h1, Real* __restrict__ l1) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const bool d = is_dir[i] != 0;
+    u[i] = d ? Real(-1) : Real(1.0 / Vi[i]);
+    const double T = d ? dirT[i] : T0;
+    const Real hi = (Real)T;
+    h0[i] = hi;
+    h1[i] = hi;
+    if (l0) {
+        const Real lo = (Real)(T - (double)hi);
+        l0[i] = lo;
+        l1[i] = lo;
+    }
+}
+
+template <typename Real>
+__global__ void k_set_source(int64_t N, const double* __restrict__ src,
+                             const int32_t* __restrict__ nperm, Real* __restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    q[i] = (Real)(src ? src[nperm ? nperm[i] : i] : 0.0);
+}
+
+template <typename Real>
+__global__ void k_get_source(int64_t N, const Real* __restrict__ q,
+                             const int32_t* __restrict__ nperm, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    out[nperm[i]] = (double)q[i];
+}
+
+template <typename Real>
+__global__ void k_read_T(int64_t N, const Real* __restrict__ hi, const Real* __restrict__ lo,
+                         const int32_t* __restrict__ nperm, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    out[nperm[i]] = (double)hi[i] + (lo ? (double)lo[i] : 0.0);
+}
+
+template <typename Real>
+__global__ void k_state_io(int64_t N, Real* __restrict__ hi, Real* __restrict__ lo,
+                           const int32_t* __restrict__ nperm, Real* __restrict__ buf,
+                           int to_buf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int64_t o = nperm[i];
+    if (to_buf) {
+        buf[o] = hi[i];
+        if (lo) buf[N + o] = lo[i];
+    } else {
+        hi[i] = buf[o];
+        if (lo) lo[i] = buf[N + o];
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---- Lanczos on B = S K S, S = diag(1/sqrt(V_i)) on free nodes, 0 else ----
+
+__device__ inline double block_sum(double v, double* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__device__ inline double hash_unit(uint64_t x) {
+    // splitmix64 finaliser, mapped to [-1, 1)
+    x += 0x9e3779b97f4a7c15ULL;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void k_lz_init(int64_t N, const double* __restrict__ Vi,
+                          const int32_t* __restrict__ is_dir, double* __restrict__ sc,
+                          double* __restrict__ v, double* __restrict__ bsum) {
+    __shared__ double sh[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double vv = 0.0;
+    if (i < N) {
+        const bool d = is_dir[i] != 0;
+        sc[i] = d ? 0.0 : 1.0 / sqrt(Vi[i]);
+        vv = d ? 0.0 : hash_unit((uint64_t)i);
+        v[i] = vv;
+    }
+    const double s = block_sum(vv * vv, sh);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+// out[0] = sum of in[0..n) (op 0), or sqrt of it (op 1); fixed order.
+__global__ void k_reduce(const double* __restrict__ in, int64_t n, double* __restrict__ out,
+                         int op) {
+    __shared__ double sh[1024];
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) s += in[k];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[0] = op ? sqrt(s) : s;
+}
+
+__global__ void k_lz_scale(int64_t N, const double* __restrict__ norm, const double* __restrict__ sc,
+                           double* __restrict__ v, double* __restrict__ vprev,
+                           double* __restrict__ xs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double nv = norm[0];
+    const double x = nv > 0.0 ? v[i] / nv : 0.0;
+    v[i] = x;
+    vprev[i] = 0.0;
+    xs[i] = sc[i] * x;
+}
+
+__global__ void k_lz_w(int64_t N, const int32_t* __restrict__ part_off,
+                       const int32_t* __restrict__ part_idx, const double* __restrict__ partial,
+                       const double* __restrict__ sc, const double* __restrict__ v,
+                       const double* __restrict__ vprev, const double* __restrict__ beta_j,
+                       double* __restrict__ w, double* __restrict__ bsum) {
+    __shared__ double sh[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double prod = 0.0;
+    if (i < N) {
+        double F = 0.0;
+        for (int k = part_off[i]; k < part_off[i + 1]; k++) F += partial[part_idx[k]];
+        const double wi = sc[i] * F - beta_j[0] * vprev[i];
+        w[i] = wi;
+        prod = v[i] * wi;
+    }
+    const double s = block_sum(prod, sh);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+__global__ void k_lz_orth(int64_t N, const double* __restrict__ alpha_j,
+                          const double* __restrict__ v, double* __restrict__ w,
+                          double* __restrict__ bsum) {
+    __shared__ double sh[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (i < N) {
+        const double wi = w[i] - alpha_j[0] * v[i];
+        w[i] = wi;
+        sq = wi * wi;
+    }
+    const double s = block_sum(sq, sh);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+__global__ void k_lz_next(int64_t N, const double* __restrict__ beta_next,
+                          const double* __restrict__ sc, const double* __restrict__ w,
+                          double* __restrict__ v, double* __restrict__ vprev,
+                          double* __restrict__ xs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double b = beta_next[0];
+    const double x = b > 1e-300 ? w[i] / b : 0.0;
+    vprev[i] = v[i];
+    v[i] = x;
+    xs[i] = sc[i] * x;
+}
+
+}  // namespace
+
+hipError_t launch_geometry(int64_t E, const double* xyz, const int32_t* conn,
+                           const int32_t* eperm, double* coef64, double* vol, int32_t* bad,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_geometry, dim3(blocks_for(E)), dim3(kBlock), 0, s, E, xyz, conn, eperm,
+                       coef64, vol, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_lump(int64_t N, const int32_t* ec_off, const int32_t* ec, const double* vol,
+                       double* Vi, hipStream_t s) {
+    hipLaunchKernelGGL(k_lump, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, ec_off, ec, vol, Vi);
+    return hipGetLastError();
+}
+
+hipError_t launch_source_nodal(int64_t N, const double* xyz, const double* Vi, int n_src,
+                               const double* src, double* q64, hipStream_t s) {
+    hipLaunchKernelGGL(k_source_nodal, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, xyz, Vi,
+                       n_src, src, q64);
+    return hipGetLastError();
+}
+
+hipError_t launch_source_consistent(int64_t N, int64_t E, const double* xyz,
+                                    const int32_t* conn, const double* vol,
+                                    const int32_t* ec_off, const int32_t* ec, int n_src,
+                                    const double* src, const double* qpts, double* slot64,
+                                    double* q64, hipStream_t s) {
+    hipLaunchKernelGGL(k_source_elem, dim3(blocks_for(E, 128)), dim3(128), 0, s, E, xyz, conn,
+                       vol, n_src, src, qpts, slot64);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, ec_off, ec,
+                       slot64, q64);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_coef(int64_t n, const double* src, float* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_init(int64_t N, const double* Vi, const int32_t* is_dir,
+                            const double* dirT, double T0, int fp32c, void* u, void* Thi0,
+                            void* Tlo0, void* Thi1, void* Tlo1, hipStream_t s) {
+    if (fp32c)
+        hipLaunchKernelGGL(k_node_init<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, Vi,
+                           is_dir, dirT, T0, (float*)u, (float*)Thi0, (float*)Tlo0,
+                           (float*)Thi1, (float*)Tlo1);
+    else
+        hipLaunchKernelGGL(k_node_init<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, Vi,
+                           is_dir, dirT, T0, (double*)u, (double*)Thi0, (double*)nullptr,
+                           (double*)Thi1, (double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_source(int64_t N, const double* src64, const int32_t* nperm, int fp32c,
+                             void* q, hipStream_t s) {
+    if (fp32c)
+        hipLaunchKernelGGL(k_set_source<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           src64, nperm, (float*)q);
+    else
+        hipLaunchKernelGGL(k_set_source<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           src64, nperm, (double*)q);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_source(int64_t N, const void* q, const int32_t* nperm, int fp32c,
+                             double* out64, hipStream_t s) {
+    if (fp32c)
+        hipLaunchKernelGGL(k_get_source<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           (const float*)q, nperm, out64);
+    else
+        hipLaunchKernelGGL(k_get_source<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           (const double*)q, nperm, out64);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_T(int64_t N, const void* Thi, const void* Tlo, const int32_t* nperm,
+                         int fp32c, double* out, hipStream_t s) {
+    if (fp32c)
+        hipLaunchKernelGGL(k_read_T<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           (const float*)Thi, (const float*)Tlo, nperm, out);
+    else
+        hipLaunchKernelGGL(k_read_T<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           (const double*)Thi, (const double*)nullptr, nperm, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_io(int64_t N, void* Thi, void* Tlo, const int32_t* nperm, int fp32c,
+                           void* buf, int to_buf, hipStream_t s) {
+    if (fp32c)
+        hipLaunchKernelGGL(k_state_io<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           (float*)Thi, (float*)Tlo, nperm, (float*)buf, to_buf);
+    else
+        hipLaunchKernelGGL(k_state_io<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
+                           (double*)Thi, (double*)nullptr, nperm, (double*)buf, to_buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos_start(int64_t N, const double* Vi, const int32_t* is_dir, double* sc,
+                                double* v, double* vprev, double* xs, double* bsum,
+                                double* scal, hipStream_t s) {
+    const unsigned nb = blocks_for(N);
+    hipLaunchKernelGGL(k_lz_init, dim3(nb), dim3(kBlock), 0, s, N, Vi, is_dir, sc, v, bsum);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, scal, 1);
+    hipLaunchKernelGGL(k_lz_scale, dim3(nb), dim3(kBlock), 0, s, N, scal, sc, v, vprev, xs);
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64, int j,
+                               const double* sc, double* v, double* vprev, double* w,
+                               double* xs, double* partial, double* bsum, double* alpha,
+                               double* beta, hipStream_t s) {
+    const unsigned nb = blocks_for(d.N);
+    hipError_t e = launch_geometry_apply(d, coef64, xs, partial, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lz_w, dim3(nb), dim3(kBlock), 0, s, d.N, d.part_off, d.part_idx,
+                       partial, sc, v, vprev, beta + j, w, bsum);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, alpha + j, 0);
+    hipLaunchKernelGGL(k_lz_orth, dim3(nb), dim3(kBlock), 0, s, d.N, alpha + j, v, w, bsum);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, beta + j + 1,
+                       1);
+    hipLaunchKernelGGL(k_lz_next, dim3(nb), dim3(kBlock), 0, s, d.N, beta + j + 1, sc, w, v,
+                       vprev, xs);
+    return hipGetLastError();
+}
+
+}  // namespace fedfem

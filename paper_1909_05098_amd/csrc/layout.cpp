@@ -1,0 +1,213 @@
+// Host-side mesh layout: Morton renumbering, element tiles with their node
+// groups, and the node -> partial / node -> element-corner lists.  Integer
+// topology only; all floating-point pre-computation runs on the GPU.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "internal.h"
+
+namespace fedfem {
+
+namespace {
+
+// Spread the low 21 bits of v so that bit i lands on bit 3i.
+inline uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffULL;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+// Stable LSD radix sort of (key, id) pairs by key, 16-bit digits.
+void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& id,
+                      int key_bits) {
+    const size_t n = key.size();
+    std::vector<uint64_t> k2(n);
+    std::vector<int32_t> i2(n);
+    std::vector<size_t> cnt(1 << 16);
+    for (int shift = 0; shift < key_bits; shift += 16) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t i = 0; i < n; i++) cnt[(key[i] >> shift) & 0xffff]++;
+        size_t run = 0;
+        for (auto& c : cnt) {
+            size_t t = c;
+            c = run;
+            run += t;
+        }
+        for (size_t i = 0; i < n; i++) {
+            size_t pos = cnt[(key[i] >> shift) & 0xffff]++;
+            k2[pos] = key[i];
+            i2[pos] = id[i];
+        }
+        key.swap(k2);
+        id.swap(i2);
+    }
+}
+
+template <typename F>
+void parallel_for(int64_t n, F&& body) {
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 4096 || nt == 1) {
+        body(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; t++) {
+        int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([&body, a, b] { body(a, b); });
+    }
+    for (auto& t : th) t.join();
+}
+
+}  // namespace
+
+std::vector<int32_t> morton_order(const double* pts, int64_t n) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = std::min(lo[a], pts[3 * i + a]);
+            hi[a] = std::max(hi[a], pts[3 * i + a]);
+        }
+    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    double scale = 2097151.0 / ext;  // 21 bits per axis, same scale on all
+    std::vector<uint64_t> key(n);
+    std::vector<int32_t> id(n);
+    for (int64_t i = 0; i < n; i++) {
+        uint64_t q[3];
+        for (int a = 0; a < 3; a++) {
+            double v = (pts[3 * i + a] - lo[a]) * scale;
+            q[a] = (uint64_t)std::min(2097151.0, std::max(0.0, v));
+        }
+        key[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+        id[i] = (int32_t)i;
+    }
+    radix_sort_pairs(key, id, 64);
+    return id;
+}
+
+bool build_tiles(Layout& L, int TE, std::string& err) {
+    if (TE < 64 || TE > 8192 || TE % 64) {
+        err = "tile_elems must be a multiple of 64 in [64, 8192]";
+        return false;
+    }
+    const int64_t E = L.E, N = L.N;
+    const int64_t T = (E + TE - 1) / TE;
+    L.tile_elems = TE;
+    L.T = T;
+    // pass 1: sort each tile's corners by (node, slot), count distinct nodes
+    std::vector<uint64_t> keys(4 * E);
+    std::vector<int32_t> ucount(T);
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; t++) {
+            int64_t e0 = t * TE, ne = std::min<int64_t>(TE, E - e0);
+            uint64_t* k = keys.data() + 4 * e0;
+            for (int64_t s = 0; s < 4 * ne; s++)
+                k[s] = ((uint64_t)(uint32_t)L.conn[4 * e0 + s] << 16) | (uint64_t)s;
+            std::sort(k, k + 4 * ne);
+            int32_t u = 0;
+            for (int64_t s = 0; s < 4 * ne; s++)
+                if (s == 0 || (k[s] >> 16) != (k[s - 1] >> 16)) u++;
+            ucount[t] = u;
+        }
+    });
+    L.tile_node_off.assign(T + 1, 0);
+    int64_t P = 0;
+    int maxn = 0;
+    for (int64_t t = 0; t < T; t++) {
+        L.tile_node_off[t] = (int32_t)P;
+        P += ucount[t];
+        maxn = std::max(maxn, ucount[t]);
+    }
+    if (P > INT32_MAX) {
+        err = "mesh too large for 32-bit partial indices";
+        return false;
+    }
+    L.tile_node_off[T] = (int32_t)P;
+    L.P = P;
+    L.max_tile_nodes = maxn;
+    L.tile_nodes.assign(P, 0);
+    L.seg_start.assign(P, 0);
+    L.slots.assign(4 * E, 0);
+    // pass 2: emit node groups
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; t++) {
+            int64_t e0 = t * TE, ne = std::min<int64_t>(TE, E - e0);
+            const uint64_t* k = keys.data() + 4 * e0;
+            int64_t p = L.tile_node_off[t] - 1;
+            for (int64_t s = 0; s < 4 * ne; s++) {
+                uint32_t node = (uint32_t)(k[s] >> 16);
+                if (s == 0 || (k[s] >> 16) != (k[s - 1] >> 16)) {
+                    p++;
+                    L.tile_nodes[p] = (int32_t)node;
+                    L.seg_start[p] = (uint16_t)s;
+                }
+                L.slots[4 * e0 + s] = (uint16_t)(k[s] & 0xffff);
+            }
+        }
+    });
+    // node -> partial slots, ascending p
+    L.part_off.assign(N + 1, 0);
+    for (int64_t p = 0; p < P; p++) L.part_off[L.tile_nodes[p] + 1]++;
+    for (int64_t i = 0; i < N; i++) L.part_off[i + 1] += L.part_off[i];
+    L.part_idx.assign(P, 0);
+    {
+        std::vector<int32_t> fill(L.part_off.begin(), L.part_off.end() - 1);
+        for (int64_t p = 0; p < P; p++) L.part_idx[fill[L.tile_nodes[p]]++] = (int32_t)p;
+    }
+    return true;
+}
+
+bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
+                  int reorder, int TE, Layout& L, std::string& err) {
+    L = Layout();
+    L.N = N;
+    L.E = E;
+    if (4 * E > INT32_MAX) {
+        err = "mesh too large for 32-bit element-corner indices";
+        return false;
+    }
+    L.nperm.resize(N);
+    L.ninv.resize(N);
+    L.eperm.resize(E);
+    if (reorder) {
+        L.nperm = morton_order(xyz, N);
+        std::vector<double> cen(3 * E);
+        for (int64_t e = 0; e < E; e++)
+            for (int a = 0; a < 3; a++) {
+                double s = 0;
+                for (int c = 0; c < 4; c++) s += xyz[3 * (int64_t)tets[4 * e + c] + a];
+                cen[3 * e + a] = 0.25 * s;
+            }
+        L.eperm = morton_order(cen.data(), E);
+    } else {
+        std::iota(L.nperm.begin(), L.nperm.end(), 0);
+        std::iota(L.eperm.begin(), L.eperm.end(), 0);
+    }
+    for (int64_t i = 0; i < N; i++) L.ninv[L.nperm[i]] = (int32_t)i;
+    L.xyz.resize(3 * N);
+    for (int64_t i = 0; i < N; i++)
+        std::memcpy(&L.xyz[3 * i], xyz + 3 * (int64_t)L.nperm[i], 3 * sizeof(double));
+    L.conn.resize(4 * E);
+    for (int64_t e = 0; e < E; e++)
+        for (int c = 0; c < 4; c++)
+            L.conn[4 * e + c] = L.ninv[tets[4 * (int64_t)L.eperm[e] + c]];
+    // node -> (element, corner), ascending internal element
+    L.ec_off.assign(N + 1, 0);
+    for (int64_t s = 0; s < 4 * E; s++) L.ec_off[L.conn[s] + 1]++;
+    for (int64_t i = 0; i < N; i++) L.ec_off[i + 1] += L.ec_off[i];
+    L.ec.assign(4 * E, 0);
+    {
+        std::vector<int32_t> fill(L.ec_off.begin(), L.ec_off.end() - 1);
+        for (int64_t s = 0; s < 4 * E; s++) L.ec[fill[L.conn[s]]++] = (int32_t)s;
+    }
+    return build_tiles(L, TE, err);
+}
+
+}  // namespace fedfem

@@ -1,0 +1,314 @@
+"""Thin ctypes binding of libfedfem.so (the gfx950 FED-FEM library).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  The binding raises if the shared library is missing; there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfedfem.so")
+
+FP64 = 0
+FP32C = 1
+SOURCE_NODAL = 0
+SOURCE_CONSISTENT = 1
+
+OK = 0
+E_INVALID = -1
+E_DEGENERATE = -2
+E_NOT_PRECOMPUTED = -3
+E_UNSTABLE = -4
+E_DIVERGED = -5
+E_HIP = -6
+E_NOMEM = -7
+E_STATE = -8
+
+MAT_FIELDS = ("rho0", "c0", "k0", "drho_dT", "dc_dT", "dk_dT", "T_ref", "T_lo",
+              "T_hi", "w_b", "c_b", "T_a", "Q_m")
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.c_void_p),
+                ("n_tets", C.c_int64), ("tets", C.c_void_p)]
+
+
+class Materials(C.Structure):
+    _fields_ = [(f, C.c_double) for f in MAT_FIELDS] + [("precision", C.c_int32)]
+
+
+class BC(C.Structure):
+    _fields_ = [("T0", C.c_double), ("n_dir", C.c_int64),
+                ("dir_nodes", C.c_void_p), ("dir_T", C.c_void_p),
+                ("dt", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("reorder", C.c_int32), ("tile_elems", C.c_int32),
+                ("threads", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64),
+                ("n_dirichlet", C.c_int64), ("n_tiles", C.c_int64),
+                ("n_partials", C.c_int64), ("max_tile_nodes", C.c_int64),
+                ("precision", C.c_int32), ("tile_elems", C.c_int32),
+                ("threads", C.c_int32), ("reorder", C.c_int32),
+                ("device_bytes", C.c_int64), ("lambda_geometry", C.c_double),
+                ("lanczos_iterations", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
+
+
+class FedFemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = C.c_void_p
+_SIGS = {
+    "fedfem_create": (C.c_int, [_P, _P, _P, _P]),
+    "fedfem_set_options": (C.c_int, [_P, _P]),
+    "fedfem_precompute": (C.c_int, [_P]),
+    "fedfem_step": (C.c_int, [_P, C.c_int64, _P]),
+    "fedfem_set_source": (C.c_int, [_P, _P]),
+    "fedfem_set_gaussian_sources": (C.c_int, [_P, C.c_int32, _P, C.c_int32]),
+    "fedfem_read_source": (C.c_int, [_P, _P]),
+    "fedfem_read_T": (C.c_int, [_P, _P]),
+    "fedfem_read_T_device": (C.c_int, [_P, _P]),
+    "fedfem_get_dt": (C.c_int, [_P, _P, _P]),
+    "fedfem_get_time": (C.c_int, [_P, _P, _P]),
+    "fedfem_set_dt": (C.c_int, [_P, C.c_double]),
+    "fedfem_set_stream": (C.c_int, [_P, _P]),
+    "fedfem_state_bytes": (C.c_int, [_P, _P]),
+    "fedfem_read_state": (C.c_int, [_P, _P, _P, _P]),
+    "fedfem_write_state": (C.c_int, [_P, _P, C.c_double, C.c_int64]),
+    "fedfem_get_info": (C.c_int, [_P, _P]),
+    "fedfem_time_kernels": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "fedfem_destroy": (C.c_int, [_P]),
+    "fedfem_strerror": (C.c_char_p, [C.c_int]),
+    "fedfem_last_error": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
+    "fedfem_batch_create": (C.c_int, [_P, C.c_int32, _P]),
+    "fedfem_batch_run": (C.c_int, [_P, _P]),
+    "fedfem_batch_last_ms": (C.c_int, [_P, _P]),
+    "fedfem_batch_destroy": (C.c_int, [_P]),
+}
+
+
+def load(path=LIB_PATH):
+    """Load libfedfem.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise FileNotFoundError(
+                f"{path} is missing: build it with __graft_entry__.build() "
+                "(there is no CPU fallback)")
+        L = C.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+class Handle:
+    """One scenario: mesh, materials, boundary conditions, device state."""
+
+    def __init__(self, xyz, tets, materials, T0=37.0, dir_nodes=(), dir_T=(),
+                 dt=-0.9, precision=FP32C, reorder=True, tile_elems=0,
+                 threads=0):
+        L = load()
+        self._L = L
+        self._h = C.c_void_p()
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tets = np.ascontiguousarray(tets, dtype=np.int32)
+        dn = np.ascontiguousarray(dir_nodes, dtype=np.int32)
+        dT = np.ascontiguousarray(np.broadcast_to(np.asarray(dir_T, np.float64),
+                                                  dn.shape))
+        self.N = len(self.xyz)
+        self.E = len(self.tets)
+        mesh = Mesh(self.N, _ptr(self.xyz), self.E, _ptr(self.tets))
+        if isinstance(materials, dict):
+            vals = [float(materials[f]) for f in MAT_FIELDS]
+        else:
+            vals = [float(getattr(materials, f)) for f in MAT_FIELDS]
+        mat = Materials(*vals, int(precision))
+        bc = BC(float(T0), len(dn), _ptr(dn) if len(dn) else None,
+                _ptr(dT) if len(dn) else None, float(dt))
+        self._check(L.fedfem_create(C.byref(mesh), C.byref(mat), C.byref(bc),
+                                    C.byref(self._h)), "fedfem_create")
+        self.precision = int(precision)
+        opt = Options(1 if reorder else 0, int(tile_elems), int(threads))
+        self._check(L.fedfem_set_options(self._h, C.byref(opt)),
+                    "fedfem_set_options")
+
+    # -- errors ---------------------------------------------------------------
+    def last_error(self):
+        buf = C.create_string_buffer(512)
+        if self._h:
+            self._L.fedfem_last_error(self._h, buf, 512)
+        return buf.value.decode()
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self._L.fedfem_strerror(rc).decode()
+            detail = self.last_error() if self._h else ""
+            raise FedFemError(rc, f"{what}: {msg}" + (f": {detail}" if detail else ""))
+
+    # -- lifecycle ------------------------------------------------------------
+    def precompute(self):
+        self._check(self._L.fedfem_precompute(self._h), "fedfem_precompute")
+        return self
+
+    def close(self):
+        if self._h:
+            self._L.fedfem_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping -------------------------------------------------------------
+    def step(self, n_steps, source=None):
+        src = None if source is None else np.ascontiguousarray(source, np.float64)
+        self._check(self._L.fedfem_step(self._h, int(n_steps), _ptr(src)),
+                    "fedfem_step")
+
+    def set_source(self, source):
+        src = None if source is None else np.ascontiguousarray(source, np.float64)
+        self._check(self._L.fedfem_set_source(self._h, _ptr(src)),
+                    "fedfem_set_source")
+
+    def set_gaussian_sources(self, params, mode=SOURCE_CONSISTENT):
+        p = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 5)
+        self._check(self._L.fedfem_set_gaussian_sources(self._h, len(p), _ptr(p),
+                                                        int(mode)),
+                    "fedfem_set_gaussian_sources")
+
+    def read_source(self):
+        out = np.empty(self.N)
+        self._check(self._L.fedfem_read_source(self._h, _ptr(out)),
+                    "fedfem_read_source")
+        return out
+
+    def read_T(self):
+        out = np.empty(self.N)
+        self._check(self._L.fedfem_read_T(self._h, _ptr(out)), "fedfem_read_T")
+        return out
+
+    def read_T_device(self, tensor):
+        """Write T into a contiguous float64 device tensor of length N."""
+        assert tensor.dtype.itemsize == 8 and tensor.numel() == self.N
+        self._check(self._L.fedfem_read_T_device(self._h,
+                                                 C.c_void_p(tensor.data_ptr())),
+                    "fedfem_read_T_device")
+
+    def dt(self):
+        dt = C.c_double()
+        dtc = C.c_double()
+        self._check(self._L.fedfem_get_dt(self._h, C.byref(dt), C.byref(dtc)),
+                    "fedfem_get_dt")
+        return dt.value, dtc.value
+
+    def set_dt(self, dt):
+        self._check(self._L.fedfem_set_dt(self._h, float(dt)), "fedfem_set_dt")
+
+    def time(self):
+        t = C.c_double()
+        n = C.c_int64()
+        self._check(self._L.fedfem_get_time(self._h, C.byref(t), C.byref(n)),
+                    "fedfem_get_time")
+        return t.value, n.value
+
+    def set_stream(self, stream_ptr):
+        self._check(self._L.fedfem_set_stream(self._h, C.c_void_p(stream_ptr)),
+                    "fedfem_set_stream")
+
+    def read_state(self):
+        nb = C.c_size_t()
+        self._check(self._L.fedfem_state_bytes(self._h, C.byref(nb)),
+                    "fedfem_state_bytes")
+        buf = np.empty(nb.value, dtype=np.uint8)
+        t = C.c_double()
+        n = C.c_int64()
+        self._check(self._L.fedfem_read_state(self._h, _ptr(buf), C.byref(t),
+                                              C.byref(n)), "fedfem_read_state")
+        return buf, t.value, n.value
+
+    def write_state(self, buf, t, steps):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self._L.fedfem_write_state(self._h, _ptr(buf), float(t),
+                                               int(steps)), "fedfem_write_state")
+
+    def info(self):
+        inf = Info()
+        self._check(self._L.fedfem_get_info(self._h, C.byref(inf)),
+                    "fedfem_get_info")
+        return {f: (getattr(inf, f) if f != "reserved" else None)
+                for f, _ in Info._fields_ if f != "reserved"}
+
+    def time_kernels(self, n_steps):
+        a = C.c_double()
+        b = C.c_double()
+        self._check(self._L.fedfem_time_kernels(self._h, int(n_steps), C.byref(a),
+                                                C.byref(b)), "fedfem_time_kernels")
+        return a.value, b.value
+
+
+class Batch:
+    """Many precomputed handles advanced by one captured launch sequence."""
+
+    def __init__(self, handles):
+        L = load()
+        self._L = L
+        self.handles = list(handles)
+        arr = (C.c_void_p * len(self.handles))(*[h._h.value for h in self.handles])
+        self._b = C.c_void_p()
+        rc = L.fedfem_batch_create(arr, len(self.handles), C.byref(self._b))
+        if rc != OK:
+            raise FedFemError(rc, "fedfem_batch_create: "
+                              + L.fedfem_strerror(rc).decode())
+
+    def run(self, n_steps):
+        n = np.ascontiguousarray(n_steps, dtype=np.int64)
+        assert len(n) == len(self.handles)
+        rc = self._L.fedfem_batch_run(self._b, _ptr(n))
+        if rc != OK:
+            raise FedFemError(rc, "fedfem_batch_run: "
+                              + self._L.fedfem_strerror(rc).decode())
+
+    def last_ms(self):
+        ms = C.c_double()
+        self._L.fedfem_batch_last_ms(self._b, C.byref(ms))
+        return ms.value
+
+    def close(self):
+        if self._b:
+            self._L.fedfem_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""CPU checks of the C ABI: the library loads, exports what the header
+declares, and rejects bad input before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1909_05098_amd import fedfem as ff
+from synth import mesh
+
+from helpers import header_functions
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fedfem.h")
+
+
+def test_header_declares_binding_surface():
+    assert header_functions(HEADER) == ff.exported_symbols()
+
+
+def test_library_exports_every_declared_symbol():
+    L = ff.load()
+    for name in header_functions(HEADER):
+        assert hasattr(L, name), name
+    out = os.popen(f"nm -D --defined-only {ff.LIB_PATH}").read()
+    exported = set(re.findall(r"\bT (fedfem_[A-Za-z_0-9]+)", out))
+    assert exported == set(header_functions(HEADER))
+
+
+def test_strerror_and_null_handling():
+    L = ff.load()
+    assert L.fedfem_strerror(0) == b"ok"
+    assert L.fedfem_strerror(ff.E_DIVERGED) == b"solution diverged"
+    assert L.fedfem_destroy(None) == ff.OK
+    assert L.fedfem_batch_destroy(None) == ff.OK
+    assert L.fedfem_create(None, None, None, None) == ff.E_INVALID
+    assert L.fedfem_step(None, 1, None) == ff.E_INVALID
+    assert L.fedfem_precompute(None) == ff.E_INVALID
+
+
+def _mat():
+    return {f: v for f, v in zip(ff.MAT_FIELDS, (1060.0, 3600.0, 0.512, 0.0, 0.0,
+                                                  0.0, 37.0, 0.0, 100.0, 6.4,
+                                                  4180.0, 37.0, 0.0))}
+
+
+@pytest.mark.parametrize("case", ["bad_id", "unused_node", "nan_xyz", "dup_dir",
+                                  "bad_prec", "bad_window", "neg_k", "bad_dt"])
+def test_create_rejects_bad_input(case):
+    xyz, tets = mesh.kuhn_box(2, 2, 2, 1e-3)
+    mat = _mat()
+    dn = [0, 1]
+    dt = -0.9
+    prec = ff.FP32C
+    if case == "bad_id":
+        tets = tets.copy()
+        tets[3, 2] = len(xyz)
+    elif case == "unused_node":
+        xyz = np.vstack([xyz, [[9.0, 9.0, 9.0]]])
+    elif case == "nan_xyz":
+        xyz = xyz.copy()
+        xyz[4, 1] = np.nan
+    elif case == "dup_dir":
+        dn = [0, 0]
+    elif case == "bad_prec":
+        prec = 7
+    elif case == "bad_window":
+        mat["T_lo"], mat["T_hi"] = 50.0, 40.0
+    elif case == "neg_k":
+        mat["dk_dT"] = -0.1
+    elif case == "bad_dt":
+        dt = -1.5
+    with pytest.raises(ff.FedFemError) as ei:
+        ff.Handle(xyz, tets, mat, 37.0, dn, [37.0] * len(dn), dt=dt,
+                  precision=prec)
+    assert ei.value.code == ff.E_INVALID
+
+
+def test_product_never_imports_oracle():
+    pkg = os.path.join(ROOT, "paper_1909_05098_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "libfedfem_oracle" not in text, f
+    for f in ("fedfem_oracle.c", "__init__.py", "dense.py"):
+        text = open(os.path.join(ROOT, "oracle", f)).read()
+        assert "paper_1909_05098_amd" not in text
