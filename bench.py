@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""FED-FEM bio-heat benchmark on one MI355X.
+
+Workload (default): the 75x50x40 mm jittered-lattice ellipsoid at h = 0.6 mm
+(17.45M linear tets, 2.98M nodes), temperature-dependent k(T) and c(T), two
+seeded Gaussian sources, compensated FP32 time stepping, nodes and elements
+renumbered along a Morton curve by the library (``--order random`` keeps the
+seeded random input order).  One benchmark step is one explicit time step
+(element loads, assembly, nodal update) over the whole mesh.  The timed
+region runs exactly --steps steps from the initial state as captured HIP
+graphs; the result after them is checked against the FP64 oracle's stored
+sample of the same run when one exists for the workload.
+
+Prints one JSON line: element-updates/s, the roofline of the dominant kernel
+(algorithmic bytes / measured kernel time, against 8 TB/s), and the FP64 CPU
+oracle timed on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = ("tet-element updates/s + achieved HBM GB/s; scenarios/s plain vs "
+          "batched/surrogate")
+GOLDEN3 = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "elem_loads_config3_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1909_05098_amd", "csrc", "kernels_step.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
+
+
+def read_traffic(n_tets):
+    """HBM bytes per element-kernel launch from the committed PMC summary,
+    if it was taken on the current kernel source; else None."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    vals = dict(re.findall(r"^(\w+)\s*=\s*(\S+)\s*$", text, flags=re.M))
+    try:
+        if vals.get("kernel_source_sha1") != kernel_sha():
+            return None
+        if int(vals["n_tets"]) != n_tets:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(scn, dt, q_params, seconds):
+    """The FP64 oracle as it stands, on the first steps of the same run."""
+    import oracle
+    t0 = time.perf_counter()
+    m = oracle.build_model(scn)
+    m.dt = dt
+    q = m.source(q_params, scn.source_mode)
+    setup = time.perf_counter() - t0
+    T = m.initial(37.0)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        T = m.run(T, 5, q)
+        steps += 5
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 400:
+            break
+    return {"value": scn.n_tets * steps / el, "unit": "element-updates/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle, {steps} steps of the same mesh, sources "
+                       f"and dt from the initial state ({el:.1f} s timed, "
+                       f"{setup:.1f} s untimed setup), OpenMP threads = "
+                       f"{oracle.max_threads()}")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--order", choices=["morton", "random"], default="morton")
+    ap.add_argument("--h", type=float, default=0.6e-3)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=20)
+    ap.add_argument("--copy-calib-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this size (for "
+                         "counter calibration) and exit")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; a multi-GPU run "
+              "(--gpus N>1) is not provided.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_calib_gib > 0:
+        n = int(args.copy_calib_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_each_way": 4 * n, "launches": 3}))
+        return
+
+    from paper_1909_05098_amd import fedfem as ff
+    from synth import scenarios as sc
+
+    t0 = time.perf_counter()
+    scn = sc.config3("random", h=args.h, n_steps=args.steps)
+    log(f"mesh {scn.n_tets} tets {scn.n_nodes} nodes ({time.perf_counter() - t0:.1f} s)")
+    golden = None
+    if abs(args.h - 0.6e-3) < 1e-12 and os.path.exists(GOLDEN3):
+        golden = json.load(open(GOLDEN3))
+        if golden["n_tets"] != scn.n_tets:
+            golden = None
+    # the oracle's own critical step where it is stored; else the library's
+    dt_spec = golden["dt"] if golden else -0.9
+    h = ff.Handle(scn.xyz, scn.tets, scn.materials, scn.T0, scn.dir_nodes,
+                  scn.dir_T, dt=dt_spec, precision=ff.FP32C,
+                  reorder=(args.order == "morton"), tile_elems=args.tile,
+                  threads=args.threads)
+    t0 = time.perf_counter()
+    h.precompute()
+    t_pre = time.perf_counter() - t0
+    info = h.info()
+    dt, dt_cr = h.dt()
+    log(f"precompute {t_pre:.2f} s, dt={dt:.6g} dt_cr={dt_cr:.6g}, tiles="
+        f"{info['n_tiles']} partials={info['n_partials']} "
+        f"lanczos={info['lanczos_iterations']}")
+    h.set_gaussian_sources(scn.sources, ff.SOURCE_CONSISTENT)
+    state0, _, _ = h.read_state()
+    h.prepare(args.steps)
+    if args.warmup:
+        h.step(args.warmup)
+    h.write_state(state0, 0.0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(args.steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {t_run * 1e3:.2f} ms")
+    E, N = scn.n_tets, scn.n_nodes
+    value = E * args.steps / t_run
+    ms_step = t_run * 1e3 / args.steps
+    max_err = None
+    if golden and golden["n_steps"] == args.steps:
+        T = h.read_T()
+        idx = np.asarray(golden["idx"])
+        max_err = float(np.max(np.abs(T[idx] - np.asarray(golden["T"]))))
+        log(f"max|T - T_oracle| on {len(idx)} sampled nodes = {max_err:.3e} K")
+    # per-kernel durations with HIP events on the handle's stream
+    elem_ms, node_ms = h.time_kernels(args.kernel_steps)
+    elem_bytes = 40.0 * E   # 4 x i32 connectivity + 6 x f32 coefficients
+    node_bytes = 24.0 * N   # T hi/lo read+write, 1/V_i, source
+    kern = {"elem_loads": (elem_ms, elem_bytes), "node_update": (node_ms, node_bytes)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms, by = kern[dom]
+    achieved = by / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": read_traffic(E) if dom == "elem_loads" else None,
+                "algorithmic_bytes_per_launch": by, "avg_launch_ms": round(ms, 5)}
+    other = [k for k in kern if k != dom][0]
+    step_gbps = (elem_bytes + node_bytes) / (ms_step * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        log("timing the FP64 CPU oracle on a bounded sample")
+        cpu = cpu_baseline(scn, dt, scn.sources, args.cpu_seconds)
+        cpu["value"] = round(cpu["value"], 1)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "element-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ellipsoid 75x50x40 mm, jittered Kuhn lattice "
+                               f"h={args.h * 1e3:g} mm, TD k(T) c(T), two "
+                               f"Gaussian sources, {args.order} order",
+                   "n_tets": E, "n_nodes": N, "dt_s": dt,
+                   "precision": "f32 element loop, compensated f32 hi/lo nodal state, f64 precompute",
+                   "tile_elems": info["tile_elems"], "threads": info["threads"],
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "other_kernel": {"kernel": other, "avg_launch_ms": round(kern[other][0], 5),
+                         "achieved_GBps": round(kern[other][1] / (kern[other][0] * 1e-3) / 1e9, 1)},
+        "step_GBps_algorithmic": round(step_gbps, 1),
+        "max_abs_dT_vs_oracle_K": max_err,
+        "precompute_s": round(t_pre, 3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -152,6 +152,13 @@ int fedfem_precompute(fedfem_handle *h);
  */
 int fedfem_step(fedfem_handle *h, int64_t n_steps, const double *source);
 
+/*
+ * Instantiate the HIP graphs that an n_steps call of fedfem_step uses (for
+ * either ping-pong parity), so that the call itself launches without
+ * capture cost, e.g. in a real-time loop.  Does not advance the state.
+ */
+int fedfem_prepare(fedfem_handle *h, int64_t n_steps);
+
 /* Replace the active nodal source [W] (NULL = zero). */
 int fedfem_set_source(fedfem_handle *h, const double *source);
 

@@ -258,7 +258,7 @@ int get_graph(fedfem_handle* h, int64_t n, int cur, hipGraphExec_t* out) {
         *out = it->second;
         return FEDFEM_OK;
     }
-    if (h->graphs.size() >= 8) drop_graphs(h);
+    if (h->graphs.size() >= 16) drop_graphs(h);
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     int c = cur;
     for (int64_t k = 0; k < n; k++) {
@@ -693,6 +693,25 @@ int fedfem_step(fedfem_handle* h, int64_t n_steps, const double* source) {
     h->steps += n_steps;
     h->t += (double)n_steps * h->dt;
     if (flag) return set_err(h, FEDFEM_E_DIVERGED, "temperature left [-1e4, 1e4] degC or NaN");
+    return FEDFEM_OK;
+}
+
+int fedfem_prepare(fedfem_handle* h, int64_t n_steps) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (n_steps < 0) return set_err(h, FEDFEM_E_INVALID, "negative step count");
+    if (!(h->dt > 0)) return set_err(h, FEDFEM_E_UNSTABLE, "no valid time step");
+    for (int parity = 0; parity < 2; parity++) {
+        int c = parity;
+        int64_t left = n_steps;
+        while (left > 0) {
+            const int64_t chunk = std::min<int64_t>(left, 512);
+            hipGraphExec_t ex;
+            if ((rc = get_graph(h, chunk, c, &ex))) return rc;
+            if (chunk & 1) c ^= 1;
+            left -= chunk;
+        }
+    }
     return FEDFEM_OK;
 }
 

@@ -79,6 +79,7 @@ _SIGS = {
     "fedfem_set_options": (C.c_int, [_P, _P]),
     "fedfem_precompute": (C.c_int, [_P]),
     "fedfem_step": (C.c_int, [_P, C.c_int64, _P]),
+    "fedfem_prepare": (C.c_int, [_P, C.c_int64]),
     "fedfem_set_source": (C.c_int, [_P, _P]),
     "fedfem_set_gaussian_sources": (C.c_int, [_P, C.c_int32, _P, C.c_int32]),
     "fedfem_read_source": (C.c_int, [_P, _P]),
@@ -193,6 +194,9 @@ class Handle:
         src = None if source is None else np.ascontiguousarray(source, np.float64)
         self._check(self._L.fedfem_step(self._h, int(n_steps), _ptr(src)),
                     "fedfem_step")
+
+    def prepare(self, n_steps):
+        self._check(self._L.fedfem_prepare(self._h, int(n_steps)), "fedfem_prepare")
 
     def set_source(self, source):
         src = None if source is None else np.ascontiguousarray(source, np.float64)
