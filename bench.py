@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--h", type=float, default=0.6e-3)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--max-nodes", type=int, default=0)
+    ap.add_argument("--xcd", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=20)
@@ -137,7 +139,8 @@ def main():
     h = ff.Handle(scn.xyz, scn.tets, scn.materials, scn.T0, scn.dir_nodes,
                   scn.dir_T, dt=dt_spec, precision=ff.FP32C,
                   reorder=(args.order == "morton"), tile_elems=args.tile,
-                  threads=args.threads)
+                  threads=args.threads, max_tile_nodes=args.max_nodes,
+                  xcd=bool(args.xcd))
     t0 = time.perf_counter()
     h.precompute()
     t_pre = time.perf_counter() - t0

@@ -91,16 +91,23 @@ typedef struct {
 /*
  * Layout options, read by fedfem_precompute.  reorder = 1 renumbers nodes
  * and elements along a Morton (Z-order) curve of their coordinates, 0 keeps
- * the caller's order.  tile_elems (64..8192, multiple of 64, 0 = default
- * 1024) is the number of consecutive elements whose loads are gathered in
- * on-chip memory before assembly.  threads is the workgroup size of the
- * element kernel (64..1024, multiple of 64, 0 = default 256).
+ * the caller's order.  Elements are processed in tiles of consecutive
+ * elements whose loads are gathered in on-chip memory before assembly:
+ * tile_elems (64..8192, multiple of 64; 0 = 2048) bounds the elements of a
+ * tile and max_tile_nodes (4..4*tile_elems; 0 = tile_elems/2 with reorder,
+ * 4*tile_elems without) the distinct nodes it may touch.  threads is the
+ * element kernel's workgroup size (64..1024, multiple of 64, dividing
+ * tile_elems into 1, 2 or 4 elements per thread; 0 = tile_elems/4 within
+ * [64, 1024]).  xcd = 1 maps workgroups so that each of the 8 XCDs walks one
+ * contiguous stretch of the element order.
  */
 typedef struct {
     int32_t reorder;
     int32_t tile_elems;
     int32_t threads;
-    int32_t reserved[5];
+    int32_t max_tile_nodes;
+    int32_t xcd;
+    int32_t reserved[3];
 } fedfem_options;
 
 /* Sizes of the pre-computed layout, for reporting. */

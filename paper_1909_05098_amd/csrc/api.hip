@@ -75,6 +75,15 @@ void window_bounds(const fedfem_materials& m, double* kmin, double* kmax, double
     }
 }
 
+// 2^S with S = 58 - ceil(log2(bound)), kept inside float range: values of
+// magnitude <= bound scale below 2^58.
+double fixed_scale(double bound) {
+    if (!(bound > 0) || !std::isfinite(bound)) return 1.0;
+    int S = 58 - (int)std::ceil(std::log2(bound));
+    S = std::max(-100, std::min(100, S));
+    return std::ldexp(1.0, S);
+}
+
 // Largest eigenvalue of the symmetric tridiagonal matrix (a[0..k), b[1..k))
 // by Sturm-sequence bisection, and the last component of its unit
 // eigenvector by shifted inverse iteration.
@@ -223,6 +232,8 @@ Props<float> props_f(const fedfem_handle* h) {
     p.Ta = (float)m.T_a;
     p.Qm = (float)m.Q_m;
     p.dt = (float)h->dt;
+    p.fxs = (float)h->fx_scale;
+    p.fxi = (float)(1.0 / h->fx_scale);
     return p;
 }
 
@@ -242,6 +253,8 @@ Props<double> props_d(const fedfem_handle* h) {
     p.Ta = m.T_a;
     p.Qm = m.Q_m;
     p.dt = h->dt;
+    p.fxs = h->fx_scale;
+    p.fxi = 1.0 / h->fx_scale;
     return p;
 }
 
@@ -310,8 +323,8 @@ int lanczos(fedfem_handle* h, const double* coef64) {
     double theta = 0.0, prev = -1.0, last = 0.0;
     int k = 0;
     for (int j = 0; j < maxit; j++) {
-        HIPCHK(h, launch_lanczos_iter(h->d, coef64, j, sc, v, vprev, w, xs, partial, bsum,
-                                      alpha, beta, h->own_stream));
+        HIPCHK(h, launch_lanczos_iter(h->d, coef64, h->fx_scale_lz, j, sc, v, vprev, w, xs,
+                                      partial, bsum, alpha, beta, h->own_stream));
         k = j + 1;
         if (k < 16 || k % 16 == 0 || k == maxit) {
             HIPCHK(h, hipMemcpyAsync(a.data(), alpha, sizeof(double) * k,
@@ -435,8 +448,10 @@ int fedfem_create(const fedfem_mesh* mesh, const fedfem_materials* mat, const fe
     }
     h->stream = h->own_stream;
     h->opt.reorder = 1;
-    h->opt.tile_elems = 1024;
-    h->opt.threads = 256;
+    h->opt.tile_elems = 2048;
+    h->opt.threads = 512;
+    h->opt.max_tile_nodes = 1024;
+    h->opt.xcd = 0;
     *out = h;
     return FEDFEM_OK;
 }
@@ -444,14 +459,18 @@ int fedfem_create(const fedfem_mesh* mesh, const fedfem_materials* mat, const fe
 int fedfem_set_options(fedfem_handle* h, const fedfem_options* o) {
     if (!h || !o) return FEDFEM_E_INVALID;
     if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "options are fixed after precompute");
-    const int te = o->tile_elems ? o->tile_elems : 1024;
-    const int th = o->threads ? o->threads : 256;
-    if (te < 64 || te > 8192 || te % 64 || th < 64 || th > 1024 || th % 64 ||
-        (o->reorder != 0 && o->reorder != 1))
+    const int te = o->tile_elems ? o->tile_elems : 2048;
+    const int th = o->threads ? o->threads : std::max(64, std::min(1024, te / 4));
+    const int mn = o->max_tile_nodes ? o->max_tile_nodes : (o->reorder ? te / 2 : 4 * te);
+    const int r = te / std::max(th, 1);
+    if (te < 64 || te > 8192 || te % 64 || th < 64 || th > 1024 || th % 64 || te % th ||
+        (r != 1 && r != 2 && r != 4) || mn < 4 || mn > 4 * te ||
+        (o->reorder != 0 && o->reorder != 1) || (o->xcd != 0 && o->xcd != 1))
         return set_err(h, FEDFEM_E_INVALID, "invalid options");
     h->opt = *o;
     h->opt.tile_elems = te;
     h->opt.threads = th;
+    h->opt.max_tile_nodes = mn;
     return FEDFEM_OK;
 }
 
@@ -468,13 +487,16 @@ int fedfem_precompute(fedfem_handle* h) {
     std::string err;
     int TE = h->opt.tile_elems;
     try {
-        if (!build_layout(h->xyz.data(), h->tets.data(), N, E, h->opt.reorder, TE, L, err))
+        int MN = h->opt.max_tile_nodes;
+        if (!build_layout(h->xyz.data(), h->tets.data(), N, E, h->opt.reorder, TE, MN, L, err))
             return set_err(h, FEDFEM_E_INVALID, "%s", err.c_str());
         // shrink tiles until the widest kernel (FP64 loads) fits in LDS
         while (tile_lds_bytes(L.tile_elems, L.max_tile_nodes, 8, false, true) > lds_limit) {
             if (L.tile_elems <= 64)
                 return set_err(h, FEDFEM_E_INVALID, "tile does not fit in LDS");
-            if (!build_tiles(L, std::max(64, L.tile_elems / 128 * 64), err))
+            const int te2 = std::max(64, L.tile_elems / 128 * 64);
+            MN = std::min(MN, 4 * te2);
+            if (!build_tiles(L, te2, MN, err))
                 return set_err(h, FEDFEM_E_INVALID, "%s", err.c_str());
         }
     } catch (const std::bad_alloc&) {
@@ -489,11 +511,13 @@ int fedfem_precompute(fedfem_handle* h) {
     d.tile_elems = L.tile_elems;
     d.max_tile_nodes = L.max_tile_nodes;
     d.threads = std::min(h->opt.threads, L.tile_elems);
+    while (elems_per_thread(d) > 4 && d.threads < 1024) d.threads *= 2;
+    d.xcd = h->opt.xcd;
     // topology
-    if ((rc = upload(h, &d.tile_node_off, L.tile_node_off)) ||
-        (rc = upload(h, &d.tile_nodes, L.tile_nodes)) ||
-        (rc = upload(h, &d.seg_start, L.seg_start)) || (rc = upload(h, &d.slots, L.slots)) ||
-        (rc = upload(h, &d.part_off, L.part_off)) || (rc = upload(h, &d.part_idx, L.part_idx)) ||
+    if ((rc = upload(h, &d.tile_elem_off, L.tile_elem_off)) ||
+        (rc = upload(h, &d.tile_node_off, L.tile_node_off)) ||
+        (rc = upload(h, &d.tile_nodes, L.tile_nodes)) || (rc = upload(h, &d.lconn, L.lconn)) ||
+        (rc = upload(h, &d.wpos, L.wpos)) || (rc = upload(h, &d.part_off, L.part_off)) ||
         (rc = upload(h, &h->d_ec_off, L.ec_off)) || (rc = upload(h, &h->d_ec, L.ec)) ||
         (rc = upload(h, &h->d_conn, L.conn)) || (rc = upload(h, &h->d_xyz, L.xyz)) ||
         (rc = upload(h, &h->d_nperm, L.nperm)))
@@ -530,6 +554,31 @@ int fedfem_precompute(fedfem_handle* h) {
         return set_err(h, FEDFEM_E_DEGENERATE, "degenerate tetrahedron %d", hbad);
     }
     HIPCHK(h, launch_lump(N, h->d_ec_off, h->d_ec, h->d_vol, h->d_Vi, s));
+    // fixed-point scales: the largest possible corner load maps below 2^58
+    {
+        unsigned long long* dbits = nullptr;
+        if ((rc = dalloc(h, &dbits, 1))) return rc;
+        HIPCHK(h, hipMemsetAsync(dbits, 0, sizeof(unsigned long long), s));
+        HIPCHK(h, launch_coef_bound(E, coef64, dbits, s));
+        unsigned long long bits = 0;
+        std::vector<double> Vi(N);
+        HIPCHK(h, hipMemcpyAsync(&bits, dbits, sizeof(bits), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(Vi.data(), h->d_Vi, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        dfree(h, dbits);
+        double amax;
+        std::memcpy(&amax, &bits, sizeof(amax));
+        double vmin = 1e300;
+        for (int64_t i = 0; i < N; i++)
+            if (!h->host_isdir[i]) vmin = std::min(vmin, Vi[i]);
+        double kmin, kmax, rcmin, rcmax;
+        window_bounds(h->mat, &kmin, &kmax, &rcmin, &rcmax);
+        // loads: k <= kmax, |T_b - T_a| <= 2e4 (both within the divergence limit)
+        h->fx_scale = fixed_scale(kmax * amax * 2.0e4);
+        // Lanczos: |x| <= 1 / sqrt(min free V_i) for a unit vector
+        h->fx_scale_lz = fixed_scale(amax * 2.0 / std::sqrt(std::max(vmin, 1e-300)));
+        h->a_max = amax;
+    }
     // time-stepping arrays in the chosen precision
     const size_t rb = h->fp32c ? sizeof(float) : sizeof(double);
     auto dalloc_bytes = [&](void** p, size_t count) -> int {
@@ -550,14 +599,17 @@ int fedfem_precompute(fedfem_handle* h) {
     } else {
         d.coef = coef64;
     }
+    // nodal state: float2 (hi, lo) or double, 8 bytes per node either way
     if ((rc = dalloc_bytes(&d.u, N)) || (rc = dalloc_bytes(&d.q, N)) ||
-        (rc = dalloc_bytes(&d.Thi[0], N)) || (rc = dalloc_bytes(&d.Thi[1], N)) ||
         (rc = dalloc_bytes(&d.partial, d.P)))
         return rc;
-    if (h->fp32c && ((rc = dalloc_bytes(&d.Tlo[0], N)) || (rc = dalloc_bytes(&d.Tlo[1], N))))
-        return rc;
-    HIPCHK(h, launch_node_init(N, h->d_Vi, h->d_isdir, h->d_dirT, h->T0, h->fp32c, d.u,
-                               d.Thi[0], d.Tlo[0], d.Thi[1], d.Tlo[1], s));
+    for (int b = 0; b < 2; b++) {
+        double* tb = nullptr;
+        if ((rc = dalloc(h, &tb, N))) return rc;
+        d.T_[b] = tb;
+    }
+    HIPCHK(h, launch_node_init(N, h->d_Vi, h->d_isdir, h->d_dirT, h->T0, h->fp32c, d.u, d.T_[0],
+                               d.T_[1], s));
     HIPCHK(h, launch_set_source(N, nullptr, nullptr, h->fp32c, d.q, s));
     // critical step (Eq 9): top eigenvalue of the geometry pencil on free
     // nodes, bounded over the property window
@@ -601,7 +653,7 @@ int fedfem_precompute(fedfem_handle* h) {
     // host copies of the big arrays are no longer needed
     std::vector<double>().swap(L.xyz);
     std::vector<int32_t>().swap(L.conn);
-    std::vector<uint16_t>().swap(L.slots);
+    std::vector<uint16_t>().swap(L.lconn);
     std::vector<int32_t>().swap(L.ec);
     return FEDFEM_OK;
 }
@@ -765,8 +817,7 @@ int fedfem_read_T(fedfem_handle* h, double* T_out) {
     if (rc) return rc;
     if (!T_out) return FEDFEM_E_INVALID;
     hipStream_t s = h->stream;
-    HIPCHK(h, launch_read_T(h->N, h->d.Thi[h->cur], h->d.Tlo[h->cur], h->d_nperm, h->fp32c,
-                            h->d_stage, s));
+    HIPCHK(h, launch_read_T(h->N, h->d.T_[h->cur], h->d_nperm, h->fp32c, h->d_stage, s));
     HIPCHK(h, hipMemcpyAsync(T_out, h->d_stage, sizeof(double) * h->N, hipMemcpyDeviceToHost,
                              s));
     HIPCHK(h, hipStreamSynchronize(s));
@@ -778,8 +829,7 @@ int fedfem_read_T_device(fedfem_handle* h, double* d_out) {
     if (rc) return rc;
     if (!d_out) return FEDFEM_E_INVALID;
     hipStream_t s = h->stream;
-    HIPCHK(h, launch_read_T(h->N, h->d.Thi[h->cur], h->d.Tlo[h->cur], h->d_nperm, h->fp32c,
-                            d_out, s));
+    HIPCHK(h, launch_read_T(h->N, h->d.T_[h->cur], h->d_nperm, h->fp32c, d_out, s));
     HIPCHK(h, hipStreamSynchronize(s));
     return FEDFEM_OK;
 }
@@ -828,8 +878,7 @@ int fedfem_read_state(fedfem_handle* h, void* buf, double* t, int64_t* steps) {
     size_t bytes = 0;
     fedfem_state_bytes(h, &bytes);
     hipStream_t s = h->stream;
-    HIPCHK(h, launch_state_io(h->N, h->d.Thi[h->cur], h->d.Tlo[h->cur], h->d_nperm, h->fp32c,
-                              h->d_stage, 1, s));
+    HIPCHK(h, launch_state_io(h->N, h->d.T_[h->cur], h->d_nperm, h->fp32c, h->d_stage, 1, s));
     HIPCHK(h, hipMemcpyAsync(buf, h->d_stage, bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (t) *t = h->t;
@@ -846,8 +895,7 @@ int fedfem_write_state(fedfem_handle* h, const void* buf, double t, int64_t step
     hipStream_t s = h->stream;
     HIPCHK(h, hipMemcpyAsync(h->d_stage, buf, bytes, hipMemcpyHostToDevice, s));
     for (int b = 0; b < 2; b++)
-        HIPCHK(h, launch_state_io(h->N, h->d.Thi[b], h->d.Tlo[b], h->d_nperm, h->fp32c,
-                                  h->d_stage, 0, s));
+        HIPCHK(h, launch_state_io(h->N, h->d.T_[b], h->d_nperm, h->fp32c, h->d_stage, 0, s));
     HIPCHK(h, hipStreamSynchronize(s));
     h->t = t;
     h->steps = steps;

@@ -30,7 +30,7 @@ struct fedfem_batch {
     DevLayout d;
     std::vector<int64_t> node_off, elem_off, tile_off, pbase;
     std::vector<int32_t> tile_count, block_count;
-    int32_t *tile_list = nullptr, *tile_elem_off = nullptr, *tile_scen = nullptr;
+    int32_t *tile_list = nullptr, *tile_scen = nullptr;
     int32_t *block_list = nullptr, *block_scen = nullptr, *flags = nullptr;
     void* props = nullptr;
     std::vector<void*> allocs;
@@ -88,6 +88,8 @@ Props<Real> props_of(const fedfem_handle* h) {
     p.Ta = (Real)m.T_a;
     p.Qm = (Real)m.Q_m;
     p.dt = (Real)h->dt;
+    p.fxs = (Real)h->fx_scale;
+    p.fxi = (Real)(1.0 / h->fx_scale);
     return p;
 }
 
@@ -174,11 +176,15 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     d.P = Pt;
     d.tile_elems = maxte;
     d.max_tile_nodes = maxn;
-    d.threads = 256;
+    d.threads = std::min(1024, maxte);
+    d.xcd = 0;
+    if (elems_per_thread(d) > 4) {
+        destroy_batch(b);
+        return FEDFEM_E_INVALID;
+    }
     // integer tables on the host
-    std::vector<int32_t> tno(Tt + 1), tnodes(Pt), poff(Nt + 1, 0), pidx(Pt), teo(Tt + 1),
-        tsc(Tt), bsc(Nt / 256);
-    std::vector<uint16_t> seg(Pt);
+    std::vector<int32_t> tno(Tt + 1), tnodes(Pt), poff(Nt + 1, 0), wp(Pt), teo(Tt + 1), tsc(Tt),
+        bsc(Nt / 256);
     for (int j = 0; j < n; j++) {
         const fedfem_handle* h = handles[j];
         const Layout& L = h->L;
@@ -186,13 +192,12 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
                       eo = b->elem_off[j];
         for (int64_t t = 0; t < h->d.T; t++) {
             tno[to + t] = (int32_t)(L.tile_node_off[t] + pb);
-            teo[to + t] = (int32_t)(eo + t * h->d.tile_elems);
+            teo[to + t] = (int32_t)(eo + L.tile_elem_off[t]);
             tsc[to + t] = j;
         }
         for (int64_t p = 0; p < h->d.P; p++) {
             tnodes[pb + p] = (int32_t)(L.tile_nodes[p] + no);
-            seg[pb + p] = L.seg_start[p];
-            pidx[pb + p] = (int32_t)(L.part_idx[p] + pb);
+            wp[pb + p] = (int32_t)(L.wpos[p] + pb);
         }
         const int64_t npad = b->node_off[j + 1] - no;
         for (int64_t i = 0; i < npad; i++)
@@ -204,10 +209,9 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     poff[Nt] = (int32_t)Pt;
     BCHK(bupload(b, &d.tile_node_off, tno));
     BCHK(bupload(b, &d.tile_nodes, tnodes));
-    BCHK(bupload(b, &d.seg_start, seg));
     BCHK(bupload(b, &d.part_off, poff));
-    BCHK(bupload(b, &d.part_idx, pidx));
-    BCHK(bupload(b, &b->tile_elem_off, teo));
+    BCHK(bupload(b, &d.wpos, wp));
+    BCHK(bupload(b, &d.tile_elem_off, teo));
     BCHK(bupload(b, &b->tile_scen, tsc));
     BCHK(bupload(b, &b->block_scen, bsc));
     BCHK(balloc(b, &b->tile_list, Tt));
@@ -221,15 +225,16 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
         *p = q;
         return e;
     };
-    BCHK(balloc(b, &d.slots, 4 * Et));
+    BCHK(balloc(b, &d.lconn, 4 * Et));
     BCHK(ralloc(&d.coef, 6 * Et));
     BCHK(ralloc(&d.u, Nt));
     BCHK(ralloc(&d.q, Nt));
     BCHK(ralloc(&d.partial, Pt));
     BCHK(ralloc(&b->props, n * (b->fp32c ? sizeof(Props<float>) : sizeof(Props<double>)) / rb + 1));
     for (int k = 0; k < 2; k++) {
-        BCHK(ralloc(&d.Thi[k], Nt));
-        if (b->fp32c) BCHK(ralloc(&d.Tlo[k], Nt));
+        double* tb = nullptr;  // float2 (hi, lo) or double: 8 bytes per node
+        BCHK(balloc(b, &tb, Nt));
+        d.T_[k] = tb;
     }
     // padding nodes: u = -1 (never updated); copy each scenario's data
     {
@@ -247,7 +252,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     for (int j = 0; j < n; j++) {
         const fedfem_handle* h = handles[j];
         const int64_t no = b->node_off[j], eo = b->elem_off[j];
-        BCHK(hipMemcpyAsync(d.slots + 4 * eo, h->d.slots, 4 * h->E * sizeof(uint16_t),
+        BCHK(hipMemcpyAsync(d.lconn + 4 * eo, h->d.lconn, 4 * h->E * sizeof(uint16_t),
                             hipMemcpyDeviceToDevice, b->stream));
         for (int k = 0; k < 6; k++)
             BCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.coef) + (k * Et + eo) * rb,
@@ -307,15 +312,9 @@ int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps) {
     for (int j = 0; j < S; j++) {
         fedfem_handle* h = b->hs[j];
         const int64_t no = b->node_off[j];
-        for (int k = 0; k < 2; k++) {
-            RCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.Thi[k]) + no * rb,
-                                h->d.Thi[h->cur], h->N * rb, hipMemcpyDeviceToDevice,
-                                b->stream));
-            if (b->fp32c)
-                RCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.Tlo[k]) + no * rb,
-                                    h->d.Tlo[h->cur], h->N * rb, hipMemcpyDeviceToDevice,
-                                    b->stream));
-        }
+        for (int k = 0; k < 2; k++)
+            RCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.T_[k]) + no * 8, h->d.T_[h->cur],
+                                h->N * 8, hipMemcpyDeviceToDevice, b->stream));
         RCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.q) + no * rb, h->d.q, h->N * rb,
                             hipMemcpyDeviceToDevice, b->stream));
     }
@@ -334,7 +333,6 @@ int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps) {
         }
         BatchTables tb;
         tb.tile_list = b->tile_list;
-        tb.tile_elem_off = b->tile_elem_off;
         tb.tile_scen = b->tile_scen;
         tb.block_list = b->block_list;
         tb.block_scen = b->block_scen;
@@ -368,12 +366,8 @@ int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps) {
         fedfem_handle* h = b->hs[j];
         const int64_t no = b->node_off[j];
         const int fin = (int)(n_steps[j] & 1);
-        RCHK(hipMemcpyAsync(h->d.Thi[h->cur], static_cast<unsigned char*>(d.Thi[fin]) + no * rb,
-                            h->N * rb, hipMemcpyDeviceToDevice, b->stream));
-        if (b->fp32c)
-            RCHK(hipMemcpyAsync(h->d.Tlo[h->cur],
-                                static_cast<unsigned char*>(d.Tlo[fin]) + no * rb, h->N * rb,
-                                hipMemcpyDeviceToDevice, b->stream));
+        RCHK(hipMemcpyAsync(h->d.T_[h->cur], static_cast<unsigned char*>(d.T_[fin]) + no * 8,
+                            h->N * 8, hipMemcpyDeviceToDevice, b->stream));
     }
     std::vector<int32_t> fl(S);
     RCHK(hipMemcpyAsync(fl.data(), b->flags, S * 4, hipMemcpyDeviceToHost, b->stream));

@@ -55,6 +55,9 @@ struct fedfem_handle {
     int lz_iters = 0;
     double lam_geo = 0.0, lam_ritz = 0.0;
     double dt = 0.0, dt_cr = 0.0;
+    double a_max = 0.0;          // largest off-diagonal row sum of |A_e|
+    double fx_scale = 1.0;       // fixed-point scale of the element loads
+    double fx_scale_lz = 1.0;    // same for the Lanczos operator
     double t = 0.0;
     int64_t steps = 0;
     int cur = 0;

@@ -13,13 +13,14 @@ namespace fedfem {
 // Host-side mesh layout (integer topology only).
 //
 // Internal numbering: nodes and elements optionally follow a Morton curve.
-// Elements are cut into tiles of `tile_elems` consecutive elements.  For
-// every tile the distinct nodes it touches are listed in ascending internal
-// id ("tile nodes"); each (tile, tile node) pair owns one partial sum slot,
-// indexed p in [tile_node_off[t], tile_node_off[t+1]).  The tile's element
-// corners ("slots", local element * 4 + corner) are listed grouped by tile
-// node, ascending slot inside each group; seg_start[p] is where p's group
-// starts, relative to the tile's first slot.
+// Elements are cut into tiles of consecutive elements, each holding at most
+// `tile_elems` elements and touching at most `max_tile_nodes` distinct nodes.
+// For every tile the distinct nodes it touches are listed in ascending
+// internal id ("tile nodes"), and each element corner stores its node's
+// position in that list (lconn, u16).  Each (tile, tile node) pair p in
+// [tile_node_off[t], tile_node_off[t+1]) produces one partial sum, stored at
+// position wpos[p] of the node-major partial array (node i owns positions
+// [part_off[i], part_off[i+1]), in ascending tile order).
 // ---------------------------------------------------------------------------
 struct Layout {
     int64_t N = 0, E = 0, T = 0, P = 0;
@@ -30,22 +31,24 @@ struct Layout {
     std::vector<int32_t> eperm;          // internal -> caller element id
     std::vector<double> xyz;             // [3N] internal order
     std::vector<int32_t> conn;           // [4E] internal ids, internal order
+    std::vector<int32_t> tile_elem_off;  // [T+1]
     std::vector<int32_t> tile_node_off;  // [T+1]
     std::vector<int32_t> tile_nodes;     // [P]
-    std::vector<uint16_t> seg_start;     // [P]
-    std::vector<uint16_t> slots;         // [4E]
-    std::vector<int32_t> part_off;       // [N+1] node -> partial slots
-    std::vector<int32_t> part_idx;       // [P]
+    std::vector<int32_t> wpos;           // [P] node-major position of p
+    std::vector<uint16_t> lconn;         // [4E] local node id per corner
+    std::vector<int32_t> part_off;       // [N+1] node -> partial positions
     std::vector<int32_t> ec_off;         // [N+1] node -> element corners
     std::vector<int32_t> ec;             // [4E] e*4+corner, ascending e
 };
 
 // Build the layout.  Returns false with a message on failure.
 bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
-                  int reorder, int tile_elems, Layout& L, std::string& err);
+                  int reorder, int tile_elems, int max_tile_nodes, Layout& L,
+                  std::string& err);
 
-// Tile-node layout only (used again when a tile size is re-tuned).
-bool build_tiles(Layout& L, int tile_elems, std::string& err);
+// Tile layout only (used again when tiles must shrink).
+bool build_tiles(Layout& L, int tile_elems, int max_tile_nodes,
+                 std::string& err);
 
 // Morton (Z-order) permutation of points; returns new -> old.
 std::vector<int32_t> morton_order(const double* pts, int64_t n);
@@ -53,27 +56,31 @@ std::vector<int32_t> morton_order(const double* pts, int64_t n);
 // ---------------------------------------------------------------------------
 // Material parameters as the kernels see them.
 // ---------------------------------------------------------------------------
+// fxs = 2^S and fxi = 2^-S scale corner loads to the 64-bit fixed-point
+// grid on which a tile sums them exactly (chosen so that the largest
+// possible load maps below 2^58).
 template <typename Real>
 struct Props {
     Real k0, dk, rho0, drho, c0, dc, Tref, Tlo, Thi, wbcb, Ta, Qm, dt;
+    Real fxs, fxi;
 };
 
 // Device copy of a layout plus the numerical arrays of one precision.
 struct DevLayout {
     int64_t N = 0, E = 0, T = 0, P = 0;
     int tile_elems = 0, max_tile_nodes = 0, threads = 256;
+    int xcd = 0;  // remap blocks so each XCD walks a contiguous stretch
+    int32_t* tile_elem_off = nullptr;
     int32_t* tile_node_off = nullptr;
     int32_t* tile_nodes = nullptr;
-    uint16_t* seg_start = nullptr;
-    uint16_t* slots = nullptr;
+    int32_t* wpos = nullptr;
+    uint16_t* lconn = nullptr;
     int32_t* part_off = nullptr;
-    int32_t* part_idx = nullptr;
     void* coef = nullptr;      // [6][E] Real, off-diagonals a01 a02 a03 a12 a13 a23
     void* u = nullptr;         // [N] Real, 1/V_i, or -1 for Dirichlet nodes
     void* q = nullptr;         // [N] Real, active nodal source [W]
-    void* Thi[2] = {nullptr, nullptr};
-    void* Tlo[2] = {nullptr, nullptr};
-    void* partial = nullptr;   // [P] Real
+    void* T_[2] = {nullptr, nullptr};  // state: float2 (hi, lo) or double
+    void* partial = nullptr;   // [P] Real, node-major
 };
 
 // ---------------------------------------------------------------------------
@@ -81,6 +88,9 @@ struct DevLayout {
 // ---------------------------------------------------------------------------
 size_t tile_lds_bytes(int tile_elems, int max_nodes, int real_bytes, bool comp,
                       bool td);
+// Elements per thread of the element kernel, rounded up to 1, 2 or 4 (the
+// instantiated counts); 8 means the workgroup is too small for the tile.
+int elems_per_thread(const DevLayout& d);
 // One explicit step: element loads then nodal update, ping-pong cur -> 1-cur.
 hipError_t launch_step_f32c(const DevLayout& d, int cur, const Props<float>& p,
                             bool td, int* flag, hipStream_t s);
@@ -99,7 +109,6 @@ hipError_t launch_node_f64(const DevLayout& d, int cur, const Props<double>& p,
 // blocks (a prefix of each list is active at any step).
 struct BatchTables {
     const int32_t* tile_list = nullptr;      // [T]
-    const int32_t* tile_elem_off = nullptr;  // [T+1]
     const int32_t* tile_scen = nullptr;      // [T]
     const int32_t* block_list = nullptr;     // [NB]
     const int32_t* block_scen = nullptr;     // [NB]
@@ -111,13 +120,17 @@ hipError_t launch_node_batch(const DevLayout& d, const BatchTables& b, int cur,
                              int n_blocks, int fp32c, int* flags,
                              hipStream_t s);
 // Element loads of x with k = 1 (geometry operator sum_e A_e), FP64.
+// fx_scale is the fixed-point scale 2^S for loads of x.
 hipError_t launch_geometry_apply(const DevLayout& d, const double* coef64,
                                  const double* x, double* partial,
-                                 hipStream_t s);
+                                 double fx_scale, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Pre-computation launchers (kernels_pre.hip), all double precision.
 // ---------------------------------------------------------------------------
+// out[0] (as u64 bits) = max over elements and corners a of sum_b |a_ab|.
+hipError_t launch_coef_bound(int64_t E, const double* coef64,
+                             unsigned long long* out, hipStream_t s);
 // bad receives the smallest caller element id with |det J| <= 1e-12 l^3.
 hipError_t launch_geometry(int64_t E, const double* xyz, const int32_t* conn,
                            const int32_t* eperm, double* coef64, double* vol,
@@ -137,8 +150,7 @@ hipError_t launch_cast_coef(int64_t n, const double* src, float* dst,
                             hipStream_t s);
 hipError_t launch_node_init(int64_t N, const double* Vi, const int32_t* is_dir,
                             const double* dirT, double T0, int fp32c, void* u,
-                            void* Thi0, void* Tlo0, void* Thi1, void* Tlo1,
-                            hipStream_t s);
+                            void* T0buf, void* T1buf, hipStream_t s);
 // q (Real, internal order) <- src64[nperm[i]] (caller order) or src64[i].
 hipError_t launch_set_source(int64_t N, const double* src64,
                              const int32_t* nperm, int fp32c, void* q,
@@ -146,12 +158,11 @@ hipError_t launch_set_source(int64_t N, const double* src64,
 // out64[nperm[i]] = q[i] (Real) : internal -> caller order.
 hipError_t launch_get_source(int64_t N, const void* q, const int32_t* nperm,
                              int fp32c, double* out64, hipStream_t s);
-hipError_t launch_read_T(int64_t N, const void* Thi, const void* Tlo,
-                         const int32_t* nperm, int fp32c, double* out,
-                         hipStream_t s);
-hipError_t launch_state_io(int64_t N, void* Thi, void* Tlo,
-                           const int32_t* nperm, int fp32c, void* buf,
-                           int to_buf, hipStream_t s);
+hipError_t launch_read_T(int64_t N, const void* T, const int32_t* nperm,
+                         int fp32c, double* out, hipStream_t s);
+// Caller-order raw state: FP32C hi[N] then lo[N] (float), FP64 T[N].
+hipError_t launch_state_io(int64_t N, void* T, const int32_t* nperm,
+                           int fp32c, void* buf, int to_buf, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 // Lanczos pieces for the critical step.
@@ -159,10 +170,10 @@ hipError_t launch_lanczos_start(int64_t N, const double* Vi,
                                 const int32_t* is_dir, double* sc, double* v,
                                 double* vprev, double* xs, double* bsum,
                                 double* scal, hipStream_t s);
-hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64, int j,
-                               const double* sc, double* v, double* vprev,
-                               double* w, double* xs, double* partial,
-                               double* bsum, double* alpha, double* beta,
-                               hipStream_t s);
+hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64,
+                               double fx_scale, int j, const double* sc,
+                               double* v, double* vprev, double* w, double* xs,
+                               double* partial, double* bsum, double* alpha,
+                               double* beta, hipStream_t s);
 
 }  // namespace fedfem

@@ -174,29 +174,52 @@ __global__ void k_gather_slots(int64_t N, const int32_t* __restrict__ off,
     q[i] = s;
 }
 
+// Largest row sum of |A_e| off the diagonal over all elements (for the
+// fixed-point scale of the element loads).  Positive doubles order like
+// their bit patterns, so an integer max over the bits is exact.
+__global__ void k_coef_bound(int64_t E, const double* __restrict__ coef,
+                             unsigned long long* __restrict__ out) {
+    __shared__ double sh[kBlock];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (e < E) {
+        double a[6];
+        for (int k = 0; k < 6; k++) a[k] = fabs(coef[k * E + e]);
+        r = fmax(fmax(a[0] + a[1] + a[2], a[0] + a[3] + a[4]),
+                 fmax(a[1] + a[3] + a[5], a[2] + a[4] + a[5]));
+    }
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sh[0]));
+}
+
 __global__ void k_cast(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
 }
 
-template <typename Real>
 __global__ void k_node_init(int64_t N, const double* __restrict__ Vi,
-                            const int32_t* __restrict__ is_dir,
-                            const double* __restrict__ dirT, double T0, Real* __restrict__ u,
-                            Real* __restrict__ h0, Real* __restrict__ l0,
-                            Real* __restrict__ h1, Real* __restrict__ l1) {
+                            const int32_t* __restrict__ is_dir, const double* __restrict__ dirT,
+                            double T0, int fp32c, void* __restrict__ u, void* __restrict__ T0buf,
+                            void* __restrict__ T1buf) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const bool d = is_dir[i] != 0;
-    u[i] = d ? Real(-1) : Real(1.0 / Vi[i]);
     const double T = d ? dirT[i] : T0;
-    const Real hi = (Real)T;
-    h0[i] = hi;
-    h1[i] = hi;
-    if (l0) {
-        const Real lo = (Real)(T - (double)hi);
-        l0[i] = lo;
-        l1[i] = lo;
+    if (fp32c) {
+        static_cast<float*>(u)[i] = d ? -1.0f : (float)(1.0 / Vi[i]);
+        const float hi = (float)T;
+        const float2 v = make_float2(hi, (float)(T - (double)hi));
+        static_cast<float2*>(T0buf)[i] = v;
+        static_cast<float2*>(T1buf)[i] = v;
+    } else {
+        static_cast<double*>(u)[i] = d ? -1.0 : 1.0 / Vi[i];
+        static_cast<double*>(T0buf)[i] = T;
+        static_cast<double*>(T1buf)[i] = T;
     }
 }
 
@@ -216,27 +239,40 @@ __global__ void k_get_source(int64_t N, const Real* __restrict__ q,
     out[nperm[i]] = (double)q[i];
 }
 
-template <typename Real>
-__global__ void k_read_T(int64_t N, const Real* __restrict__ hi, const Real* __restrict__ lo,
-                         const int32_t* __restrict__ nperm, double* __restrict__ out) {
+__global__ void k_read_T(int64_t N, const void* __restrict__ T, const int32_t* __restrict__ nperm,
+                         int fp32c, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    out[nperm[i]] = (double)hi[i] + (lo ? (double)lo[i] : 0.0);
+    if (fp32c) {
+        const float2 v = static_cast<const float2*>(T)[i];
+        out[nperm[i]] = (double)v.x + (double)v.y;
+    } else {
+        out[nperm[i]] = static_cast<const double*>(T)[i];
+    }
 }
 
-template <typename Real>
-__global__ void k_state_io(int64_t N, Real* __restrict__ hi, Real* __restrict__ lo,
-                           const int32_t* __restrict__ nperm, Real* __restrict__ buf,
-                           int to_buf) {
+__global__ void k_state_io(int64_t N, void* __restrict__ T, const int32_t* __restrict__ nperm,
+                           int fp32c, void* __restrict__ buf, int to_buf) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int64_t o = nperm[i];
-    if (to_buf) {
-        buf[o] = hi[i];
-        if (lo) buf[N + o] = lo[i];
+    if (fp32c) {
+        float2* t = static_cast<float2*>(T);
+        float* b = static_cast<float*>(buf);
+        if (to_buf) {
+            const float2 v = t[i];
+            b[o] = v.x;
+            b[N + o] = v.y;
+        } else {
+            t[i] = make_float2(b[o], b[N + o]);
+        }
     } else {
-        hi[i] = buf[o];
-        if (lo) lo[i] = buf[N + o];
+        double* t = static_cast<double*>(T);
+        double* b = static_cast<double*>(buf);
+        if (to_buf)
+            b[o] = t[i];
+        else
+            t[i] = b[o];
     }
 }
 
@@ -306,7 +342,7 @@ __global__ void k_lz_scale(int64_t N, const double* __restrict__ norm, const dou
 }
 
 __global__ void k_lz_w(int64_t N, const int32_t* __restrict__ part_off,
-                       const int32_t* __restrict__ part_idx, const double* __restrict__ partial,
+                       const double* __restrict__ partial,
                        const double* __restrict__ sc, const double* __restrict__ v,
                        const double* __restrict__ vprev, const double* __restrict__ beta_j,
                        double* __restrict__ w, double* __restrict__ bsum) {
@@ -315,7 +351,7 @@ __global__ void k_lz_w(int64_t N, const int32_t* __restrict__ part_off,
     double prod = 0.0;
     if (i < N) {
         double F = 0.0;
-        for (int k = part_off[i]; k < part_off[i + 1]; k++) F += partial[part_idx[k]];
+        for (int k = part_off[i]; k < part_off[i + 1]; k++) F += partial[k];
         const double wi = sc[i] * F - beta_j[0] * vprev[i];
         w[i] = wi;
         prod = v[i] * wi;
@@ -389,22 +425,22 @@ hipError_t launch_source_consistent(int64_t N, int64_t E, const double* xyz,
     return hipGetLastError();
 }
 
+hipError_t launch_coef_bound(int64_t E, const double* coef64, unsigned long long* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_coef_bound, dim3(blocks_for(E)), dim3(kBlock), 0, s, E, coef64, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_cast_coef(int64_t n, const double* src, float* dst, hipStream_t s) {
     hipLaunchKernelGGL(k_cast, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, src, dst);
     return hipGetLastError();
 }
 
 hipError_t launch_node_init(int64_t N, const double* Vi, const int32_t* is_dir,
-                            const double* dirT, double T0, int fp32c, void* u, void* Thi0,
-                            void* Tlo0, void* Thi1, void* Tlo1, hipStream_t s) {
-    if (fp32c)
-        hipLaunchKernelGGL(k_node_init<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, Vi,
-                           is_dir, dirT, T0, (float*)u, (float*)Thi0, (float*)Tlo0,
-                           (float*)Thi1, (float*)Tlo1);
-    else
-        hipLaunchKernelGGL(k_node_init<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, Vi,
-                           is_dir, dirT, T0, (double*)u, (double*)Thi0, (double*)nullptr,
-                           (double*)Thi1, (double*)nullptr);
+                            const double* dirT, double T0, int fp32c, void* u, void* T0buf,
+                            void* T1buf, hipStream_t s) {
+    hipLaunchKernelGGL(k_node_init, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, Vi, is_dir, dirT,
+                       T0, fp32c, u, T0buf, T1buf);
     return hipGetLastError();
 }
 
@@ -430,25 +466,16 @@ hipError_t launch_get_source(int64_t N, const void* q, const int32_t* nperm, int
     return hipGetLastError();
 }
 
-hipError_t launch_read_T(int64_t N, const void* Thi, const void* Tlo, const int32_t* nperm,
-                         int fp32c, double* out, hipStream_t s) {
-    if (fp32c)
-        hipLaunchKernelGGL(k_read_T<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
-                           (const float*)Thi, (const float*)Tlo, nperm, out);
-    else
-        hipLaunchKernelGGL(k_read_T<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
-                           (const double*)Thi, (const double*)nullptr, nperm, out);
+hipError_t launch_read_T(int64_t N, const void* T, const int32_t* nperm, int fp32c,
+                         double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_read_T, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, T, nperm, fp32c, out);
     return hipGetLastError();
 }
 
-hipError_t launch_state_io(int64_t N, void* Thi, void* Tlo, const int32_t* nperm, int fp32c,
-                           void* buf, int to_buf, hipStream_t s) {
-    if (fp32c)
-        hipLaunchKernelGGL(k_state_io<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
-                           (float*)Thi, (float*)Tlo, nperm, (float*)buf, to_buf);
-    else
-        hipLaunchKernelGGL(k_state_io<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, N,
-                           (double*)Thi, (double*)nullptr, nperm, (double*)buf, to_buf);
+hipError_t launch_state_io(int64_t N, void* T, const int32_t* nperm, int fp32c, void* buf,
+                           int to_buf, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_io, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, T, nperm, fp32c,
+                       buf, to_buf);
     return hipGetLastError();
 }
 
@@ -467,15 +494,15 @@ hipError_t launch_lanczos_start(int64_t N, const double* Vi, const int32_t* is_d
     return hipGetLastError();
 }
 
-hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64, int j,
+hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64, double fx_scale, int j,
                                const double* sc, double* v, double* vprev, double* w,
                                double* xs, double* partial, double* bsum, double* alpha,
                                double* beta, hipStream_t s) {
     const unsigned nb = blocks_for(d.N);
-    hipError_t e = launch_geometry_apply(d, coef64, xs, partial, s);
+    hipError_t e = launch_geometry_apply(d, coef64, xs, partial, fx_scale, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lz_w, dim3(nb), dim3(kBlock), 0, s, d.N, d.part_off, d.part_idx,
-                       partial, sc, v, vprev, beta + j, w, bsum);
+    hipLaunchKernelGGL(k_lz_w, dim3(nb), dim3(kBlock), 0, s, d.N, d.part_off, partial, sc, v,
+                       vprev, beta + j, w, bsum);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, alpha + j, 0);
     hipLaunchKernelGGL(k_lz_orth, dim3(nb), dim3(kBlock), 0, s, d.N, alpha + j, v, w, bsum);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, beta + j + 1,

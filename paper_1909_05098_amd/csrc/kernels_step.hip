@@ -1,23 +1,39 @@
 // Time-stepping kernels for gfx950 (Algorithm 1, time-stepping block).
 //
-// Element pass (Eq 13, 17): one workgroup per tile of consecutive elements.
-// The tile's distinct nodes are staged in LDS (temperature, and k(T) when the
-// conductivity depends on temperature); each thread evaluates whole elements
-// with the precomputed off-diagonal entries a_ab of A = V_tet B^T B (Eq 16).
-// Because every row of A sums to zero,
+// Element pass (Eq 13, 17): one workgroup per tile of consecutive elements
+// (Morton order), R elements per thread.  Each thread first issues the loads
+// of its elements' six precomputed coefficients a_ab of A = V_tet B^T B
+// (Eq 16) and their four local node ids into registers, so they are in
+// flight while the tile's distinct nodes (temperature, and k(T) when
+// conductivity depends on temperature) are staged in LDS.  Because every row
+// of A sums to zero,
 //     F_e,a = k_e sum_{b != a} a_ab (T_b - T_a),
 // and with T = hi + lo the difference is formed as (hi_b - hi_a) +
-// (lo_b - lo_a), which keeps it accurate to float precision of the
-// difference itself.  The four corner loads go to LDS; then each tile node
-// sums its corners in a fixed order and writes one partial per (tile, node).
+// (lo_b - lo_a), accurate to float precision of the difference itself.
+//
+// Assembly inside the tile (Eq 11): each corner load is scaled by 2^S
+// (exact) and rounded to a 64-bit integer, and the integers are added into
+// one LDS accumulator per tile node with integer atomics.  Integer addition
+// is associative, so the tile sums are exact and independent of the order in
+// which lanes arrive: the step is bit-reproducible without floating-point
+// atomics.  S is chosen per scenario so that the largest possible load maps
+// below 2^58 (see the pre-computation), leaving 5 bits of headroom for the
+// sum; loads are resolved to 2^-S, far below float precision of any load.
+// Each tile node's sum, converted back once, is written as one partial, node
+// major, so the node pass reads a node's partials contiguously.
 //
 // Node pass (Eq 11, 19): one thread per node adds its partials in ascending
-// tile order (no floating-point atomics, so results are bit-reproducible)
-// and applies the explicit update with lumped capacity, perfusion, metabolic
-// heat and the nodal source.  In the compensated float mode the increment is
-// added to hi with an error-free TwoSum and the rounding error folded into
-// lo (Knuth's TwoSum, Dekker's Fast2Sum renormalisation).  Dirichlet nodes
-// (u <= 0) are never written: both ping-pong buffers hold T_Gamma.
+// tile order and applies the explicit update with lumped capacity,
+// perfusion, metabolic heat and the nodal source.  In the compensated float
+// mode T is an interleaved (hi, lo) pair; the increment is added with an
+// error-free TwoSum and the rounding error folded into lo (Knuth's TwoSum,
+// Dekker's Fast2Sum renormalisation).  Dirichlet nodes (u <= 0) are never
+// written: both ping-pong buffers hold T_Gamma.
+//
+// Block mapping: gfx950 deals workgroups to its 8 XCDs round-robin.  With
+// xcd = 1 the kernels remap block b to tile (b % 8) * ceil(T / 8) + b / 8, so
+// each XCD (and its L2) works through one contiguous stretch of the Morton
+// curve; the node pass maps 256-node blocks the same way.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -27,6 +43,7 @@ namespace fedfem {
 namespace {
 
 constexpr float kDivergeLimit = 1.0e4f;
+constexpr int kXcds = 8;
 
 template <typename Real>
 __device__ __forceinline__ Real clampT(Real T, const Props<Real>& p) {
@@ -35,177 +52,201 @@ __device__ __forceinline__ Real clampT(Real T, const Props<Real>& p) {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
-struct LdsCarve {
-    size_t slot, conn, f, T, Tlo, k, total;
+// Nodal state access: FP32C stores float2 (hi, lo), FP64 stores double.
+template <typename Real, bool COMP>
+struct State;
+template <>
+struct State<float, true> {
+    __device__ static void load(const void* T, int64_t i, float& hi, float& lo) {
+        const float2 v = static_cast<const float2*>(T)[i];
+        hi = v.x;
+        lo = v.y;
+    }
+    __device__ static void store(void* T, int64_t i, float hi, float lo) {
+        static_cast<float2*>(T)[i] = make_float2(hi, lo);
+    }
+};
+template <>
+struct State<double, false> {
+    __device__ static void load(const void* T, int64_t i, double& hi, double& lo) {
+        hi = static_cast<const double*>(T)[i];
+        lo = 0.0;
+    }
+    __device__ static void store(void* T, int64_t i, double hi, double) {
+        static_cast<double*>(T)[i] = hi;
+    }
 };
 
+struct LdsCarve {
+    size_t acc, T, Tlo, k, total;
+};
+
+// Per tile node: a 64-bit accumulator, T (hi, lo) and k(T).
 __host__ __device__ inline LdsCarve carve(int TE, int maxn, int rb, bool comp, bool td) {
+    (void)TE;
     LdsCarve c;
-    c.slot = 0;
-    c.conn = align16(c.slot + sizeof(uint16_t) * 4 * (size_t)TE);
-    c.f = align16(c.conn + sizeof(uint16_t) * 4 * (size_t)TE);
-    c.T = align16(c.f + (size_t)rb * 4 * TE);
+    c.acc = 0;
+    c.T = align16(c.acc + sizeof(unsigned long long) * (size_t)maxn);
     c.Tlo = align16(c.T + (size_t)rb * maxn);
     c.k = align16(c.Tlo + (comp ? (size_t)rb * maxn : 0));
     c.total = align16(c.k + (td ? (size_t)rb * maxn : 0));
     return c;
 }
 
-template <typename Real, bool COMP, bool TD>
-__device__ __forceinline__ void elem_tile(int64_t E, int TE, int maxn, int64_t t, int64_t e0,
-                                          int ne,
-                                          const int32_t* __restrict__ tile_node_off,
-                                          const int32_t* __restrict__ tile_nodes,
-                                          const uint16_t* __restrict__ seg_start,
-                                          const uint16_t* __restrict__ slots,
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t n) {
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+struct TileArgs {
+    int64_t E;     // plane stride of the coefficient arrays
+    int64_t T;     // number of tiles
+    int TE, maxn;  // LDS sizing
+    int xcd;       // remap blocks to XCD-contiguous tiles
+    const int32_t* tile_elem_off;
+    const int32_t* tile_node_off;
+    const int32_t* tile_nodes;
+    const int32_t* wpos;
+    const uint16_t* lconn;
+};
+
+__device__ __forceinline__ long long to_fixed(float f, float scale) {
+    return __float2ll_rn(f * scale);
+}
+__device__ __forceinline__ long long to_fixed(double f, double scale) {
+    return __double2ll_rn(f * scale);
+}
+
+template <typename Real, bool COMP, bool TD, int R>
+__device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
                                           const Real* __restrict__ coef,
-                                          const Real* __restrict__ Thi,
-                                          const Real* __restrict__ Tlo,
+                                          const void* __restrict__ Tin,
                                           Real* __restrict__ partial, const Props<Real>& pr) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const LdsCarve c = carve(TE, maxn, sizeof(Real), COMP, TD);
-    uint16_t* s_slot = reinterpret_cast<uint16_t*>(lds + c.slot);
-    uint16_t* s_conn = reinterpret_cast<uint16_t*>(lds + c.conn);
-    Real* s_f = reinterpret_cast<Real*>(lds + c.f);
+    const LdsCarve c = carve(a.TE, a.maxn, sizeof(Real), COMP, TD);
+    unsigned long long* s_acc = reinterpret_cast<unsigned long long*>(lds + c.acc);
     Real* s_T = reinterpret_cast<Real*>(lds + c.T);
     Real* s_Tlo = reinterpret_cast<Real*>(lds + c.Tlo);
     Real* s_k = reinterpret_cast<Real*>(lds + c.k);
 
     const int tid = threadIdx.x, bs = blockDim.x;
-    const int ns = 4 * ne;
-    const int p0 = tile_node_off[t];
-    const int m = tile_node_off[t + 1] - p0;
+    const int64_t e0 = a.tile_elem_off[t];
+    const int ne = (int)(a.tile_elem_off[t + 1] - e0);
+    const int p0 = a.tile_node_off[t];
+    const int m = a.tile_node_off[t + 1] - p0;
 
-    // stage the corner list (4 x u16 per element) and the tile's nodes
-    const uint2* gslot = reinterpret_cast<const uint2*>(slots) + e0;
-    uint2* sslot2 = reinterpret_cast<uint2*>(s_slot);
-    for (int el = tid; el < ne; el += bs) sslot2[el] = gslot[el];
-    for (int j = tid; j < m; j += bs) {
-        const int g = tile_nodes[p0 + j];
-        const Real th = Thi[g];
-        s_T[j] = th;
-        if (COMP) s_Tlo[j] = Tlo[g];
-        if (TD) s_k[j] = pr.k0 + pr.dk * (clampT(th, pr) - pr.Tref);
-    }
-    __syncthreads();
-    // invert the node groups into per-corner local node ids
-    for (int j = tid; j < m; j += bs) {
-        const int a = seg_start[p0 + j];
-        const int b = (j + 1 < m) ? (int)seg_start[p0 + j + 1] : ns;
-        for (int k = a; k < b; k++) s_conn[s_slot[k]] = (uint16_t)j;
-    }
-    __syncthreads();
-    // element loads
-    const Real* c01 = coef;
-    const Real* c02 = coef + E;
-    const Real* c03 = coef + 2 * E;
-    const Real* c12 = coef + 3 * E;
-    const Real* c13 = coef + 4 * E;
-    const Real* c23 = coef + 5 * E;
-    const uint2* sconn2 = reinterpret_cast<const uint2*>(s_conn);
-    for (int el = tid; el < ne; el += bs) {
-        const int64_t e = e0 + el;
-        const Real a01 = c01[e], a02 = c02[e], a03 = c03[e];
-        const Real a12 = c12[e], a13 = c13[e], a23 = c23[e];
-        const uint2 cc = sconn2[el];
-        const int n0 = cc.x & 0xffff, n1 = cc.x >> 16, n2 = cc.y & 0xffff, n3 = cc.y >> 16;
-        const Real h0 = s_T[n0], h1 = s_T[n1], h2 = s_T[n2], h3 = s_T[n3];
-        Real d01 = h1 - h0, d02 = h2 - h0, d03 = h3 - h0;
-        Real d12 = h2 - h1, d13 = h3 - h1, d23 = h3 - h2;
-        if (COMP) {
-            const Real l0 = s_Tlo[n0], l1 = s_Tlo[n1], l2 = s_Tlo[n2], l3 = s_Tlo[n3];
-            d01 += l1 - l0;
-            d02 += l2 - l0;
-            d03 += l3 - l0;
-            d12 += l2 - l1;
-            d13 += l3 - l1;
-            d23 += l3 - l2;
+    // 1. coefficient and local-connectivity loads in flight during staging
+    Real cf[R][6];
+    uint2 lc[R];
+    const uint2* glc = reinterpret_cast<const uint2*>(a.lconn) + e0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int el = tid + r * bs;
+        if (el < ne) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) cf[r][k] = coef[k * a.E + e0 + el];
+            lc[r] = glc[el];
         }
-        Real ke;
-        if (TD)
-            ke = (s_k[n0] + s_k[n1] + s_k[n2] + s_k[n3]) * Real(0.25);
-        else
-            ke = pr.k0;
-        const Real g01 = a01 * d01, g02 = a02 * d02, g03 = a03 * d03;
-        const Real g12 = a12 * d12, g13 = a13 * d13, g23 = a23 * d23;
-        Real* f = s_f + 4 * el;
-        f[0] = ke * ((g01 + g02) + g03);
-        f[1] = ke * ((g12 + g13) - g01);
-        f[2] = ke * (g23 - (g02 + g12));
-        f[3] = -ke * ((g03 + g13) + g23);
+    }
+    // 2. tile nodes: temperature, conductivity, zeroed accumulators
+    for (int j = tid; j < m; j += bs) {
+        const int g = a.tile_nodes[p0 + j];
+        Real hi, lo;
+        State<Real, COMP>::load(Tin, g, hi, lo);
+        s_T[j] = hi;
+        if (COMP) s_Tlo[j] = lo;
+        if (TD) s_k[j] = pr.k0 + pr.dk * (clampT(hi, pr) - pr.Tref);
+        s_acc[j] = 0ull;
     }
     __syncthreads();
-    // per tile node: fixed-order sum of its corners
-    for (int j = tid; j < m; j += bs) {
-        const int a = seg_start[p0 + j];
-        const int b = (j + 1 < m) ? (int)seg_start[p0 + j + 1] : ns;
-        Real s = 0;
-        for (int k = a; k < b; k++) s += s_f[s_slot[k]];
-        partial[p0 + j] = s;
+    // 3. element loads, accumulated exactly on the fixed-point grid
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int el = tid + r * bs;
+        if (el < ne) {
+            const int n[4] = {(int)(lc[r].x & 0xffff), (int)(lc[r].x >> 16),
+                              (int)(lc[r].y & 0xffff), (int)(lc[r].y >> 16)};
+            const Real h0 = s_T[n[0]], h1 = s_T[n[1]], h2 = s_T[n[2]], h3 = s_T[n[3]];
+            Real d01 = h1 - h0, d02 = h2 - h0, d03 = h3 - h0;
+            Real d12 = h2 - h1, d13 = h3 - h1, d23 = h3 - h2;
+            if (COMP) {
+                const Real l0 = s_Tlo[n[0]], l1 = s_Tlo[n[1]], l2 = s_Tlo[n[2]],
+                           l3 = s_Tlo[n[3]];
+                d01 += l1 - l0;
+                d02 += l2 - l0;
+                d03 += l3 - l0;
+                d12 += l2 - l1;
+                d13 += l3 - l1;
+                d23 += l3 - l2;
+            }
+            Real ke;
+            if (TD)
+                ke = (s_k[n[0]] + s_k[n[1]] + s_k[n[2]] + s_k[n[3]]) * Real(0.25);
+            else
+                ke = pr.k0;
+            const Real g01 = cf[r][0] * d01, g02 = cf[r][1] * d02, g03 = cf[r][2] * d03;
+            const Real g12 = cf[r][3] * d12, g13 = cf[r][4] * d13, g23 = cf[r][5] * d23;
+            const long long v[4] = {to_fixed(ke * ((g01 + g02) + g03), pr.fxs),
+                                    to_fixed(ke * ((g12 + g13) - g01), pr.fxs),
+                                    to_fixed(ke * (g23 - (g02 + g12)), pr.fxs),
+                                    to_fixed(-ke * ((g03 + g13) + g23), pr.fxs)};
+            // rotate the corner order across lanes to spread LDS conflicts
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int cc = (q + tid) & 3;
+                atomicAdd(&s_acc[n[cc]], (unsigned long long)v[cc]);
+            }
+        }
     }
+    __syncthreads();
+    // 4. one partial per tile node, node-major
+    for (int j = tid; j < m; j += bs)
+        partial[a.wpos[p0 + j]] = (Real)(long long)s_acc[j] * pr.fxi;
 }
 
-template <typename Real, bool COMP, bool TD>
+template <typename Real, bool COMP, bool TD, int R>
 __global__ void __launch_bounds__(1024)
-k_elem_loads(int64_t E, int TE, int maxn, const int32_t* __restrict__ tile_node_off,
-             const int32_t* __restrict__ tile_nodes, const uint16_t* __restrict__ seg_start,
-             const uint16_t* __restrict__ slots, const Real* __restrict__ coef,
-             const Real* __restrict__ Thi, const Real* __restrict__ Tlo,
+k_elem_loads(TileArgs a, const Real* __restrict__ coef, const void* __restrict__ Tin,
              Real* __restrict__ partial, Props<Real> pr) {
-    const int64_t t = blockIdx.x;
-    const int64_t e0 = t * TE;
-    const int ne = (int)min<int64_t>(TE, E - e0);
-    elem_tile<Real, COMP, TD>(E, TE, maxn, t, e0, ne, tile_node_off, tile_nodes, seg_start,
-                              slots, coef, Thi, Tlo, partial, pr);
+    const int64_t t = a.xcd ? xcd_remap(blockIdx.x, a.T) : (int64_t)blockIdx.x;
+    if (t >= a.T) return;
+    elem_tile<Real, COMP, TD, R>(a, t, coef, Tin, partial, pr);
 }
 
-// Batched form: the workgroup's tile comes from a list of active tiles, its
-// element range from per-tile offsets, and its material from the tile's
-// scenario.
-template <typename Real, bool COMP>
+// Batched form: the workgroup's tile comes from a list of active tiles and
+// its material from the tile's scenario.
+template <typename Real, bool COMP, int R>
 __global__ void __launch_bounds__(1024)
-k_elem_loads_batch(int64_t E, int TE, int maxn, const int32_t* __restrict__ tile_list,
-                   const int32_t* __restrict__ tile_elem_off,
-                   const int32_t* __restrict__ tile_scen,
-                   const int32_t* __restrict__ tile_node_off,
-                   const int32_t* __restrict__ tile_nodes,
-                   const uint16_t* __restrict__ seg_start, const uint16_t* __restrict__ slots,
-                   const Real* __restrict__ coef, const Real* __restrict__ Thi,
-                   const Real* __restrict__ Tlo, Real* __restrict__ partial,
+k_elem_loads_batch(TileArgs a, const int32_t* __restrict__ tile_list,
+                   const int32_t* __restrict__ tile_scen, const Real* __restrict__ coef,
+                   const void* __restrict__ Tin, Real* __restrict__ partial,
                    const Props<Real>* __restrict__ props) {
     const int64_t t = tile_list[blockIdx.x];
-    const int64_t e0 = tile_elem_off[t];
-    const int ne = (int)(tile_elem_off[t + 1] - e0);
     const Props<Real> pr = props[tile_scen[t]];
-    elem_tile<Real, COMP, true>(E, TE, maxn, t, e0, ne, tile_node_off, tile_nodes, seg_start,
-                                slots, coef, Thi, Tlo, partial, pr);
+    elem_tile<Real, COMP, true, R>(a, t, coef, Tin, partial, pr);
 }
 
 template <typename Real, bool COMP>
 __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict__ part_off,
-                                            const int32_t* __restrict__ part_idx,
                                             const Real* __restrict__ partial,
                                             const Real* __restrict__ u,
                                             const Real* __restrict__ q,
-                                            const Real* __restrict__ Thi_in,
-                                            const Real* __restrict__ Tlo_in,
-                                            Real* __restrict__ Thi_out,
-                                            Real* __restrict__ Tlo_out, const Props<Real>& pr,
-                                            int* __restrict__ flag) {
+                                            const void* __restrict__ Tin, void* __restrict__ Tout,
+                                            const Props<Real>& pr, int* __restrict__ flag) {
     const Real ui = u[i];
     if (!(ui > Real(0))) return;  // Dirichlet node: held at T_Gamma
     const int a = part_off[i], b = part_off[i + 1];
     Real F = 0;
-    for (int k = a; k < b; k++) F += partial[part_idx[k]];
-    const Real hi = Thi_in[i];
-    const Real lo = COMP ? Tlo_in[i] : Real(0);
+    for (int k = a; k < b; k++) F += partial[k];
+    Real hi, lo;
+    State<Real, COMP>::load(Tin, i, hi, lo);
     const Real dT = clampT(hi, pr) - pr.Tref;
     const Real rc = (pr.rho0 + pr.drho * dT) * (pr.c0 + pr.dc * dT);
     // heat flow per unit volume [W/m^3]: source and conduction per lumped
     // volume, metabolic heat, perfusion towards T_a
     const Real R = (q[i] - F) * ui + pr.Qm + pr.wbcb * ((pr.Ta - hi) - lo);
     const Real d = pr.dt * R / rc;
-    Real nh, nl;
+    Real nh, nl = 0;
     if (COMP) {
         // TwoSum(hi, d) = s + err exactly
         const Real s = hi + d;
@@ -215,26 +256,24 @@ __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict
         // Fast2Sum(s, l2): |s| >= |l2|
         nh = s + l2;
         nl = l2 - (nh - s);
-        Tlo_out[i] = nl;
     } else {
         nh = hi + d;
     }
-    Thi_out[i] = nh;
+    State<Real, COMP>::store(Tout, i, nh, nl);
     if (!(nh < Real(kDivergeLimit) && nh > -Real(kDivergeLimit))) *flag = 1;
 }
 
 template <typename Real, bool COMP>
 __global__ void __launch_bounds__(256)
-k_node_update(int64_t N, const int32_t* __restrict__ part_off,
-              const int32_t* __restrict__ part_idx, const Real* __restrict__ partial,
-              const Real* __restrict__ u, const Real* __restrict__ q,
-              const Real* __restrict__ Thi_in, const Real* __restrict__ Tlo_in,
-              Real* __restrict__ Thi_out, Real* __restrict__ Tlo_out, Props<Real> pr,
-              int* __restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+k_node_update(int64_t N, int xcd, const int32_t* __restrict__ part_off,
+              const Real* __restrict__ partial, const Real* __restrict__ u,
+              const Real* __restrict__ q, const void* __restrict__ Tin, void* __restrict__ Tout,
+              Props<Real> pr, int* __restrict__ flag) {
+    const int64_t nb = (N + 255) / 256;
+    const int64_t blk = xcd ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
+    const int64_t i = blk * 256 + threadIdx.x;
     if (i >= N) return;
-    node_update<Real, COMP>(i, part_off, part_idx, partial, u, q, Thi_in, Tlo_in, Thi_out,
-                            Tlo_out, pr, flag);
+    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flag);
 }
 
 // Batched form: 256-node blocks never straddle scenarios; the block comes
@@ -243,53 +282,105 @@ template <typename Real, bool COMP>
 __global__ void __launch_bounds__(256)
 k_node_update_batch(const int32_t* __restrict__ block_list,
                     const int32_t* __restrict__ block_scen,
-                    const int32_t* __restrict__ part_off, const int32_t* __restrict__ part_idx,
-                    const Real* __restrict__ partial, const Real* __restrict__ u,
-                    const Real* __restrict__ q, const Real* __restrict__ Thi_in,
-                    const Real* __restrict__ Tlo_in, Real* __restrict__ Thi_out,
-                    Real* __restrict__ Tlo_out, const Props<Real>* __restrict__ props,
-                    int* __restrict__ flags) {
+                    const int32_t* __restrict__ part_off, const Real* __restrict__ partial,
+                    const Real* __restrict__ u, const Real* __restrict__ q,
+                    const void* __restrict__ Tin, void* __restrict__ Tout,
+                    const Props<Real>* __restrict__ props, int* __restrict__ flags) {
     const int blk = block_list[blockIdx.x];
     const int sc = block_scen[blk];
     const Props<Real> pr = props[sc];
     const int64_t i = (int64_t)blk * 256 + threadIdx.x;
-    node_update<Real, COMP>(i, part_off, part_idx, partial, u, q, Thi_in, Tlo_in, Thi_out,
-                            Tlo_out, pr, flags + sc);
+    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flags + sc);
+}
+
+TileArgs tile_args(const DevLayout& d) {
+    TileArgs a;
+    a.E = d.E;
+    a.T = d.T;
+    a.TE = d.tile_elems;
+    a.maxn = d.max_tile_nodes;
+    a.xcd = d.xcd;
+    a.tile_elem_off = d.tile_elem_off;
+    a.tile_node_off = d.tile_node_off;
+    a.tile_nodes = d.tile_nodes;
+    a.wpos = d.wpos;
+    a.lconn = d.lconn;
+    return a;
+}
+
+template <typename K>
+hipError_t allow_lds(K kern, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename Real, bool COMP, bool TD, int R>
+hipError_t launch_elem_r(const DevLayout& d, const Real* coef, const Props<Real>& p,
+                         const void* Tin, Real* partial, hipStream_t s) {
+    const size_t lds = carve(d.tile_elems, d.max_tile_nodes, sizeof(Real), COMP, TD).total;
+    auto kern = k_elem_loads<Real, COMP, TD, R>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    const int64_t grid = d.xcd ? (d.T + kXcds - 1) / kXcds * kXcds : d.T;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(d.threads), lds, s, tile_args(d), coef,
+                       Tin, partial, p);
+    return hipGetLastError();
 }
 
 template <typename Real, bool COMP, bool TD>
 hipError_t launch_elem_t(const DevLayout& d, const Real* coef, const Props<Real>& p,
-                         const Real* Thi, const Real* Tlo, Real* partial,
-                         hipStream_t s) {
-    const size_t lds = carve(d.tile_elems, d.max_tile_nodes, sizeof(Real), COMP, TD).total;
-    auto kern = k_elem_loads<Real, COMP, TD>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
+                         const void* Tin, Real* partial, hipStream_t s) {
+    switch (elems_per_thread(d)) {
+        case 1: return launch_elem_r<Real, COMP, TD, 1>(d, coef, p, Tin, partial, s);
+        case 2: return launch_elem_r<Real, COMP, TD, 2>(d, coef, p, Tin, partial, s);
+        case 4: return launch_elem_r<Real, COMP, TD, 4>(d, coef, p, Tin, partial, s);
+        default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)d.T), dim3(d.threads), lds, s, d.E,
-                       d.tile_elems, d.max_tile_nodes, d.tile_node_off, d.tile_nodes,
-                       d.seg_start, d.slots, coef, Thi, Tlo, partial, p);
-    return hipGetLastError();
 }
 
 template <typename Real, bool COMP>
 hipError_t launch_node_t(const DevLayout& d, int cur, const Props<Real>& p, int* flag,
                          hipStream_t s) {
-    const unsigned blocks = (unsigned)((d.N + 255) / 256);
-    hipLaunchKernelGGL((k_node_update<Real, COMP>), dim3(blocks), dim3(256), 0, s, d.N,
-                       d.part_off, d.part_idx, static_cast<const Real*>(d.partial),
-                       static_cast<const Real*>(d.u), static_cast<const Real*>(d.q),
-                       static_cast<const Real*>(d.Thi[cur]),
-                       static_cast<const Real*>(d.Tlo[cur]),
-                       static_cast<Real*>(d.Thi[1 - cur]),
-                       static_cast<Real*>(d.Tlo[1 - cur]), p, flag);
+    const int64_t nb = (d.N + 255) / 256;
+    const int64_t grid = d.xcd ? (nb + kXcds - 1) / kXcds * kXcds : nb;
+    hipLaunchKernelGGL((k_node_update<Real, COMP>), dim3((unsigned)grid), dim3(256), 0, s, d.N,
+                       d.xcd, d.part_off, static_cast<const Real*>(d.partial),
+                       static_cast<const Real*>(d.u), static_cast<const Real*>(d.q), d.T_[cur],
+                       d.T_[1 - cur], p, flag);
     return hipGetLastError();
 }
 
+template <typename Real, bool COMP, int R>
+hipError_t launch_elem_batch_r(const DevLayout& d, const BatchTables& b, int cur, int n_tiles,
+                               hipStream_t s) {
+    const size_t lds = carve(d.tile_elems, d.max_tile_nodes, sizeof(Real), COMP, true).total;
+    auto kern = k_elem_loads_batch<Real, COMP, R>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(d.threads), lds, s, tile_args(d), b.tile_list,
+                       b.tile_scen, static_cast<const Real*>(d.coef), d.T_[cur],
+                       static_cast<Real*>(d.partial), static_cast<const Props<Real>*>(b.props));
+    return hipGetLastError();
+}
+
+template <typename Real, bool COMP>
+hipError_t launch_elem_batch_t(const DevLayout& d, const BatchTables& b, int cur, int n_tiles,
+                               hipStream_t s) {
+    switch (elems_per_thread(d)) {
+        case 1: return launch_elem_batch_r<Real, COMP, 1>(d, b, cur, n_tiles, s);
+        case 2: return launch_elem_batch_r<Real, COMP, 2>(d, b, cur, n_tiles, s);
+        case 4: return launch_elem_batch_r<Real, COMP, 4>(d, b, cur, n_tiles, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+int elems_per_thread(const DevLayout& d) {
+    const int r = (d.tile_elems + d.threads - 1) / d.threads;
+    return r <= 1 ? 1 : (r <= 2 ? 2 : (r <= 4 ? 4 : 8));
+}
 
 size_t tile_lds_bytes(int TE, int maxn, int rb, bool comp, bool td) {
     return carve(TE, maxn, rb, comp, td).total;
@@ -297,12 +388,10 @@ size_t tile_lds_bytes(int TE, int maxn, int rb, bool comp, bool td) {
 
 hipError_t launch_elem_f32c(const DevLayout& d, int cur, const Props<float>& p, bool td,
                             hipStream_t s) {
-    const float* hi = static_cast<const float*>(d.Thi[cur]);
-    const float* lo = static_cast<const float*>(d.Tlo[cur]);
     const float* cf = static_cast<const float*>(d.coef);
     float* part = static_cast<float*>(d.partial);
-    return td ? launch_elem_t<float, true, true>(d, cf, p, hi, lo, part, s)
-              : launch_elem_t<float, true, false>(d, cf, p, hi, lo, part, s);
+    return td ? launch_elem_t<float, true, true>(d, cf, p, d.T_[cur], part, s)
+              : launch_elem_t<float, true, false>(d, cf, p, d.T_[cur], part, s);
 }
 
 hipError_t launch_node_f32c(const DevLayout& d, int cur, const Props<float>& p, int* flag,
@@ -312,11 +401,10 @@ hipError_t launch_node_f32c(const DevLayout& d, int cur, const Props<float>& p, 
 
 hipError_t launch_elem_f64(const DevLayout& d, int cur, const Props<double>& p, bool td,
                            hipStream_t s) {
-    const double* hi = static_cast<const double*>(d.Thi[cur]);
     const double* cf = static_cast<const double*>(d.coef);
     double* part = static_cast<double*>(d.partial);
-    return td ? launch_elem_t<double, false, true>(d, cf, p, hi, nullptr, part, s)
-              : launch_elem_t<double, false, false>(d, cf, p, hi, nullptr, part, s);
+    return td ? launch_elem_t<double, false, true>(d, cf, p, d.T_[cur], part, s)
+              : launch_elem_t<double, false, false>(d, cf, p, d.T_[cur], part, s);
 }
 
 hipError_t launch_node_f64(const DevLayout& d, int cur, const Props<double>& p, int* flag,
@@ -339,51 +427,19 @@ hipError_t launch_step_f64(const DevLayout& d, int cur, const Props<double>& p, 
 }
 
 hipError_t launch_geometry_apply(const DevLayout& d, const double* coef64, const double* x,
-                                 double* partial, hipStream_t s) {
+                                 double* partial, double fx_scale, hipStream_t s) {
     Props<double> p{};
     p.k0 = 1.0;
-    return launch_elem_t<double, false, false>(d, coef64, p, x, nullptr, partial, s);
+    p.fxs = fx_scale;
+    p.fxi = 1.0 / fx_scale;
+    return launch_elem_t<double, false, false>(d, coef64, p, x, partial, s);
 }
 
 hipError_t launch_elem_batch(const DevLayout& d, const BatchTables& b, int cur, int n_tiles,
                              int fp32c, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    const int rb = fp32c ? 4 : 8;
-    const size_t lds = carve(d.tile_elems, d.max_tile_nodes, rb, fp32c != 0, true).total;
-    if (fp32c) {
-        auto kern = k_elem_loads_batch<float, true>;
-        if (lds > 65536) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds);
-            if (e != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(d.threads), lds, s, d.E, d.tile_elems,
-                           d.max_tile_nodes, b.tile_list, b.tile_elem_off, b.tile_scen,
-                           d.tile_node_off, d.tile_nodes, d.seg_start, d.slots,
-                           static_cast<const float*>(d.coef),
-                           static_cast<const float*>(d.Thi[cur]),
-                           static_cast<const float*>(d.Tlo[cur]),
-                           static_cast<float*>(d.partial),
-                           static_cast<const Props<float>*>(b.props));
-    } else {
-        auto kern = k_elem_loads_batch<double, false>;
-        if (lds > 65536) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds);
-            if (e != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(d.threads), lds, s, d.E, d.tile_elems,
-                           d.max_tile_nodes, b.tile_list, b.tile_elem_off, b.tile_scen,
-                           d.tile_node_off, d.tile_nodes, d.seg_start, d.slots,
-                           static_cast<const double*>(d.coef),
-                           static_cast<const double*>(d.Thi[cur]),
-                           static_cast<const double*>(nullptr),
-                           static_cast<double*>(d.partial),
-                           static_cast<const Props<double>*>(b.props));
-    }
-    return hipGetLastError();
+    return fp32c ? launch_elem_batch_t<float, true>(d, b, cur, n_tiles, s)
+                 : launch_elem_batch_t<double, false>(d, b, cur, n_tiles, s);
 }
 
 hipError_t launch_node_batch(const DevLayout& d, const BatchTables& b, int cur, int n_blocks,
@@ -391,24 +447,17 @@ hipError_t launch_node_batch(const DevLayout& d, const BatchTables& b, int cur, 
     if (n_blocks <= 0) return hipSuccess;
     if (fp32c)
         hipLaunchKernelGGL((k_node_update_batch<float, true>), dim3(n_blocks), dim3(256), 0, s,
-                           b.block_list, b.block_scen, d.part_off, d.part_idx,
-                           static_cast<const float*>(d.partial),
-                           static_cast<const float*>(d.u), static_cast<const float*>(d.q),
-                           static_cast<const float*>(d.Thi[cur]),
-                           static_cast<const float*>(d.Tlo[cur]),
-                           static_cast<float*>(d.Thi[1 - cur]),
-                           static_cast<float*>(d.Tlo[1 - cur]),
+                           b.block_list, b.block_scen, d.part_off,
+                           static_cast<const float*>(d.partial), static_cast<const float*>(d.u),
+                           static_cast<const float*>(d.q), d.T_[cur], d.T_[1 - cur],
                            static_cast<const Props<float>*>(b.props), flags);
     else
         hipLaunchKernelGGL((k_node_update_batch<double, false>), dim3(n_blocks), dim3(256), 0,
-                           s, b.block_list, b.block_scen, d.part_off, d.part_idx,
+                           s, b.block_list, b.block_scen, d.part_off,
                            static_cast<const double*>(d.partial),
                            static_cast<const double*>(d.u), static_cast<const double*>(d.q),
-                           static_cast<const double*>(d.Thi[cur]),
-                           static_cast<const double*>(nullptr),
-                           static_cast<double*>(d.Thi[1 - cur]),
-                           static_cast<double*>(nullptr),
-                           static_cast<const Props<double>*>(b.props), flags);
+                           d.T_[cur], d.T_[1 - cur], static_cast<const Props<double>*>(b.props),
+                           flags);
     return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
-// Host-side mesh layout: Morton renumbering, element tiles with their node
-// groups, and the node -> partial / node -> element-corner lists.  Integer
+// Host-side mesh layout: Morton renumbering, element tiles with their local
+// node lists, and the node -> partial / node -> element-corner lists.  Integer
 // topology only; all floating-point pre-computation runs on the GPU.
 #include <algorithm>
 #include <cstring>
@@ -92,21 +92,58 @@ std::vector<int32_t> morton_order(const double* pts, int64_t n) {
     return id;
 }
 
-bool build_tiles(Layout& L, int TE, std::string& err) {
+bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     if (TE < 64 || TE > 8192 || TE % 64) {
         err = "tile_elems must be a multiple of 64 in [64, 8192]";
         return false;
     }
+    if (MN < 4 || MN > 4 * TE) {
+        err = "max_tile_nodes must lie in [4, 4 * tile_elems]";
+        return false;
+    }
     const int64_t E = L.E, N = L.N;
-    const int64_t T = (E + TE - 1) / TE;
     L.tile_elems = TE;
+    // greedy cut along the element order: close a tile when it holds TE
+    // elements or the next element would bring it past MN distinct nodes
+    L.tile_elem_off.assign(1, 0);
+    {
+        std::vector<int32_t> mark(N, -1);
+        int32_t t = 0;
+        int cnt = 0, ne = 0;
+        for (int64_t e = 0; e < E; e++) {
+            const int32_t* n = &L.conn[4 * e];
+            int nnew = 0;
+            for (int c = 0; c < 4; c++) {
+                bool dup = false;
+                for (int d = 0; d < c; d++) dup |= (n[d] == n[c]);
+                if (!dup && mark[n[c]] != t) nnew++;
+            }
+            if (ne == TE || cnt + nnew > MN) {
+                L.tile_elem_off.push_back((int32_t)e);
+                t++;
+                cnt = 0;
+                ne = 0;
+                nnew = 0;
+                for (int c = 0; c < 4; c++) {
+                    bool dup = false;
+                    for (int d = 0; d < c; d++) dup |= (n[d] == n[c]);
+                    if (!dup) nnew++;
+                }
+            }
+            for (int c = 0; c < 4; c++) mark[n[c]] = t;
+            cnt += nnew;
+            ne++;
+        }
+        L.tile_elem_off.push_back((int32_t)E);
+    }
+    const int64_t T = (int64_t)L.tile_elem_off.size() - 1;
     L.T = T;
     // pass 1: sort each tile's corners by (node, slot), count distinct nodes
     std::vector<uint64_t> keys(4 * E);
     std::vector<int32_t> ucount(T);
     parallel_for(T, [&](int64_t a, int64_t b) {
         for (int64_t t = a; t < b; t++) {
-            int64_t e0 = t * TE, ne = std::min<int64_t>(TE, E - e0);
+            const int64_t e0 = L.tile_elem_off[t], ne = L.tile_elem_off[t + 1] - e0;
             uint64_t* k = keys.data() + 4 * e0;
             for (int64_t s = 0; s < 4 * ne; s++)
                 k[s] = ((uint64_t)(uint32_t)L.conn[4 * e0 + s] << 16) | (uint64_t)s;
@@ -133,39 +170,37 @@ bool build_tiles(Layout& L, int TE, std::string& err) {
     L.P = P;
     L.max_tile_nodes = maxn;
     L.tile_nodes.assign(P, 0);
-    L.seg_start.assign(P, 0);
-    L.slots.assign(4 * E, 0);
-    // pass 2: emit node groups
+    L.lconn.assign(4 * E, 0);
+    // pass 2: tile node lists and each corner's local node id
     parallel_for(T, [&](int64_t a, int64_t b) {
         for (int64_t t = a; t < b; t++) {
-            int64_t e0 = t * TE, ne = std::min<int64_t>(TE, E - e0);
+            const int64_t e0 = L.tile_elem_off[t], ne = L.tile_elem_off[t + 1] - e0;
             const uint64_t* k = keys.data() + 4 * e0;
             int64_t p = L.tile_node_off[t] - 1;
             for (int64_t s = 0; s < 4 * ne; s++) {
-                uint32_t node = (uint32_t)(k[s] >> 16);
+                const uint32_t node = (uint32_t)(k[s] >> 16);
                 if (s == 0 || (k[s] >> 16) != (k[s - 1] >> 16)) {
                     p++;
                     L.tile_nodes[p] = (int32_t)node;
-                    L.seg_start[p] = (uint16_t)s;
                 }
-                L.slots[4 * e0 + s] = (uint16_t)(k[s] & 0xffff);
+                L.lconn[4 * e0 + (k[s] & 0xffff)] = (uint16_t)(p - L.tile_node_off[t]);
             }
         }
     });
-    // node -> partial slots, ascending p
+    // node-major partial positions, ascending tile inside each node
     L.part_off.assign(N + 1, 0);
     for (int64_t p = 0; p < P; p++) L.part_off[L.tile_nodes[p] + 1]++;
     for (int64_t i = 0; i < N; i++) L.part_off[i + 1] += L.part_off[i];
-    L.part_idx.assign(P, 0);
+    L.wpos.assign(P, 0);
     {
         std::vector<int32_t> fill(L.part_off.begin(), L.part_off.end() - 1);
-        for (int64_t p = 0; p < P; p++) L.part_idx[fill[L.tile_nodes[p]]++] = (int32_t)p;
+        for (int64_t p = 0; p < P; p++) L.wpos[p] = fill[L.tile_nodes[p]]++;
     }
     return true;
 }
 
 bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
-                  int reorder, int TE, Layout& L, std::string& err) {
+                  int reorder, int TE, int MN, Layout& L, std::string& err) {
     L = Layout();
     L.N = N;
     L.E = E;
@@ -207,7 +242,7 @@ bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
         std::vector<int32_t> fill(L.ec_off.begin(), L.ec_off.end() - 1);
         for (int64_t s = 0; s < 4 * E; s++) L.ec[fill[L.conn[s]]++] = (int32_t)s;
     }
-    return build_tiles(L, TE, err);
+    return build_tiles(L, TE, MN, err);
 }
 
 }  // namespace fedfem

@@ -50,7 +50,8 @@ class BC(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("reorder", C.c_int32), ("tile_elems", C.c_int32),
-                ("threads", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("threads", C.c_int32), ("max_tile_nodes", C.c_int32),
+                ("xcd", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Info(C.Structure):
@@ -134,7 +135,7 @@ class Handle:
 
     def __init__(self, xyz, tets, materials, T0=37.0, dir_nodes=(), dir_T=(),
                  dt=-0.9, precision=FP32C, reorder=True, tile_elems=0,
-                 threads=0):
+                 threads=0, max_tile_nodes=0, xcd=False):
         L = load()
         self._L = L
         self._h = C.c_void_p()
@@ -156,7 +157,8 @@ class Handle:
         self._check(L.fedfem_create(C.byref(mesh), C.byref(mat), C.byref(bc),
                                     C.byref(self._h)), "fedfem_create")
         self.precision = int(precision)
-        opt = Options(1 if reorder else 0, int(tile_elems), int(threads))
+        opt = Options(1 if reorder else 0, int(tile_elems), int(threads),
+                      int(max_tile_nodes), 1 if xcd else 0)
         self._check(L.fedfem_set_options(self._h, C.byref(opt)),
                     "fedfem_set_options")
 
