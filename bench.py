@@ -84,6 +84,86 @@ def cpu_baseline(scn, dt, q_params, seconds):
                        f"{oracle.max_threads()}")}
 
 
+def _gen_sweep_one(j):
+    from synth import scenarios as sc
+    return sc.sweep_scenario(j)
+
+
+def gen_sweep(count, workers):
+    """Seeded planning-sweep scenarios, built on host cores before any GPU
+    use in this process (the pool forks)."""
+    from multiprocessing import get_context
+    with get_context("fork").Pool(workers) as pool:
+        return pool.map(_gen_sweep_one, range(count))
+
+
+def run_sweep(scns):
+    """Scenarios/s for the planning sweep: plain per-scenario use of the
+    library versus one batched graph launch, on the same GPU."""
+    import numpy as np
+    from paper_1909_05098_amd import fedfem as ff
+    from synth import scenarios as sc
+
+    def handle(s):
+        h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
+                      dt=-0.9, precision=ff.FP32C)
+        h.precompute()
+        h.set_gaussian_sources(s.sources, s.source_mode)
+        _, dtcr = h.dt()
+        n, dt = sc.steps_for(s.t_end, dtcr)
+        h.set_dt(dt)
+        return h, n
+
+    # plain: create -> precompute -> step -> read, one scenario at a time
+    plain_T, ns = [], []
+    t_all = t_steps = 0.0
+    for s in scns:
+        t0 = time.perf_counter()
+        h, n = handle(s)
+        t1 = time.perf_counter()
+        h.step(n)
+        plain_T.append(h.read_T())
+        t2 = time.perf_counter()
+        h.close()
+        t_all += t2 - t0
+        t_steps += t2 - t1
+        ns.append(n)
+    log(f"sweep plain: {len(scns)} scenarios in {t_all:.2f} s ({t_steps:.2f} s stepping)")
+    # batched: all handles, one captured launch sequence
+    t0 = time.perf_counter()
+    hs = [handle(s)[0] for s in scns]
+    t1 = time.perf_counter()
+    b = ff.Batch(hs)
+    t2 = time.perf_counter()
+    b.run(ns)
+    t3 = time.perf_counter()
+    dT = max(float(np.max(np.abs(h.read_T() - T))) for h, T in zip(hs, plain_T))
+    first_graph_ms = b.last_ms()
+    # steady state: the same launch sequence again (graph already captured)
+    b.run(ns)
+    graph_ms = b.last_ms()
+    t4 = time.perf_counter()
+    b.close()
+    for h in hs:
+        h.close()
+    S = len(scns)
+    upd = float(sum(s.n_tets * n for s, n in zip(scns, ns)))
+    log(f"sweep batched: precompute {t1 - t0:.2f} s, batch create {t2 - t1:.2f} s, "
+        f"first run {t3 - t2:.3f} s, graph {graph_ms:.2f} ms")
+    return {"workload": f"planning sweep: {S} seeded ellipsoids, 20k-400k tets, "
+                        f"TD properties, 300 s each, FP32C",
+            "scenarios": S, "element_updates": upd,
+            "steps_min_max": [int(min(ns)), int(max(ns))],
+            "plain_scenarios_per_s": round(S / t_all, 2),
+            "plain_scenarios_per_s_excl_precompute": round(S / t_steps, 2),
+            "batched_scenarios_per_s": round(S / (graph_ms * 1e-3), 1),
+            "batched_scenarios_per_s_incl_precompute": round(S / ((t1 - t0) + (t2 - t1) + (t3 - t2)), 2),
+            "batched_graph_ms": round(graph_ms, 3),
+            "batched_first_run_ms": round(first_graph_ms, 3),
+            "batched_element_updates_per_s": round(upd / (graph_ms * 1e-3), 1),
+            "max_abs_dT_batched_vs_plain_K": dT}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +178,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=20)
+    ap.add_argument("--sweep", type=int, default=256,
+                    help="planning-sweep scenarios for the batched leg (0 = skip)")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for "
                          "counter calibration) and exit")
@@ -109,6 +191,12 @@ def main():
         sys.exit(2)
 
     import numpy as np
+    sweep_scns = None
+    if args.sweep and not args.copy_calib_gib:
+        t0 = time.perf_counter()
+        sweep_scns = gen_sweep(args.sweep, min(16, os.cpu_count() or 1))
+        log(f"sweep meshes: {len(sweep_scns)} scenarios "
+            f"({sum(s.n_tets for s in sweep_scns)} tets, {time.perf_counter() - t0:.1f} s)")
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -185,6 +273,8 @@ def main():
                 "algorithmic_bytes_per_launch": by, "avg_launch_ms": round(ms, 5)}
     other = [k for k in kern if k != dom][0]
     step_gbps = (elem_bytes + node_bytes) / (ms_step * 1e-3) / 1e9
+    h.close()
+    batched = run_sweep(sweep_scns) if sweep_scns else None
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -209,10 +299,10 @@ def main():
         "step_GBps_algorithmic": round(step_gbps, 1),
         "max_abs_dT_vs_oracle_K": max_err,
         "precompute_s": round(t_pre, 3),
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    h.close()
 
 
 if __name__ == "__main__":

@@ -1,0 +1,88 @@
+"""Batched execution: many scenarios of the planning sweep advanced by one
+graph launch must give exactly what per-handle stepping gives, and match the
+FP64 oracle per scenario."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_1909_05098_amd import fedfem as ff
+from synth import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [5, 8, 9, 13, 16, 30]
+
+
+@pytest.fixture(scope="module")
+def scenarios():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    out = []
+    for j in SMALL:
+        s = sc.sweep_scenario(j)
+        om = oracle.build_model(s)
+        dtcr, _ = dense.critical_dt_from_lambda(om.geometry_lambda(), om.mat)
+        n, dt = sc.steps_for(s.t_end, dtcr)
+        om.dt = dt
+        q = om.source(s.sources, s.source_mode)
+        out.append((s, om, q, n, dt))
+    return out
+
+
+def make(s, dt):
+    h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=dt,
+                  precision=ff.FP32C)
+    h.precompute()
+    h.set_gaussian_sources(s.sources, s.source_mode)
+    return h
+
+
+def test_batch_equals_single_and_oracle(scenarios):
+    hb = [make(s, dt) for s, _, _, _, dt in scenarios]
+    hs = [make(s, dt) for s, _, _, _, dt in scenarios]
+    ns = np.array([n for _, _, _, n, _ in scenarios])
+    b = ff.Batch(hb)
+    b.run(ns)
+    print(f"[batch] {len(hb)} scenarios, steps {ns.tolist()}, graph {b.last_ms():.3f} ms",
+          flush=True)
+    worst = 0.0
+    for (s, om, q, n, dt), h1, h2 in zip(scenarios, hb, hs):
+        h2.step(n)
+        Tb = h1.read_T()
+        assert np.array_equal(h1.read_state()[0], h2.read_state()[0]), s.name
+        assert h1.time()[1] == n
+        T_ref = om.run(om.initial(37.0), n, q)
+        err = float(np.max(np.abs(Tb - T_ref)))
+        worst = max(worst, err)
+        print(f"[parity] batch {s.name}: n={n} tets={s.n_tets} peak={T_ref.max():.2f} "
+              f"max|dT|={err:.3e} K", flush=True)
+    assert worst <= 1e-3
+    # a second run continues from the end state; one scenario stays put
+    ns2 = ns // 3
+    ns2[2] = 0
+    before = hb[2].read_state()[0]
+    b.run(ns2)
+    for h1, h2, k in zip(hb, hs, ns2):
+        h2.step(int(k))
+        assert np.array_equal(h1.read_state()[0], h2.read_state()[0])
+    assert np.array_equal(hb[2].read_state()[0], before)
+    b.close()
+
+
+def test_batch_rejects_mixed_or_unprepared(scenarios):
+    s, _, _, _, dt = scenarios[0]
+    h = make(s, dt)
+    h64 = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=dt,
+                    precision=ff.FP64)
+    h64.precompute()
+    with pytest.raises(ff.FedFemError) as ei:
+        ff.Batch([h, h64])
+    assert ei.value.code == ff.E_INVALID
+    raw = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=dt)
+    with pytest.raises(ff.FedFemError) as ei:
+        ff.Batch([h, raw])
+    assert ei.value.code == ff.E_NOT_PRECOMPUTED
+    with pytest.raises(ff.FedFemError):
+        ff.Batch([h, h])
