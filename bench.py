@@ -32,6 +32,7 @@ METRIC = ("tet-element updates/s + achieved HBM GB/s; scenarios/s plain vs "
 GOLDEN3 = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "elem_loads_config3_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_05098_amd", "csrc", "kernels_step.hip")
+TUNE_CACHE = os.path.join(os.environ.get("TMPDIR", "/tmp"), "fedfem_tune_cache.txt")
 
 
 def log(msg):
@@ -97,7 +98,7 @@ def gen_sweep(count, workers):
         return pool.map(_gen_sweep_one, range(count))
 
 
-def run_sweep(scns):
+def run_sweep(scns, autotune=True):
     """Scenarios/s for the planning sweep: plain per-scenario use of the
     library versus one batched graph launch, on the same GPU."""
     import numpy as np
@@ -107,6 +108,8 @@ def run_sweep(scns):
     def handle(s):
         h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
                       dt=-0.9, precision=ff.FP32C)
+        if autotune:
+            h.autotune(TUNE_CACHE, for_batch=True)
         h.precompute()
         h.set_gaussian_sources(s.sources, s.source_mode)
         _, dtcr = h.dt()
@@ -114,6 +117,17 @@ def run_sweep(scns):
         h.set_dt(dt)
         return h, n
 
+    # tune each mesh-size class once (untimed); both legs then hit the cache
+    t_tune = 0.0
+    if autotune:
+        t0 = time.perf_counter()
+        for s in scns:
+            h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
+                          dt=-0.9, precision=ff.FP32C)
+            h.autotune(TUNE_CACHE, for_batch=True)
+            h.close()
+        t_tune = time.perf_counter() - t0
+        log(f"sweep autotune (all size classes) {t_tune:.2f} s")
     # plain: create -> precompute -> step -> read, one scenario at a time
     plain_T, ns = [], []
     t_all = t_steps = 0.0
@@ -159,6 +173,7 @@ def run_sweep(scns):
             "batched_scenarios_per_s": round(S / (graph_ms * 1e-3), 1),
             "batched_scenarios_per_s_incl_precompute": round(S / ((t1 - t0) + (t2 - t1) + (t3 - t2)), 2),
             "batched_graph_ms": round(graph_ms, 3),
+            "autotune_s_untimed": round(t_tune, 2),
             "batched_first_run_ms": round(first_graph_ms, 3),
             "batched_element_updates_per_s": round(upd / (graph_ms * 1e-3), 1),
             "max_abs_dT_batched_vs_plain_K": dT}
@@ -175,6 +190,9 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--max-nodes", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the given/default layout options instead of "
+                         "letting the library's autotuner choose")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=20)
@@ -229,6 +247,11 @@ def main():
                   reorder=(args.order == "morton"), tile_elems=args.tile,
                   threads=args.threads, max_tile_nodes=args.max_nodes,
                   xcd=bool(args.xcd))
+    tuned = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuned = h.autotune(TUNE_CACHE)
+        log(f"autotune {time.perf_counter() - t0:.2f} s -> {tuned}")
     t0 = time.perf_counter()
     h.precompute()
     t_pre = time.perf_counter() - t0
@@ -274,7 +297,7 @@ def main():
     other = [k for k in kern if k != dom][0]
     step_gbps = (elem_bytes + node_bytes) / (ms_step * 1e-3) / 1e9
     h.close()
-    batched = run_sweep(sweep_scns) if sweep_scns else None
+    batched = run_sweep(sweep_scns, not args.no_autotune) if sweep_scns else None
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -292,6 +315,7 @@ def main():
                    "n_tets": E, "n_nodes": N, "dt_s": dt,
                    "precision": "f32 element loop, compensated f32 hi/lo nodal state, f64 precompute",
                    "tile_elems": info["tile_elems"], "threads": info["threads"],
+                   "autotuned": tuned is not None,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "other_kernel": {"kernel": other, "avg_launch_ms": round(kern[other][0], 5),

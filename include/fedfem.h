@@ -137,6 +137,24 @@ int fedfem_create(const fedfem_mesh *mesh, const fedfem_materials *mat,
 int fedfem_set_options(fedfem_handle *h, const fedfem_options *opt);
 
 /*
+ * Autotuner: choose layout options for this handle's mesh by timing
+ * candidate layouts (Morton order with 1024, 2048 and 4096-element tiles,
+ * the caller's order with 1024-element tiles; each with two workgroup sizes
+ * and both XCD mappings) on the GPU with HIP events, and set the fastest
+ * (element pass + node pass per step) as the handle's options.  With
+ * FEDFEM_TUNE_BATCH in flags only layouts that share one workgroup size in a
+ * batch are tried (Morton order, 1024 or 2048-element tiles, 4 elements per
+ * thread).  Must run before fedfem_precompute.  cache_path (NULL = no cache)
+ * is a text file of earlier choices keyed by flags, precision and mesh size
+ * (quarter-octave buckets of the element count); a hit skips the timing, a
+ * miss appends a line.  chosen (NULL allowed) receives the options.
+ * Temporary device memory of one extra layout at a time is used.
+ */
+#define FEDFEM_TUNE_BATCH 1
+int fedfem_autotune(fedfem_handle *h, const char *cache_path, int32_t flags,
+                    fedfem_options *chosen);
+
+/*
  * Pre-computation (Algorithm 1, pre-computation block; Sec 2.3.5), on the
  * GPU in double precision: Jacobians, volumes, gradients and element
  * matrices (Eq 15-16), lumped nodal volumes (Sec 2.3.4), the critical step

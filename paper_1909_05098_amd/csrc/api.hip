@@ -613,7 +613,10 @@ int fedfem_precompute(fedfem_handle* h) {
     HIPCHK(h, launch_set_source(N, nullptr, nullptr, h->fp32c, d.q, s));
     // critical step (Eq 9): top eigenvalue of the geometry pencil on free
     // nodes, bounded over the property window
-    if (h->n_dir < N) {
+    if (h->timing_trial) {
+        h->lam_geo = h->lam_ritz = 0.0;
+        h->lz_iters = 0;
+    } else if (h->n_dir < N) {
         rc = lanczos(h, coef64);
         if (rc) return rc;
     } else {
@@ -631,7 +634,11 @@ int fedfem_precompute(fedfem_handle* h) {
         if ((rc = upload(h, &h->d_qpts, q))) return rc;
     }
     HIPCHK(h, hipStreamSynchronize(s));
-    if (h->dt_spec > 0) {
+    if (h->timing_trial) {
+        // kernels are timed only; any positive step keeps them well defined
+        h->dt = 1e-9;
+        h->dt_cr = INFINITY;
+    } else if (h->dt_spec > 0) {
         if (!(h->dt_spec < h->dt_cr)) {
             h->dt = 0.0;
             h->precomputed = true;
@@ -919,6 +926,98 @@ int fedfem_get_info(const fedfem_handle* h, fedfem_info* info) {
     info->device_bytes = h->dev_bytes;
     info->lambda_geometry = h->lam_geo;
     info->lanczos_iterations = h->lz_iters;
+    return FEDFEM_OK;
+}
+
+int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
+                    fedfem_options* chosen) {
+    if (!h || (flags & ~FEDFEM_TUNE_BATCH)) return FEDFEM_E_INVALID;
+    const bool batch = (flags & FEDFEM_TUNE_BATCH) != 0;
+    if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "autotune must run before precompute");
+    int rc = check_handle(h, false);
+    if (rc) return rc;
+    char key[128];
+    std::snprintf(key, sizeof(key), "f%d_prec%d_td%d_e%d", flags, h->mat.precision,
+                  h->mat.dk_dT != 0.0 ? 1 : 0,
+                  (int)std::lround(4.0 * std::log2((double)h->E)));
+    fedfem_options best{};
+    bool found = false;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char k[128];
+            fedfem_options o{};
+            while (std::fscanf(f, "%127s %d %d %d %d %d", k, &o.reorder, &o.tile_elems,
+                               &o.threads, &o.max_tile_nodes, &o.xcd) == 6)
+                if (std::strcmp(k, key) == 0) {
+                    best = o;
+                    found = true;
+                }
+            std::fclose(f);
+        }
+    }
+    if (!found) {
+        struct Build {
+            int reorder, te;
+        };
+        const Build all[] = {{1, 1024}, {1, 2048}, {1, 4096}, {0, 1024}};
+        const Build for_batch[] = {{1, 1024}, {1, 2048}};
+        const Build* builds = batch ? for_batch : all;
+        const int n_builds = batch ? 2 : 4;
+        double best_ms = 1e300;
+        fedfem_mesh mesh{h->N, h->xyz.data(), h->E, h->tets.data()};
+        fedfem_bc bc{h->T0, (int64_t)h->dir_nodes.size(), h->dir_nodes.data(), h->dir_T.data(),
+                     -0.5};
+        for (int bi = 0; bi < n_builds; bi++) {
+            const Build& bd = builds[bi];
+            if (bd.te > 64 && (int64_t)bd.te > 8 * h->E) continue;  // tiny meshes
+            fedfem_handle* t = nullptr;
+            if ((rc = fedfem_create(&mesh, &h->mat, &bc, &t))) return set_err(h, rc, "autotune");
+            t->timing_trial = true;
+            fedfem_options o{};
+            o.reorder = bd.reorder;
+            o.tile_elems = bd.te;
+            if ((rc = fedfem_set_options(t, &o)) || (rc = fedfem_precompute(t))) {
+                fedfem_destroy(t);
+                if (rc == FEDFEM_E_HIP) return hip_fail(h, hipErrorUnknown, "autotune trial");
+                continue;  // e.g. the tile does not fit: skip the candidate
+            }
+            const int te = t->d.tile_elems;
+            const int ths[2] = {std::max(64, std::min(1024, te / 4)),
+                                std::max(64, std::min(1024, te / 2))};
+            for (int ti = 0; ti < (batch ? 1 : 2); ti++)
+                for (int xcd = 0; xcd < (batch ? 1 : 2); xcd++) {
+                    t->d.threads = ths[ti];
+                    t->d.xcd = xcd;
+                    if (elems_per_thread(t->d) > 4) continue;
+                    double e1, n1;
+                    if ((rc = fedfem_time_kernels(t, 3, &e1, &n1)) ||
+                        (rc = fedfem_time_kernels(t, 10, &e1, &n1))) {
+                        fedfem_destroy(t);
+                        return set_err(h, rc, "autotune timing failed");
+                    }
+                    if (e1 + n1 < best_ms) {
+                        best_ms = e1 + n1;
+                        best = fedfem_options{};
+                        best.reorder = bd.reorder;
+                        best.tile_elems = te;
+                        best.threads = ths[ti];
+                        best.max_tile_nodes = t->opt.max_tile_nodes;
+                        best.xcd = xcd;
+                    }
+                }
+            fedfem_destroy(t);
+        }
+        if (best_ms == 1e300) return set_err(h, FEDFEM_E_INVALID, "no autotune candidate ran");
+        if (cache_path) {
+            if (FILE* f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "%s %d %d %d %d %d\n", key, best.reorder, best.tile_elems,
+                             best.threads, best.max_tile_nodes, best.xcd);
+                std::fclose(f);
+            }
+        }
+    }
+    if ((rc = fedfem_set_options(h, &best))) return rc;
+    if (chosen) *chosen = h->opt;
     return FEDFEM_OK;
 }
 

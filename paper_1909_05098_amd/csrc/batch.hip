@@ -176,7 +176,9 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     d.P = Pt;
     d.tile_elems = maxte;
     d.max_tile_nodes = maxn;
-    d.threads = std::min(1024, maxte);
+    // one workgroup size for every tile: four elements per thread for the
+    // largest tiles (layouts tuned with FEDFEM_TUNE_BATCH share it)
+    d.threads = std::max(64, std::min(1024, (maxte / 4 + 63) / 64 * 64));
     d.xcd = 0;
     if (elems_per_thread(d) > 4) {
         destroy_batch(b);

@@ -29,6 +29,7 @@ struct fedfem_handle {
     hipStream_t cap_stream = nullptr;
     hipStream_t stream = nullptr;
     bool precomputed = false;
+    bool timing_trial = false;  // autotuner trial: skip the critical-step estimate
     bool broken = false;
     std::string err;
     fedfem::Layout L;

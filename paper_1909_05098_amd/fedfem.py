@@ -18,6 +18,7 @@ FP64 = 0
 FP32C = 1
 SOURCE_NODAL = 0
 SOURCE_CONSISTENT = 1
+TUNE_BATCH = 1
 
 OK = 0
 E_INVALID = -1
@@ -94,6 +95,7 @@ _SIGS = {
     "fedfem_read_state": (C.c_int, [_P, _P, _P, _P]),
     "fedfem_write_state": (C.c_int, [_P, _P, C.c_double, C.c_int64]),
     "fedfem_get_info": (C.c_int, [_P, _P]),
+    "fedfem_autotune": (C.c_int, [_P, C.c_char_p, C.c_int32, _P]),
     "fedfem_time_kernels": (C.c_int, [_P, C.c_int64, _P, _P]),
     "fedfem_destroy": (C.c_int, [_P]),
     "fedfem_strerror": (C.c_char_p, [C.c_int]),
@@ -265,6 +267,14 @@ class Handle:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._check(self._L.fedfem_write_state(self._h, _ptr(buf), float(t),
                                                int(steps)), "fedfem_write_state")
+
+    def autotune(self, cache_path=None, for_batch=False):
+        """Let the library time candidate layouts and keep the fastest."""
+        o = Options()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self._L.fedfem_autotune(self._h, path, TUNE_BATCH if for_batch else 0,
+                                            C.byref(o)), "fedfem_autotune")
+        return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}
 
     def info(self):
         inf = Info()
