@@ -10,6 +10,14 @@ pinned by central finite differences in the tests.
 
 Tensors are channels-last: [B, G, G, G, C] (z, y, x, channel), float64.
 Weights of a 3x3x3 convolution are [Cout, 3, 3, 3, Cin] (dz, dy, dx, ci).
+
+`forward` and `backward` take an optional storage rounding q (default: none,
+i.e. FP64 throughout).  When given, q is applied wherever a tensor is
+stored between operations -- every activation after a convolution, pooled
+tensor, gradient leaving the head, a convolution's input gradient, and the
+upsampling / pooling backward sums -- so the reference can mirror kernels
+that keep such tensors in a narrower format while computing in wider
+precision.
 """
 from __future__ import annotations
 
@@ -94,19 +102,24 @@ def init_params(rng, scale=1.0):
     return P
 
 
-def forward(P, x):
+def _ident(a):
+    return a
+
+
+def forward(P, x, q=None):
     """Returns the output [B, G, G, G] and the cache for backward."""
-    c = {}
+    q = q or _ident
+    c = {"q": q}
 
     def cv(name, inp):
         pre = conv3(inp, P[name + ".w"], P[name + ".b"])
         c[name + ".in"] = inp
-        c[name + ".out"] = relu(pre)
+        c[name + ".out"] = q(relu(pre))
         return c[name + ".out"]
 
     e1 = cv("e1b", cv("e1a", x))
-    e2 = cv("e2b", cv("e2a", pool2(e1)))
-    e3 = cv("e3b", cv("e3a", pool2(e2)))
+    e2 = cv("e2b", cv("e2a", q(pool2(e1))))
+    e3 = cv("e3b", cv("e3a", q(pool2(e2))))
     cat2 = np.concatenate([up2(e3), e2], axis=-1)
     d2 = cv("d2b", cv("d2a", cat2))
     cat1 = np.concatenate([up2(d2), e1], axis=-1)
@@ -118,37 +131,38 @@ def forward(P, x):
 
 def backward(P, c, dy):
     """Gradients of every parameter and of the network input."""
+    q = c.get("q", _ident)
     g = {}
     d1 = c["d1"]
     g["head.w"] = np.einsum("bzyxc,bzyx->c", d1, dy)
     g["head.b"] = np.array([dy.sum()])
-    dd1 = dy[..., None] * P["head.w"]
+    dd1 = q(dy[..., None] * P["head.w"])
 
     def cvb(name, dout):
         dpre = dout * (c[name + ".out"] > 0)
         dx, dW, db = conv3_backward(c[name + ".in"], P[name + ".w"], dpre)
         g[name + ".w"] = dW
         g[name + ".b"] = db
-        return dx
+        return q(dx)
 
     dcat1 = cvb("d1a", cvb("d1b", dd1))
     C1 = P["d1a.w"].shape[-1] - 32
-    dd2 = up2_backward(dcat1[..., :C1])
+    dd2 = q(up2_backward(dcat1[..., :C1]))
     de1 = dcat1[..., C1:]
     dcat2 = cvb("d2a", cvb("d2b", dd2))
     C2 = P["d2a.w"].shape[-1] - 64
-    de3 = up2_backward(dcat2[..., :C2])
+    de3 = q(up2_backward(dcat2[..., :C2]))
     de2 = dcat2[..., C2:]
     dp2 = cvb("e3a", cvb("e3b", de3))
-    de2 = de2 + pool2_backward(dp2)
+    de2 = q(de2 + pool2_backward(dp2))
     dp1 = cvb("e2a", cvb("e2b", de2))
-    de1 = de1 + pool2_backward(dp1)
+    de1 = q(de1 + pool2_backward(dp1))
     dx = cvb("e1a", cvb("e1b", de1))
     return g, dx
 
 
-def loss_and_grads(P, x, t, m):
-    y, c = forward(P, x)
+def loss_and_grads(P, x, t, m, q=None):
+    y, c = forward(P, x, q)
     L, dy = masked_mse(y, t, m)
     g, dx = backward(P, c, dy)
     return L, g, dx, y

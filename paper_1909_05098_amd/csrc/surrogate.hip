@@ -1,0 +1,1207 @@
+// Learned surrogate for gfx950: a 3-level 3-D convolutional encoder-decoder
+// trained and run by hand-written kernels.  Convolutions are implicit GEMMs
+// on the matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
+// accumulation):
+//   forward   M = voxels, N = output channels, K = 27 * input channels
+//             (offset-major, channel-minor), each lane loading 8 consecutive
+//             input channels of one voxel (16 bytes, channels-last);
+//   data grad the same kernel with the weights flipped in space and
+//             transposed in channels (a 3x3x3 correlation of the gradient);
+//   weight grad M = output channels, N = 27 * input channels, K = voxels:
+//             64-voxel chunks of the gradient and of the gathered input are
+//             staged transposed in LDS so that each lane reads 8 consecutive
+//             voxels of one channel, partial sums per voxel split are reduced
+//             in a fixed order (bit-reproducible).
+// The remaining kernels are memory-bound elementwise passes: ReLU backward,
+// pooling, upsampling, the 1x1x1 head, the masked loss, Adam, weight
+// packing, input rasterisation and the resampling of FED-FEM fields.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fedfem.h"
+#include "../../include/fedfem_surrogate.h"
+#include "handle.h"
+#include "internal.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; j++) v[j] = (bf16)0.0f;
+    return v;
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------------------
+// Convolution forward / data gradient
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+    const bf16* in;
+    int ip, io, cin;  // input pitch, channel offset, channels (multiple of 8)
+    const bf16* w;    // [cout][kp], k = offset * cin + ci, zero beyond 27 cin
+    int kp;
+    const float* bias;  // may be null
+    bf16* out;
+    int op, oo, cout;   // output pitch, channel offset, channels
+    int G, ks, relu;    // grid edge, kernel size (1 or 3), ReLU on output
+    int64_t V;          // voxels (batch * G^3)
+};
+
+// Each wave computes 64 voxels x (16 NT) channels; a workgroup of 4 waves
+// covers 256 voxels; blockIdx.y selects a block of 64 output channels.
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t vb = ((int64_t)blockIdx.x * 4 + wave) * 64;
+    const int n0 = blockIdx.y * 64;
+    const int G = a.G;
+    const int64_t G3 = (int64_t)G * G * G;
+    int64_t vbat[4];
+    int vz[4], vy[4], vx[4];
+    bool ok[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+        const int64_t v = vb + mt * 16 + (lane & 15);
+        ok[mt] = v < a.V;
+        const int64_t vv = ok[mt] ? v : 0;
+        vbat[mt] = vv / G3;
+        const int64_t r = vv - vbat[mt] * G3;
+        vz[mt] = (int)(r / ((int64_t)G * G));
+        vy[mt] = (int)((r / G) % G);
+        vx[mt] = (int)(r % G);
+    }
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kg = (lane >> 4) * 8;
+    const int K = (a.ks == 3 ? 27 : 1) * a.cin;
+    for (int kc = 0; kc < a.kp; kc += 32) {
+        const int k = kc + kg;
+        bf16x8 A[4];
+        if (k < K) {
+            const int off = k / a.cin;
+            const int ci = k - off * a.cin;
+            int dz = 0, dy = 0, dx = 0;
+            if (a.ks == 3) {
+                dz = off / 9 - 1;
+                dy = (off / 3) % 3 - 1;
+                dx = off % 3 - 1;
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++) {
+                const int z2 = vz[mt] + dz, y2 = vy[mt] + dy, x2 = vx[mt] + dx;
+                const bool in = ok[mt] && z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 &&
+                                x2 < G;
+                if (in) {
+                    const int64_t nv = ((vbat[mt] * G + z2) * G + y2) * G + x2;
+                    A[mt] = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + ci);
+                } else {
+                    A[mt] = zero8();
+                }
+            }
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++) A[mt] = zero8();
+        }
+        bf16x8 B[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int co = n0 + nt * 16 + (lane & 15);
+            B[nt] = co < a.cout ? *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k)
+                                : zero8();
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++)
+                acc[mt][nt] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+    }
+    // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int co = n0 + nt * 16 + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int64_t v = vb + mt * 16 + (lane >> 4) * 4 + i;
+                if (v >= a.V) continue;
+                float val = acc[mt][nt][i] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                a.out[v * a.op + a.oo + co] = (bf16)val;
+            }
+        }
+}
+
+hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(a.V, 256), (unsigned)((a.cout + 63) / 64));
+    if (a.cout <= 16)
+        hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, a);
+    else if (a.cout <= 32)
+        hipLaunchKernelGGL(k_conv_fwd<2>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient (and bias gradient from the k-block 0 workgroups)
+// ---------------------------------------------------------------------------
+struct WgradArgs {
+    const bf16* d;  // gradient of the pre-activation output
+    int dp, doff, cout;
+    const bf16* in;  // convolution input
+    int ip, io, cin;
+    int G, ks;
+    int64_t V, vsplit;
+    int kp2;       // k extent of the partial buffer (multiple of 64)
+    float* part;   // [splits][cout][kp2]
+    float* partb;  // [splits][cout]
+};
+
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
+    __shared__ __align__(16) bf16 sD[64][72];
+    __shared__ __align__(16) bf16 sX[64][72];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int k0 = blockIdx.x * 64, co0 = blockIdx.y * 64;
+    const int64_t vs = (int64_t)blockIdx.z * a.vsplit;
+    const int64_t ve = min(a.V, vs + a.vsplit);
+    const int G = a.G;
+    const int64_t G3 = (int64_t)G * G * G;
+    const int K = (a.ks == 3 ? 27 : 1) * a.cin;
+    const int g8 = (t & 7) * 8;
+    // the gathered input's k group is fixed per thread
+    const int kk = k0 + g8;
+    int dz = 0, dy = 0, dx = 0, ci = 0;
+    const bool kvalid = kk < K;
+    if (kvalid) {
+        const int off = kk / a.cin;
+        ci = kk - off * a.cin;
+        if (a.ks == 3) {
+            dz = off / 9 - 1;
+            dy = (off / 3) % 3 - 1;
+            dx = off % 3 - 1;
+        }
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    for (int64_t vc = vs; vc < ve; vc += 64) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int vl = (t >> 3) + h * 32;
+            const int64_t v = vc + vl;
+            bf16x8 dv = zero8();
+            if (v < ve && co0 + g8 < a.cout)
+                dv = *reinterpret_cast<const bf16x8*>(a.d + v * a.dp + a.doff + co0 + g8);
+#pragma unroll
+            for (int j = 0; j < 8; j++) sD[g8 + j][vl] = dv[j];
+            bf16x8 xv = zero8();
+            if (v < ve && kvalid) {
+                const int64_t b = v / G3;
+                const int64_t r = v - b * G3;
+                const int z2 = (int)(r / ((int64_t)G * G)) + dz;
+                const int y2 = (int)((r / G) % G) + dy;
+                const int x2 = (int)(r % G) + dx;
+                if (z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 && x2 < G) {
+                    const int64_t nv = ((b * G + z2) * G + y2) * G + x2;
+                    xv = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + ci);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; j++) sX[g8 + j][vl] = xv[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < 2; s2++) {
+            const int vg = s2 * 32 + (lane >> 4) * 8;
+            const bf16x8 Af = *reinterpret_cast<const bf16x8*>(&sD[wave * 16 + (lane & 15)][vg]);
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) {
+                const bf16x8 Bf = *reinterpret_cast<const bf16x8*>(&sX[nt * 16 + (lane & 15)][vg]);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[nt], 0, 0, 0);
+            }
+        }
+        if (blockIdx.x == 0 && t < 64)
+            for (int vl = 0; vl < 64; vl++) bsum += (float)sD[t][vl];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int co = co0 + wave * 16 + (lane >> 4) * 4 + i;
+            const int k = k0 + nt * 16 + (lane & 15);
+            if (co < a.cout)
+                a.part[((int64_t)blockIdx.z * a.cout + co) * a.kp2 + k] = acc[nt][i];
+        }
+    if (blockIdx.x == 0 && t < 64 && co0 + t < a.cout)
+        a.partb[(int64_t)blockIdx.z * a.cout + co0 + t] = bsum;
+}
+
+// dW[co][k] (k < K) and db[co]: fixed-order sums over the voxel splits.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ partb,
+                               int splits, int cout, int kp2, int K, float* __restrict__ dW,
+                               float* __restrict__ db) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nW = (int64_t)cout * K;
+    if (i < nW) {
+        const int co = (int)(i / K), k = (int)(i % K);
+        float s = 0.0f;
+        for (int z = 0; z < splits; z++) s += part[((int64_t)z * cout + co) * kp2 + k];
+        dW[i] = s;
+    } else if (i < nW + cout) {
+        const int co = (int)(i - nW);
+        float s = 0.0f;
+        for (int z = 0; z < splits; z++) s += partb[(int64_t)z * cout + co];
+        db[co] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise passes (8 channels per thread)
+// ---------------------------------------------------------------------------
+// out[v][c] (contiguous) = g[v][c] if y[v][c] > 0 else 0
+__global__ void k_relu_bwd(const bf16* __restrict__ g, int gp, int go, const bf16* __restrict__ y,
+                           int yp, int yo, int C, int64_t V, bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8 = C / 8;
+    if (i >= V * c8) return;
+    const int64_t v = i / c8;
+    const int c = (int)(i % c8) * 8;
+    const bf16x8 gv = *reinterpret_cast<const bf16x8*>(g + v * gp + go + c);
+    const bf16x8 yv = *reinterpret_cast<const bf16x8*>(y + v * yp + yo + c);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; j++) o[j] = ((float)yv[j] > 0.0f) ? gv[j] : (bf16)0.0f;
+    *reinterpret_cast<bf16x8*>(out + v * C + c) = o;
+}
+
+// out (contiguous, grid G/2) = mean of the 2x2x2 children of in (grid G)
+__global__ void k_pool_fwd(const bf16* __restrict__ in, int ip, int io, int C, int G, int B,
+                           bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int H = G / 2, c8 = C / 8;
+    const int64_t n = (int64_t)B * H * H * H * c8;
+    if (i >= n) return;
+    const int c = (int)(i % c8) * 8;
+    int64_t u = i / c8;
+    const int X = (int)(u % H), Y = (int)((u / H) % H), Z = (int)((u / ((int64_t)H * H)) % H);
+    const int64_t b = u / ((int64_t)H * H * H);
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int d = 0; d < 8; d++) {
+        const int64_t v = ((b * G + 2 * Z + (d >> 2)) * G + 2 * Y + ((d >> 1) & 1)) * G + 2 * X + (d & 1);
+        const bf16x8 x = *reinterpret_cast<const bf16x8*>(in + v * ip + io + c);
+#pragma unroll
+        for (int j = 0; j < 8; j++) s[j] += (float)x[j];
+    }
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; j++) o[j] = (bf16)(s[j] * 0.125f);
+    *reinterpret_cast<bf16x8*>(out + u * C + c) = o;
+}
+
+// out[v][c] (contiguous, grid G) = a[v][c] + gp[parent(v)][c] / 8
+__global__ void k_pool_bwd_add(const bf16* __restrict__ a, int ap, int ao,
+                               const bf16* __restrict__ gpar, int C, int G, int B,
+                               bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8 = C / 8, H = G / 2;
+    const int64_t n = (int64_t)B * G * G * G * c8;
+    if (i >= n) return;
+    const int c = (int)(i % c8) * 8;
+    const int64_t v = i / c8;
+    const int x = (int)(v % G), y = (int)((v / G) % G), z = (int)((v / ((int64_t)G * G)) % G);
+    const int64_t b = v / ((int64_t)G * G * G);
+    const int64_t u = ((b * H + z / 2) * H + y / 2) * H + x / 2;
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + v * ap + ao + c);
+    const bf16x8 gv = *reinterpret_cast<const bf16x8*>(gpar + u * C + c);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; j++) o[j] = (bf16)((float)av[j] + 0.125f * (float)gv[j]);
+    *reinterpret_cast<bf16x8*>(out + v * C + c) = o;
+}
+
+// out[v][oo + c] (grid G) = in[parent(v)][c] (contiguous, grid G/2)
+__global__ void k_up_fwd(const bf16* __restrict__ in, int C, int G, int B, bf16* __restrict__ out,
+                         int op, int oo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8 = C / 8, H = G / 2;
+    const int64_t n = (int64_t)B * G * G * G * c8;
+    if (i >= n) return;
+    const int c = (int)(i % c8) * 8;
+    const int64_t v = i / c8;
+    const int x = (int)(v % G), y = (int)((v / G) % G), z = (int)((v / ((int64_t)G * G)) % G);
+    const int64_t b = v / ((int64_t)G * G * G);
+    const int64_t u = ((b * H + z / 2) * H + y / 2) * H + x / 2;
+    *reinterpret_cast<bf16x8*>(out + v * op + oo + c) =
+        *reinterpret_cast<const bf16x8*>(in + u * C + c);
+}
+
+// out[u][c] (contiguous, grid G/2) = sum of g over the 2x2x2 children of u
+__global__ void k_up_bwd(const bf16* __restrict__ g, int gp, int go, int C, int G, int B,
+                         bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int H = G / 2, c8 = C / 8;
+    const int64_t n = (int64_t)B * H * H * H * c8;
+    if (i >= n) return;
+    const int c = (int)(i % c8) * 8;
+    const int64_t u = i / c8;
+    const int X = (int)(u % H), Y = (int)((u / H) % H), Z = (int)((u / ((int64_t)H * H)) % H);
+    const int64_t b = u / ((int64_t)H * H * H);
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int d = 0; d < 8; d++) {
+        const int64_t v = ((b * G + 2 * Z + (d >> 2)) * G + 2 * Y + ((d >> 1) & 1)) * G + 2 * X + (d & 1);
+        const bf16x8 x = *reinterpret_cast<const bf16x8*>(g + v * gp + go + c);
+#pragma unroll
+        for (int j = 0; j < 8; j++) s[j] += (float)x[j];
+    }
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; j++) o[j] = (bf16)s[j];
+    *reinterpret_cast<bf16x8*>(out + u * C + c) = o;
+}
+
+// y[v] = sum_c w[c] d[v][c] + b (32 channels)
+__global__ void k_head_fwd(const bf16* __restrict__ d, const float* __restrict__ w, int64_t V,
+                           float* __restrict__ y) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    float s = w[32];
+#pragma unroll
+    for (int c8 = 0; c8 < 4; c8++) {
+        const bf16x8 x = *reinterpret_cast<const bf16x8*>(d + v * 32 + c8 * 8);
+#pragma unroll
+        for (int j = 0; j < 8; j++) s += w[c8 * 8 + j] * (float)x[j];
+    }
+    y[v] = s;
+}
+
+// block sums in a fixed tree order
+__device__ float block_sum256(float v, float* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const float r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// g[v][c] = dy[v] w[c]; partials of dL/dw[c] = sum dy d[v][c] and dL/db
+__global__ void __launch_bounds__(256) k_head_bwd(const float* __restrict__ dy,
+                                                  const bf16* __restrict__ d,
+                                                  const float* __restrict__ w, int64_t V,
+                                                  bf16* __restrict__ g, float* __restrict__ part) {
+    __shared__ float sh[256];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float dv = 0.0f;
+    float x[32];
+    if (v < V) {
+        dv = dy[v];
+#pragma unroll
+        for (int c8 = 0; c8 < 4; c8++) {
+            const bf16x8 xv = *reinterpret_cast<const bf16x8*>(d + v * 32 + c8 * 8);
+            bf16x8 o;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                x[c8 * 8 + j] = (float)xv[j];
+                o[j] = (bf16)(dv * w[c8 * 8 + j]);
+            }
+            *reinterpret_cast<bf16x8*>(g + v * 32 + c8 * 8) = o;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 32; c++) x[c] = 0.0f;
+    }
+    for (int c = 0; c < 32; c++) {
+        const float s = block_sum256(dv * x[c], sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 33 + c] = s;
+    }
+    const float s = block_sum256(dv, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 33 + 32] = s;
+}
+
+// out[j] = sum_b part[b][j], j < width (fixed order)
+__global__ void k_colreduce(const float* __restrict__ part, int64_t nb, int width,
+                            float* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= width) return;
+    float s = 0.0f;
+    for (int64_t b = 0; b < nb; b++) s += part[b * width + j];
+    out[j] = s;
+}
+
+__global__ void __launch_bounds__(256) k_sum(const float* __restrict__ a, int64_t n,
+                                             float* __restrict__ part) {
+    __shared__ float sh[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float s = block_sum256(i < n ? a[i] : 0.0f, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// dy = 2 m (y - t) / msum; partial sums of m (y - t)^2
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                             const float* __restrict__ m, int64_t n,
+                                             const float* __restrict__ msum,
+                                             float* __restrict__ dy, float* __restrict__ part) {
+    __shared__ float sh[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (i < n) {
+        const float r = y[i] - t[i];
+        const float mr = m[i] * r;
+        dy[i] = 2.0f * mr / msum[0];
+        l = mr * r;
+    }
+    const float s = block_sum256(l, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Adam (Kingma & Ba) with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// W[co][k] = master[co][k] (k < 27 cin) and Wt[ci][k'] with k' = (26 - off) cout + co
+__global__ void k_pack(const float* __restrict__ master, int cin, int cout, int kp, int kpt,
+                       bf16* __restrict__ W, bf16* __restrict__ Wt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nW = (int64_t)cout * kp, nT = (int64_t)cin * kpt;
+    const int K = 27 * cin, Kt = 27 * cout;
+    if (i < nW) {
+        const int co = (int)(i / kp), k = (int)(i % kp);
+        W[i] = (bf16)(k < K ? master[(int64_t)co * K + k] : 0.0f);
+    } else if (Wt && i < nW + nT) {
+        const int64_t j = i - nW;
+        const int ci = (int)(j / kpt), kt = (int)(j % kpt);
+        float val = 0.0f;
+        if (kt < Kt) {
+            const int offp = kt / cout, co = kt % cout;
+            const int off = 26 - offp;
+            val = master[((int64_t)co * 27 + off) * cin + ci];
+        }
+        Wt[j] = (bf16)val;
+    }
+}
+
+__device__ inline uint64_t mix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ULL;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+    return x ^ (x >> 31);
+}
+
+// p[i] = std * N(0,1) by Box-Muller on two counter-based uniforms
+__global__ void k_init_normal(float* __restrict__ p, int64_t n, float stdv, uint64_t seed,
+                              uint64_t stream) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t a = mix64(seed ^ mix64(stream * 0x100000001b3ULL + 2 * (uint64_t)i));
+    const uint64_t b = mix64(seed ^ mix64(stream * 0x100000001b3ULL + 2 * (uint64_t)i + 1));
+    const double u1 = ((double)(a >> 11) + 1.0) / 9007199254740993.0;
+    const double u2 = (double)(b >> 11) / 9007199254740992.0;
+    p[i] = (float)(stdv * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_bf16_to_f32(const bf16* __restrict__ a, int ap, int ao, int C, int64_t V,
+                              float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * C) return;
+    const int64_t v = i / C;
+    const int c = (int)(i % C);
+    out[i] = (float)a[v * ap + ao + c];
+}
+
+// ---------------------------------------------------------------------------
+// Input rasterisation and FED-FEM resampling
+// ---------------------------------------------------------------------------
+__device__ inline double cell_avg_1d(double x0, double h, double c, double s) {
+    const double k = 1.0 / (s * 1.4142135623730951);
+    return (s * 1.2533141373155003 / h) * (erf((x0 + h - c) * k) - erf((x0 - c) * k));
+}
+
+__global__ void k_rasterize(int G, double fx, double fy, double fz, double h, int B,
+                            const double* __restrict__ prm, const uint8_t* __restrict__ mask,
+                            bf16* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t G3 = (int64_t)G * G * G;
+    if (i >= (int64_t)B * G3) return;
+    const int64_t b = i / G3;
+    const int64_t r = i - b * G3;
+    const int iz = (int)(r / ((int64_t)G * G)), iy = (int)((r / G) % G), ix = (int)(r % G);
+    const double* p = prm + 7 * b;
+    const double q = p[4] * cell_avg_1d(fx + ix * h, h, p[0], p[3]) *
+                     cell_avg_1d(fy + iy * h, h, p[1], p[3]) *
+                     cell_avg_1d(fz + iz * h, h, p[2], p[3]);
+    const float mk = mask ? (float)mask[i] : 1.0f;
+    bf16x8 o = zero8();
+    o[0] = (bf16)(float)(q * 1e-7);
+    o[1] = (bf16)(mk * (float)((p[5] - 0.525) / 0.075));
+    o[2] = (bf16)(mk * (float)((p[6] - 0.011) / 0.009));
+    o[3] = (bf16)mk;
+    *reinterpret_cast<bf16x8*>(x + i * 8) = o;
+}
+
+struct ResampleArgs {
+    int64_t E;
+    const double* xyz;
+    const int32_t* conn;
+    const void* T;
+    int fp32c;
+    int G;
+    double fx, fy, fz, h;
+    int32_t* owner;
+    float* out;
+    uint8_t* mask;
+};
+
+// barycentric coordinates of p in tet e (returns false if degenerate)
+__device__ bool bary(const ResampleArgs& a, int64_t e, const double* p, double lam[4]) {
+    double q[4][3];
+    for (int c = 0; c < 4; c++) {
+        const int64_t n = a.conn[4 * e + c];
+        for (int d = 0; d < 3; d++) q[c][d] = a.xyz[3 * n + d];
+    }
+    double e1[3], e2[3], e3[3], r[3];
+    for (int d = 0; d < 3; d++) {
+        e1[d] = q[1][d] - q[0][d];
+        e2[d] = q[2][d] - q[0][d];
+        e3[d] = q[3][d] - q[0][d];
+        r[d] = p[d] - q[0][d];
+    }
+    const double c23[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2],
+                           e2[0] * e3[1] - e2[1] * e3[0]};
+    const double c31[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2],
+                           e3[0] * e1[1] - e3[1] * e1[0]};
+    const double c12[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                           e1[0] * e2[1] - e1[1] * e2[0]};
+    const double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
+    if (det == 0.0) return false;
+    lam[1] = (r[0] * c23[0] + r[1] * c23[1] + r[2] * c23[2]) / det;
+    lam[2] = (r[0] * c31[0] + r[1] * c31[1] + r[2] * c31[2]) / det;
+    lam[3] = (r[0] * c12[0] + r[1] * c12[1] + r[2] * c12[2]) / det;
+    lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+    return true;
+}
+
+template <int PASS>
+__global__ void k_resample(ResampleArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.E) return;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int c = 0; c < 4; c++) {
+        const int64_t n = a.conn[4 * e + c];
+        for (int d = 0; d < 3; d++) {
+            lo[d] = fmin(lo[d], a.xyz[3 * n + d]);
+            hi[d] = fmax(hi[d], a.xyz[3 * n + d]);
+        }
+    }
+    const double f[3] = {a.fx, a.fy, a.fz};
+    int i0[3], i1[3];
+    for (int d = 0; d < 3; d++) {
+        i0[d] = max(0, (int)ceil((lo[d] - f[d]) / a.h - 0.5));
+        i1[d] = min(a.G - 1, (int)floor((hi[d] - f[d]) / a.h - 0.5));
+    }
+    for (int iz = i0[2]; iz <= i1[2]; iz++)
+        for (int iy = i0[1]; iy <= i1[1]; iy++)
+            for (int ix = i0[0]; ix <= i1[0]; ix++) {
+                const double p[3] = {f[0] + (ix + 0.5) * a.h, f[1] + (iy + 0.5) * a.h,
+                                     f[2] + (iz + 0.5) * a.h};
+                double lam[4];
+                if (!bary(a, e, p, lam)) continue;
+                if (lam[0] < -1e-10 || lam[1] < -1e-10 || lam[2] < -1e-10 || lam[3] < -1e-10)
+                    continue;
+                const int64_t v = ((int64_t)iz * a.G + iy) * a.G + ix;
+                if (PASS == 0) {
+                    atomicMin(&a.owner[v], (int32_t)e);
+                } else if (a.owner[v] == (int32_t)e) {
+                    double T = 0.0;
+                    for (int c = 0; c < 4; c++) {
+                        const int64_t n = a.conn[4 * e + c];
+                        double Tn;
+                        if (a.fp32c) {
+                            const float2 s = static_cast<const float2*>(a.T)[n];
+                            Tn = (double)s.x + (double)s.y;
+                        } else {
+                            Tn = static_cast<const double*>(a.T)[n];
+                        }
+                        T += lam[c] * Tn;
+                    }
+                    a.out[v] = (float)T;
+                    a.mask[v] = 1;
+                }
+            }
+}
+
+__global__ void k_resample_clear(int64_t n, int32_t* owner, float* out, uint8_t* mask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    owner[i] = INT32_MAX;
+    out[i] = 0.0f;
+    mask[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Network description
+// ---------------------------------------------------------------------------
+struct LayerDef {
+    int cin, cout, lvl;
+};
+const LayerDef kLayers[FEDSUR_LAYERS] = {{8, 32, 0},    {32, 32, 0},  {32, 64, 1},  {64, 64, 1},
+                                         {64, 128, 2},  {128, 128, 2}, {192, 64, 1}, {64, 64, 1},
+                                         {96, 32, 0},   {32, 32, 0}};
+enum { E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B };
+
+struct View {
+    bf16* p;
+    int pitch, off, c, lvl;
+};
+
+}  // namespace
+
+struct fedsur_net {
+    int G = 0, Bmax = 0, device = 0;
+    hipStream_t own = nullptr, stream = nullptr;
+    int64_t nparams = 0;
+    int64_t w_off[FEDSUR_LAYERS], b_off[FEDSUR_LAYERS], head_off = 0;
+    int kp[FEDSUR_LAYERS], kpt[FEDSUR_LAYERS], kp2[FEDSUR_LAYERS];
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // FP32 master etc.
+    bf16 *W[FEDSUR_LAYERS], *Wt[FEDSUR_LAYERS];
+    // activations
+    bf16 *e1a, *cat1, *p1, *e2a, *cat2, *p2, *e3a, *e3b, *d2a, *d2b, *d1a, *d1b;
+    float* y = nullptr;
+    // gradients
+    float *dy = nullptr, *red = nullptr, *part = nullptr, *partb = nullptr, *scal = nullptr;
+    int64_t part_cap = 0, partb_cap = 0, red_cap = 0;
+    bf16 *gA0, *gB0, *gcat1, *gA1, *gB1, *gcat2, *gA2, *gB2, *gp1, *gp2;
+    int64_t adam_t = 0;
+    std::vector<void*> allocs;
+    int B = 0;  // batch of the last forward
+};
+
+namespace {
+
+int64_t vox(const fedsur_net* n, int lvl, int B) {
+    const int64_t g = n->G >> lvl;
+    return (int64_t)B * g * g * g;
+}
+
+template <typename T>
+hipError_t nalloc(fedsur_net* n, T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(16, count * sizeof(T)));
+    if (e != hipSuccess) return e;
+    n->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return hipSuccess;
+}
+
+View out_view(fedsur_net* n, int L) {
+    switch (L) {
+        case E1A: return {n->e1a, 32, 0, 32, 0};
+        case E1B: return {n->cat1, 96, 64, 32, 0};
+        case E2A: return {n->e2a, 64, 0, 64, 1};
+        case E2B: return {n->cat2, 192, 128, 64, 1};
+        case E3A: return {n->e3a, 128, 0, 128, 2};
+        case E3B: return {n->e3b, 128, 0, 128, 2};
+        case D2A: return {n->d2a, 64, 0, 64, 1};
+        case D2B: return {n->d2b, 64, 0, 64, 1};
+        case D1A: return {n->d1a, 32, 0, 32, 0};
+        default: return {n->d1b, 32, 0, 32, 0};
+    }
+}
+
+View in_view(fedsur_net* n, int L, const bf16* x) {
+    switch (L) {
+        case E1A: return {const_cast<bf16*>(x), 8, 0, 8, 0};
+        case E1B: return {n->e1a, 32, 0, 32, 0};
+        case E2A: return {n->p1, 32, 0, 32, 1};
+        case E2B: return {n->e2a, 64, 0, 64, 1};
+        case E3A: return {n->p2, 64, 0, 64, 2};
+        case E3B: return {n->e3a, 128, 0, 128, 2};
+        case D2A: return {n->cat2, 192, 0, 192, 1};
+        case D2B: return {n->d2a, 64, 0, 64, 1};
+        case D1A: return {n->cat1, 96, 0, 96, 0};
+        default: return {n->d1a, 32, 0, 32, 0};
+    }
+}
+
+hipError_t run_conv(fedsur_net* n, int L, const bf16* x, int B) {
+    const View in = in_view(n, L, x), out = out_view(n, L);
+    ConvArgs a;
+    a.in = in.p;
+    a.ip = in.pitch;
+    a.io = in.off;
+    a.cin = kLayers[L].cin;
+    a.w = n->W[L];
+    a.kp = n->kp[L];
+    a.bias = n->p + n->b_off[L];
+    a.out = out.p;
+    a.op = out.pitch;
+    a.oo = out.off;
+    a.cout = kLayers[L].cout;
+    a.G = n->G >> kLayers[L].lvl;
+    a.ks = 3;
+    a.relu = 1;
+    a.V = vox(n, kLayers[L].lvl, B);
+    return conv_fwd(a, n->stream);
+}
+
+// pre-activation gradient of layer L into dpre (contiguous [V][cout]),
+// then weight/bias gradients, then (if dx) the input gradient into dx
+hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View& gout,
+                         bf16* dpre, const View* dx) {
+    const LayerDef& d = kLayers[L];
+    const View out = out_view(n, L), in = in_view(n, L, x);
+    const int64_t V = vox(n, d.lvl, B);
+    const int G = n->G >> d.lvl;
+    hipStream_t s = n->stream;
+    hipLaunchKernelGGL(k_relu_bwd, dim3(nblocks(V * (d.cout / 8), 256)), dim3(256), 0, s, gout.p,
+                       gout.pitch, gout.off, out.p, out.pitch, out.off, d.cout, V, dpre);
+    // weight gradient: split the voxels so that there are enough workgroups
+    const int kb = n->kp2[L] / 64, cb = (d.cout + 63) / 64;
+    int64_t vsplit = 64;
+    while ((V + vsplit - 1) / vsplit > 128) vsplit *= 2;
+    const int64_t splits = (V + vsplit - 1) / vsplit;
+    if (splits * d.cout * n->kp2[L] > n->part_cap || splits * d.cout > n->partb_cap)
+        return hipErrorInvalidValue;
+    WgradArgs w;
+    w.d = dpre;
+    w.dp = d.cout;
+    w.doff = 0;
+    w.cout = d.cout;
+    w.in = in.p;
+    w.ip = in.pitch;
+    w.io = in.off;
+    w.cin = d.cin;
+    w.G = G;
+    w.ks = 3;
+    w.V = V;
+    w.vsplit = vsplit;
+    w.kp2 = n->kp2[L];
+    w.part = n->part;
+    w.partb = n->partb;
+    hipLaunchKernelGGL(k_wgrad, dim3(kb, cb, (unsigned)splits), dim3(256), 0, s, w);
+    const int64_t nred = (int64_t)d.cout * 27 * d.cin + d.cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nred, 256)), dim3(256), 0, s, n->part,
+                       n->partb, (int)splits, d.cout, n->kp2[L], 27 * d.cin, n->g + n->w_off[L],
+                       n->g + n->b_off[L]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !dx) return e;
+    ConvArgs a;
+    a.in = dpre;
+    a.ip = d.cout;
+    a.io = 0;
+    a.cin = d.cout;
+    a.w = n->Wt[L];
+    a.kp = n->kpt[L];
+    a.bias = nullptr;
+    a.out = dx->p;
+    a.op = dx->pitch;
+    a.oo = dx->off;
+    a.cout = d.cin;
+    a.G = G;
+    a.ks = 3;
+    a.relu = 0;
+    a.V = V;
+    return conv_fwd(a, s);
+}
+
+hipError_t pack_all(fedsur_net* n) {
+    for (int L = 0; L < FEDSUR_LAYERS; L++) {
+        const LayerDef& d = kLayers[L];
+        const int64_t tot = (int64_t)d.cout * n->kp[L] + (int64_t)d.cin * n->kpt[L];
+        hipLaunchKernelGGL(k_pack, dim3(nblocks(tot, 256)), dim3(256), 0, n->stream,
+                           n->p + n->w_off[L], d.cin, d.cout, n->kp[L], n->kpt[L], n->W[L],
+                           n->Wt[L]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t reduce_to(fedsur_net* n, const float* a, int64_t len, float* out) {
+    // two fixed-order passes: block sums, then one block over the partials
+    const int64_t nb = (len + 255) / 256;
+    if (nb > n->red_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sum, dim3((unsigned)nb), dim3(256), 0, n->stream, a, len, n->red);
+    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(1), 0, n->stream, n->red, nb, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t forward_impl(fedsur_net* n, int B, const bf16* x, float* y) {
+    hipStream_t s = n->stream;
+    const int G = n->G;
+    hipError_t e;
+    if ((e = run_conv(n, E1A, x, B)) || (e = run_conv(n, E1B, x, B))) return e;
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 1, B) * 4, 256)), dim3(256), 0, s, n->cat1,
+                       96, 64, 32, G, B, n->p1);
+    if ((e = run_conv(n, E2A, x, B)) || (e = run_conv(n, E2B, x, B))) return e;
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 2, B) * 8, 256)), dim3(256), 0, s, n->cat2,
+                       192, 128, 64, G / 2, B, n->p2);
+    if ((e = run_conv(n, E3A, x, B)) || (e = run_conv(n, E3B, x, B))) return e;
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 1, B) * 16, 256)), dim3(256), 0, s, n->e3b,
+                       128, G / 2, B, n->cat2, 192, 0);
+    if ((e = run_conv(n, D2A, x, B)) || (e = run_conv(n, D2B, x, B))) return e;
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 0, B) * 8, 256)), dim3(256), 0, s, n->d2b,
+                       64, G, B, n->cat1, 96, 0);
+    if ((e = run_conv(n, D1A, x, B)) || (e = run_conv(n, D1B, x, B))) return e;
+    hipLaunchKernelGGL(k_head_fwd, dim3(nblocks(vox(n, 0, B), 256)), dim3(256), 0, s, n->d1b,
+                       n->p + n->head_off, vox(n, 0, B), y);
+    n->B = B;
+    return hipGetLastError();
+}
+
+hipError_t backward_impl(fedsur_net* n, int B, const bf16* x) {
+    hipStream_t s = n->stream;
+    const int G = n->G;
+    const int64_t V0 = vox(n, 0, B), V1 = vox(n, 1, B), V2 = vox(n, 2, B);
+    hipError_t e;
+    // head: dL/d(d1b) into gA0 [V0][32], head weight/bias partials
+    const int64_t nb = (V0 + 255) / 256;
+    if (nb * 33 > n->part_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)nb), dim3(256), 0, s, n->dy, n->d1b,
+                       n->p + n->head_off, V0, n->gA0, n->part);
+    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(64), 0, s, n->part, nb, 33, n->g + n->head_off);
+    // d1b, d1a (input: cat1 -> gcat1)
+    const View gA0{n->gA0, 32, 0, 32, 0}, gB0{n->gB0, 32, 0, 32, 0};
+    const View gc1{n->gcat1, 96, 0, 96, 0};
+    // pre-activation gradients go to gB0 / gA0 alternately (contiguous [V][32])
+    if ((e = conv_backward(n, D1B, x, B, gA0, n->gB0, &gA0))) return e;
+    if ((e = conv_backward(n, D1A, x, B, gA0, n->gB0, &gc1))) return e;
+    // upsample backward: channels [0, 64) of gcat1 -> g(d2b) in gA1 [V1][64]
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(V1 * 8, 256)), dim3(256), 0, s, n->gcat1, 96, 0, 64,
+                       G, B, n->gA1);
+    const View gA1{n->gA1, 64, 0, 64, 1};
+    const View gc2{n->gcat2, 192, 0, 192, 1};
+    if ((e = conv_backward(n, D2B, x, B, gA1, n->gB1, &gA1))) return e;
+    if ((e = conv_backward(n, D2A, x, B, gA1, n->gB1, &gc2))) return e;
+    // channels [0, 128) of gcat2 -> g(e3b) in gA2 [V2][128]
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(V2 * 16, 256)), dim3(256), 0, s, n->gcat2, 192, 0,
+                       128, G / 2, B, n->gA2);
+    const View gA2{n->gA2, 128, 0, 128, 2};
+    const View gp2{n->gp2, 64, 0, 64, 2};
+    if ((e = conv_backward(n, E3B, x, B, gA2, n->gB2, &gA2))) return e;
+    if ((e = conv_backward(n, E3A, x, B, gA2, n->gB2, &gp2))) return e;
+    // g(e2b) = gcat2[:, 128:192] + pool backward of g(p2), into gA1
+    hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V1 * 8, 256)), dim3(256), 0, s, n->gcat2, 192,
+                       128, n->gp2, 64, G / 2, B, n->gA1);
+    const View gp1{n->gp1, 32, 0, 32, 1};
+    if ((e = conv_backward(n, E2B, x, B, gA1, n->gB1, &gA1))) return e;
+    if ((e = conv_backward(n, E2A, x, B, gA1, n->gB1, &gp1))) return e;
+    // g(e1b) = gcat1[:, 64:96] + pool backward of g(p1), into gA0
+    hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V0 * 4, 256)), dim3(256), 0, s, n->gcat1, 96,
+                       64, n->gp1, 32, G, B, n->gA0);
+    if ((e = conv_backward(n, E1B, x, B, gA0, n->gB0, &gA0))) return e;
+    if ((e = conv_backward(n, E1A, x, B, gA0, n->gB0, nullptr))) return e;
+    (void)gB0;
+    return hipGetLastError();
+}
+
+void destroy_net(fedsur_net* n) {
+    if (!n) return;
+    (void)hipSetDevice(n->device);
+    if (n->own) (void)hipStreamSynchronize(n->own);
+    for (void* p : n->allocs) (void)hipFree(p);
+    if (n->own) (void)hipStreamDestroy(n->own);
+    delete n;
+}
+
+#define NCHK(expr)                                       \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return FEDFEM_E_HIP;       \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed, fedsur_net** out) {
+    if (!out || grid < 4 || grid % 4 || grid > 256 || batch_max < 1 || batch_max > 4096)
+        return FEDFEM_E_INVALID;
+    *out = nullptr;
+    fedsur_net* n = new (std::nothrow) fedsur_net();
+    if (!n) return FEDFEM_E_NOMEM;
+    n->G = grid;
+    n->Bmax = batch_max;
+    auto fail = [&](int code) {
+        destroy_net(n);
+        return code;
+    };
+    if (hipGetDevice(&n->device) != hipSuccess) return fail(FEDFEM_E_HIP);
+    if (hipStreamCreateWithFlags(&n->own, hipStreamNonBlocking) != hipSuccess)
+        return fail(FEDFEM_E_HIP);
+    n->stream = n->own;
+    int64_t off = 0;
+    int64_t max_part = 0;
+    for (int L = 0; L < FEDSUR_LAYERS; L++) {
+        const LayerDef& d = kLayers[L];
+        n->w_off[L] = off;
+        off += (int64_t)d.cout * 27 * d.cin;
+        n->b_off[L] = off;
+        off += d.cout;
+        n->kp[L] = round_up(27 * d.cin, 32);
+        n->kpt[L] = round_up(27 * d.cout, 32);
+        n->kp2[L] = round_up(27 * d.cin, 64);
+        max_part = std::max(max_part, (int64_t)d.cout * n->kp2[L]);
+    }
+    n->head_off = off;
+    off += 33;
+    n->nparams = off;
+    const int B = batch_max;
+    const int64_t V0 = vox(n, 0, B), V1 = vox(n, 1, B), V2 = vox(n, 2, B);
+    bool ok = nalloc(n, &n->p, off) == hipSuccess && nalloc(n, &n->g, off) == hipSuccess &&
+              nalloc(n, &n->m, off) == hipSuccess && nalloc(n, &n->v, off) == hipSuccess;
+    for (int L = 0; ok && L < FEDSUR_LAYERS; L++) {
+        const LayerDef& d = kLayers[L];
+        ok = nalloc(n, &n->W[L], (size_t)d.cout * n->kp[L]) == hipSuccess &&
+             nalloc(n, &n->Wt[L], (size_t)d.cin * n->kpt[L]) == hipSuccess;
+    }
+    ok = ok && nalloc(n, &n->e1a, V0 * 32) == hipSuccess &&
+         nalloc(n, &n->cat1, V0 * 96) == hipSuccess && nalloc(n, &n->p1, V1 * 32) == hipSuccess &&
+         nalloc(n, &n->e2a, V1 * 64) == hipSuccess && nalloc(n, &n->cat2, V1 * 192) == hipSuccess &&
+         nalloc(n, &n->p2, V2 * 64) == hipSuccess && nalloc(n, &n->e3a, V2 * 128) == hipSuccess &&
+         nalloc(n, &n->e3b, V2 * 128) == hipSuccess && nalloc(n, &n->d2a, V1 * 64) == hipSuccess &&
+         nalloc(n, &n->d2b, V1 * 64) == hipSuccess && nalloc(n, &n->d1a, V0 * 32) == hipSuccess &&
+         nalloc(n, &n->d1b, V0 * 32) == hipSuccess && nalloc(n, &n->y, V0) == hipSuccess &&
+         nalloc(n, &n->dy, V0) == hipSuccess && nalloc(n, &n->gA0, V0 * 32) == hipSuccess &&
+         nalloc(n, &n->gB0, V0 * 32) == hipSuccess && nalloc(n, &n->gcat1, V0 * 96) == hipSuccess &&
+         nalloc(n, &n->gA1, V1 * 64) == hipSuccess && nalloc(n, &n->gB1, V1 * 64) == hipSuccess &&
+         nalloc(n, &n->gcat2, V1 * 192) == hipSuccess && nalloc(n, &n->gA2, V2 * 128) == hipSuccess &&
+         nalloc(n, &n->gB2, V2 * 128) == hipSuccess && nalloc(n, &n->gp1, V1 * 32) == hipSuccess &&
+         nalloc(n, &n->gp2, V2 * 64) == hipSuccess && nalloc(n, &n->scal, 8) == hipSuccess;
+    // split-K partials: at most 128 voxel splits per layer; head partials too
+    n->part_cap = std::max<int64_t>(128 * max_part, ((V0 + 255) / 256) * 33);
+    n->partb_cap = 128 * 128;
+    n->red_cap = (V0 + 255) / 256 + 1;
+    ok = ok && nalloc(n, &n->part, n->part_cap) == hipSuccess &&
+         nalloc(n, &n->partb, n->partb_cap) == hipSuccess &&
+         nalloc(n, &n->red, n->red_cap) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return fail(FEDFEM_E_NOMEM);
+    }
+    // He initialisation, zero biases and moments
+    hipStream_t s = n->stream;
+    for (int L = 0; L < FEDSUR_LAYERS; L++) {
+        const LayerDef& d = kLayers[L];
+        const int64_t cnt = (int64_t)d.cout * 27 * d.cin;
+        hipLaunchKernelGGL(k_init_normal, dim3(nblocks(cnt, 256)), dim3(256), 0, s,
+                           n->p + n->w_off[L], cnt, (float)std::sqrt(2.0 / (27.0 * d.cin)), seed,
+                           (uint64_t)L);
+        hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(128), 0, s, n->p + n->b_off[L],
+                           (int64_t)d.cout, 0.0f);
+    }
+    hipLaunchKernelGGL(k_init_normal, dim3(1), dim3(64), 0, s, n->p + n->head_off, (int64_t)32,
+                       (float)std::sqrt(1.0 / 32.0), seed, (uint64_t)FEDSUR_LAYERS);
+    hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(1), 0, s, n->p + n->head_off + 32, (int64_t)1,
+                       0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(off, 256)), dim3(256), 0, s, n->m, off, 0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(off, 256)), dim3(256), 0, s, n->v, off, 0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(off, 256)), dim3(256), 0, s, n->g, off, 0.0f);
+    if (pack_all(n) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail(FEDFEM_E_HIP);
+    *out = n;
+    return FEDFEM_OK;
+}
+
+int fedsur_destroy(fedsur_net* n) {
+    destroy_net(n);
+    return FEDFEM_OK;
+}
+
+int fedsur_set_stream(fedsur_net* n, void* stream) {
+    if (!n) return FEDFEM_E_INVALID;
+    n->stream = stream ? static_cast<hipStream_t>(stream) : n->own;
+    return FEDFEM_OK;
+}
+
+int fedsur_param_count(const fedsur_net* n, int64_t* count) {
+    if (!n || !count) return FEDFEM_E_INVALID;
+    *count = n->nparams;
+    return FEDFEM_OK;
+}
+
+int fedsur_get_params(fedsur_net* n, float* host) {
+    if (!n || !host) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(n->device));
+    NCHK(hipMemcpyAsync(host, n->p, n->nparams * 4, hipMemcpyDeviceToHost, n->stream));
+    NCHK(hipStreamSynchronize(n->stream));
+    return FEDFEM_OK;
+}
+
+int fedsur_get_grads(fedsur_net* n, float* host) {
+    if (!n || !host) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(n->device));
+    NCHK(hipMemcpyAsync(host, n->g, n->nparams * 4, hipMemcpyDeviceToHost, n->stream));
+    NCHK(hipStreamSynchronize(n->stream));
+    return FEDFEM_OK;
+}
+
+int fedsur_set_params(fedsur_net* n, const float* host) {
+    if (!n || !host) return FEDFEM_E_INVALID;
+    for (int64_t i = 0; i < n->nparams; i++)
+        if (!std::isfinite(host[i])) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(n->device));
+    hipStream_t s = n->stream;
+    NCHK(hipMemcpyAsync(n->p, host, n->nparams * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(n->nparams, 256)), dim3(256), 0, s, n->m,
+                       n->nparams, 0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(n->nparams, 256)), dim3(256), 0, s, n->v,
+                       n->nparams, 0.0f);
+    n->adam_t = 0;
+    NCHK(pack_all(n));
+    NCHK(hipStreamSynchronize(s));
+    return FEDFEM_OK;
+}
+
+int fedsur_forward(fedsur_net* n, int32_t batch, const void* x, float* y) {
+    if (!n || !x || !y || batch < 1 || batch > n->Bmax) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(n->device));
+    NCHK(forward_impl(n, batch, static_cast<const bf16*>(x), y));
+    NCHK(hipStreamSynchronize(n->stream));
+    return FEDFEM_OK;
+}
+
+int fedsur_loss_backward(fedsur_net* n, int32_t batch, const void* x, const float* target,
+                         const float* mask, float* loss) {
+    if (!n || !x || !target || !mask || batch < 1 || batch > n->Bmax) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(n->device));
+    hipStream_t s = n->stream;
+    const bf16* xb = static_cast<const bf16*>(x);
+    NCHK(forward_impl(n, batch, xb, n->y));
+    const int64_t V0 = vox(n, 0, batch);
+    NCHK(reduce_to(n, mask, V0, n->scal));  // sum of the mask
+    const int64_t nb = (V0 + 255) / 256;
+    hipLaunchKernelGGL(k_mse, dim3((unsigned)nb), dim3(256), 0, s, n->y, target, mask, V0, n->scal,
+                       n->dy, n->red);
+    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(1), 0, s, n->red, nb, 1, n->scal + 1);
+    NCHK(hipGetLastError());
+    NCHK(backward_impl(n, batch, xb));
+    float h[2] = {0, 0};
+    NCHK(hipMemcpyAsync(h, n->scal, 8, hipMemcpyDeviceToHost, s));
+    NCHK(hipStreamSynchronize(s));
+    if (loss) *loss = h[0] > 0 ? h[1] / h[0] : 0.0f;
+    return FEDFEM_OK;
+}
+
+int fedsur_adam_step(fedsur_net* n, float lr) {
+    if (!n || !(lr > 0)) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(n->device));
+    n->adam_t++;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)n->adam_t));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)n->adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(n->nparams, 256)), dim3(256), 0, n->stream, n->p, n->g,
+                       n->m, n->v, n->nparams, lr, c1, c2);
+    NCHK(hipGetLastError());
+    NCHK(pack_all(n));
+    NCHK(hipStreamSynchronize(n->stream));
+    return FEDFEM_OK;
+}
+
+int fedsur_read_activation(fedsur_net* n, int32_t layer, float* host) {
+    if (!n || !host || layer < 0 || layer >= FEDSUR_LAYERS || n->B < 1) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(n->device));
+    const View o = out_view(n, layer);
+    const int64_t V = vox(n, o.lvl, n->B);
+    float* tmp = nullptr;
+    NCHK(hipMalloc(&tmp, V * o.c * 4));
+    hipLaunchKernelGGL(k_bf16_to_f32, dim3(nblocks(V * o.c, 256)), dim3(256), 0, n->stream, o.p,
+                       o.pitch, o.off, o.c, V, tmp);
+    hipError_t e = hipMemcpyAsync(host, tmp, V * o.c * 4, hipMemcpyDeviceToHost, n->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    (void)hipFree(tmp);
+    return e == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
+}
+
+int fedsur_rasterize(int32_t grid, const double* frame, int32_t batch, const double* params,
+                     const uint8_t* mask, void* x, void* stream) {
+    if (grid < 1 || !frame || batch < 1 || !params || !x) return FEDFEM_E_INVALID;
+    if (!(frame[3] > 0)) return FEDFEM_E_INVALID;
+    for (int b = 0; b < batch; b++)
+        if (!(params[7 * b + 3] > 0)) return FEDFEM_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* dp = nullptr;
+    NCHK(hipMalloc(&dp, sizeof(double) * 7 * batch));
+    hipError_t e = hipMemcpyAsync(dp, params, sizeof(double) * 7 * batch, hipMemcpyHostToDevice, s);
+    const int64_t n = (int64_t)batch * grid * grid * grid;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_rasterize, dim3(nblocks(n, 256)), dim3(256), 0, s, grid, frame[0],
+                           frame[1], frame[2], frame[3], batch, dp, mask, static_cast<bf16*>(x));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dp);
+    return e == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
+}
+
+int fedfem_resample(fedfem_handle* h, int32_t grid, const double* frame, float* T_out,
+                    uint8_t* mask_out) {
+    if (!h || grid < 1 || grid > 1024 || !frame || !T_out || !mask_out) return FEDFEM_E_INVALID;
+    if (!h->precomputed) return FEDFEM_E_NOT_PRECOMPUTED;
+    if (h->broken) return FEDFEM_E_HIP;
+    if (!(frame[3] > 0)) return FEDFEM_E_INVALID;
+    NCHK(hipSetDevice(h->device));
+    hipStream_t s = h->stream;
+    const int64_t nv = (int64_t)grid * grid * grid;
+    int32_t* owner = nullptr;
+    NCHK(hipMalloc(&owner, nv * sizeof(int32_t)));
+    hipLaunchKernelGGL(k_resample_clear, dim3(nblocks(nv, 256)), dim3(256), 0, s, nv, owner, T_out,
+                       mask_out);
+    ResampleArgs a;
+    a.E = h->E;
+    a.xyz = h->d_xyz;
+    a.conn = h->d_conn;
+    a.T = h->d.T_[h->cur];
+    a.fp32c = h->fp32c ? 1 : 0;
+    a.G = grid;
+    a.fx = frame[0];
+    a.fy = frame[1];
+    a.fz = frame[2];
+    a.h = frame[3];
+    a.owner = owner;
+    a.out = T_out;
+    a.mask = mask_out;
+    hipLaunchKernelGGL(k_resample<0>, dim3(nblocks(h->E, 128)), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(k_resample<1>, dim3(nblocks(h->E, 128)), dim3(128), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(owner);
+    return e == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
+}
+
+}  // extern "C"

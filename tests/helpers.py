@@ -19,4 +19,4 @@ def header_functions(path):
     import re
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fedfem_[A-Za-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:fedfem|fedsur)_[A-Za-z_0-9]+)\s*\(", text)))

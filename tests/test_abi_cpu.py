@@ -14,19 +14,25 @@ from helpers import header_functions
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "fedfem.h")
+HEADER_SUR = os.path.join(ROOT, "include", "fedfem_surrogate.h")
+
+
+def declared():
+    return sorted(set(header_functions(HEADER)) | set(header_functions(HEADER_SUR)))
 
 
 def test_header_declares_binding_surface():
-    assert header_functions(HEADER) == ff.exported_symbols()
+    from paper_1909_05098_amd import surrogate as sg
+    assert declared() == sorted(set(ff.exported_symbols()) | set(sg.exported_symbols()))
 
 
 def test_library_exports_every_declared_symbol():
     L = ff.load()
-    for name in header_functions(HEADER):
+    for name in declared():
         assert hasattr(L, name), name
     out = os.popen(f"nm -D --defined-only {ff.LIB_PATH}").read()
-    exported = set(re.findall(r"\bT (fedfem_[A-Za-z_0-9]+)", out))
-    assert exported == set(header_functions(HEADER))
+    exported = set(re.findall(r"\bT ((?:fedfem|fedsur)_[A-Za-z_0-9]+)", out))
+    assert exported == set(declared())
 
 
 def test_strerror_and_null_handling():

@@ -1,0 +1,276 @@
+"""GPU parity of the surrogate's BF16-MFMA kernels with the FP64 NumPy
+reference (oracle/surrogate_ref.py), plus the rasteriser and the resampler.
+
+The reference is given the same BF16-rounded weights and inputs the GPU
+uses, so the comparison measures the kernels' own arithmetic: FP32
+accumulation with BF16 storage of every activation and gradient.
+Tolerances: one convolution layer fed the GPU's own input, 2^-7 relative
+(two BF16 roundings); the whole forward pass and the loss, relative 1e-2.
+Gradients are checked twice, with the reference rounding to BF16 wherever
+the kernels store BF16 (oracle/surrogate_ref.py, storage rounding q):
+  * backward alone -- the reference's backward pass run on the GPU's own
+    forward activations and output -- every parameter gradient within
+    relative L2 1e-3 (it differs only where an FP32 sum, accumulated in
+    another order, rounds to a neighbouring BF16 value);
+  * end to end, within 1e-1: forward roundings flip a few ReLU masks, and
+    the flips reach every gradient below them, growing with depth to a few
+    per cent for this random-weight network and random target.
+"""
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import surrogate_ref as S
+from paper_1909_05098_amd import fedfem as ff
+from paper_1909_05098_amd import surrogate as sg
+from synth import scenarios as sc
+
+from helpers import jittered_box
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+GRAD_TOL_E2E = 1e-1
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+def bf16(a, torch):
+    return torch.tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(
+        torch.float64).numpy()
+
+
+def quantised(P, torch):
+    """Weights as the kernels see them: conv weights BF16, the rest FP32."""
+    Q = {}
+    for k, v in P.items():
+        if k.endswith(".w") and not k.startswith("head"):
+            Q[k] = bf16(v, torch)
+        else:
+            Q[k] = np.asarray(v, dtype=np.float32).astype(np.float64)
+    return Q
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+def setup(torch, G, B, seed):
+    rng = np.random.default_rng(seed)
+    P = S.init_params(rng)
+    net = sg.Net(G, B, seed=1)
+    net.set_params(sg.flatten(P).astype(np.float32))
+    Q = quantised(sg.unflatten(net.get_params().astype(np.float64)), torch)
+    x = bf16(rng.normal(size=(B, G, G, G, S.IN_CHANNELS)), torch)
+    X = torch.tensor(x, dtype=torch.bfloat16, device="cuda")
+    return rng, net, Q, x, X
+
+
+def test_forward_layers_and_network(torch_cuda):
+    torch = torch_cuda
+    G, B = 8, 2
+    rng, net, Q, x, X = setup(torch, G, B, 0)
+    Y = torch.empty((B, G, G, G), dtype=torch.float32, device="cuda")
+    net.forward(X, Y)
+    acts = [net.activation(L, B).astype(np.float64) for L in range(10)]
+    # each layer from the GPU's own input (pooling / upsampling / concatenation
+    # of BF16 values are exact, so the inputs below are what the kernel read)
+    ins = {0: x, 1: acts[0], 2: S.pool2(acts[1]), 3: acts[2], 4: S.pool2(acts[3]),
+           5: acts[4], 6: np.concatenate([S.up2(acts[5]), acts[3]], -1), 7: acts[6],
+           8: np.concatenate([S.up2(acts[7]), acts[1]], -1), 9: acts[8]}
+    for L, (name, ci, co) in enumerate(S.LAYERS):
+        inp = bf16(ins[L], torch)
+        ref = S.relu(S.conv3(inp, Q[name + ".w"], Q[name + ".b"]))
+        err = np.abs(acts[L] - ref)
+        tol = 2.0 ** -7 * np.abs(ref) + 1e-6 * np.abs(ref).max()
+        print(f"[surrogate] layer {name}: max rel {float((err / (np.abs(ref) + 1e-12)).max()):.2e}",
+              flush=True)
+        assert np.all(err <= tol), name
+    y_ref = S.forward(Q, x)[0]
+    e = rel_l2(Y.cpu().numpy(), y_ref)
+    print(f"[surrogate] forward rel L2 {e:.3e}", flush=True)
+    assert e <= 1e-2
+
+
+def gpu_cache(net, x, B, q):
+    """Backward cache of the reference built from the GPU's own activations
+    (upsampling and concatenation of BF16 values are exact; the pooled mean
+    is stored as BF16 by the kernels)."""
+    a = [net.activation(L, B).astype(np.float64) for L in range(10)]
+    ins = [x, a[0], q(S.pool2(a[1])), a[2], q(S.pool2(a[3])), a[4],
+           np.concatenate([S.up2(a[5]), a[3]], -1), a[6],
+           np.concatenate([S.up2(a[7]), a[1]], -1), a[8]]
+    c = {"q": q, "d1": a[9]}
+    for L, (name, _, _) in enumerate(S.LAYERS):
+        c[name + ".in"] = ins[L]
+        c[name + ".out"] = a[L]
+    return c
+
+
+def test_loss_and_gradients(torch_cuda):
+    torch = torch_cuda
+    G, B = 8, 2
+    rng, net, Q, x, X = setup(torch, G, B, 5)
+    t = rng.normal(size=(B, G, G, G)).astype(np.float32)
+    m = (rng.random((B, G, G, G)) < 0.7).astype(np.float32)
+    T = torch.tensor(t, device="cuda")
+    M = torch.tensor(m, device="cuda")
+    loss = net.loss_backward(X, T, M)
+    g = sg.unflatten(net.get_grads().astype(np.float64))
+    Y = torch.empty((B, G, G, G), dtype=torch.float32, device="cuda")
+    net.forward(X, Y)
+    y = Y.cpu().numpy().astype(np.float64)
+    t64, m64 = t.astype(np.float64), m.astype(np.float64)
+    q = lambda a: bf16(a, torch)  # noqa: E731
+    # (1) backward alone: the reference's backward from the GPU's forward
+    L_gpu_fwd, dy = S.masked_mse(y, t64, m64)
+    g_bwd, _ = S.backward(Q, gpu_cache(net, x, B, q), dy)
+    # (2) end to end, the reference storing BF16 where the kernels do
+    L_ref, g_ref, _, _ = S.loss_and_grads(Q, x, t64, m64, q=q)
+    print(f"[surrogate] loss gpu {loss:.6f} from gpu fwd {L_gpu_fwd:.6f} ref {L_ref:.6f}",
+          flush=True)
+    assert abs(loss - L_gpu_fwd) <= 1e-5 * abs(L_gpu_fwd)
+    assert abs(loss - L_ref) <= 1e-2 * abs(L_ref)
+    e_bwd = {k: rel_l2(g[k], g_bwd[k]) for k in g_bwd}
+    e_e2e = {k: rel_l2(g[k], g_ref[k]) for k in g_ref}
+    for k in g_ref:
+        print(f"[surrogate] grad {k}: backward-only {e_bwd[k]:.3e} end-to-end {e_e2e[k]:.3e}",
+              flush=True)
+    print(f"[surrogate] worst: backward-only {max(e_bwd.values()):.3e} "
+          f"end-to-end {max(e_e2e.values()):.3e}", flush=True)
+    assert max(e_bwd.values()) <= GRAD_TOL
+    assert max(e_e2e.values()) <= GRAD_TOL_E2E
+    # bit-reproducible backward
+    net.loss_backward(X, T, M)
+    assert np.array_equal(net.get_grads(), sg.flatten(g).astype(np.float32))
+
+
+def test_adam_matches_reference(torch_cuda):
+    """Two Adam steps on the GPU's own gradients against the reference update."""
+    torch = torch_cuda
+    G, B = 8, 1
+    rng, net, Q, x, X = setup(torch, G, B, 21)
+    t = torch.tensor(rng.normal(size=(B, G, G, G)).astype(np.float32), device="cuda")
+    M = torch.ones((B, G, G, G), dtype=torch.float32, device="cuda")
+    p = net.get_params().astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step, lr in ((1, 1e-3), (2, 3e-3)):
+        net.loss_backward(X, t, M)
+        g = net.get_grads().astype(np.float64)
+        net.adam_step(lr)
+        p, m, v = S.adam_step(p, g, m, v, step, lr)
+        got = net.get_params().astype(np.float64)
+        err = np.abs(got - p).max()
+        print(f"[surrogate] adam step {step}: max |dp| {err:.2e}", flush=True)
+        assert err <= 1e-6 * np.abs(p).max() + 1e-3 * lr
+        p = got
+
+
+def test_training_reduces_loss(torch_cuda):
+    """Fitting a smooth field of Gaussian-source inputs (the surrogate's own
+    kind of map) must cut the loss well down within 150 Adam steps."""
+    torch = torch_cuda
+    G, B = 16, 4
+    net = sg.Net(G, B, seed=3)
+    rng = np.random.default_rng(9)
+    frame = np.array([-0.02, -0.02, -0.02, 0.0025])
+    prm = np.column_stack([rng.uniform(-0.008, 0.008, (B, 3)), rng.uniform(0.002, 0.004, B),
+                           rng.uniform(1e7, 3e7, B), rng.uniform(0.45, 0.6, B),
+                           rng.uniform(0.002, 0.02, B)])
+    mask = torch.ones((B, G, G, G), dtype=torch.uint8, device="cuda")
+    X = torch.empty((B, G, G, G, 8), dtype=torch.bfloat16, device="cuda")
+    sg.rasterize(G, frame, prm, mask, X)
+    x = X.float().cpu().numpy().astype(np.float64)
+    # target: the source raster blurred twice by a 3x3x3 box, scaled by k0
+    box = np.ones((1, 3, 3, 3, 1)) / 27.0
+    f = x[..., 0:1]
+    for _ in range(2):
+        f = S.conv3(f, box, np.zeros(1))
+    t = f[..., 0] * (1.0 + 0.5 * x[..., 1])
+    t = t / np.abs(t).max()
+    T = torch.tensor(t.astype(np.float32), device="cuda")
+    M = torch.ones((B, G, G, G), dtype=torch.float32, device="cuda")
+    losses = []
+    for _ in range(150):
+        losses.append(net.loss_backward(X, T, M))
+        net.adam_step(1e-3)
+    print(f"[surrogate] training loss {losses[0]:.4f} -> {min(losses):.4f} (last "
+          f"{losses[-1]:.4f})", flush=True)
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_rasterize_matches_formula(torch_cuda):
+    torch = torch_cuda
+    G = 16
+    frame = np.array([-0.02, -0.02, -0.02, 0.0025])
+    prm = np.array([[0.001, -0.003, 0.002, 0.003, 2e7, 0.5, 0.008],
+                    [-0.005, 0.004, 0.0, 0.002, 3e7, 0.58, 0.019]])
+    mask = torch.ones((2, G, G, G), dtype=torch.uint8, device="cuda")
+    mask[1, :4] = 0
+    X = torch.empty((2, G, G, G, 8), dtype=torch.bfloat16, device="cuda")
+    sg.rasterize(G, frame, prm, mask, X)
+    got = X.float().cpu().numpy()
+    edges = frame[0] + np.arange(G + 1) * frame[3]
+    for b in range(2):
+        cx, cy, cz, s, q0, k0, wb = prm[b]
+        f = [np.diff(special.erf((edges - c) / (s * np.sqrt(2)))) * s * np.sqrt(np.pi / 2) / frame[3]
+             for c in (cx, cy, cz)]
+        ref = q0 * f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :] * 1e-7
+        assert np.allclose(got[b, ..., 0], bf16(ref, torch), rtol=1e-2, atol=1e-6)
+        mk = mask[b].cpu().numpy()
+        assert np.allclose(got[b, ..., 1], bf16(mk * (k0 - 0.525) / 0.075, torch), atol=1e-2)
+        assert np.allclose(got[b, ..., 2], bf16(mk * (wb - 0.011) / 0.009, torch), atol=1e-2)
+        assert np.array_equal(got[b, ..., 3], mk.astype(np.float32))
+        assert np.all(got[b, ..., 4:] == 0)
+    # total power of a resolved source is the analytic integral
+    tot = got[0, ..., 0].astype(np.float64).sum() * frame[3] ** 3 / 1e-7
+    assert abs(tot / (2e7 * (2 * np.pi) ** 1.5 * 0.003 ** 3) - 1) < 1e-2
+
+
+def test_resample_linear_field_and_mask(torch_cuda):
+    torch = torch_cuda
+    xyz, tets, bnd = jittered_box(10, 9, 8, 1e-3, seed=17)
+    mat = sc.td_materials()
+    h = ff.Handle(xyz, tets, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=-0.9,
+                  precision=ff.FP32C)
+    h.precompute()
+    gvec = np.array([800.0, -500.0, 300.0])
+    lin = 40.0 + xyz @ gvec
+    hi = lin.astype(np.float32)
+    lo = (lin - hi.astype(np.float64)).astype(np.float32)
+    h.write_state(np.concatenate([hi, lo]).view(np.uint8), 0.0, 0)
+    G = 16
+    frame = np.array([-0.0015, -0.0013, -0.0012, 0.0008])
+    Tv = torch.empty(G ** 3, dtype=torch.float32, device="cuda")
+    Mv = torch.empty(G ** 3, dtype=torch.uint8, device="cuda")
+    sg.resample(h, G, frame, Tv, Mv)
+    T = Tv.cpu().numpy()
+    m = Mv.cpu().numpy().astype(bool)
+    idx = np.arange(G)
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    P = np.stack([frame[0] + (xx.ravel() + 0.5) * frame[3],
+                  frame[1] + (yy.ravel() + 0.5) * frame[3],
+                  frame[2] + (zz.ravel() + 0.5) * frame[3]], axis=1)
+    # brute-force containment with the same tolerance
+    X = xyz[tets]
+    inside = np.zeros(len(P), bool)
+    for e0 in range(0, len(tets), 2000):
+        Xe = X[e0:e0 + 2000]
+        Jm = np.transpose(Xe[:, 1:] - Xe[:, :1], (0, 2, 1))
+        Ji = np.linalg.inv(Jm)
+        lam = np.einsum("eij,pej->pei", Ji, P[:, None, :] - Xe[None, :, 0, :])
+        lam0 = 1 - lam.sum(-1)
+        ok = (lam >= -1e-10).all(-1) & (lam0 >= -1e-10)
+        inside |= ok.any(1)
+    assert np.array_equal(m, inside)
+    assert m.sum() > 100 and (~m).sum() > 100
+    ref = 40.0 + P @ gvec
+    assert np.max(np.abs(T[m] - ref[m])) <= 2e-5 * np.abs(ref[m]).max()
+    assert np.all(T[~m] == 0)
