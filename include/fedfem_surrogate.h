@@ -57,9 +57,10 @@ int fedsur_get_grads(fedsur_net *n, float *host);
 int fedsur_forward(fedsur_net *n, int32_t batch, const void *x, float *y);
 
 /*
- * Forward pass, masked mean-squared error L = sum m (y - t)^2 / sum m over
- * the batch, and the backward pass into the gradient vector.  target and
- * mask are FP32 [B][G^3] device arrays; loss (host, may be NULL) receives L.
+ * Forward pass, weighted mean-squared error L = sum m (y - t)^2 / sum m over
+ * the batch (m: a 0/1 mask or non-negative weights), and the backward pass
+ * into the gradient vector.  target and mask are FP32 [B][G^3] device
+ * arrays; loss (host, may be NULL) receives L.
  */
 int fedsur_loss_backward(fedsur_net *n, int32_t batch, const void *x,
                          const float *target, const float *mask, float *loss);
@@ -71,17 +72,86 @@ int fedsur_adam_step(fedsur_net *n, float lr);
 int fedsur_read_activation(fedsur_net *n, int32_t layer, float *host);
 
 /*
- * Network input on a G^3 grid of cubic voxels: frame = (x0, y0, z0, h), the
- * lower corner and voxel edge [m].  params per sample: (cx, cy, cz, sigma,
- * Q0, k0, omega_b).  Channel 0 is the voxel average of
- * Q0 exp(-|x - c|^2 / (2 sigma^2)) (a product of error-function differences)
- * times 1e-7, channel 1 (k0 - 0.525) / 0.075, channel 2
- * (omega_b - 0.011) / 0.009, channel 3 the occupancy mask (uint8 device
- * array [B][G^3]); channels 1-3 are zero outside the mask, 4-7 are zero.
- * x is BF16 [B][G^3][8] on the device.
+ * One surrogate sample: the source, the material parameters and the domain
+ * of one scenario (SI units).  The domain is the ellipsoid with semi-axes
+ * (ax, ay, az) centred on the voxel frame; hmesh is the spacing of the
+ * FED-FEM mesh whose results the network learns.
+ */
+typedef struct fedsur_sample {
+    double cx, cy, cz; /* source centre [m] */
+    double sigma;      /* source width [m] (> 0) */
+    double q0;         /* source peak power density [W/m^3] */
+    double k0;         /* conductivity at the reference temperature [W/(m K)] (> 0) */
+    double omega_b;    /* perfusion rate [1/s] */
+    double ax, ay, az; /* ellipsoid semi-axes [m] */
+    double hmesh;      /* FED-FEM mesh spacing [m] */
+    double reserved;   /* unused, keeps the record at 96 bytes */
+} fedsur_sample;
+
+/* Constants shared by a batch: density, specific heat at the reference
+ * temperature, blood density times blood specific heat, heating time. */
+typedef struct fedsur_phys {
+    double rho0, c0, rhob_cb, t_heat;
+} fedsur_phys;
+
+/*
+ * Network input, prior and scale for `batch` samples on a G^3 grid of cubic
+ * voxels; frame = (x0, y0, z0, h) is the grid's lower corner and voxel edge
+ * [m] (host array).  samples: device array [batch]; phys: host.
+ *
+ * The prior is the closed-form temperature rise of the sample's Gaussian
+ * source Q0 exp(-|x - c|^2 / (2 sigma^2)), switched on at t = 0 and held
+ * for t_heat, in an infinite medium of constant properties (k0, rho0 c0)
+ * with perfusion omega_b rho_b c_b, i.e. the Pennes equation (Eq. 1)
+ * without boundaries or temperature dependence.  It is evaluated at every
+ * voxel centre in FP64 (an 8-point Gauss-Legendre rule on 8 geometric
+ * pieces of [0, t_heat]) and stored as FP32 in prior [batch][G^3] (device,
+ * may be NULL when not needed); scale [batch] (device) receives its value
+ * at the source centre, P.  The network learns (dT - prior) / P.
+ *
+ * x (BF16 device [batch][G^3][8]) channels: 0 the voxel average of the
+ * source shape exp(-|x - c|^2 / (2 sigma^2)), 1 (k0 - 0.525) / 0.075,
+ * 2 (omega_b - 0.011) / 0.009, 3 the ellipsoid mask (voxel centre inside),
+ * 4 prior / P, 5 prior / 100 K, 6 hmesh / 2 mm - 1, 7 sigma / 4 mm - 1;
+ * channels 1-3 and 5-7 are zero outside the mask.
+ *
+ * Asynchronous on `stream` (NULL: the default stream).  Sample values live
+ * in device memory and are not checked: sigma <= 0 or k0 <= 0 give
+ * non-finite outputs, never an out-of-range access.
  */
 int fedsur_rasterize(int32_t grid, const double *frame, int32_t batch,
-                     const double *params, const uint8_t *mask, void *x,
+                     const fedsur_sample *samples, const fedsur_phys *phys,
+                     void *x, float *prior, float *scale, void *stream);
+
+/*
+ * Training target from FED-FEM temperatures resampled onto the grid
+ * (fedfem_resample): target = (T - T_a - prior) / P where mask is set and 0
+ * elsewhere, and the loss weight 1 + focus max(prior / P, 0) where mask is
+ * set and 0 elsewhere (focus >= 0; 0 gives the plain mask), which leans
+ * the masked mean-squared error (fedsur_loss_backward) towards the heated
+ * region where the largest errors lie.  All arrays [batch][G^3] on the
+ * device; asynchronous on `stream`.
+ */
+int fedsur_target(int32_t grid, int32_t batch, const float *prior,
+                  const float *scale, const float *T, const uint8_t *mask,
+                  float T_a, float focus, float *target, float *weight,
+                  void *stream);
+
+/*
+ * Predicted temperature from the network's output y (fedsur_forward), in
+ * place: y <- T_a + prior + P y (device arrays [batch][G^3]; asynchronous).
+ */
+int fedsur_decode(int32_t grid, int32_t batch, const float *prior,
+                  const float *scale, float T_a, float *y, void *stream);
+
+/*
+ * err[b] (device, FP32) = max over voxels with mask set of |Tp[b] - T[b]|:
+ * a predicted temperature field against FED-FEM's (fedfem_resample) for
+ * each sample, 0 for a sample with an empty mask, NaN if any compared value
+ * is NaN.  Asynchronous on `stream`; batch <= 65535.
+ */
+int fedsur_max_error(int32_t grid, int32_t batch, const float *Tp,
+                     const float *T, const uint8_t *mask, float *err,
                      void *stream);
 
 /*

@@ -443,14 +443,16 @@ __global__ void __launch_bounds__(256) k_head_bwd(const float* __restrict__ dy,
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 33 + 32] = s;
 }
 
-// out[j] = sum_b part[b][j], j < width (fixed order)
-__global__ void k_colreduce(const float* __restrict__ part, int64_t nb, int width,
-                            float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= width) return;
+// out[j] = sum_b part[b][j]: one workgroup per column j, each thread summing
+// the rows t, t + 256, ... and the workgroup tree-summing those (fixed order)
+__global__ void __launch_bounds__(256) k_colreduce(const float* __restrict__ part, int64_t nb,
+                                                   int width, float* __restrict__ out) {
+    __shared__ float sh[256];
+    const int j = blockIdx.x;
     float s = 0.0f;
-    for (int64_t b = 0; b < nb; b++) s += part[b * width + j];
-    out[j] = s;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) s += part[b * width + j];
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) out[j] = s;
 }
 
 __global__ void __launch_bounds__(256) k_sum(const float* __restrict__ a, int64_t n,
@@ -550,31 +552,147 @@ __global__ void k_bf16_to_f32(const bf16* __restrict__ a, int ap, int ao, int C,
 // ---------------------------------------------------------------------------
 // Input rasterisation and FED-FEM resampling
 // ---------------------------------------------------------------------------
+// one sample of the network input (layout of fedsur_sample)
+struct RasterSample {
+    double cx, cy, cz, sigma, q0, k0, omega_b, ax, ay, az, hmesh, reserved;
+};
+struct RasterPhys {
+    double rho0, c0, rhob_cb, t_heat;
+};
+static_assert(sizeof(RasterSample) == sizeof(fedsur_sample), "sample layout");
+
 __device__ inline double cell_avg_1d(double x0, double h, double c, double s) {
     const double k = 1.0 / (s * 1.4142135623730951);
     return (s * 1.2533141373155003 / h) * (erf((x0 + h - c) * k) - erf((x0 - c) * k));
 }
 
+// Gauss-Legendre rule of order 8 on [-1, 1] (Abramowitz & Stegun, Table 25.4)
+__constant__ double kGLx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267,
+                               0.9602898564975363};
+__constant__ double kGLw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745,
+                               0.1012285362903763};
+
+// Temperature rise at squared distance r2 from the centre of a Gaussian
+// source switched on at t = 0 in an infinite medium of constant properties
+// with perfusion: the heat released at time t - tau has spread to variance
+// sigma^2 + 2 alpha tau and decayed by exp(-m tau), so
+//   dT = Q0 / (rho c) int_0^t exp(-m tau) (s0 / s)^(3/2) exp(-r2 / (2 s)) dtau,
+//   s = s0 + 2 alpha tau, s0 = sigma^2, alpha = k0 / (rho c),
+//   m = omega_b rho_b c_b / (rho c).
+// The integral is taken over the geometric pieces [0, t/128], [t/128, t/64],
+// ..., [t/2, t] with 8 Gauss-Legendre points each (FP64).
+__device__ double prior_rise(double r2, const RasterSample& p, const RasterPhys& ph) {
+    const double rc = ph.rho0 * ph.c0;
+    const double alpha = p.k0 / rc, m = p.omega_b * ph.rhob_cb / rc, s0 = p.sigma * p.sigma;
+    double sum = 0.0, lo = 0.0, hi = ph.t_heat / 128.0;
+    for (int seg = 0; seg < 8; seg++) {
+        const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+        for (int j = 0; j < 8; j++) {
+            const double tau = mid + (j < 4 ? -half * kGLx[j] : half * kGLx[j - 4]);
+            const double sv = s0 + 2.0 * alpha * tau;
+            const double g = s0 / sv;
+            sum += half * kGLw[j & 3] * exp(-m * tau - 0.5 * r2 / sv) * g * sqrt(g);
+        }
+        lo = hi;
+        hi *= 2.0;
+    }
+    return p.q0 / rc * sum;
+}
+
+__global__ void k_prior_scale(int B, const RasterSample* __restrict__ smp, RasterPhys ph,
+                              float* __restrict__ scale) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) scale[b] = (float)prior_rise(0.0, smp[b], ph);
+}
+
 __global__ void k_rasterize(int G, double fx, double fy, double fz, double h, int B,
-                            const double* __restrict__ prm, const uint8_t* __restrict__ mask,
-                            bf16* __restrict__ x) {
+                            const RasterSample* __restrict__ smp, RasterPhys ph,
+                            const float* __restrict__ scale, bf16* __restrict__ x,
+                            float* __restrict__ prior) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t G3 = (int64_t)G * G * G;
     if (i >= (int64_t)B * G3) return;
     const int64_t b = i / G3;
     const int64_t r = i - b * G3;
     const int iz = (int)(r / ((int64_t)G * G)), iy = (int)((r / G) % G), ix = (int)(r % G);
-    const double* p = prm + 7 * b;
-    const double q = p[4] * cell_avg_1d(fx + ix * h, h, p[0], p[3]) *
-                     cell_avg_1d(fy + iy * h, h, p[1], p[3]) *
-                     cell_avg_1d(fz + iz * h, h, p[2], p[3]);
-    const float mk = mask ? (float)mask[i] : 1.0f;
-    bf16x8 o = zero8();
-    o[0] = (bf16)(float)(q * 1e-7);
-    o[1] = (bf16)(mk * (float)((p[5] - 0.525) / 0.075));
-    o[2] = (bf16)(mk * (float)((p[6] - 0.011) / 0.009));
+    const RasterSample p = smp[b];
+    // voxel average of the source shape exp(-|x - c|^2 / (2 sigma^2))
+    const double q = cell_avg_1d(fx + ix * h, h, p.cx, p.sigma) *
+                     cell_avg_1d(fy + iy * h, h, p.cy, p.sigma) *
+                     cell_avg_1d(fz + iz * h, h, p.cz, p.sigma);
+    // voxel centre, relative to the source and to the frame centre
+    const double half = 0.5 * G * h;
+    const double vx = fx + (ix + 0.5) * h, vy = fy + (iy + 0.5) * h, vz = fz + (iz + 0.5) * h;
+    const double ex = (vx - fx - half) / p.ax, ey = (vy - fy - half) / p.ay,
+                 ez = (vz - fz - half) / p.az;
+    const float mk = (ex * ex + ey * ey + ez * ez <= 1.0) ? 1.0f : 0.0f;
+    const double r2 = (vx - p.cx) * (vx - p.cx) + (vy - p.cy) * (vy - p.cy) + (vz - p.cz) * (vz - p.cz);
+    const double pr = prior_rise(r2, p, ph);
+    const float P = scale[b];
+    bf16x8 o;
+    o[0] = (bf16)(float)q;
+    o[1] = (bf16)(mk * (float)((p.k0 - 0.525) / 0.075));
+    o[2] = (bf16)(mk * (float)((p.omega_b - 0.011) / 0.009));
     o[3] = (bf16)mk;
+    o[4] = (bf16)(float)(pr / P);
+    o[5] = (bf16)(mk * (float)(pr * 0.01));
+    o[6] = (bf16)(mk * (float)(p.hmesh / 2e-3 - 1.0));
+    o[7] = (bf16)(mk * (float)(p.sigma / 4e-3 - 1.0));
     *reinterpret_cast<bf16x8*>(x + i * 8) = o;
+    if (prior) prior[i] = (float)pr;
+}
+
+// target = (T - Ta - prior) / P inside the mesh (0 outside); loss weight
+// 1 + focus prior / P inside the mesh, 0 outside
+__global__ void k_target(int64_t G3, int B, const float* __restrict__ prior,
+                         const float* __restrict__ scale, const float* __restrict__ T,
+                         const uint8_t* __restrict__ mask, float Ta, float focus,
+                         float* __restrict__ target, float* __restrict__ weight) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * G3) return;
+    const float P = scale[i / G3];
+    const bool in = mask[i] != 0;
+    target[i] = in ? (T[i] - Ta - prior[i]) / P : 0.0f;
+    weight[i] = in ? 1.0f + focus * fmaxf(prior[i] / P, 0.0f) : 0.0f;
+}
+
+// y <- Ta + prior + P y (the predicted temperature)
+__global__ void k_decode(int64_t G3, int B, const float* __restrict__ prior,
+                         const float* __restrict__ scale, float Ta, float* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * G3) return;
+    y[i] = Ta + (prior[i] + scale[i / G3] * y[i]);
+}
+
+// err[b] = max over the mesh's voxels of |Tp - T|; non-negative floats
+// order like their bit patterns, so the maximum is an integer atomic max
+// (NaN, whose pattern exceeds every finite one, propagates)
+__global__ void __launch_bounds__(256) k_max_err(int64_t G3, int B, const float* __restrict__ Tp,
+                                                 const float* __restrict__ T,
+                                                 const uint8_t* __restrict__ mask,
+                                                 unsigned* __restrict__ err) {
+    __shared__ unsigned sh[256];
+    const int b = blockIdx.y;
+    unsigned m = 0u;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < G3; v += (int64_t)gridDim.x * 256) {
+        const int64_t i = (int64_t)b * G3 + v;
+        if (mask[i]) {
+            const float d = fabsf(Tp[i] - T[i]);
+            m = max(m, __float_as_uint(d));
+        }
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(err + b, sh[0]);
+}
+
+__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 struct ResampleArgs {
@@ -858,7 +976,7 @@ hipError_t reduce_to(fedsur_net* n, const float* a, int64_t len, float* out) {
     const int64_t nb = (len + 255) / 256;
     if (nb > n->red_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sum, dim3((unsigned)nb), dim3(256), 0, n->stream, a, len, n->red);
-    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(1), 0, n->stream, n->red, nb, 1, out);
+    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(256), 0, n->stream, n->red, nb, 1, out);
     return hipGetLastError();
 }
 
@@ -895,7 +1013,7 @@ hipError_t backward_impl(fedsur_net* n, int B, const bf16* x) {
     if (nb * 33 > n->part_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)nb), dim3(256), 0, s, n->dy, n->d1b,
                        n->p + n->head_off, V0, n->gA0, n->part);
-    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(64), 0, s, n->part, nb, 33, n->g + n->head_off);
+    hipLaunchKernelGGL(k_colreduce, dim3(33), dim3(256), 0, s, n->part, nb, 33, n->g + n->head_off);
     // d1b, d1a (input: cat1 -> gcat1)
     const View gA0{n->gA0, 32, 0, 32, 0}, gB0{n->gB0, 32, 0, 32, 0};
     const View gc1{n->gcat1, 96, 0, 96, 0};
@@ -1109,7 +1227,7 @@ int fedsur_loss_backward(fedsur_net* n, int32_t batch, const void* x, const floa
     const int64_t nb = (V0 + 255) / 256;
     hipLaunchKernelGGL(k_mse, dim3((unsigned)nb), dim3(256), 0, s, n->y, target, mask, V0, n->scal,
                        n->dy, n->red);
-    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(1), 0, s, n->red, nb, 1, n->scal + 1);
+    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(256), 0, s, n->red, nb, 1, n->scal + 1);
     NCHK(hipGetLastError());
     NCHK(backward_impl(n, batch, xb));
     float h[2] = {0, 0};
@@ -1148,25 +1266,60 @@ int fedsur_read_activation(fedsur_net* n, int32_t layer, float* host) {
     return e == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
 }
 
-int fedsur_rasterize(int32_t grid, const double* frame, int32_t batch, const double* params,
-                     const uint8_t* mask, void* x, void* stream) {
-    if (grid < 1 || !frame || batch < 1 || !params || !x) return FEDFEM_E_INVALID;
-    if (!(frame[3] > 0)) return FEDFEM_E_INVALID;
-    for (int b = 0; b < batch; b++)
-        if (!(params[7 * b + 3] > 0)) return FEDFEM_E_INVALID;
+int fedsur_rasterize(int32_t grid, const double* frame, int32_t batch,
+                     const fedsur_sample* samples, const fedsur_phys* phys, void* x, float* prior,
+                     float* scale, void* stream) {
+    if (grid < 1 || grid > 1024 || !frame || batch < 1 || !samples || !phys || !x || !scale)
+        return FEDFEM_E_INVALID;
+    if (!(frame[3] > 0) || !(phys->rho0 > 0) || !(phys->c0 > 0) || !(phys->rhob_cb >= 0) ||
+        !(phys->t_heat > 0))
+        return FEDFEM_E_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double* dp = nullptr;
-    NCHK(hipMalloc(&dp, sizeof(double) * 7 * batch));
-    hipError_t e = hipMemcpyAsync(dp, params, sizeof(double) * 7 * batch, hipMemcpyHostToDevice, s);
+    RasterPhys ph{phys->rho0, phys->c0, phys->rhob_cb, phys->t_heat};
+    const RasterSample* smp = reinterpret_cast<const RasterSample*>(samples);
+    hipLaunchKernelGGL(k_prior_scale, dim3(nblocks(batch, 64)), dim3(64), 0, s, batch, smp, ph,
+                       scale);
     const int64_t n = (int64_t)batch * grid * grid * grid;
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_rasterize, dim3(nblocks(n, 256)), dim3(256), 0, s, grid, frame[0],
-                           frame[1], frame[2], frame[3], batch, dp, mask, static_cast<bf16*>(x));
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(dp);
-    return e == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
+    hipLaunchKernelGGL(k_rasterize, dim3(nblocks(n, 256)), dim3(256), 0, s, grid, frame[0],
+                       frame[1], frame[2], frame[3], batch, smp, ph, scale, static_cast<bf16*>(x),
+                       prior);
+    return hipGetLastError() == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
+}
+
+int fedsur_target(int32_t grid, int32_t batch, const float* prior, const float* scale,
+                  const float* T, const uint8_t* mask, float T_a, float focus, float* target,
+                  float* weight, void* stream) {
+    if (grid < 1 || grid > 1024 || batch < 1 || !prior || !scale || !T || !mask || !target ||
+        !weight || !(focus >= 0.0f))
+        return FEDFEM_E_INVALID;
+    const int64_t G3 = (int64_t)grid * grid * grid;
+    hipLaunchKernelGGL(k_target, dim3(nblocks(G3 * batch, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), G3, batch, prior, scale, T, mask, T_a,
+                       focus, target, weight);
+    return hipGetLastError() == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
+}
+
+int fedsur_decode(int32_t grid, int32_t batch, const float* prior, const float* scale, float T_a,
+                  float* y, void* stream) {
+    if (grid < 1 || grid > 1024 || batch < 1 || !prior || !scale || !y) return FEDFEM_E_INVALID;
+    const int64_t G3 = (int64_t)grid * grid * grid;
+    hipLaunchKernelGGL(k_decode, dim3(nblocks(G3 * batch, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), G3, batch, prior, scale, T_a, y);
+    return hipGetLastError() == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
+}
+
+int fedsur_max_error(int32_t grid, int32_t batch, const float* Tp, const float* T,
+                     const uint8_t* mask, float* err, void* stream) {
+    if (grid < 1 || grid > 1024 || batch < 1 || batch > 65535 || !Tp || !T || !mask || !err)
+        return FEDFEM_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t G3 = (int64_t)grid * grid * grid;
+    unsigned* e = reinterpret_cast<unsigned*>(err);
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(batch, 256)), dim3(256), 0, s, e, batch, 0u);
+    const unsigned nx = (unsigned)std::min<int64_t>(64, (G3 + 255) / 256);
+    hipLaunchKernelGGL(k_max_err, dim3(nx, (unsigned)batch), dim3(256), 0, s, G3, batch, Tp, T,
+                       mask, e);
+    return hipGetLastError() == hipSuccess ? FEDFEM_OK : FEDFEM_E_HIP;
 }
 
 int fedfem_resample(fedfem_handle* h, int32_t grid, const double* frame, float* T_out,

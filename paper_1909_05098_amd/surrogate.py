@@ -31,10 +31,18 @@ _SIGS = {
     "fedsur_loss_backward": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
     "fedsur_adam_step": (C.c_int, [_P, C.c_float]),
     "fedsur_read_activation": (C.c_int, [_P, C.c_int32, _P]),
-    "fedsur_rasterize": (C.c_int, [C.c_int32, _P, C.c_int32, _P, _P, _P, _P]),
+    "fedsur_rasterize": (C.c_int, [C.c_int32, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "fedsur_target": (C.c_int, [C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_float, C.c_float, _P,
+                                _P, _P]),
+    "fedsur_decode": (C.c_int, [C.c_int32, C.c_int32, _P, _P, C.c_float, _P, _P]),
+    "fedsur_max_error": (C.c_int, [C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
     "fedfem_resample": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
 }
 _bound = False
+
+# fedsur_sample: one record of 12 doubles per sample
+SAMPLE_FIELDS = ("cx", "cy", "cz", "sigma", "q0", "k0", "omega_b", "ax", "ay", "az",
+                 "hmesh", "reserved")
 
 
 def lib():
@@ -110,6 +118,12 @@ class Net:
         except Exception:
             pass
 
+    def set_stream(self, stream):
+        """Run the network's kernels on `stream` (a HIP stream handle, e.g.
+        torch.cuda.current_stream().cuda_stream; 0 = the network's own)."""
+        _check(self._L.fedsur_set_stream(self._n, C.c_void_p(stream or None)),
+               "fedsur_set_stream")
+
     def get_params(self):
         out = np.empty(self.n_params, dtype=np.float32)
         _check(self._L.fedsur_get_params(self._n, out.ctypes.data_as(_P)), "fedsur_get_params")
@@ -147,16 +161,42 @@ class Net:
         return out
 
 
-def rasterize(grid, frame, params, mask, x, stream=None):
-    """Fill x (bf16 cuda [B, G, G, G, 8]) from per-sample (cx, cy, cz, sigma,
-    Q0, k0, omega_b); mask: uint8 cuda [B, G, G, G] or None."""
+def _stream(stream):
+    return None if not stream else C.c_void_p(stream)
+
+
+def rasterize(grid, frame, samples, phys, x, prior, scale, stream=None):
+    """Network input x (bf16 cuda [B, G, G, G, 8]), prior (float32 cuda
+    [B, G, G, G] or None) and scale (float32 cuda [B]) from samples
+    (float64 cuda [B, 12], fields SAMPLE_FIELDS) and phys = (rho0, c0,
+    rho_b c_b, t_heat)."""
     fr = np.ascontiguousarray(frame, dtype=np.float64)
-    pr = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 7)
-    _check(lib().fedsur_rasterize(int(grid), fr.ctypes.data_as(_P), len(pr),
-                                  pr.ctypes.data_as(_P),
-                                  None if mask is None else _dptr(mask), _dptr(x),
-                                  None if stream is None else C.c_void_p(stream)),
-           "fedsur_rasterize")
+    ph = np.ascontiguousarray(phys, dtype=np.float64)
+    assert samples.shape[-1] == len(SAMPLE_FIELDS) and ph.size == 4
+    _check(lib().fedsur_rasterize(int(grid), fr.ctypes.data_as(_P), samples.shape[0],
+                                  _dptr(samples), ph.ctypes.data_as(_P), _dptr(x),
+                                  None if prior is None else _dptr(prior), _dptr(scale),
+                                  _stream(stream)), "fedsur_rasterize")
+
+
+def target(grid, prior, scale, T, mask, T_a, out, weight, focus=0.0, stream=None):
+    """out = (T - T_a - prior) / scale inside mask, weight = mask (1 +
+    focus prior / scale) (cuda)."""
+    _check(lib().fedsur_target(int(grid), prior.shape[0], _dptr(prior), _dptr(scale), _dptr(T),
+                               _dptr(mask), C.c_float(T_a), C.c_float(focus), _dptr(out),
+                               _dptr(weight), _stream(stream)), "fedsur_target")
+
+
+def decode(grid, prior, scale, T_a, y, stream=None):
+    """y <- T_a + prior + scale * y in place (cuda)."""
+    _check(lib().fedsur_decode(int(grid), prior.shape[0], _dptr(prior), _dptr(scale),
+                               C.c_float(T_a), _dptr(y), _stream(stream)), "fedsur_decode")
+
+
+def max_error(grid, Tp, T, mask, err, stream=None):
+    """err[b] = max over mask of |Tp - T| (cuda float32 [B])."""
+    _check(lib().fedsur_max_error(int(grid), Tp.shape[0], _dptr(Tp), _dptr(T), _dptr(mask),
+                                  _dptr(err), _stream(stream)), "fedsur_max_error")
 
 
 def resample(handle, grid, frame, T_out, mask_out):
