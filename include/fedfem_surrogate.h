@@ -41,6 +41,14 @@ typedef struct fedsur_net fedsur_net;
 int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed,
                   fedsur_net **out);
 int fedsur_destroy(fedsur_net *n);
+
+/*
+ * Stream for the network's kernels.  A new network uses a stream of its own
+ * that is ordered with the legacy default stream (not a non-blocking one),
+ * so inputs written there are complete before the network reads them.
+ * stream = NULL selects the legacy default stream itself.  Every network
+ * entry point synchronises this stream before it returns.
+ */
 int fedsur_set_stream(fedsur_net *n, void *stream);
 
 /*

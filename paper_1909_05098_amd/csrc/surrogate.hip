@@ -1081,7 +1081,9 @@ int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed, fedsur_net** o
         return code;
     };
     if (hipGetDevice(&n->device) != hipSuccess) return fail(FEDFEM_E_HIP);
-    if (hipStreamCreateWithFlags(&n->own, hipStreamNonBlocking) != hipSuccess)
+    // a blocking stream: ordered with work on the legacy default stream, where
+    // callers (and torch's default stream) put the inputs the network reads
+    if (hipStreamCreateWithFlags(&n->own, hipStreamDefault) != hipSuccess)
         return fail(FEDFEM_E_HIP);
     n->stream = n->own;
     int64_t off = 0;
@@ -1164,7 +1166,7 @@ int fedsur_destroy(fedsur_net* n) {
 
 int fedsur_set_stream(fedsur_net* n, void* stream) {
     if (!n) return FEDFEM_E_INVALID;
-    n->stream = stream ? static_cast<hipStream_t>(stream) : n->own;
+    n->stream = static_cast<hipStream_t>(stream);
     return FEDFEM_OK;
 }
 

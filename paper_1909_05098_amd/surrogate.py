@@ -120,7 +120,8 @@ class Net:
 
     def set_stream(self, stream):
         """Run the network's kernels on `stream` (a HIP stream handle, e.g.
-        torch.cuda.current_stream().cuda_stream; 0 = the network's own)."""
+        torch.cuda.current_stream().cuda_stream; 0 = the legacy default
+        stream)."""
         _check(self._L.fedsur_set_stream(self._n, C.c_void_p(stream or None)),
                "fedsur_set_stream")
 

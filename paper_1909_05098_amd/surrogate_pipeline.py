@@ -182,7 +182,8 @@ def infer_with_fallback(net, scns, samples, phys, out, batch=64, grid=GRID, fr=N
     scenario is off by more than `tol` kelvin (or not finite), the whole
     batch falls back to FED-FEM.  Checked scenarios keep their FED-FEM
     field.  out: float32 cuda [S, G, G, G] temperature (FED-FEM fields are 0
-    outside their mesh).  Returns a dict of counts.
+    outside their mesh).  Returns a dict of counts and `from_fedfem`, the
+    scenarios whose field came from FED-FEM.
     """
     fr = frame(grid) if fr is None else fr
     S = len(scns)
@@ -194,6 +195,7 @@ def infer_with_fallback(net, scns, samples, phys, out, batch=64, grid=GRID, fr=N
     G = grid
     n_check = n_fallback_batches = n_fem = 0
     worst_check = 0.0
+    from_fem = np.zeros(S, dtype=bool)
     for b0 in range(0, S, batch):
         ids = order[b0:b0 + batch]
         n = len(ids)
@@ -216,6 +218,7 @@ def infer_with_fallback(net, scns, samples, phys, out, batch=64, grid=GRID, fr=N
         worst_check = max(worst_check, float(np.nan_to_num(e, nan=np.inf).max()))
         # checked scenarios take their FED-FEM field (computed anyway)
         pred[ci] = Tc
+        from_fem[ids[chk]] = True
         if not np.all(e <= tol):
             n_fallback_batches += 1
             rest = np.setdiff1d(np.arange(n), chk)
@@ -225,10 +228,11 @@ def infer_with_fallback(net, scns, samples, phys, out, batch=64, grid=GRID, fr=N
                 fem_on_grid([scns[ids[j]] for j in rest], Tr, Mr, grid, fr, tune_cache)
                 pred[torch.tensor(rest, device="cuda")] = Tr
                 n_fem += len(rest)
+                from_fem[ids[rest]] = True
         out[sel] = pred
     return {"scenarios": S, "batches": (S + batch - 1) // batch,
             "fallback_batches": n_fallback_batches, "spot_checks": n_check,
-            "fedfem_runs": n_fem, "worst_spot_check_K": worst_check}
+            "fedfem_runs": n_fem, "worst_spot_check_K": worst_check, "from_fedfem": from_fem}
 
 
 def save_params(net, path):

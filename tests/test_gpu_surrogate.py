@@ -382,3 +382,30 @@ def test_resample_linear_field_and_mask(torch_cuda):
     ref = 40.0 + P @ gvec
     assert np.max(np.abs(T[m] - ref[m])) <= 2e-5 * np.abs(ref[m]).max()
     assert np.all(T[~m] == 0)
+
+
+def test_output_independent_of_batch_and_stream(torch_cuda):
+    """Inputs rasterised on the default stream, then the network: the output
+    of every sample is bit-identical whatever the network's batch size (a
+    network kernel starting before its input is written would show here)."""
+    torch = torch_cuda
+    from paper_1909_05098_amd import surrogate_pipeline as pl
+    G, S = 32, 12
+    rng = np.random.default_rng(11)
+    rows = [dict(cx=c[0], cy=c[1], cz=c[2], sigma=s_, q0=q, k0=k, omega_b=w, ax=0.05, ay=0.04,
+                 az=0.035, hmesh=2e-3)
+            for c, s_, q, k, w in zip(rng.uniform(-0.02, 0.02, (S, 3)), rng.uniform(0.002, 0.006, S),
+                                      rng.uniform(5e6, 3e7, S), rng.uniform(0.45, 0.6, S),
+                                      rng.uniform(0.002, 0.02, S))]
+    smp = torch.tensor(samples_array(rows), device="cuda")
+    fr = pl.frame(G)
+    outs = []
+    for nb in (1, 4, 12):
+        net = sg.Net(G, nb, seed=5)
+        out = torch.empty((S, G, G, G), dtype=torch.float32, device="cuda")
+        pl.predict(net, smp, PHYS, out, nb, G, fr)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        net.close()
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
