@@ -7,11 +7,12 @@
 //             input channels of one voxel (16 bytes, channels-last);
 //   data grad the same kernel with the weights flipped in space and
 //             transposed in channels (a 3x3x3 correlation of the gradient);
-//   weight grad M = output channels, N = 27 * input channels, K = voxels:
-//             64-voxel chunks of the gradient and of the gathered input are
-//             staged transposed in LDS so that each lane reads 8 consecutive
-//             voxels of one channel, partial sums per voxel split are reduced
-//             in a fixed order (bit-reproducible).
+//   weight grad M = output channels, N = 27 * input channels + 1 (the
+//             bias), K = voxels: 64-voxel chunks of the gradient and of the
+//             gathered input are transposed in registers and staged in LDS
+//             so that each lane reads 8 consecutive voxels of one channel;
+//             partial sums per voxel split are reduced in a fixed order
+//             (bit-reproducible).
 // The remaining kernels are memory-bound elementwise passes: ReLU backward,
 // pooling, upsampling, the 1x1x1 head, the masked loss, Adam, weight
 // packing, input rasterisation and the resampling of FED-FEM fields.
@@ -163,105 +164,169 @@ hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient (and bias gradient from the k-block 0 workgroups)
+// Weight and bias gradient
 // ---------------------------------------------------------------------------
+// dW[co][k] = sum_v D[v][co] X[v + off(k)][ci(k)] and db[co] = sum_v D[v][co]:
+// an MFMA product with the voxels as the reduction dimension.  The bias is
+// the extra column k = K of X, equal to 1 on every voxel.  A workgroup owns
+// a COT x KN tile (output channels x k) and one split of the voxels, which
+// it walks in 64-voxel chunks.  Each chunk is staged transposed in LDS
+// (channel-major rows of 64 voxels): a thread gathers an 8-voxel x
+// 8-channel block with 16-byte loads, transposes it in registers and writes
+// 8 rows of 16 bytes.  Each wave then multiplies an (MT x 16) x (NT x 16)
+// block, reusing its MT + NT fragments for MT x NT MFMAs per 32 voxels.
 struct WgradArgs {
-    const bf16* d;  // gradient of the pre-activation output
+    const bf16* d;  // gradient of the pre-activation output, [V][dp]
     int dp, doff, cout;
     const bf16* in;  // convolution input
     int ip, io, cin;
-    int G, ks;
+    int G;
     int64_t V, vsplit;
-    int kp2;       // k extent of the partial buffer (multiple of 64)
-    float* part;   // [splits][cout][kp2]
-    float* partb;  // [splits][cout]
+    int kp2;      // k extent of the partial buffer (multiple of KN, > 27 cin)
+    float* part;  // [splits][cout][kp2]
 };
 
+__device__ __forceinline__ void transpose_store8(const bf16x8 (&r)[8], bf16* row0, int pitch) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        bf16x8 o;
+#pragma unroll
+        for (int i = 0; i < 8; i++) o[i] = r[i][j];
+        *reinterpret_cast<bf16x8*>(row0 + j * pitch) = o;
+    }
+}
+
+template <int MT, int NT, int WM, int WN>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
-    __shared__ __align__(16) bf16 sD[64][72];
-    __shared__ __align__(16) bf16 sX[64][72];
+    constexpr int COT = 16 * MT * WM, KN = 16 * NT * WN, LP = 72;
+    static_assert(WM * WN == 4, "four waves");
+    __shared__ __align__(16) bf16 sD[COT][LP];
+    __shared__ __align__(16) bf16 sX[KN][LP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int k0 = blockIdx.x * 64, co0 = blockIdx.y * 64;
+    const int wm = wave / WN, wn = wave % WN;
+    const int k0 = blockIdx.x * KN, co0 = blockIdx.y * COT;
     const int64_t vs = (int64_t)blockIdx.z * a.vsplit;
     const int64_t ve = min(a.V, vs + a.vsplit);
     const int G = a.G;
     const int64_t G3 = (int64_t)G * G * G;
-    const int K = (a.ks == 3 ? 27 : 1) * a.cin;
-    const int g8 = (t & 7) * 8;
-    // the gathered input's k group is fixed per thread
-    const int kk = k0 + g8;
-    int dz = 0, dy = 0, dx = 0, ci = 0;
-    const bool kvalid = kk < K;
-    if (kvalid) {
-        const int off = kk / a.cin;
-        ci = kk - off * a.cin;
-        if (a.ks == 3) {
-            dz = off / 9 - 1;
-            dy = (off / 3) % 3 - 1;
-            dx = off % 3 - 1;
-        }
-    }
-    f32x4 acc[4];
+    const int K = 27 * a.cin;
+    f32x4 acc[MT][NT];
 #pragma unroll
-    for (int nt = 0; nt < 4; nt++) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.0f;
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int64_t vc = vs; vc < ve; vc += 64) {
+        // input blocks: KN / 8 k-groups x 8 voxel-groups; a k-group of 8
+        // consecutive k never straddles an offset or K (cin % 8 == 0)
+        for (int blk = t; blk < KN; blk += 256) {
+            const int kg = blk >> 3, vg = blk & 7;
+            const int kk = k0 + kg * 8;
+            bf16x8 r[8];
+            if (kk < K) {
+                const int off = kk / a.cin;
+                const int ci = kk - off * a.cin;
+                const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int vl = (t >> 3) + h * 32;
-            const int64_t v = vc + vl;
-            bf16x8 dv = zero8();
-            if (v < ve && co0 + g8 < a.cout)
-                dv = *reinterpret_cast<const bf16x8*>(a.d + v * a.dp + a.doff + co0 + g8);
+                for (int i = 0; i < 8; i++) {
+                    const int64_t v = vc + vg * 8 + i;
+                    r[i] = zero8();
+                    if (v < ve) {
+                        const int64_t b = v / G3;
+                        const int64_t rr = v - b * G3;
+                        const int z2 = (int)(rr / ((int64_t)G * G)) + dz;
+                        const int y2 = (int)((rr / G) % G) + dy;
+                        const int x2 = (int)(rr % G) + dx;
+                        if (z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 && x2 < G) {
+                            const int64_t nv = ((b * G + z2) * G + y2) * G + x2;
+                            r[i] = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + ci);
+                        }
+                    }
+                }
+            } else {
 #pragma unroll
-            for (int j = 0; j < 8; j++) sD[g8 + j][vl] = dv[j];
-            bf16x8 xv = zero8();
-            if (v < ve && kvalid) {
-                const int64_t b = v / G3;
-                const int64_t r = v - b * G3;
-                const int z2 = (int)(r / ((int64_t)G * G)) + dz;
-                const int y2 = (int)((r / G) % G) + dy;
-                const int x2 = (int)(r % G) + dx;
-                if (z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 && x2 < G) {
-                    const int64_t nv = ((b * G + z2) * G + y2) * G + x2;
-                    xv = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + ci);
+                for (int i = 0; i < 8; i++) {
+                    r[i] = zero8();
+                    if (kk == K && vc + vg * 8 + i < ve) r[i][0] = (bf16)1.0f;  // bias column
                 }
             }
+            transpose_store8(r, &sX[kg * 8][vg * 8], LP);
+        }
+        // gradient blocks: COT / 8 channel-groups x 8 voxel-groups
+        for (int blk = t; blk < COT; blk += 256) {
+            const int cg = blk >> 3, vg = blk & 7;
+            const int co = co0 + cg * 8;
+            bf16x8 r[8];
 #pragma unroll
-            for (int j = 0; j < 8; j++) sX[g8 + j][vl] = xv[j];
+            for (int i = 0; i < 8; i++) {
+                const int64_t v = vc + vg * 8 + i;
+                r[i] = (v < ve && co < a.cout)
+                           ? *reinterpret_cast<const bf16x8*>(a.d + v * a.dp + a.doff + co)
+                           : zero8();
+            }
+            transpose_store8(r, &sD[cg * 8][vg * 8], LP);
         }
         __syncthreads();
 #pragma unroll
         for (int s2 = 0; s2 < 2; s2++) {
-            const int vg = s2 * 32 + (lane >> 4) * 8;
-            const bf16x8 Af = *reinterpret_cast<const bf16x8*>(&sD[wave * 16 + (lane & 15)][vg]);
+            const int vo = s2 * 32 + (lane >> 4) * 8;
+            bf16x8 A[MT], Bf[NT];
 #pragma unroll
-            for (int nt = 0; nt < 4; nt++) {
-                const bf16x8 Bf = *reinterpret_cast<const bf16x8*>(&sX[nt * 16 + (lane & 15)][vg]);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Af, Bf, acc[nt], 0, 0, 0);
-            }
+            for (int mt = 0; mt < MT; mt++)
+                A[mt] = *reinterpret_cast<const bf16x8*>(&sD[(wm * MT + mt) * 16 + (lane & 15)][vo]);
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++)
+                Bf[nt] = *reinterpret_cast<const bf16x8*>(&sX[(wn * NT + nt) * 16 + (lane & 15)][vo]);
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++)
+                    acc[mt][nt] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bf[nt], acc[mt][nt], 0, 0, 0);
         }
-        if (blockIdx.x == 0 && t < 64)
-            for (int vl = 0; vl < 64; vl++) bsum += (float)sD[t][vl];
         __syncthreads();
     }
+    // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
 #pragma unroll
-    for (int nt = 0; nt < 4; nt++)
+    for (int mt = 0; mt < MT; mt++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int co = co0 + wave * 16 + (lane >> 4) * 4 + i;
-            const int k = k0 + nt * 16 + (lane & 15);
-            if (co < a.cout)
-                a.part[((int64_t)blockIdx.z * a.cout + co) * a.kp2 + k] = acc[nt][i];
-        }
-    if (blockIdx.x == 0 && t < 64 && co0 + t < a.cout)
-        a.partb[(int64_t)blockIdx.z * a.cout + co0 + t] = bsum;
+        for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int co = co0 + (wm * MT + mt) * 16 + (lane >> 4) * 4 + i;
+                const int k = k0 + (wn * NT + nt) * 16 + (lane & 15);
+                if (co < a.cout)
+                    a.part[((int64_t)blockIdx.z * a.cout + co) * a.kp2 + k] = acc[mt][nt][i];
+            }
 }
 
-// dW[co][k] (k < K) and db[co]: fixed-order sums over the voxel splits.
-__global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ partb,
-                               int splits, int cout, int kp2, int K, float* __restrict__ dW,
-                               float* __restrict__ db) {
+// tile shape of the weight gradient for a layer with `cout` output channels
+inline int wgrad_kn(int cout) { return cout <= 32 ? 256 : 128; }
+inline int wgrad_cot(int cout) { return cout <= 32 ? 32 : (cout <= 64 ? 64 : 128); }
+constexpr int kWgradBlocks = 1024;  // workgroups aimed at per layer
+
+// voxel split of a layer's weight gradient: ~kWgradBlocks workgroups, splits
+// of whole 64-voxel chunks; never more than kWgradBlocks / tiles splits
+inline int64_t wgrad_vsplit(int64_t V, int tiles) {
+    const int64_t want = std::max<int64_t>(1, (kWgradBlocks + tiles - 1) / tiles);
+    const int64_t vs = (V + want - 1) / want;
+    return std::max<int64_t>(64, (vs + 63) / 64 * 64);
+}
+
+hipError_t launch_wgrad(const WgradArgs& w, int tiles_k, int tiles_c, int64_t splits,
+                        hipStream_t s) {
+    const dim3 grid((unsigned)tiles_k, (unsigned)tiles_c, (unsigned)splits);
+    if (w.cout <= 32)
+        hipLaunchKernelGGL((k_wgrad<2, 4, 1, 4>), grid, dim3(256), 0, s, w);
+    else if (w.cout <= 64)
+        hipLaunchKernelGGL((k_wgrad<2, 4, 2, 2>), grid, dim3(256), 0, s, w);
+    else
+        hipLaunchKernelGGL((k_wgrad<4, 4, 2, 2>), grid, dim3(256), 0, s, w);
+    return hipGetLastError();
+}
+
+// dW[co][k] (k < K) and db[co] (column K): fixed-order sums over the splits
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, int cout, int kp2,
+                               int K, float* __restrict__ dW, float* __restrict__ db) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nW = (int64_t)cout * K;
     if (i < nW) {
@@ -272,7 +337,7 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __re
     } else if (i < nW + cout) {
         const int co = (int)(i - nW);
         float s = 0.0f;
-        for (int z = 0; z < splits; z++) s += partb[(int64_t)z * cout + co];
+        for (int z = 0; z < splits; z++) s += part[((int64_t)z * cout + co) * kp2 + K];
         db[co] = s;
     }
 }
@@ -824,8 +889,8 @@ struct fedsur_net {
     bf16 *e1a, *cat1, *p1, *e2a, *cat2, *p2, *e3a, *e3b, *d2a, *d2b, *d1a, *d1b;
     float* y = nullptr;
     // gradients
-    float *dy = nullptr, *red = nullptr, *part = nullptr, *partb = nullptr, *scal = nullptr;
-    int64_t part_cap = 0, partb_cap = 0, red_cap = 0;
+    float *dy = nullptr, *red = nullptr, *part = nullptr, *scal = nullptr;
+    int64_t part_cap = 0, red_cap = 0;
     bf16 *gA0, *gB0, *gcat1, *gA1, *gB1, *gcat2, *gA2, *gB2, *gp1, *gp2;
     int64_t adam_t = 0;
     std::vector<void*> allocs;
@@ -911,13 +976,12 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     hipStream_t s = n->stream;
     hipLaunchKernelGGL(k_relu_bwd, dim3(nblocks(V * (d.cout / 8), 256)), dim3(256), 0, s, gout.p,
                        gout.pitch, gout.off, out.p, out.pitch, out.off, d.cout, V, dpre);
-    // weight gradient: split the voxels so that there are enough workgroups
-    const int kb = n->kp2[L] / 64, cb = (d.cout + 63) / 64;
-    int64_t vsplit = 64;
-    while ((V + vsplit - 1) / vsplit > 128) vsplit *= 2;
+    // weight and bias gradient: ~kWgradBlocks workgroups over tiles x splits
+    const int KN = wgrad_kn(d.cout), COT = wgrad_cot(d.cout);
+    const int kb = n->kp2[L] / KN, cb = (d.cout + COT - 1) / COT;
+    const int64_t vsplit = wgrad_vsplit(V, kb * cb);
     const int64_t splits = (V + vsplit - 1) / vsplit;
-    if (splits * d.cout * n->kp2[L] > n->part_cap || splits * d.cout > n->partb_cap)
-        return hipErrorInvalidValue;
+    if (splits * d.cout * n->kp2[L] > n->part_cap || splits > 65535) return hipErrorInvalidValue;
     WgradArgs w;
     w.d = dpre;
     w.dp = d.cout;
@@ -928,16 +992,14 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     w.io = in.off;
     w.cin = d.cin;
     w.G = G;
-    w.ks = 3;
     w.V = V;
     w.vsplit = vsplit;
     w.kp2 = n->kp2[L];
     w.part = n->part;
-    w.partb = n->partb;
-    hipLaunchKernelGGL(k_wgrad, dim3(kb, cb, (unsigned)splits), dim3(256), 0, s, w);
+    if (hipError_t e0 = launch_wgrad(w, kb, cb, splits, s)) return e0;
     const int64_t nred = (int64_t)d.cout * 27 * d.cin + d.cout;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nred, 256)), dim3(256), 0, s, n->part,
-                       n->partb, (int)splits, d.cout, n->kp2[L], 27 * d.cin, n->g + n->w_off[L],
+                       (int)splits, d.cout, n->kp2[L], 27 * d.cin, n->g + n->w_off[L],
                        n->g + n->b_off[L]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !dx) return e;
@@ -1096,8 +1158,12 @@ int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed, fedsur_net** o
         off += d.cout;
         n->kp[L] = round_up(27 * d.cin, 32);
         n->kpt[L] = round_up(27 * d.cout, 32);
-        n->kp2[L] = round_up(27 * d.cin, 64);
-        max_part = std::max(max_part, (int64_t)d.cout * n->kp2[L]);
+        // room for the bias column k = 27 cin; whole KN tiles
+        n->kp2[L] = round_up(27 * d.cin + 1, wgrad_kn(d.cout));
+        const int tiles = (n->kp2[L] / wgrad_kn(d.cout)) *
+                          ((d.cout + wgrad_cot(d.cout) - 1) / wgrad_cot(d.cout));
+        const int64_t max_splits = std::max(1, (kWgradBlocks + tiles - 1) / tiles);
+        max_part = std::max(max_part, max_splits * d.cout * n->kp2[L]);
     }
     n->head_off = off;
     off += 33;
@@ -1125,11 +1191,9 @@ int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed, fedsur_net** o
          nalloc(n, &n->gB2, V2 * 128) == hipSuccess && nalloc(n, &n->gp1, V1 * 32) == hipSuccess &&
          nalloc(n, &n->gp2, V2 * 64) == hipSuccess && nalloc(n, &n->scal, 8) == hipSuccess;
     // split-K partials: at most 128 voxel splits per layer; head partials too
-    n->part_cap = std::max<int64_t>(128 * max_part, ((V0 + 255) / 256) * 33);
-    n->partb_cap = 128 * 128;
+    n->part_cap = std::max<int64_t>(max_part, ((V0 + 255) / 256) * 33);
     n->red_cap = (V0 + 255) / 256 + 1;
     ok = ok && nalloc(n, &n->part, n->part_cap) == hipSuccess &&
-         nalloc(n, &n->partb, n->partb_cap) == hipSuccess &&
          nalloc(n, &n->red, n->red_cap) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
