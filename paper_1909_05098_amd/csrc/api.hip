@@ -480,9 +480,10 @@ int fedfem_precompute(fedfem_handle* h) {
     if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "already precomputed");
     release_device(h);
     const int64_t N = h->N, E = h->E;
-    hipDeviceProp_t prop;
-    HIPCHK(h, hipGetDeviceProperties(&prop, h->device));
-    const size_t lds_limit = prop.sharedMemPerBlock;
+    int lds_attr = 0;
+    HIPCHK(h, hipDeviceGetAttribute(&lds_attr, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                    h->device));
+    const size_t lds_limit = (size_t)lds_attr;
     Layout& L = h->L;
     std::string err;
     int TE = h->opt.tile_elems;

@@ -163,9 +163,9 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
         destroy_batch(b);
         return FEDFEM_E_INVALID;
     }
-    hipDeviceProp_t prop;
-    BCHK(hipGetDeviceProperties(&prop, b->device));
-    if (tile_lds_bytes(maxte, maxn, b->fp32c ? 4 : 8, b->fp32c, true) > prop.sharedMemPerBlock) {
+    int lds_attr = 0;
+    BCHK(hipDeviceGetAttribute(&lds_attr, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device));
+    if (tile_lds_bytes(maxte, maxn, b->fp32c ? 4 : 8, b->fp32c, true) > (size_t)lds_attr) {
         destroy_batch(b);
         return FEDFEM_E_INVALID;
     }

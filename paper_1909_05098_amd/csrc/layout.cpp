@@ -23,16 +23,18 @@ inline uint64_t spread3(uint64_t v) {
     return v;
 }
 
-// Stable LSD radix sort of (key, id) pairs by key, 16-bit digits.
+// Stable LSD radix sort of (key, id) pairs by key, 11-bit digits.
 void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& id,
                       int key_bits) {
+    constexpr int kDigit = 11;
+    constexpr uint64_t kMask = (1u << kDigit) - 1;
     const size_t n = key.size();
     std::vector<uint64_t> k2(n);
     std::vector<int32_t> i2(n);
-    std::vector<size_t> cnt(1 << 16);
-    for (int shift = 0; shift < key_bits; shift += 16) {
+    std::vector<size_t> cnt(size_t(1) << kDigit);
+    for (int shift = 0; shift < key_bits; shift += kDigit) {
         std::fill(cnt.begin(), cnt.end(), 0);
-        for (size_t i = 0; i < n; i++) cnt[(key[i] >> shift) & 0xffff]++;
+        for (size_t i = 0; i < n; i++) cnt[(key[i] >> shift) & kMask]++;
         size_t run = 0;
         for (auto& c : cnt) {
             size_t t = c;
@@ -40,7 +42,7 @@ void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& id,
             run += t;
         }
         for (size_t i = 0; i < n; i++) {
-            size_t pos = cnt[(key[i] >> shift) & 0xffff]++;
+            size_t pos = cnt[(key[i] >> shift) & kMask]++;
             k2[pos] = key[i];
             i2[pos] = id[i];
         }
@@ -49,10 +51,13 @@ void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& id,
     }
 }
 
+// body(a, b) over [0, n) split across up to 16 host threads; ranges of fewer
+// than `grain` items run on the calling thread
 template <typename F>
-void parallel_for(int64_t n, F&& body) {
+void parallel_for(int64_t n, F&& body, int64_t grain = 4096) {
     unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 4096 || nt == 1) {
+    nt = (unsigned)std::min<int64_t>(nt, std::max<int64_t>(1, n / std::max<int64_t>(1, grain)));
+    if (nt <= 1) {
         body(0, n);
         return;
     }
@@ -76,19 +81,26 @@ std::vector<int32_t> morton_order(const double* pts, int64_t n) {
             hi[a] = std::max(hi[a], pts[3 * i + a]);
         }
     double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
-    double scale = 2097151.0 / ext;  // 21 bits per axis, same scale on all
+    // bits per axis: about 16 cells per point along the curve, at most 21
+    int lg = 0;
+    while ((int64_t(1) << lg) < std::max<int64_t>(n, 2)) lg++;
+    const int bits = std::min(21, (lg + 2) / 3 + 4);
+    const double cells = double((1u << bits) - 1);
+    const double scale = cells / ext;  // same scale on all axes
     std::vector<uint64_t> key(n);
     std::vector<int32_t> id(n);
-    for (int64_t i = 0; i < n; i++) {
-        uint64_t q[3];
-        for (int a = 0; a < 3; a++) {
-            double v = (pts[3 * i + a] - lo[a]) * scale;
-            q[a] = (uint64_t)std::min(2097151.0, std::max(0.0, v));
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; i++) {
+            uint64_t q[3];
+            for (int ax = 0; ax < 3; ax++) {
+                double v = (pts[3 * i + ax] - lo[ax]) * scale;
+                q[ax] = (uint64_t)std::min(cells, std::max(0.0, v));
+            }
+            key[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+            id[i] = (int32_t)i;
         }
-        key[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
-        id[i] = (int32_t)i;
-    }
-    radix_sort_pairs(key, id, 64);
+    }, 16384);
+    radix_sort_pairs(key, id, 3 * bits);
     return id;
 }
 
@@ -138,22 +150,31 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     }
     const int64_t T = (int64_t)L.tile_elem_off.size() - 1;
     L.T = T;
-    // pass 1: sort each tile's corners by (node, slot), count distinct nodes
-    std::vector<uint64_t> keys(4 * E);
+    // pass 1: each tile's distinct nodes in ascending id (a marker array per
+    // worker finds them; only the distinct nodes are sorted) and every
+    // corner's position in that list
+    std::vector<int32_t> uniq(4 * E);  // tile t's list at 4 * tile_elem_off[t]
     std::vector<int32_t> ucount(T);
+    L.lconn.assign(4 * E, 0);
     parallel_for(T, [&](int64_t a, int64_t b) {
+        std::vector<int32_t> loc(N, -1);
         for (int64_t t = a; t < b; t++) {
-            const int64_t e0 = L.tile_elem_off[t], ne = L.tile_elem_off[t + 1] - e0;
-            uint64_t* k = keys.data() + 4 * e0;
-            for (int64_t s = 0; s < 4 * ne; s++)
-                k[s] = ((uint64_t)(uint32_t)L.conn[4 * e0 + s] << 16) | (uint64_t)s;
-            std::sort(k, k + 4 * ne);
-            int32_t u = 0;
-            for (int64_t s = 0; s < 4 * ne; s++)
-                if (s == 0 || (k[s] >> 16) != (k[s - 1] >> 16)) u++;
-            ucount[t] = u;
+            const int64_t e0 = L.tile_elem_off[t], nc = 4 * (L.tile_elem_off[t + 1] - e0);
+            const int32_t* c = L.conn.data() + 4 * e0;
+            int32_t* u = uniq.data() + 4 * e0;
+            int32_t nu = 0;
+            for (int64_t s2 = 0; s2 < nc; s2++)
+                if (loc[c[s2]] < 0) {
+                    loc[c[s2]] = 0;
+                    u[nu++] = c[s2];
+                }
+            std::sort(u, u + nu);
+            for (int32_t i = 0; i < nu; i++) loc[u[i]] = i;
+            for (int64_t s2 = 0; s2 < nc; s2++) L.lconn[4 * e0 + s2] = (uint16_t)loc[c[s2]];
+            for (int32_t i = 0; i < nu; i++) loc[u[i]] = -1;
+            ucount[t] = nu;
         }
-    });
+    }, 4);
     L.tile_node_off.assign(T + 1, 0);
     int64_t P = 0;
     int maxn = 0;
@@ -169,24 +190,14 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     L.tile_node_off[T] = (int32_t)P;
     L.P = P;
     L.max_tile_nodes = maxn;
+    // pass 2: the tile node lists, packed
     L.tile_nodes.assign(P, 0);
-    L.lconn.assign(4 * E, 0);
-    // pass 2: tile node lists and each corner's local node id
     parallel_for(T, [&](int64_t a, int64_t b) {
-        for (int64_t t = a; t < b; t++) {
-            const int64_t e0 = L.tile_elem_off[t], ne = L.tile_elem_off[t + 1] - e0;
-            const uint64_t* k = keys.data() + 4 * e0;
-            int64_t p = L.tile_node_off[t] - 1;
-            for (int64_t s = 0; s < 4 * ne; s++) {
-                const uint32_t node = (uint32_t)(k[s] >> 16);
-                if (s == 0 || (k[s] >> 16) != (k[s - 1] >> 16)) {
-                    p++;
-                    L.tile_nodes[p] = (int32_t)node;
-                }
-                L.lconn[4 * e0 + (k[s] & 0xffff)] = (uint16_t)(p - L.tile_node_off[t]);
-            }
-        }
-    });
+        for (int64_t t = a; t < b; t++)
+            std::memcpy(L.tile_nodes.data() + L.tile_node_off[t],
+                        uniq.data() + 4 * (int64_t)L.tile_elem_off[t],
+                        sizeof(int32_t) * ucount[t]);
+    }, 4);
     // node-major partial positions, ascending tile inside each node
     L.part_off.assign(N + 1, 0);
     for (int64_t p = 0; p < P; p++) L.part_off[L.tile_nodes[p] + 1]++;
@@ -212,15 +223,18 @@ bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
     L.ninv.resize(N);
     L.eperm.resize(E);
     if (reorder) {
-        L.nperm = morton_order(xyz, N);
+        std::thread nodes([&] { L.nperm = morton_order(xyz, N); });
         std::vector<double> cen(3 * E);
-        for (int64_t e = 0; e < E; e++)
-            for (int a = 0; a < 3; a++) {
-                double s = 0;
-                for (int c = 0; c < 4; c++) s += xyz[3 * (int64_t)tets[4 * e + c] + a];
-                cen[3 * e + a] = 0.25 * s;
-            }
+        parallel_for(E, [&](int64_t a, int64_t b) {
+            for (int64_t e = a; e < b; e++)
+                for (int ax = 0; ax < 3; ax++) {
+                    double s = 0;
+                    for (int c = 0; c < 4; c++) s += xyz[3 * (int64_t)tets[4 * e + c] + ax];
+                    cen[3 * e + ax] = 0.25 * s;
+                }
+        });
         L.eperm = morton_order(cen.data(), E);
+        nodes.join();
     } else {
         std::iota(L.nperm.begin(), L.nperm.end(), 0);
         std::iota(L.eperm.begin(), L.eperm.end(), 0);
