@@ -14,6 +14,11 @@ sample of the same run when one exists for the workload.
 Prints one JSON line: element-updates/s, the roofline of the dominant kernel
 (algorithmic bytes / measured kernel time, against 8 TB/s), and the FP64 CPU
 oracle timed on a bounded sample of the same workload on the host cores.
+Beside it: the planning sweep (256 seeded scenarios, one at a time versus one
+batched launch) and the learned surrogate on 512 held-out scenarios (FED-FEM
+one at a time and batched, the network alone, and the network with its
+FED-FEM spot check and fallback), each with scenarios/s and its error
+against FED-FEM.
 """
 import argparse
 import hashlib
@@ -90,12 +95,12 @@ def _gen_sweep_one(j):
     return sc.sweep_scenario(j)
 
 
-def gen_sweep(count, workers):
+def gen_sweep(ids, workers):
     """Seeded planning-sweep scenarios, built on host cores before any GPU
     use in this process (the pool forks)."""
     from multiprocessing import get_context
     with get_context("fork").Pool(workers) as pool:
-        return pool.map(_gen_sweep_one, range(count))
+        return pool.map(_gen_sweep_one, list(ids))
 
 
 def run_sweep(scns, autotune=True):
@@ -179,6 +184,110 @@ def run_sweep(scns, autotune=True):
             "max_abs_dT_batched_vs_plain_K": dT}
 
 
+def forward_flops(G):
+    """Multiply-adds x 2 of one forward pass of the surrogate on a G^3 grid."""
+    from paper_1909_05098_amd import surrogate as sg
+    f = sum(2 * 27 * ci * co * (G >> lv) ** 3 for (_, ci, co), lv in zip(sg.LAYERS, sg.LEVEL))
+    return f + 2 * 32 * G ** 3
+
+
+def run_surrogate(scns, weights, net_batch=16, check_batch=64):
+    """Scenarios/s of FED-FEM (one at a time, batched) and of the trained
+    surrogate (raw, and with the 1/16 FED-FEM spot check and fallback) on
+    held-out scenarios, with each path's error against FED-FEM on the grid."""
+    import numpy as np
+    import torch
+    from paper_1909_05098_amd import surrogate as sg
+    from paper_1909_05098_amd import surrogate_pipeline as pl
+
+    S, G = len(scns), pl.GRID
+    fr = pl.frame(G)
+    phys = pl.phys_of(scns[0].materials)
+    stream = torch.cuda.current_stream().cuda_stream
+    samples = torch.tensor(np.array([pl.sample_row(s) for s in scns]), device="cuda")
+    f32, u8 = torch.float32, torch.uint8
+
+    def field():
+        return torch.empty((S, G, G, G), dtype=f32, device="cuda")
+
+    def errors(Tp, T, M):
+        e = torch.empty(S, dtype=f32, device="cuda")
+        sg.max_error(G, Tp, T, M, e, stream)
+        return e.cpu().numpy().astype(np.float64)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    T, M = field(), torch.empty((S, G, G, G), dtype=u8, device="cuda")
+    t_batched, _ = timed(lambda: pl.fem_on_grid(scns, T, M, G, fr))
+    log(f"surrogate leg: FED-FEM batched {S} scenarios {t_batched:.2f} s")
+    T1, M1 = field(), torch.empty_like(M)
+    t_plain, _ = timed(lambda: pl.fem_on_grid(scns, T1, M1, G, fr, batched=False))
+    d_plain = float(errors(T1, T, M).max())
+    del T1, M1
+    log(f"surrogate leg: FED-FEM plain {t_plain:.2f} s (max diff to batched {d_plain:.2e} K)")
+    net = sg.Net(G, net_batch, seed=0)
+    pl.load_params(net, weights)
+    pred = field()
+    pl.predict(net, samples[:net_batch], phys, pred[:net_batch], net_batch, G, fr)  # warm-up
+    t_raw, _ = timed(lambda: pl.predict(net, samples, phys, pred, net_batch, G, fr))
+    e_raw = errors(pred, T, M)
+    zero = sg.Net(G, net_batch, seed=0)
+    zero.set_params(np.zeros(zero.n_params, dtype=np.float32))
+    pl.predict(zero, samples, phys, pred, net_batch, G, fr)
+    e_prior = errors(pred, T, M)
+    zero.close()
+    out = field()
+    t_fb, stats = timed(lambda: pl.infer_with_fallback(net, scns, samples, phys, out,
+                                                        batch=check_batch, grid=G, fr=fr,
+                                                        net_batch=net_batch))
+    e_fb = errors(out, T, M)
+    log(f"surrogate leg: raw {t_raw:.3f} s, with fallback {t_fb:.2f} s, "
+        f"fallback batches {stats['fallback_batches']}/{stats['batches']}")
+    # training throughput of the same network (a fresh copy, 12 steps timed)
+    tr = sg.Net(G, 8, seed=1)
+    tr.set_stream(stream)
+    ws = pl.Workspace(8, G)
+    idx = torch.arange(8, device="cuda")
+
+    def train_steps(n):
+        for _ in range(n):
+            sg.rasterize(G, fr, samples[:8], phys, ws.X, ws.prior, ws.scale, stream)
+            sg.target(G, ws.prior, ws.scale, T.index_select(0, idx), M.index_select(0, idx),
+                      37.0, ws.target, ws.maskf, pl.FOCUS, stream)
+            tr.loss_backward(ws.X, ws.target, ws.maskf)
+            tr.adam_step(1e-4)
+
+    train_steps(2)
+    t_tr, _ = timed(lambda: train_steps(12))
+    tr.close()
+    net.close()
+    ff_flops = forward_flops(G)
+    q = lambda e: {"median": round(float(np.median(e)), 3),  # noqa: E731
+                   "p90": round(float(np.quantile(e, 0.9)), 3), "max": round(float(e.max()), 3)}
+    return {"workload": f"learned surrogate on a {G}^3 frame (2.5 mm voxels), {S} held-out "
+                        f"planning-sweep seeds 10000..{10000 + S - 1}, 300 s heating",
+            "scenarios": S,
+            "fedfem_plain_scenarios_per_s": round(S / t_plain, 2),
+            "fedfem_batched_scenarios_per_s": round(S / t_batched, 2),
+            "surrogate_raw_scenarios_per_s": round(S / t_raw, 1),
+            "surrogate_with_fallback_scenarios_per_s": round(S / t_fb, 2),
+            "gain_raw_vs_batched": round(t_batched / t_raw, 1),
+            "gain_with_fallback_vs_batched": round(t_batched / t_fb, 3),
+            "spot_check_tol_K": pl.TOL_K, "fallback_batches": stats["fallback_batches"],
+            "batches": stats["batches"], "fedfem_runs_in_surrogate_path": stats["fedfem_runs"],
+            "max_abs_dT_K": {"surrogate_raw": q(e_raw), "prior_only": q(e_prior),
+                             "with_fallback": q(e_fb), "fedfem_plain_vs_batched": d_plain},
+            "forward_TFLOPs": round(ff_flops * S / t_raw / 1e12, 1),
+            "forward_mfma_frac_bf16": round(ff_flops * S / t_raw / 1e12 / 2500.0, 4),
+            "train_sample_steps_per_s": round(12 * 8 / t_tr, 1),
+            "train_TFLOPs": round(3 * ff_flops * 12 * 8 / t_tr / 1e12, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +307,10 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=20)
     ap.add_argument("--sweep", type=int, default=256,
                     help="planning-sweep scenarios for the batched leg (0 = skip)")
+    ap.add_argument("--surrogate", type=int, default=512,
+                    help="held-out scenarios for the surrogate leg (0 = skip)")
+    ap.add_argument("--surrogate-weights", default=os.path.join(
+        ROOT, "paper_1909_05098_amd", "weights", "surrogate_g64.npy"))
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for "
                          "counter calibration) and exit")
@@ -212,9 +325,14 @@ def main():
     sweep_scns = None
     if args.sweep and not args.copy_calib_gib:
         t0 = time.perf_counter()
-        sweep_scns = gen_sweep(args.sweep, min(16, os.cpu_count() or 1))
+        sweep_scns = gen_sweep(range(args.sweep), min(16, os.cpu_count() or 1))
         log(f"sweep meshes: {len(sweep_scns)} scenarios "
             f"({sum(s.n_tets for s in sweep_scns)} tets, {time.perf_counter() - t0:.1f} s)")
+    sur_scns = None
+    if args.surrogate and not args.copy_calib_gib:
+        t0 = time.perf_counter()
+        sur_scns = gen_sweep(range(10000, 10000 + args.surrogate), min(16, os.cpu_count() or 1))
+        log(f"surrogate held-out meshes: {len(sur_scns)} ({time.perf_counter() - t0:.1f} s)")
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -283,7 +401,9 @@ def main():
         log(f"max|T - T_oracle| on {len(idx)} sampled nodes = {max_err:.3e} K")
     # per-kernel durations with HIP events on the handle's stream
     elem_ms, node_ms = h.time_kernels(args.kernel_steps)
-    elem_bytes = 40.0 * E   # 4 x i32 connectivity + 6 x f32 coefficients
+    # algorithmic bytes per element-update of the stencil: six f32 coefficients
+    # and four 32-bit node ids (the layout itself stores u16 tile-local ids)
+    elem_bytes = 40.0 * E
     node_bytes = 24.0 * N   # T hi/lo read+write, 1/V_i, source
     kern = {"elem_loads": (elem_ms, elem_bytes), "node_update": (node_ms, node_bytes)}
     dom = max(kern, key=lambda k: kern[k][0])
@@ -298,6 +418,7 @@ def main():
     step_gbps = (elem_bytes + node_bytes) / (ms_step * 1e-3) / 1e9
     h.close()
     batched = run_sweep(sweep_scns, not args.no_autotune) if sweep_scns else None
+    surrogate = run_surrogate(sur_scns, args.surrogate_weights) if sur_scns else None
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -324,6 +445,7 @@ def main():
         "max_abs_dT_vs_oracle_K": max_err,
         "precompute_s": round(t_pre, 3),
         "batched": batched,
+        "surrogate": surrogate,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
