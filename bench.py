@@ -148,9 +148,20 @@ def run_sweep(scns, autotune=True):
         t_steps += t2 - t1
         ns.append(n)
     log(f"sweep plain: {len(scns)} scenarios in {t_all:.2f} s ({t_steps:.2f} s stepping)")
-    # batched: all handles, one captured launch sequence
+    # batched: all handles (precompute overlapped on host threads), one
+    # captured launch sequence
     t0 = time.perf_counter()
-    hs = [handle(s)[0] for s in scns]
+    hs = []
+    for s in scns:
+        h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
+                      dt=-0.9, precision=ff.FP32C)
+        if autotune:
+            h.autotune(TUNE_CACHE, for_batch=True)
+        hs.append(h)
+    ff.precompute_many(hs)
+    for h, s in zip(hs, scns):
+        h.set_gaussian_sources(s.sources, s.source_mode)
+        h.set_dt(sc.steps_for(s.t_end, h.dt()[1])[1])
     t1 = time.perf_counter()
     b = ff.Batch(hs)
     t2 = time.perf_counter()
@@ -311,6 +322,9 @@ def main():
                     help="held-out scenarios for the surrogate leg (0 = skip)")
     ap.add_argument("--surrogate-weights", default=os.path.join(
         ROOT, "paper_1909_05098_amd", "weights", "surrogate_g64.npy"))
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="run only the surrogate leg and print its result (for profiling "
+                         "its kernels); not a benchmark line")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for "
                          "counter calibration) and exit")
@@ -323,7 +337,7 @@ def main():
 
     import numpy as np
     sweep_scns = None
-    if args.sweep and not args.copy_calib_gib:
+    if args.sweep and not args.copy_calib_gib and not args.surrogate_only:
         t0 = time.perf_counter()
         sweep_scns = gen_sweep(range(args.sweep), min(16, os.cpu_count() or 1))
         log(f"sweep meshes: {len(sweep_scns)} scenarios "
@@ -345,6 +359,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_each_way": 4 * n, "launches": 3}))
+        return
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": run_surrogate(sur_scns, args.surrogate_weights)}),
+              flush=True)
         return
 
     from paper_1909_05098_amd import fedfem as ff

@@ -166,6 +166,18 @@ int fedfem_autotune(fedfem_handle *h, const char *cache_path, int32_t flags,
 int fedfem_precompute(fedfem_handle *h);
 
 /*
+ * fedfem_precompute on n distinct handles at once, by `threads` host
+ * threads (0: up to 16, one per core) that each take the next handle:
+ * one scenario's host-side layout overlaps another's device work, each on
+ * its handle's own stream.  rcs (may be NULL) receives each handle's return
+ * code; the function returns the first nonzero one in handle order, else
+ * FEDFEM_OK.  A NULL or repeated handle gives FEDFEM_E_INVALID before any
+ * work starts.  The handles must not be used by other threads meanwhile.
+ */
+int fedfem_precompute_many(fedfem_handle *const *handles, int32_t n,
+                           int32_t threads, int32_t *rcs);
+
+/*
  * Advance n_steps explicit steps (Algorithm 1, time-stepping block;
  * Eq 13, 17, 11, 19).  source is a nodal heat flow Q_r [W] per node
  * (length n_nodes, caller's numbering); when non-NULL it replaces the active
@@ -250,6 +262,15 @@ int fedfem_destroy(fedfem_handle *h);
 
 /* Text for a return code, and the handle's last error message. */
 const char *fedfem_strerror(int code);
+
+/*
+ * Device blocks freed by destroyed handles and batches are kept by the
+ * library for reuse (per device and size class, up to FEDFEM_DEVICE_CACHE_MB
+ * megabytes, default 16384; 0 disables the cache).  This returns every
+ * cached block to the device and gives the number of bytes released.
+ * Thread-safe.
+ */
+size_t fedfem_release_cached_memory(void);
 int fedfem_last_error(const fedfem_handle *h, char *buf, size_t len);
 
 /* ---- batched execution ------------------------------------------------- */

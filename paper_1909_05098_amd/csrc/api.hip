@@ -3,9 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <system_error>
+#include <thread>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -182,23 +187,33 @@ template <typename T>
 int dalloc(fedfem_handle* h, T** p, size_t count) {
     void* q = nullptr;
     const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-    hipError_t e = hipMalloc(&q, bytes);
+    size_t granted = 0;
+    hipError_t e = cached_malloc(&q, bytes, &granted);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return set_err(h, FEDFEM_E_NOMEM, "device allocation of %zu bytes failed", bytes);
     }
-    h->allocs.push_back(q);
-    h->dev_bytes += (int64_t)bytes;
+    h->allocs.emplace_back(q, granted);
+    h->dev_bytes += (int64_t)granted;
     *p = static_cast<T*>(q);
     return FEDFEM_OK;
 }
 
+// the handle's streams are idle before a block goes back to the cache
+void quiesce(fedfem_handle* h) {
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->own_stream && h->own_stream != h->stream) (void)hipStreamSynchronize(h->own_stream);
+}
+
 void dfree(fedfem_handle* h, void* p) {
     if (!p) return;
-    auto it = std::find(h->allocs.begin(), h->allocs.end(), p);
+    auto it = std::find_if(h->allocs.begin(), h->allocs.end(),
+                           [p](const std::pair<void*, size_t>& a) { return a.first == p; });
     if (it != h->allocs.end()) {
+        quiesce(h);
+        h->dev_bytes -= (int64_t)it->second;
+        cached_free(it->first, it->second);
         h->allocs.erase(it);
-        (void)hipFree(p);
     }
 }
 
@@ -349,7 +364,8 @@ int lanczos(fedfem_handle* h, const double* coef64) {
 
 int release_device(fedfem_handle* h) {
     drop_graphs(h);
-    for (void* p : h->allocs) (void)hipFree(p);
+    quiesce(h);
+    for (auto& a : h->allocs) cached_free(a.first, a.second);
     h->allocs.clear();
     h->dev_bytes = 0;
     h->d = DevLayout();
@@ -474,12 +490,33 @@ int fedfem_set_options(fedfem_handle* h, const fedfem_options* o) {
     return FEDFEM_OK;
 }
 
+// Wall-clock phases of fedfem_precompute, printed to stderr when the
+// environment variable FEDFEM_TRACE is set (diagnostics only).
+struct PhaseClock {
+    bool on = std::getenv("FEDFEM_TRACE") != nullptr;
+    std::chrono::steady_clock::time_point last = std::chrono::steady_clock::now();
+    std::string line;
+    void mark(const char* name) {
+        if (!on) return;
+        const auto now = std::chrono::steady_clock::now();
+        char buf[64];
+        std::snprintf(buf, sizeof buf, " %s %.2f", name,
+                      std::chrono::duration<double, std::milli>(now - last).count());
+        line += buf;
+        last = now;
+    }
+    void print(int64_t E) const {
+        if (on) std::fprintf(stderr, "[fedfem] precompute E=%lld ms:%s\n", (long long)E, line.c_str());
+    }
+};
+
 int fedfem_precompute(fedfem_handle* h) {
     int rc = check_handle(h, false);
     if (rc) return rc;
     if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "already precomputed");
     release_device(h);
     const int64_t N = h->N, E = h->E;
+    PhaseClock clk;
     int lds_attr = 0;
     HIPCHK(h, hipDeviceGetAttribute(&lds_attr, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                     h->device));
@@ -503,6 +540,7 @@ int fedfem_precompute(fedfem_handle* h) {
     } catch (const std::bad_alloc&) {
         return set_err(h, FEDFEM_E_NOMEM, "host allocation failed");
     }
+    clk.mark("layout");
     hipStream_t s = h->own_stream;
     DevLayout& d = h->d;
     d.N = N;
@@ -534,6 +572,7 @@ int fedfem_precompute(fedfem_handle* h) {
         if ((rc = upload(h, &h->d_isdir, isd)) || (rc = upload(h, &h->d_dirT, dT))) return rc;
         h->host_isdir.swap(isd);
     }
+    clk.mark("upload");
     // geometry (Eq 15-16)
     double* coef64 = nullptr;
     int32_t* bad = nullptr;
@@ -554,6 +593,7 @@ int fedfem_precompute(fedfem_handle* h) {
         release_device(h);
         return set_err(h, FEDFEM_E_DEGENERATE, "degenerate tetrahedron %d", hbad);
     }
+    clk.mark("geometry");
     HIPCHK(h, launch_lump(N, h->d_ec_off, h->d_ec, h->d_vol, h->d_Vi, s));
     // fixed-point scales: the largest possible corner load maps below 2^58
     {
@@ -612,6 +652,7 @@ int fedfem_precompute(fedfem_handle* h) {
     HIPCHK(h, launch_node_init(N, h->d_Vi, h->d_isdir, h->d_dirT, h->T0, h->fp32c, d.u, d.T_[0],
                                d.T_[1], s));
     HIPCHK(h, launch_set_source(N, nullptr, nullptr, h->fp32c, d.q, s));
+    clk.mark("scales+init");
     // critical step (Eq 9): top eigenvalue of the geometry pencil on free
     // nodes, bounded over the property window
     if (h->timing_trial) {
@@ -624,6 +665,7 @@ int fedfem_precompute(fedfem_handle* h) {
         h->lam_geo = h->lam_ritz = 0.0;
         h->lz_iters = 0;
     }
+    clk.mark("lanczos");
     if (h->fp32c) dfree(h, coef64);
     double kmin, kmax, rcmin, rcmax;
     window_bounds(h->mat, &kmin, &kmax, &rcmin, &rcmax);
@@ -658,12 +700,50 @@ int fedfem_precompute(fedfem_handle* h) {
     h->steps = 0;
     h->cur = 0;
     h->precomputed = true;
+    clk.mark("finish");
+    clk.print(E);
     // host copies of the big arrays are no longer needed
     std::vector<double>().swap(L.xyz);
     std::vector<int32_t>().swap(L.conn);
     std::vector<uint16_t>().swap(L.lconn);
     std::vector<int32_t>().swap(L.ec);
     return FEDFEM_OK;
+}
+
+int fedfem_precompute_many(fedfem_handle* const* handles, int32_t n, int32_t threads,
+                           int32_t* rcs) {
+    if (!handles || n < 0 || threads < 0) return FEDFEM_E_INVALID;
+    {
+        std::unordered_set<const fedfem_handle*> seen;
+        for (int32_t j = 0; j < n; j++)
+            if (!handles[j] || !seen.insert(handles[j]).second) return FEDFEM_E_INVALID;
+    }
+    std::vector<int> res(n, FEDFEM_OK);
+    std::atomic<int32_t> next{0};
+    auto work = [&] {
+        for (;;) {
+            const int32_t j = next.fetch_add(1);
+            if (j >= n) break;
+            res[j] = fedfem_precompute(handles[j]);
+        }
+    };
+    int32_t nt = threads > 0 ? threads
+                             : (int32_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nt = std::max<int32_t>(1, std::min(nt, n));
+    std::vector<std::thread> pool;
+    try {
+        for (int32_t t = 1; t < nt; t++) pool.emplace_back(work);
+    } catch (const std::system_error&) {
+        // fewer workers than asked: the remaining ones share the work
+    }
+    work();
+    for (auto& t : pool) t.join();
+    int first = FEDFEM_OK;
+    for (int32_t j = 0; j < n; j++) {
+        if (rcs) rcs[j] = res[j];
+        if (first == FEDFEM_OK && res[j] != FEDFEM_OK) first = res[j];
+    }
+    return first;
 }
 
 int fedfem_set_source(fedfem_handle* h, const double* source) {

@@ -33,7 +33,7 @@ struct fedfem_batch {
     int32_t *tile_list = nullptr, *tile_scen = nullptr;
     int32_t *block_list = nullptr, *block_scen = nullptr, *flags = nullptr;
     void* props = nullptr;
-    std::vector<void*> allocs;
+    std::vector<std::pair<void*, size_t>> allocs;  // device blocks and their sizes
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
@@ -44,9 +44,10 @@ namespace {
 template <typename T>
 hipError_t balloc(fedfem_batch* b, T** p, size_t count) {
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(16, count * sizeof(T)));
+    size_t granted = 0;
+    hipError_t e = cached_malloc(&q, std::max<size_t>(16, count * sizeof(T)), &granted);
     if (e != hipSuccess) return e;
-    b->allocs.push_back(q);
+    b->allocs.emplace_back(q, granted);
     *p = static_cast<T*>(q);
     return hipSuccess;
 }
@@ -63,7 +64,7 @@ void destroy_batch(fedfem_batch* b) {
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (void* p : b->allocs) (void)hipFree(p);
+    for (auto& a : b->allocs) cached_free(a.first, a.second);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->stream) (void)hipStreamDestroy(b->stream);

@@ -34,7 +34,7 @@ struct fedfem_handle {
     std::string err;
     fedfem::Layout L;
     fedfem::DevLayout d;
-    std::vector<void*> allocs;
+    std::vector<std::pair<void*, size_t>> allocs;  // device blocks and their sizes
     int64_t dev_bytes = 0;
     int64_t n_dir = 0;
     std::vector<int32_t> host_isdir;  // internal order

@@ -53,6 +53,12 @@ bool build_tiles(Layout& L, int tile_elems, int max_tile_nodes,
 // Morton (Z-order) permutation of points; returns new -> old.
 std::vector<int32_t> morton_order(const double* pts, int64_t n);
 
+// Caching device allocator (devcache.cpp): blocks come from per-device free
+// lists when one of the right size class is there; `granted` is the block's
+// class size, to be handed back to cached_free once no stream uses it.
+hipError_t cached_malloc(void** p, size_t bytes, size_t* granted);
+void cached_free(void* p, size_t granted);
+
 // ---------------------------------------------------------------------------
 // Material parameters as the kernels see them.
 // ---------------------------------------------------------------------------

@@ -80,6 +80,8 @@ _SIGS = {
     "fedfem_create": (C.c_int, [_P, _P, _P, _P]),
     "fedfem_set_options": (C.c_int, [_P, _P]),
     "fedfem_precompute": (C.c_int, [_P]),
+    "fedfem_precompute_many": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    "fedfem_release_cached_memory": (C.c_size_t, []),
     "fedfem_step": (C.c_int, [_P, C.c_int64, _P]),
     "fedfem_prepare": (C.c_int, [_P, C.c_int64]),
     "fedfem_set_source": (C.c_int, [_P, _P]),
@@ -289,6 +291,26 @@ class Handle:
         self._check(self._L.fedfem_time_kernels(self._h, int(n_steps), C.byref(a),
                                                 C.byref(b)), "fedfem_time_kernels")
         return a.value, b.value
+
+
+def precompute_many(handles, threads=0):
+    """fedfem_precompute on all handles, overlapped on host threads."""
+    hs = list(handles)
+    if not hs:
+        return
+    L = load()
+    arr = (C.c_void_p * len(hs))(*[h._h.value for h in hs])
+    rcs = np.zeros(len(hs), dtype=np.int32)
+    rc = L.fedfem_precompute_many(arr, len(hs), int(threads), _ptr(rcs))
+    if rc != OK:
+        j = int(np.nonzero(rcs)[0][0]) if np.any(rcs) else -1
+        msg = hs[j].last_error() if j >= 0 else ""
+        raise FedFemError(rc, f"fedfem_precompute_many: handle {j}: {msg}")
+
+
+def release_cached_memory():
+    """Return the library's cached device blocks; gives the bytes released."""
+    return int(load().fedfem_release_cached_memory())
 
 
 class Batch:

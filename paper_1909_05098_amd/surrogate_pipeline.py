@@ -54,19 +54,22 @@ def steps_for(t_end, dt_cr, fraction=0.9):
 
 
 # -- FED-FEM fields on the grid ---------------------------------------------
-def fem_handles(scns, tune_cache=None):
+def fem_handles(scns, tune_cache=None, threads=0):
+    """Created and precomputed handles (precompute overlapped on host threads)
+    with their sources and step counts."""
     hs, ns = [], []
     for s in scns:
         h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=-0.9,
                       precision=ff.FP32C)
         if tune_cache:
             h.autotune(tune_cache, for_batch=True)
-        h.precompute()
+        hs.append(h)
+    ff.precompute_many(hs, threads)
+    for h, s in zip(hs, scns):
         h.set_gaussian_sources(s.sources, s.source_mode)
         _, dtcr = h.dt()
         n, dt = steps_for(s.t_end, dtcr)
         h.set_dt(dt)
-        hs.append(h)
         ns.append(n)
     return hs, ns
 

@@ -44,6 +44,14 @@ def test_strerror_and_null_handling():
     assert L.fedfem_create(None, None, None, None) == ff.E_INVALID
     assert L.fedfem_step(None, 1, None) == ff.E_INVALID
     assert L.fedfem_precompute(None) == ff.E_INVALID
+    # precompute_many checks its arguments before any device work
+    L.fedfem_precompute_many.argtypes = [C.c_void_p, C.c_int32, C.c_int32,
+                                         C.c_void_p]
+    arr = (C.c_void_p * 2)(None, None)
+    assert L.fedfem_precompute_many(arr, 2, 0, None) == ff.E_INVALID
+    assert L.fedfem_precompute_many(None, 1, 0, None) == ff.E_INVALID
+    assert L.fedfem_precompute_many(arr, -1, 0, None) == ff.E_INVALID
+    assert L.fedfem_precompute_many(arr, 0, 0, None) == ff.OK
 
 
 def _mat():

@@ -86,3 +86,67 @@ def test_batch_rejects_mixed_or_unprepared(scenarios):
     assert ei.value.code == ff.E_NOT_PRECOMPUTED
     with pytest.raises(ff.FedFemError):
         ff.Batch([h, h])
+
+
+def test_precompute_many_equals_sequential_and_reports_errors(scenarios):
+    """Precompute overlapped on host threads gives every handle exactly what
+    its own precompute gives (critical step, then 20 steps bit for bit), and
+    a degenerate mesh among them is reported at its own index."""
+    seq, par = [], []
+    for s, _, _, _, _ in scenarios:
+        h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=-0.9,
+                      precision=ff.FP32C)
+        h.precompute()
+        seq.append(h)
+        par.append(ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=-0.9,
+                             precision=ff.FP32C))
+    ff.precompute_many(par, threads=4)
+    for (s, _, _, _, _), a, b in zip(scenarios, seq, par):
+        assert a.dt() == b.dt()
+        for h in (a, b):
+            h.set_gaussian_sources(s.sources, s.source_mode)
+            h.step(20)
+        assert np.array_equal(a.read_state()[0], b.read_state()[0])
+    for h in seq + par:
+        h.close()
+    # a flattened tet in the third scenario
+    hs = []
+    for k, (s, _, _, _, _) in enumerate(scenarios[:4]):
+        xyz = s.xyz.copy()
+        if k == 2:
+            t = s.tets[11]
+            xyz[t[3]] = (xyz[t[0]] + xyz[t[1]] + xyz[t[2]]) / 3.0
+        hs.append(ff.Handle(xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=-0.9,
+                            precision=ff.FP32C))
+    with pytest.raises(ff.FedFemError) as ei:
+        ff.precompute_many(hs, threads=3)
+    assert ei.value.code == ff.E_DEGENERATE
+    assert "handle 2:" in str(ei.value)
+    for h in hs:
+        h.close()
+
+
+def test_recycled_device_memory_gives_identical_results(scenarios):
+    """Handles built on blocks recycled by the library's device cache (left
+    dirty by other scenarios) step exactly as on fresh memory."""
+    ff.release_cached_memory()
+
+    def run(s):
+        h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=-0.9,
+                      precision=ff.FP32C)
+        h.precompute()
+        h.set_gaussian_sources(s.sources, s.source_mode)
+        h.step(30)
+        out = (h.dt(), h.read_state()[0])
+        h.close()
+        return out
+
+    s0 = scenarios[0][0]
+    fresh = run(s0)
+    for s, _, _, _, _ in scenarios[1:]:
+        run(s)  # leaves its blocks, dirty, in the cache
+    recycled = run(s0)
+    assert fresh[0] == recycled[0]
+    assert np.array_equal(fresh[1], recycled[1])
+    assert ff.release_cached_memory() > 0
+    assert ff.release_cached_memory() == 0
