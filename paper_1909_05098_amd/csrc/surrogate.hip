@@ -91,9 +91,9 @@ __global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
         for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kg = (lane >> 4) * 8;
     const int K = (a.ks == 3 ? 27 : 1) * a.cin;
-    for (int kc = 0; kc < a.kp; kc += 32) {
+    // operands of K-step kc: the gathered input (A) and the weights (B)
+    auto load = [&](int kc, bf16x8 (&A)[4], bf16x8 (&B)[NT]) {
         const int k = kc + kg;
-        bf16x8 A[4];
         if (k < K) {
             const int off = k / a.cin;
             const int ci = k - off * a.cin;
@@ -119,19 +119,31 @@ __global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
 #pragma unroll
             for (int mt = 0; mt < 4; mt++) A[mt] = zero8();
         }
-        bf16x8 B[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
             const int co = n0 + nt * 16 + (lane & 15);
             B[nt] = co < a.cout ? *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k)
                                 : zero8();
         }
+    };
+    bf16x8 A[4], B[NT];
+    load(0, A, B);
+    for (int kc = 0; kc < a.kp; kc += 32) {
+        // the next K-step's loads are in flight while this one multiplies
+        bf16x8 An[4], Bn[NT];
+        if (kc + 32 < a.kp) load(kc + 32, An, Bn);
 #pragma unroll
         for (int mt = 0; mt < 4; mt++)
 #pragma unroll
             for (int nt = 0; nt < NT; nt++)
                 acc[mt][nt] =
                     __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+        if (kc + 32 < a.kp) {
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) B[nt] = Bn[nt];
+        }
     }
     // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
 #pragma unroll
