@@ -164,7 +164,132 @@ __global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
         }
 }
 
+// LDS-staged 3x3x3 convolution for cin % 32 == 0 and G >= 8.  A workgroup
+// owns a brick of 256 voxels of one sample (BX x BY x BZ, x fastest) and
+// walks the input channels 32 at a time: it stages the brick and its one-
+// voxel halo (32 channels, rows padded to 80 bytes) in LDS, then for each of
+// the 27 offsets every wave reads its four 16-voxel A fragments from LDS
+// (K = the 32 channels of that offset) and the weights from global memory
+// (shared by all waves, so mostly cache hits).  Each wave computes 64
+// voxels x (16 NT) output channels; blockIdx.y selects 64 output channels.
+constexpr int kHaloMax = 720;  // (2+2) x (8+2) x (16+2)
+constexpr int kHaloPitch = 40;  // 32 channels + 8 pad (bf16)
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, int BZ) {
+    __shared__ __align__(16) bf16 halo[kHaloMax][kHaloPitch];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int G = a.G;
+    const int HX = BX + 2, HY = BY + 2, HZ = BZ + 2, H = HX * HY * HZ;
+    const int nbx = G / BX, nby = G / BY, nbz = G / BZ;
+    int64_t id = blockIdx.x;
+    const int bx = (int)(id % nbx), by = (int)((id / nbx) % nby),
+              bz = (int)((id / ((int64_t)nbx * nby)) % nbz);
+    const int64_t bs = id / ((int64_t)nbx * nby * nbz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
+    const int n0 = blockIdx.y * 64;
+    // this lane's four voxels (rows lane % 16 of the wave's four M tiles)
+    int hv[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+        const int li = wave * 64 + mt * 16 + (lane & 15);
+        const int lx = li % BX, ly = (li / BX) % BY, lz = li / (BX * BY);
+        hv[mt] = ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1);  // halo index of offset 0
+    }
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kg = (lane >> 4) * 8;
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        __syncthreads();  // the previous chunk's fragments have been read
+#pragma unroll 4
+        for (int q = t; q < H * 4; q += 256) {
+            const int h = q >> 2, part = (q & 3) * 8;
+            const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+            bf16x8 v = zero8();
+            if (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
+                const int64_t gv = ((bs * G + z) * G + y) * G + x;
+                v = *reinterpret_cast<const bf16x8*>(a.in + gv * a.ip + a.io + c0 + part);
+            }
+            *reinterpret_cast<bf16x8*>(&halo[h][part]) = v;
+        }
+        __syncthreads();
+        // fragments of offset `off`: A from the halo, B (weights) from memory
+        auto load = [&](int off, bf16x8 (&A)[4], bf16x8 (&B)[NT]) {
+            const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
+            const int dh = (dz * HY + dy) * HX + dx;
+            const int k = off * a.cin + c0 + kg;
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) {
+                const int co = n0 + nt * 16 + (lane & 15);
+                B[nt] = co < a.cout
+                            ? *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k)
+                            : zero8();
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+                A[mt] = *reinterpret_cast<const bf16x8*>(&halo[hv[mt] + dh][kg]);
+        };
+        bf16x8 A[4], B[NT];
+        load(0, A, B);
+#pragma unroll 3
+        for (int off = 0; off < 27; off++) {
+            // the next offset's fragments are in flight while this one multiplies
+            bf16x8 An[4], Bn[NT];
+            if (off + 1 < 27) load(off + 1, An, Bn);
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++)
+                    acc[mt][nt] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+            if (off + 1 < 27) {
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) B[nt] = Bn[nt];
+            }
+        }
+    }
+    // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int co = n0 + nt * 16 + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int li = wave * 64 + mt * 16 + (lane >> 4) * 4 + i;
+                const int lx = li % BX, ly = (li / BX) % BY, lz = li / (BX * BY);
+                const int64_t v = ((bs * G + z0 + lz) * G + y0 + ly) * G + x0 + lx;
+                float val = acc[mt][nt][i] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                a.out[v * a.op + a.oo + co] = (bf16)val;
+            }
+        }
+}
+
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
+    const int G = a.G;
+    if (a.ks == 3 && a.cin % 32 == 0 && G >= 8 && (G & (G - 1)) == 0) {
+        // bricks of 256 voxels: 16 x 8 x 2, or 8 x 8 x 4 on an 8^3 grid
+        const int BX = G >= 16 ? 16 : 8, BY = 8, BZ = 256 / (BX * BY);
+        const int64_t G3 = (int64_t)G * G * G;
+        const int64_t nsamp = a.V / G3;
+        const dim3 grid((unsigned)(nsamp * (G3 / 256)), (unsigned)((a.cout + 63) / 64));
+        if (a.cout <= 16)
+            hipLaunchKernelGGL(k_conv_lds<1>, grid, dim3(256), 0, s, a, BX, BY, BZ);
+        else if (a.cout <= 32)
+            hipLaunchKernelGGL(k_conv_lds<2>, grid, dim3(256), 0, s, a, BX, BY, BZ);
+        else
+            hipLaunchKernelGGL(k_conv_lds<4>, grid, dim3(256), 0, s, a, BX, BY, BZ);
+        return hipGetLastError();
+    }
     const dim3 grid(nblocks(a.V, 256), (unsigned)((a.cout + 63) / 64));
     if (a.cout <= 16)
         hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, a);
