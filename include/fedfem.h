@@ -166,6 +166,26 @@ int fedfem_autotune(fedfem_handle *h, const char *cache_path, int32_t flags,
 int fedfem_precompute(fedfem_handle *h);
 
 /*
+ * Temperature-dependent properties from tables (Eq 2; Sec 3.1.6 gives the
+ * tissue's density, conductivity and specific heat at two temperatures and
+ * interpolates linearly): n points (T [degC] strictly increasing, value > 0)
+ * per property, interpolated linearly and held constant outside the table
+ * (the constant extension used for the clamped linear laws).  n = 0 keeps
+ * the material's linear law for that property (k0 + dk_dT (T - T_ref) on
+ * [T_lo, T_hi], and likewise rho, c).  k(T) enters the element loads
+ * (Eq 13: nodal k averaged over the element), rho(T) c(T) the lumped
+ * capacity (Eq 19), and the critical step (Eq 9) uses the largest k and the
+ * smallest rho c over all temperatures.  Must precede fedfem_precompute
+ * (FEDFEM_E_STATE after); at most FEDFEM_MAX_TABLE points per table.
+ */
+#define FEDFEM_MAX_TABLE 16
+int fedfem_set_property_tables(fedfem_handle *h, int32_t n_k, const double *T_k,
+                               const double *k, int32_t n_rho,
+                               const double *T_rho, const double *rho,
+                               int32_t n_c, const double *T_c,
+                               const double *c);
+
+/*
  * fedfem_precompute on n distinct handles at once, by `threads` host
  * threads (0: up to 16, one per core) that each take the next handle:
  * one scenario's host-side layout overlaps another's device work, each on
@@ -214,6 +234,40 @@ int fedfem_set_gaussian_sources(fedfem_handle *h, int32_t n_src,
 
 /* Copy the active nodal source [W] to host memory (length n_nodes). */
 int fedfem_read_source(fedfem_handle *h, double *out);
+
+/*
+ * Time-varying sources on the device (Algorithm 1 applies the external heat
+ * at every step; Sec 3.1.5 heats, then lets the tissue relax).  Pattern p is
+ * a nodal heat-flow vector Q_p [W] in caller order (patterns: [n][N]); its
+ * amplitude a_p(t) is piecewise linear through the points (times, amps) of
+ * that pattern (n_points[p] points each, concatenated over the patterns,
+ * times non-decreasing), constant before the first and after the last
+ * point; where a time repeats, the last point given at it holds from that
+ * time on, so a jump is two points at the same time.  Step n, from t_n to
+ * t_n + dt, uses the source  q + sum_p a_p(t_n) Q_p,  where q is the source
+ * of fedfem_set_source / fedfem_step and t_n the handle's time at the start
+ * of the step (fedfem_get_time).  Amplitudes are evaluated in FP64 on the
+ * host per graph chunk and applied in the working precision by the nodal
+ * update.  n_patterns = 0 removes the schedule.  Requires a precomputed
+ * handle; a batch refuses handles with a schedule (FEDFEM_E_STATE).
+ */
+#define FEDFEM_MAX_PATTERNS 4
+int fedfem_set_schedule(fedfem_handle *h, int32_t n_patterns,
+                        const double *patterns, const int32_t *n_points,
+                        const double *times, const double *amps);
+
+/*
+ * Nodal loads of a prescribed surface heat flux on Gamma_H (Eq 4): each
+ * triangle f = faces[3f..3f+2] (caller node ids, three distinct) with flux
+ * flux[f] [W/m^2] into the body gives each of its three nodes
+ * flux[f] |f| / 3, the integral of the flux against the linear shape
+ * functions over the face.  out [N] (host, caller order) receives the
+ * nodal sums [W], ready for fedfem_set_source or a schedule pattern.  Face
+ * areas are computed on the device in FP64 and summed per node in ascending
+ * face order.
+ */
+int fedfem_flux_loads(fedfem_handle *h, int64_t n_faces, const int32_t *faces,
+                      const double *flux, double *out);
 
 /* Blocking copy of the nodal temperatures (hi + lo in double) to host. */
 int fedfem_read_T(fedfem_handle *h, double *T_out);

@@ -30,7 +30,27 @@ class _Problem(C.Structure):
                 ("mat", C.c_void_p), ("is_dir", C.c_void_p),
                 ("T_dir", C.c_void_p), ("q", C.c_void_p),
                 ("csr_off", C.c_void_p), ("csr_ec", C.c_void_p),
-                ("dt", C.c_double), ("n_threads", C.c_int)]
+                ("dt", C.c_double), ("n_threads", C.c_int), ("tabs", C.c_void_p)]
+
+MAX_TAB = 16
+TAB_NAMES = ("k", "rho", "c")
+
+
+def table_array(tables):
+    """Property tables {name: (T, values)} -> the oracle's flat layout
+    [3][count, MAX_TAB temperatures, MAX_TAB values] (None if empty)."""
+    if not tables:
+        return None
+    out = np.zeros(3 * (1 + 2 * MAX_TAB))
+    for p, name in enumerate(TAB_NAMES):
+        if name in tables and tables[name] is not None:
+            T, V = (np.asarray(a, dtype=np.float64) for a in tables[name])
+            assert 1 <= len(T) == len(V) <= MAX_TAB and np.all(np.diff(T) > 0)
+            b = p * (1 + 2 * MAX_TAB)
+            out[b] = len(T)
+            out[b + 1:b + 1 + len(T)] = T
+            out[b + 1 + MAX_TAB:b + 1 + MAX_TAB + len(V)] = V
+    return out
 
 
 def lib():
@@ -76,13 +96,15 @@ class OracleModel:
     """Precomputed FED-FEM model (Algorithm 1, pre-computation block)."""
 
     def __init__(self, xyz, tets, materials, dir_nodes=(), dir_T=(),
-                 n_threads=0):
+                 n_threads=0, tables=None):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.tets = np.ascontiguousarray(tets, dtype=np.int32)
         self.N = len(self.xyz)
         self.E = len(self.tets)
         self.n_threads = int(n_threads)
         self.mat = mat_vector(materials)
+        self.tables = dict(tables) if tables else None
+        self.tabs = table_array(self.tables)
         L = lib()
         self.A = np.empty((self.E, 4, 4))
         self.vol = np.empty(self.E)
@@ -140,7 +162,8 @@ class OracleModel:
                         None if self._q_keep is None else
                         _p(self._q_keep).value,
                         _p(self.csr_off).value, _p(self.csr_ec).value,
-                        float(self.dt), self.n_threads)
+                        float(self.dt), self.n_threads,
+                        None if self.tabs is None else _p(self.tabs).value)
 
     def step(self, T, q=None):
         """One step; returns (T_next, F, C) with F the assembled loads."""
@@ -162,6 +185,21 @@ class OracleModel:
             raise MemoryError("oracle_run failed")
         return T
 
+    def run_schedule(self, T, n_steps, patterns, schedules, q=None, t0=0.0):
+        """n_steps steps where step n (starting at t_n = t0 + n dt) uses the
+        source q + sum_p a_p(t_n) Q_p (Algorithm 1 applies the external heat
+        at every step); a copy of T is returned."""
+        T = np.array(T, dtype=np.float64, copy=True)
+        base = np.zeros(self.N) if q is None else np.asarray(q, dtype=np.float64)
+        pats = [np.asarray(Q, dtype=np.float64) for Q in patterns]
+        for n in range(int(n_steps)):
+            t = t0 + n * self.dt
+            qn = base.copy()
+            for Q, (ts, am) in zip(pats, schedules):
+                qn += schedule_amplitude(ts, am, t) * Q
+            T = self.step(T, qn)[0]
+        return T
+
     def initial(self, T0):
         T = np.full(self.N, float(T0))
         T[self.is_dir.astype(bool)] = self.T_dir[self.is_dir.astype(bool)]
@@ -175,6 +213,35 @@ class OracleModel:
     def dt_cr(self, method="auto"):
         from . import dense
         return dense.critical_dt(self, method=method)
+
+
+def schedule_amplitude(times, amps, t):
+    """Piecewise-linear amplitude through the points (times[k], amps[k]):
+    amps[0] before the first time, amps[-1] from the last time on, and where
+    a time repeats, the last point given at it holds from that time on."""
+    if t < times[0]:
+        return float(amps[0])
+    k = 0
+    while k + 1 < len(times) and times[k + 1] <= t:
+        k += 1
+    if k + 1 == len(times):
+        return float(amps[-1])
+    w = (t - times[k]) / (times[k + 1] - times[k])
+    return float(amps[k] + w * (amps[k + 1] - amps[k]))
+
+
+def flux_loads(xyz, faces, flux):
+    """Nodal loads of a surface heat flux (Eq 4): triangle f with flux q_f
+    [W/m^2] gives each of its nodes q_f |f| / 3, |f| = |(b - a) x (c - a)| / 2."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    faces = np.asarray(faces, dtype=np.int64).reshape(-1, 3)
+    flux = np.asarray(flux, dtype=np.float64).reshape(-1)
+    out = np.zeros(len(xyz))
+    for f, (a, b, c) in enumerate(faces):
+        area = 0.5 * np.linalg.norm(np.cross(xyz[b] - xyz[a], xyz[c] - xyz[a]))
+        for v in (a, b, c):
+            out[v] += flux[f] * area / 3.0
+    return out
 
 
 def quadrature_points():

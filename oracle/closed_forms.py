@@ -97,3 +97,39 @@ def kirchhoff_slab(x, L, T_left, T_right, k0, beta, T_r):
 def gaussian_total_power(Q0, sigma):
     """Integral of Q0 exp(-r^2 / (2 sigma^2)) over R^3."""
     return Q0 * (2.0 * np.pi) ** 1.5 * sigma**3
+
+
+def kirchhoff_slab_table(x, L, T_left, T_right, Tk, kv):
+    """Steady 1-D conduction with k(T) piecewise linear through (Tk, kv),
+    constant outside.  U(T) = integral of k from Tk[0] is piecewise
+    quadratic; U'' = 0 makes U linear in x between its boundary values, and
+    each U is inverted on the piece where it falls."""
+    Tk = np.asarray(Tk, dtype=np.float64)
+    kv = np.asarray(kv, dtype=np.float64)
+    # U at the table points (exact for piecewise-linear k)
+    Uk = np.concatenate([[0.0], np.cumsum(0.5 * (kv[1:] + kv[:-1]) * np.diff(Tk))])
+
+    def U(T):
+        if T <= Tk[0]:
+            return kv[0] * (T - Tk[0])
+        if T >= Tk[-1]:
+            return Uk[-1] + kv[-1] * (T - Tk[-1])
+        j = np.searchsorted(Tk, T, side="right") - 1
+        s = (kv[j + 1] - kv[j]) / (Tk[j + 1] - Tk[j])
+        d = T - Tk[j]
+        return Uk[j] + kv[j] * d + 0.5 * s * d * d
+
+    def U_inv(u):
+        if u <= 0.0:
+            return Tk[0] + u / kv[0]
+        if u >= Uk[-1]:
+            return Tk[-1] + (u - Uk[-1]) / kv[-1]
+        j = np.searchsorted(Uk, u, side="right") - 1
+        s = (kv[j + 1] - kv[j]) / (Tk[j + 1] - Tk[j])
+        r = u - Uk[j]
+        if s == 0.0:
+            return Tk[j] + r / kv[j]
+        return Tk[j] + (-kv[j] + np.sqrt(kv[j] ** 2 + 2.0 * s * r)) / s
+
+    ua, ub = U(T_left), U(T_right)
+    return np.array([U_inv(ua + (ub - ua) * xi / L) for xi in np.asarray(x)])

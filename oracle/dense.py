@@ -148,8 +148,48 @@ def geometry_lambda_from(n_nodes, tets, A, Vi, is_dir, method="auto"):
     return float(vals[-1])
 
 
-def material_window(m):
-    """(k_max, rhoc_min) of the clamped linear laws over [T_lo, T_hi]."""
+def table_value(T, table):
+    """Linear interpolation in (temperatures, values), constant outside."""
+    t, v = (np.asarray(a, dtype=np.float64) for a in table)
+    return np.interp(T, t, v)
+
+
+def prop_value(T, m, tables, name):
+    """k, rho or c at T: the table when given, else the clamped linear law."""
+    if tables and tables.get(name) is not None:
+        return table_value(T, tables[name])
+    d = _clamp(np.asarray(T, dtype=np.float64), m) - m[M["T_ref"]]
+    p0, dp = {"k": ("k0", "dk_dT"), "rho": ("rho0", "drho_dT"), "c": ("c0", "dc_dT")}[name]
+    return m[M[p0]] + m[M[dp]] * d
+
+
+def material_window(m, tables=None):
+    """(k_max, rhoc_min) over all temperatures.  Every property is piecewise
+    linear, with breakpoints at its table points or its window ends; k peaks
+    at a breakpoint, rho c (quadratic between consecutive breakpoints) at a
+    breakpoint or at the vertex of that quadratic."""
+    if tables:
+        pts = []
+        for name in ("k", "rho", "c"):
+            if tables.get(name) is not None:
+                pts += list(np.asarray(tables[name][0], dtype=np.float64))
+            else:
+                pts += [m[M["T_lo"]], m[M["T_hi"]]]
+        pts = np.unique(np.array(pts))
+        cand = list(pts)
+        for a, b in zip(pts[:-1], pts[1:]):
+            r = prop_value(np.array([a, b]), m, tables, "rho")
+            c = prop_value(np.array([a, b]), m, tables, "c")
+            sr, scc = (r[1] - r[0]) / (b - a), (c[1] - c[0]) / (b - a)
+            if sr * scc != 0.0:
+                x = a - (r[0] * scc + c[0] * sr) / (2.0 * sr * scc)
+                if a < x < b:
+                    cand.append(x)
+        cand = np.array(cand)
+        k = prop_value(cand, m, tables, "k")
+        rc = prop_value(cand, m, tables, "rho") * prop_value(cand, m, tables, "c")
+        return float(np.max(k)), float(np.min(rc))
+    # clamped linear laws over [T_lo, T_hi]
     lo, hi = m[M["T_lo"]], m[M["T_hi"]]
     ts = [lo, hi]
     # rho(T) c(T) is quadratic in T; its vertex may lie inside the window
@@ -163,9 +203,9 @@ def material_window(m):
     return float(np.max(k_of(ts, m))), float(np.min(rho_c_of(ts, m)))
 
 
-def critical_dt_from_lambda(lam_geo, m):
+def critical_dt_from_lambda(lam_geo, m, tables=None):
     """Eq 9 with lambda_max bounded over the property window."""
-    kmax, rcmin = material_window(m)
+    kmax, rcmin = material_window(m, tables)
     lam = lam_geo * kmax / rcmin + m[M["w_b"]] * m[M["c_b"]] / rcmin
     return 2.0 / lam, lam
 
@@ -179,4 +219,4 @@ def geometry_lambda(model, method="auto"):
 
 def critical_dt(model, method="auto"):
     lam = geometry_lambda(model, method)
-    return critical_dt_from_lambda(lam, model.mat)[0]
+    return critical_dt_from_lambda(lam, model.mat, getattr(model, "tables", None))[0]

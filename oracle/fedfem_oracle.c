@@ -65,7 +65,14 @@ typedef struct {
     const int64_t *csr_ec;  /* [4E]  entries e*4+corner, ascending e         */
     double dt;
     int n_threads;
+    const double *tabs;     /* NULL, or property tables (see prop_table)     */
 } oracle_problem;
+
+/* Property tables: for property p (0 k, 1 rho, 2 c) the block
+ * tabs[p * ORACLE_TAB_STRIDE ...] holds the point count n (0 = use the
+ * linear law), then ORACLE_MAX_TAB temperatures, then ORACLE_MAX_TAB values. */
+#define ORACLE_MAX_TAB 16
+#define ORACLE_TAB_STRIDE (1 + 2 * ORACLE_MAX_TAB)
 
 static double clamp_T(double T, const double *m)
 {
@@ -74,16 +81,38 @@ static double clamp_T(double T, const double *m)
     return T;
 }
 
-/* p(T) = p0 + dp/dT (clamp(T) - T_ref) */
-static double prop_k(double T, const double *m)
+/* Linear interpolation in a table of n points (temperatures increasing),
+ * constant beyond its first and last point; returns 0 for n = 0. */
+static int prop_table(const double *tabs, int p, double T, double *out)
 {
+    if (!tabs) return 0;
+    const double *b = tabs + p * ORACLE_TAB_STRIDE;
+    int n = (int)b[0];
+    const double *t = b + 1, *v = b + 1 + ORACLE_MAX_TAB;
+    if (n <= 0) return 0;
+    if (T <= t[0]) { *out = v[0]; return 1; }
+    if (T >= t[n - 1]) { *out = v[n - 1]; return 1; }
+    int k = 0;
+    while (t[k + 1] <= T) k++;
+    *out = v[k] + (v[k + 1] - v[k]) * (T - t[k]) / (t[k + 1] - t[k]);
+    return 1;
+}
+
+/* p(T) = p0 + dp/dT (clamp(T) - T_ref), or the property's table */
+static double prop_k(double T, const double *m, const double *tabs)
+{
+    double v;
+    if (prop_table(tabs, 0, T, &v)) return v;
     return m[M_K0] + m[M_DK] * (clamp_T(T, m) - m[M_TREF]);
 }
 
-static double prop_rho_c(double T, const double *m)
+static double prop_rho_c(double T, const double *m, const double *tabs)
 {
     double Tc = clamp_T(T, m) - m[M_TREF];
-    return (m[M_RHO0] + m[M_DRHO] * Tc) * (m[M_C0] + m[M_DC] * Tc);
+    double rho = m[M_RHO0] + m[M_DRHO] * Tc, c = m[M_C0] + m[M_DC] * Tc;
+    prop_table(tabs, 1, T, &rho);
+    prop_table(tabs, 2, T, &c);
+    return rho * c;
 }
 
 static void set_threads(int n)
@@ -227,7 +256,7 @@ void oracle_step(const oracle_problem *p, const double *T_in, double *T_out,
         double ke = 0.0;
         for (int a = 0; a < 4; a++) {
             Te[a] = T_in[n[a]];
-            ke += prop_k(Te[a], m);
+            ke += prop_k(Te[a], m, p->tabs);
         }
         ke /= 4.0;
         const double *Ae = p->A + 16 * e;
@@ -245,7 +274,7 @@ void oracle_step(const oracle_problem *p, const double *T_in, double *T_out,
         for (int64_t k = p->csr_off[i]; k < p->csr_off[i + 1]; k++)
             Fi += Fe[p->csr_ec[k]];
         double Ti = T_in[i];
-        double Ci = prop_rho_c(Ti, m) * p->Vi[i];
+        double Ci = prop_rho_c(Ti, m, p->tabs) * p->Vi[i];
         if (F) F[i] = Fi;
         if (C) C[i] = Ci;
         if (p->is_dir[i]) {

@@ -80,6 +80,64 @@ void window_bounds(const fedfem_materials& m, double* kmin, double* kmax, double
     }
 }
 
+// Property p (0 k, 1 rho, 2 c) at T: the handle's table if it has one, else
+// the material's clamped linear law.
+double prop_at(const fedfem_handle* h, int p, double T) {
+    const std::vector<double>& t = h->tab_t[p];
+    const std::vector<double>& v = h->tab_v[p];
+    if (!t.empty()) {
+        if (T <= t[0]) return v[0];
+        if (T >= t.back()) return v.back();
+        size_t k = (size_t)(std::upper_bound(t.begin(), t.end(), T) - t.begin()) - 1;
+        return v[k] + (v[k + 1] - v[k]) * (T - t[k]) / (t[k + 1] - t[k]);
+    }
+    const fedfem_materials& m = h->mat;
+    const double d = std::min(std::max(T, m.T_lo), m.T_hi) - m.T_ref;
+    return p == 0 ? m.k0 + m.dk_dT * d : (p == 1 ? m.rho0 + m.drho_dT * d : m.c0 + m.dc_dT * d);
+}
+
+// Extremes of k and rho c over all temperatures for a handle with tables:
+// every property is piecewise linear with breakpoints at its table points
+// (or its window ends), so k peaks at a breakpoint and rho c, quadratic
+// between consecutive breakpoints, at a breakpoint or a vertex.
+void window_bounds_h(const fedfem_handle* h, double* kmin, double* kmax, double* rcmin,
+                     double* rcmax) {
+    bool any = false;
+    for (int p = 0; p < 3; p++) any |= !h->tab_t[p].empty();
+    if (!any) return window_bounds(h->mat, kmin, kmax, rcmin, rcmax);
+    std::vector<double> ts;
+    for (int p = 0; p < 3; p++) {
+        if (h->tab_t[p].empty()) {
+            ts.push_back(h->mat.T_lo);
+            ts.push_back(h->mat.T_hi);
+        } else {
+            ts.insert(ts.end(), h->tab_t[p].begin(), h->tab_t[p].end());
+        }
+    }
+    std::sort(ts.begin(), ts.end());
+    ts.erase(std::unique(ts.begin(), ts.end()), ts.end());
+    std::vector<double> cand = ts;
+    for (size_t i = 0; i + 1 < ts.size(); i++) {
+        const double a = ts[i], b = ts[i + 1];
+        const double r0 = prop_at(h, 1, a), r1 = prop_at(h, 1, b);
+        const double c0 = prop_at(h, 2, a), c1 = prop_at(h, 2, b);
+        const double sr = (r1 - r0) / (b - a), sc = (c1 - c0) / (b - a);
+        if (sr * sc != 0.0) {
+            const double x = a - (r0 * sc + c0 * sr) / (2.0 * sr * sc);
+            if (x > a && x < b) cand.push_back(x);
+        }
+    }
+    *kmin = *rcmin = 1e300;
+    *kmax = *rcmax = -1e300;
+    for (double T : cand) {
+        const double k = prop_at(h, 0, T), rc = prop_at(h, 1, T) * prop_at(h, 2, T);
+        *kmin = std::min(*kmin, k);
+        *kmax = std::max(*kmax, k);
+        *rcmin = std::min(*rcmin, rc);
+        *rcmax = std::max(*rcmax, rc);
+    }
+}
+
 // 2^S with S = 58 - ceil(log2(bound)), kept inside float range: values of
 // magnitude <= bound scale below 2^58.
 double fixed_scale(double bound) {
@@ -249,6 +307,8 @@ Props<float> props_f(const fedfem_handle* h) {
     p.dt = (float)h->dt;
     p.fxs = (float)h->fx_scale;
     p.fxi = (float)(1.0 / h->fx_scale);
+    p.tab = static_cast<const float*>(h->d_tab);
+    for (int k = 0; k < 3; k++) p.nt[k] = h->d_tab ? (int)h->tab_t[k].size() : 0;
     return p;
 }
 
@@ -270,13 +330,25 @@ Props<double> props_d(const fedfem_handle* h) {
     p.dt = h->dt;
     p.fxs = h->fx_scale;
     p.fxi = 1.0 / h->fx_scale;
+    p.tab = static_cast<const double*>(h->d_tab);
+    for (int k = 0; k < 3; k++) p.nt[k] = h->d_tab ? (int)h->tab_t[k].size() : 0;
     return p;
 }
 
-hipError_t launch_one_step(fedfem_handle* h, int cur, hipStream_t s) {
-    const bool td = h->mat.dk_dT != 0.0;
-    if (h->fp32c) return launch_step_f32c(h->d, cur, props_f(h), td, h->d_flag, s);
-    return launch_step_f64(h->d, cur, props_d(h), td, h->d_flag, s);
+hipError_t launch_one_step(fedfem_handle* h, int cur, hipStream_t s, int j) {
+    const bool td = h->mat.dk_dT != 0.0 || !h->tab_t[0].empty();
+    if (h->fp32c) return launch_step_f32c(h->d, cur, props_f(h), td, h->d_flag, s, j);
+    return launch_step_f64(h->d, cur, props_d(h), td, h->d_flag, s, j);
+}
+
+// Amplitude of a schedule at time x: piecewise linear through (t[k], a[k]),
+// constant before the first and after the last point; where times repeat,
+// the last point at that time holds from it on.
+double sched_amp(const std::vector<double>& t, const std::vector<double>& a, double x) {
+    if (x < t[0]) return a[0];
+    const size_t k = (size_t)(std::upper_bound(t.begin(), t.end(), x) - t.begin()) - 1;
+    if (k + 1 >= t.size()) return a.back();
+    return a[k] + (a[k + 1] - a[k]) * (x - t[k]) / (t[k + 1] - t[k]);
 }
 
 int get_graph(fedfem_handle* h, int64_t n, int cur, hipGraphExec_t* out) {
@@ -290,7 +362,7 @@ int get_graph(fedfem_handle* h, int64_t n, int cur, hipGraphExec_t* out) {
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     int c = cur;
     for (int64_t k = 0; k < n; k++) {
-        hipError_t e = launch_one_step(h, c, h->cap_stream);
+        hipError_t e = launch_one_step(h, c, h->cap_stream, (int)k);
         if (e != hipSuccess) {
             hipGraph_t g;
             (void)hipStreamEndCapture(h->cap_stream, &g);
@@ -369,6 +441,7 @@ int release_device(fedfem_handle* h) {
     h->allocs.clear();
     h->dev_bytes = 0;
     h->d = DevLayout();
+    h->d_tab = nullptr;
     return FEDFEM_OK;
 }
 
@@ -613,7 +686,7 @@ int fedfem_precompute(fedfem_handle* h) {
         for (int64_t i = 0; i < N; i++)
             if (!h->host_isdir[i]) vmin = std::min(vmin, Vi[i]);
         double kmin, kmax, rcmin, rcmax;
-        window_bounds(h->mat, &kmin, &kmax, &rcmin, &rcmax);
+        window_bounds_h(h, &kmin, &kmax, &rcmin, &rcmax);
         // loads: k <= kmax, |T_b - T_a| <= 2e4 (both within the divergence limit)
         h->fx_scale = fixed_scale(kmax * amax * 2.0e4);
         // Lanczos: |x| <= 1 / sqrt(min free V_i) for a unit vector
@@ -652,6 +725,30 @@ int fedfem_precompute(fedfem_handle* h) {
     HIPCHK(h, launch_node_init(N, h->d_Vi, h->d_isdir, h->d_dirT, h->T0, h->fp32c, d.u, d.T_[0],
                                d.T_[1], s));
     HIPCHK(h, launch_set_source(N, nullptr, nullptr, h->fp32c, d.q, s));
+    // property tables: times, values and slopes in the working precision
+    if (!h->tab_t[0].empty() || !h->tab_t[1].empty() || !h->tab_t[2].empty()) {
+        std::vector<double> tb(9 * kMaxTab, 0.0);
+        for (int p = 0; p < 3; p++) {
+            const std::vector<double>& t = h->tab_t[p];
+            const std::vector<double>& v = h->tab_v[p];
+            for (size_t k = 0; k < t.size(); k++) {
+                tb[p * 3 * kMaxTab + k] = t[k];
+                tb[p * 3 * kMaxTab + kMaxTab + k] = v[k];
+                if (k + 1 < t.size())
+                    tb[p * 3 * kMaxTab + 2 * kMaxTab + k] = (v[k + 1] - v[k]) / (t[k + 1] - t[k]);
+            }
+        }
+        if (h->fp32c) {
+            std::vector<float> tf(tb.begin(), tb.end());
+            float* dt_ = nullptr;
+            if ((rc = upload(h, &dt_, tf))) return rc;
+            h->d_tab = dt_;
+        } else {
+            double* dt_ = nullptr;
+            if ((rc = upload(h, &dt_, tb))) return rc;
+            h->d_tab = dt_;
+        }
+    }
     clk.mark("scales+init");
     // critical step (Eq 9): top eigenvalue of the geometry pencil on free
     // nodes, bounded over the property window
@@ -668,7 +765,7 @@ int fedfem_precompute(fedfem_handle* h) {
     clk.mark("lanczos");
     if (h->fp32c) dfree(h, coef64);
     double kmin, kmax, rcmin, rcmax;
-    window_bounds(h->mat, &kmin, &kmax, &rcmin, &rcmax);
+    window_bounds_h(h, &kmin, &kmax, &rcmin, &rcmax);
     const double lam = h->lam_geo * kmax / rcmin + h->mat.w_b * h->mat.c_b / rcmin;
     h->dt_cr = lam > 0 ? 2.0 / lam : INFINITY;
     {
@@ -746,6 +843,142 @@ int fedfem_precompute_many(fedfem_handle* const* handles, int32_t n, int32_t thr
     return first;
 }
 
+int fedfem_set_property_tables(fedfem_handle* h, int32_t n_k, const double* T_k,
+                               const double* k, int32_t n_rho, const double* T_rho,
+                               const double* rho, int32_t n_c, const double* T_c,
+                               const double* c) {
+    if (!h) return FEDFEM_E_INVALID;
+    if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "tables must be set before precompute");
+    const int32_t n[3] = {n_k, n_rho, n_c};
+    const double* ts[3] = {T_k, T_rho, T_c};
+    const double* vs[3] = {k, rho, c};
+    static const char* names[3] = {"k", "rho", "c"};
+    for (int p = 0; p < 3; p++) {
+        if (n[p] < 0 || n[p] > FEDFEM_MAX_TABLE || (n[p] > 0 && (!ts[p] || !vs[p])))
+            return set_err(h, FEDFEM_E_INVALID, "table %s: bad point count or NULL", names[p]);
+        if (!finite_all(ts[p], n[p]) || !finite_all(vs[p], n[p]))
+            return set_err(h, FEDFEM_E_INVALID, "table %s: non-finite entry", names[p]);
+        for (int32_t j = 0; j < n[p]; j++) {
+            if (!(vs[p][j] > 0.0))
+                return set_err(h, FEDFEM_E_INVALID, "table %s: values must be positive", names[p]);
+            if (j > 0 && !(ts[p][j] > ts[p][j - 1]))
+                return set_err(h, FEDFEM_E_INVALID, "table %s: temperatures must increase",
+                               names[p]);
+        }
+    }
+    for (int p = 0; p < 3; p++) {
+        h->tab_t[p].assign(ts[p], ts[p] + n[p]);
+        h->tab_v[p].assign(vs[p], vs[p] + n[p]);
+    }
+    return FEDFEM_OK;
+}
+
+int fedfem_set_schedule(fedfem_handle* h, int32_t n_patterns, const double* patterns,
+                        const int32_t* n_points, const double* times, const double* amps) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (n_patterns < 0 || n_patterns > FEDFEM_MAX_PATTERNS)
+        return set_err(h, FEDFEM_E_INVALID, "n_patterns must lie in [0, %d]", FEDFEM_MAX_PATTERNS);
+    if (n_patterns > 0 && (!patterns || !n_points || !times || !amps))
+        return set_err(h, FEDFEM_E_INVALID, "NULL schedule array");
+    const int64_t N = h->N;
+    std::vector<std::vector<double>> st(n_patterns), sa(n_patterns);
+    int64_t off = 0;
+    for (int p = 0; p < n_patterns; p++) {
+        const int32_t m = n_points[p];
+        if (m < 1 || m > (1 << 20)) return set_err(h, FEDFEM_E_INVALID, "pattern %d: bad point count", p);
+        if (!finite_all(times + off, m) || !finite_all(amps + off, m))
+            return set_err(h, FEDFEM_E_INVALID, "pattern %d: non-finite schedule", p);
+        for (int32_t k = 1; k < m; k++)
+            if (times[off + k] < times[off + k - 1])
+                return set_err(h, FEDFEM_E_INVALID, "pattern %d: times decrease", p);
+        st[p].assign(times + off, times + off + m);
+        sa[p].assign(amps + off, amps + off + m);
+        off += m;
+        if (!finite_all(patterns + (int64_t)p * N, N))
+            return set_err(h, FEDFEM_E_INVALID, "pattern %d: non-finite loads", p);
+    }
+    hipStream_t s = h->stream;
+    drop_graphs(h);  // captured steps hold the pattern pointers
+    dfree(h, h->d.pat);
+    dfree(h, h->d.amp);
+    h->d.pat = h->d.amp = nullptr;
+    h->d.n_pat = 0;
+    h->sched_t.clear();
+    h->sched_a.clear();
+    if (n_patterns == 0) return FEDFEM_OK;
+    const size_t rb = h->fp32c ? sizeof(float) : sizeof(double);
+    char* pat = nullptr;
+    char* amp = nullptr;
+    if ((rc = dalloc(h, &pat, rb * (size_t)n_patterns * N)) ||
+        (rc = dalloc(h, &amp, rb * 512 * (size_t)n_patterns)))
+        return rc;
+    for (int p = 0; p < n_patterns; p++) {
+        HIPCHK(h, hipMemcpyAsync(h->d_stage, patterns + (int64_t)p * N, sizeof(double) * N,
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(h, launch_set_source(N, h->d_stage, h->d_nperm, h->fp32c,
+                                    pat + rb * (size_t)p * N, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->d.pat = pat;
+    h->d.amp = amp;
+    h->d.n_pat = n_patterns;
+    h->sched_t.swap(st);
+    h->sched_a.swap(sa);
+    return FEDFEM_OK;
+}
+
+int fedfem_flux_loads(fedfem_handle* h, int64_t n_faces, const int32_t* faces, const double* flux,
+                      double* out) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    const int64_t N = h->N;
+    if (n_faces < 0 || n_faces > INT32_MAX / 3 || !out || (n_faces > 0 && (!faces || !flux)))
+        return set_err(h, FEDFEM_E_INVALID, "bad flux arguments");
+    if (!finite_all(flux, n_faces)) return set_err(h, FEDFEM_E_INVALID, "non-finite flux");
+    std::vector<int32_t> fi(3 * (size_t)n_faces);
+    for (int64_t f = 0; f < n_faces; f++) {
+        for (int c = 0; c < 3; c++) {
+            const int32_t v = faces[3 * f + c];
+            if (v < 0 || v >= N) return set_err(h, FEDFEM_E_INVALID, "face %lld: bad node id", (long long)f);
+            fi[3 * f + c] = h->L.ninv[v];
+        }
+        if (faces[3 * f] == faces[3 * f + 1] || faces[3 * f] == faces[3 * f + 2] ||
+            faces[3 * f + 1] == faces[3 * f + 2])
+            return set_err(h, FEDFEM_E_INVALID, "face %lld repeats a node", (long long)f);
+    }
+    if (n_faces == 0) {
+        std::fill(out, out + N, 0.0);
+        return FEDFEM_OK;
+    }
+    // node -> face corners (3 f + c), ascending face order
+    std::vector<int32_t> foff(N + 1, 0), fidx(3 * (size_t)n_faces);
+    for (size_t k = 0; k < fi.size(); k++) foff[fi[k] + 1]++;
+    for (int64_t i = 0; i < N; i++) foff[i + 1] += foff[i];
+    {
+        std::vector<int32_t> fill(foff.begin(), foff.end() - 1);
+        for (size_t k = 0; k < fi.size(); k++) fidx[fill[fi[k]]++] = (int32_t)k;
+    }
+    std::vector<double> fl(flux, flux + n_faces);
+    hipStream_t s = h->stream;
+    int32_t *d_faces = nullptr, *d_off = nullptr, *d_idx = nullptr;
+    double *d_flux = nullptr, *d_slot = nullptr;
+    if ((rc = upload(h, &d_faces, fi)) || (rc = upload(h, &d_off, foff)) ||
+        (rc = upload(h, &d_idx, fidx)) || (rc = upload(h, &d_flux, fl)) ||
+        (rc = dalloc(h, &d_slot, 3 * (size_t)n_faces)))
+        return rc;
+    HIPCHK(h, hipStreamSynchronize(h->own_stream));  // uploads ran there
+    HIPCHK(h, launch_face_loads(N, n_faces, h->d_xyz, d_faces, d_flux, d_off, d_idx, d_slot,
+                                h->d_stage, s));
+    std::vector<double> tmp(N);
+    HIPCHK(h, hipMemcpyAsync(tmp.data(), h->d_stage, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (int64_t i = 0; i < N; i++) out[h->L.nperm[i]] = tmp[i];
+    for (void* p : {(void*)d_faces, (void*)d_off, (void*)d_idx, (void*)d_flux, (void*)d_slot})
+        dfree(h, p);
+    return FEDFEM_OK;
+}
+
 int fedfem_set_source(fedfem_handle* h, const double* source) {
     int rc = check_handle(h, true);
     if (rc) return rc;
@@ -818,14 +1051,38 @@ int fedfem_step(fedfem_handle* h, int64_t n_steps, const double* source) {
     if (n_steps == 0) return FEDFEM_OK;
     hipStream_t s = h->stream;
     HIPCHK(h, launch_fill_i32(h->d_flag, 1, 0, s));
-    int64_t left = n_steps;
-    while (left > 0) {
-        const int64_t chunk = std::min<int64_t>(left, 512);
+    // amplitudes of the scheduled patterns at the start of every step of
+    // this call, in the working precision; each chunk's rows are copied in
+    // before its graph runs (stream order keeps the previous chunk's reads)
+    const int P = h->d.n_pat;
+    std::vector<float> amp32;
+    std::vector<double> amp64;
+    if (P > 0) {
+        const size_t cnt = (size_t)n_steps * P;
+        if (h->fp32c) amp32.resize(cnt); else amp64.resize(cnt);
+        for (int64_t k = 0; k < n_steps; k++) {
+            const double x = h->t + (double)k * h->dt;
+            for (int p = 0; p < P; p++) {
+                const double v = sched_amp(h->sched_t[p], h->sched_a[p], x);
+                if (h->fp32c) amp32[k * P + p] = (float)v; else amp64[k * P + p] = v;
+            }
+        }
+    }
+    int64_t done = 0;
+    while (done < n_steps) {
+        const int64_t chunk = std::min<int64_t>(n_steps - done, 512);
         hipGraphExec_t ex;
         if ((rc = get_graph(h, chunk, h->cur, &ex))) return rc;
+        if (P > 0) {
+            const void* src = h->fp32c ? (const void*)(amp32.data() + done * P)
+                                       : (const void*)(amp64.data() + done * P);
+            const size_t rb = h->fp32c ? sizeof(float) : sizeof(double);
+            HIPCHK(h, hipMemcpyAsync(h->d.amp, src, (size_t)chunk * P * rb,
+                                     hipMemcpyHostToDevice, s));
+        }
         HIPCHK(h, hipGraphLaunch(ex, s));
         if (chunk & 1) h->cur ^= 1;
-        left -= chunk;
+        done += chunk;
     }
     int32_t flag = 0;
     HIPCHK(h, hipMemcpyAsync(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -864,7 +1121,7 @@ int fedfem_time_kernels(fedfem_handle* h, int64_t n_steps, double* elem_ms, doub
     hipStream_t s = h->stream;
     std::vector<hipEvent_t> ev(2 * n_steps + 1);
     for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
-    const bool td = h->mat.dk_dT != 0.0;
+    const bool td = h->mat.dk_dT != 0.0 || !h->tab_t[0].empty();
     HIPCHK(h, launch_fill_i32(h->d_flag, 1, 0, s));
     HIPCHK(h, hipEventRecord(ev[0], s));
     for (int64_t k = 0; k < n_steps; k++) {
@@ -1019,7 +1276,7 @@ int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
     if (rc) return rc;
     char key[128];
     std::snprintf(key, sizeof(key), "f%d_prec%d_td%d_e%d", flags, h->mat.precision,
-                  h->mat.dk_dT != 0.0 ? 1 : 0,
+                  (h->mat.dk_dT != 0.0 || !h->tab_t[0].empty()) ? 1 : 0,
                   (int)std::lround(4.0 * std::log2((double)h->E)));
     fedfem_options best{};
     bool found = false;

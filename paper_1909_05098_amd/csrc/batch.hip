@@ -91,6 +91,8 @@ Props<Real> props_of(const fedfem_handle* h) {
     p.dt = (Real)h->dt;
     p.fxs = (Real)h->fx_scale;
     p.fxi = (Real)(1.0 / h->fx_scale);
+    p.tab = static_cast<const Real*>(h->d_tab);  // the handle's device copy
+    for (int k = 0; k < 3; k++) p.nt[k] = h->d_tab ? (int)h->tab_t[k].size() : 0;
     return p;
 }
 
@@ -119,6 +121,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     for (int j = 0; j < n; j++) {
         const fedfem_handle* h = handles[j];
         if (!h || h->broken) return FEDFEM_E_INVALID;
+        if (h->d.n_pat > 0) return FEDFEM_E_STATE;  // schedules run per handle only
         if (!h->precomputed || !(h->dt > 0)) return FEDFEM_E_NOT_PRECOMPUTED;
         if (h->fp32c != handles[0]->fp32c || h->device != handles[0]->device)
             return FEDFEM_E_INVALID;

@@ -63,4 +63,12 @@ struct fedfem_handle {
     int64_t steps = 0;
     int cur = 0;
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    // scheduled source patterns (fedfem_set_schedule); device arrays in d.pat
+    // and d.amp, amplitude tables (times, values) per pattern on the host
+    std::vector<std::vector<double>> sched_t, sched_a;
+    // property tables (fedfem_set_property_tables): points of k, rho, c;
+    // empty keeps the material's linear law.  d_tab holds them on the device
+    // in the working precision as [3][times, values, slopes][kMaxTab].
+    std::vector<double> tab_t[3], tab_v[3];
+    void* d_tab = nullptr;
 };

@@ -69,7 +69,13 @@ template <typename Real>
 struct Props {
     Real k0, dk, rho0, drho, c0, dc, Tref, Tlo, Thi, wbcb, Ta, Qm, dt;
     Real fxs, fxi;
+    // property tables (fedfem_set_property_tables): nt[p] points of property
+    // p (0 k, 1 rho, 2 c) at tab + p * 3 * kMaxTab as times, values, slopes;
+    // nt[p] == 0 keeps the linear law of that property
+    const Real* tab = nullptr;
+    int nt[3] = {0, 0, 0};
 };
+constexpr int kMaxTab = 16;  // FEDFEM_MAX_TABLE
 
 // Device copy of a layout plus the numerical arrays of one precision.
 struct DevLayout {
@@ -87,6 +93,11 @@ struct DevLayout {
     void* q = nullptr;         // [N] Real, active nodal source [W]
     void* T_[2] = {nullptr, nullptr};  // state: float2 (hi, lo) or double
     void* partial = nullptr;   // [P] Real, node-major
+    // scheduled source patterns (fedfem_set_schedule): node i receives
+    // sum_p amp[j][p] pat[p][i] on top of q in the j-th step of a graph chunk
+    void* pat = nullptr;       // [n_pat][N] Real
+    void* amp = nullptr;       // [512][n_pat] Real, refilled before each chunk
+    int n_pat = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -97,11 +108,12 @@ size_t tile_lds_bytes(int tile_elems, int max_nodes, int real_bytes, bool comp,
 // Elements per thread of the element kernel, rounded up to 1, 2 or 4 (the
 // instantiated counts); 8 means the workgroup is too small for the tile.
 int elems_per_thread(const DevLayout& d);
-// One explicit step: element loads then nodal update, ping-pong cur -> 1-cur.
+// One explicit step: element loads then nodal update, ping-pong cur -> 1-cur;
+// j is the step's position in its graph chunk (row j of the amplitudes).
 hipError_t launch_step_f32c(const DevLayout& d, int cur, const Props<float>& p,
-                            bool td, int* flag, hipStream_t s);
+                            bool td, int* flag, hipStream_t s, int j = 0);
 hipError_t launch_step_f64(const DevLayout& d, int cur, const Props<double>& p,
-                           bool td, int* flag, hipStream_t s);
+                           bool td, int* flag, hipStream_t s, int j = 0);
 hipError_t launch_elem_f32c(const DevLayout& d, int cur, const Props<float>& p,
                             bool td, hipStream_t s);
 hipError_t launch_node_f32c(const DevLayout& d, int cur, const Props<float>& p,
@@ -158,6 +170,11 @@ hipError_t launch_node_init(int64_t N, const double* Vi, const int32_t* is_dir,
                             const double* dirT, double T0, int fp32c, void* u,
                             void* T0buf, void* T1buf, hipStream_t s);
 // q (Real, internal order) <- src64[nperm[i]] (caller order) or src64[i].
+// Nodal loads of a surface heat flux: per-face shares, then a fixed-order
+// gather over the node -> face-corner list (off, idx).
+hipError_t launch_face_loads(int64_t N, int64_t F, const double* xyz, const int32_t* faces,
+                             const double* flux, const int32_t* off, const int32_t* idx,
+                             double* slot, double* out, hipStream_t s);
 hipError_t launch_set_source(int64_t N, const double* src64,
                              const int32_t* nperm, int fp32c, void* q,
                              hipStream_t s);

@@ -174,6 +174,26 @@ __global__ void k_gather_slots(int64_t N, const int32_t* __restrict__ off,
     q[i] = s;
 }
 
+// Nodal loads of a surface heat flux (Eq 4): triangle f with flux q_f [W/m^2]
+// gives each of its corners q_f |f| / 3 (the integral of q_f N_i over the
+// face for linear N_i); slot[3 f + c] holds corner c's share.
+__global__ void k_face_loads(int64_t F, const double* __restrict__ xyz,
+                             const int32_t* __restrict__ faces, const double* __restrict__ flux,
+                             double* __restrict__ slot) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double* a = xyz + 3 * (int64_t)faces[3 * f];
+    const double* b = xyz + 3 * (int64_t)faces[3 * f + 1];
+    const double* c = xyz + 3 * (int64_t)faces[3 * f + 2];
+    const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2],
+                         u[0] * v[1] - u[1] * v[0]};
+    const double area = 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double share = flux[f] * area / 3.0;
+    for (int k = 0; k < 3; k++) slot[3 * f + k] = share;
+}
+
 // Largest row sum of |A_e| off the diagonal over all elements (for the
 // fixed-point scale of the element loads).  Positive doubles order like
 // their bit patterns, so an integer max over the bits is exact.
@@ -422,6 +442,18 @@ hipError_t launch_source_consistent(int64_t N, int64_t E, const double* xyz,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, ec_off, ec,
                        slot64, q64);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_loads(int64_t N, int64_t F, const double* xyz, const int32_t* faces,
+                             const double* flux, const int32_t* off, const int32_t* idx,
+                             double* slot, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_face_loads, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, xyz, faces, flux,
+                       slot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, off, idx, slot,
+                       out);
     return hipGetLastError();
 }
 

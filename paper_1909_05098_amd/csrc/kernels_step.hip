@@ -50,6 +50,35 @@ __device__ __forceinline__ Real clampT(Real T, const Props<Real>& p) {
     return T < p.Tlo ? p.Tlo : (T > p.Thi ? p.Thi : T);
 }
 
+// piecewise-linear table (times t, values v, slopes s of n points),
+// constant outside its range
+template <typename Real>
+__device__ __forceinline__ Real tab_eval(const Real* __restrict__ tb, int n, Real x) {
+    const Real* t = tb;
+    const Real* v = tb + kMaxTab;
+    const Real* sl = tb + 2 * kMaxTab;
+    if (!(x > t[0])) return v[0];
+    int k = 0;
+    while (k + 1 < n && t[k + 1] <= x) k++;
+    if (k + 1 >= n) return v[n - 1];
+    return v[k] + sl[k] * (x - t[k]);
+}
+
+// k(T) (Eq 13) and rho(T) c(T) (Eq 19): clamped linear laws or tables
+template <typename Real>
+__device__ __forceinline__ Real prop_k(Real T, const Props<Real>& p) {
+    if (p.nt[0]) return tab_eval(p.tab, p.nt[0], T);
+    return p.k0 + p.dk * (clampT(T, p) - p.Tref);
+}
+
+template <typename Real>
+__device__ __forceinline__ Real prop_rho_c(Real T, const Props<Real>& p) {
+    const Real dT = clampT(T, p) - p.Tref;
+    const Real rho = p.nt[1] ? tab_eval(p.tab + 3 * kMaxTab, p.nt[1], T) : p.rho0 + p.drho * dT;
+    const Real c = p.nt[2] ? tab_eval(p.tab + 6 * kMaxTab, p.nt[2], T) : p.c0 + p.dc * dT;
+    return rho * c;
+}
+
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 // Nodal state access: FP32C stores float2 (hi, lo), FP64 stores double.
@@ -155,7 +184,7 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
         State<Real, COMP>::load(Tin, g, hi, lo);
         s_T[j] = hi;
         if (COMP) s_Tlo[j] = lo;
-        if (TD) s_k[j] = pr.k0 + pr.dk * (clampT(hi, pr) - pr.Tref);
+        if (TD) s_k[j] = prop_k(hi, pr);
         s_acc[j] = 0ull;
     }
     __syncthreads();
@@ -226,25 +255,37 @@ k_elem_loads_batch(TileArgs a, const int32_t* __restrict__ tile_list,
     elem_tile<Real, COMP, true, R>(a, t, coef, Tin, partial, pr);
 }
 
+// Scheduled source patterns of one step: n_pat patterns [n_pat][N] and this
+// step's amplitudes amp[0..n_pat) (none when n_pat == 0).
+template <typename Real>
+struct Sched {
+    const Real* pat;
+    const Real* amp;
+    int n_pat;
+    int64_t N;
+};
+
 template <typename Real, bool COMP>
 __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict__ part_off,
                                             const Real* __restrict__ partial,
                                             const Real* __restrict__ u,
                                             const Real* __restrict__ q,
                                             const void* __restrict__ Tin, void* __restrict__ Tout,
-                                            const Props<Real>& pr, int* __restrict__ flag) {
+                                            const Props<Real>& pr, int* __restrict__ flag,
+                                            const Sched<Real>& sch) {
     const Real ui = u[i];
     if (!(ui > Real(0))) return;  // Dirichlet node: held at T_Gamma
     const int a = part_off[i], b = part_off[i + 1];
     Real F = 0;
     for (int k = a; k < b; k++) F += partial[k];
+    Real qi = q[i];
+    for (int p = 0; p < sch.n_pat; p++) qi += sch.amp[p] * sch.pat[p * sch.N + i];
     Real hi, lo;
     State<Real, COMP>::load(Tin, i, hi, lo);
-    const Real dT = clampT(hi, pr) - pr.Tref;
-    const Real rc = (pr.rho0 + pr.drho * dT) * (pr.c0 + pr.dc * dT);
+    const Real rc = prop_rho_c(hi, pr);
     // heat flow per unit volume [W/m^3]: source and conduction per lumped
     // volume, metabolic heat, perfusion towards T_a
-    const Real R = (q[i] - F) * ui + pr.Qm + pr.wbcb * ((pr.Ta - hi) - lo);
+    const Real R = (qi - F) * ui + pr.Qm + pr.wbcb * ((pr.Ta - hi) - lo);
     const Real d = pr.dt * R / rc;
     Real nh, nl = 0;
     if (COMP) {
@@ -268,12 +309,12 @@ __global__ void __launch_bounds__(256)
 k_node_update(int64_t N, int xcd, const int32_t* __restrict__ part_off,
               const Real* __restrict__ partial, const Real* __restrict__ u,
               const Real* __restrict__ q, const void* __restrict__ Tin, void* __restrict__ Tout,
-              Props<Real> pr, int* __restrict__ flag) {
+              Props<Real> pr, int* __restrict__ flag, Sched<Real> sch) {
     const int64_t nb = (N + 255) / 256;
     const int64_t blk = xcd ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
     const int64_t i = blk * 256 + threadIdx.x;
     if (i >= N) return;
-    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flag);
+    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flag, sch);
 }
 
 // Batched form: 256-node blocks never straddle scenarios; the block comes
@@ -290,7 +331,8 @@ k_node_update_batch(const int32_t* __restrict__ block_list,
     const int sc = block_scen[blk];
     const Props<Real> pr = props[sc];
     const int64_t i = (int64_t)blk * 256 + threadIdx.x;
-    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flags + sc);
+    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flags + sc,
+                            Sched<Real>{nullptr, nullptr, 0, 0});
 }
 
 TileArgs tile_args(const DevLayout& d) {
@@ -341,13 +383,16 @@ hipError_t launch_elem_t(const DevLayout& d, const Real* coef, const Props<Real>
 
 template <typename Real, bool COMP>
 hipError_t launch_node_t(const DevLayout& d, int cur, const Props<Real>& p, int* flag,
-                         hipStream_t s) {
+                         hipStream_t s, int j) {
     const int64_t nb = (d.N + 255) / 256;
     const int64_t grid = d.xcd ? (nb + kXcds - 1) / kXcds * kXcds : nb;
+    Sched<Real> sch{static_cast<const Real*>(d.pat),
+                    d.n_pat ? static_cast<const Real*>(d.amp) + (int64_t)j * d.n_pat : nullptr,
+                    d.n_pat, d.N};
     hipLaunchKernelGGL((k_node_update<Real, COMP>), dim3((unsigned)grid), dim3(256), 0, s, d.N,
                        d.xcd, d.part_off, static_cast<const Real*>(d.partial),
                        static_cast<const Real*>(d.u), static_cast<const Real*>(d.q), d.T_[cur],
-                       d.T_[1 - cur], p, flag);
+                       d.T_[1 - cur], p, flag, sch);
     return hipGetLastError();
 }
 
@@ -396,7 +441,7 @@ hipError_t launch_elem_f32c(const DevLayout& d, int cur, const Props<float>& p, 
 
 hipError_t launch_node_f32c(const DevLayout& d, int cur, const Props<float>& p, int* flag,
                             hipStream_t s) {
-    return launch_node_t<float, true>(d, cur, p, flag, s);
+    return launch_node_t<float, true>(d, cur, p, flag, s, 0);
 }
 
 hipError_t launch_elem_f64(const DevLayout& d, int cur, const Props<double>& p, bool td,
@@ -409,21 +454,21 @@ hipError_t launch_elem_f64(const DevLayout& d, int cur, const Props<double>& p, 
 
 hipError_t launch_node_f64(const DevLayout& d, int cur, const Props<double>& p, int* flag,
                            hipStream_t s) {
-    return launch_node_t<double, false>(d, cur, p, flag, s);
+    return launch_node_t<double, false>(d, cur, p, flag, s, 0);
 }
 
 hipError_t launch_step_f32c(const DevLayout& d, int cur, const Props<float>& p, bool td,
-                            int* flag, hipStream_t s) {
+                            int* flag, hipStream_t s, int j) {
     hipError_t e = launch_elem_f32c(d, cur, p, td, s);
     if (e != hipSuccess) return e;
-    return launch_node_f32c(d, cur, p, flag, s);
+    return launch_node_t<float, true>(d, cur, p, flag, s, j);
 }
 
 hipError_t launch_step_f64(const DevLayout& d, int cur, const Props<double>& p, bool td,
-                           int* flag, hipStream_t s) {
+                           int* flag, hipStream_t s, int j) {
     hipError_t e = launch_elem_f64(d, cur, p, td, s);
     if (e != hipSuccess) return e;
-    return launch_node_f64(d, cur, p, flag, s);
+    return launch_node_t<double, false>(d, cur, p, flag, s, j);
 }
 
 hipError_t launch_geometry_apply(const DevLayout& d, const double* coef64, const double* x,

@@ -82,6 +82,10 @@ _SIGS = {
     "fedfem_precompute": (C.c_int, [_P]),
     "fedfem_precompute_many": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
     "fedfem_release_cached_memory": (C.c_size_t, []),
+    "fedfem_set_schedule": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
+    "fedfem_set_property_tables": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, _P, _P,
+                                             C.c_int32, _P, _P]),
+    "fedfem_flux_loads": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
     "fedfem_step": (C.c_int, [_P, C.c_int64, _P]),
     "fedfem_prepare": (C.c_int, [_P, C.c_int64]),
     "fedfem_set_source": (C.c_int, [_P, _P]),
@@ -214,6 +218,48 @@ class Handle:
         self._check(self._L.fedfem_set_gaussian_sources(self._h, len(p), _ptr(p),
                                                         int(mode)),
                     "fedfem_set_gaussian_sources")
+
+    def set_property_tables(self, tables):
+        """Tables {"k" | "rho" | "c": (T, values)} replacing the linear laws
+        (before precompute)."""
+        args = []
+        keep = []
+        for name in ("k", "rho", "c"):
+            tab = (tables or {}).get(name)
+            if tab is None:
+                args += [0, None, None]
+                continue
+            T = np.ascontiguousarray(tab[0], dtype=np.float64)
+            V = np.ascontiguousarray(tab[1], dtype=np.float64)
+            keep += [T, V]
+            args += [len(T), _ptr(T), _ptr(V)]
+        self._check(self._L.fedfem_set_property_tables(self._h, *args),
+                    "fedfem_set_property_tables")
+
+    def set_schedule(self, patterns, schedules):
+        """Scheduled source patterns: patterns [P, N] (W, caller order) and,
+        per pattern, (times, amplitudes) of its piecewise-linear amplitude.
+        An empty list removes the schedule."""
+        P = len(schedules)
+        if P == 0:
+            self._check(self._L.fedfem_set_schedule(self._h, 0, None, None, None, None),
+                        "fedfem_set_schedule")
+            return
+        pat = np.ascontiguousarray(patterns, dtype=np.float64).reshape(P, -1)
+        npts = np.array([len(t) for t, _ in schedules], dtype=np.int32)
+        ts = np.ascontiguousarray(np.concatenate([np.asarray(t, float) for t, _ in schedules]))
+        am = np.ascontiguousarray(np.concatenate([np.asarray(a, float) for _, a in schedules]))
+        self._check(self._L.fedfem_set_schedule(self._h, P, _ptr(pat), _ptr(npts), _ptr(ts),
+                                                _ptr(am)), "fedfem_set_schedule")
+
+    def flux_loads(self, faces, flux):
+        """Nodal loads [W] of surface flux `flux` [W/m^2] on triangles `faces`."""
+        f = np.ascontiguousarray(faces, dtype=np.int32).reshape(-1, 3)
+        q = np.ascontiguousarray(flux, dtype=np.float64).reshape(-1)
+        out = np.empty(len(self.xyz))
+        self._check(self._L.fedfem_flux_loads(self._h, len(f), _ptr(f), _ptr(q), _ptr(out)),
+                    "fedfem_flux_loads")
+        return out
 
     def read_source(self):
         out = np.empty(self.N)

@@ -85,6 +85,16 @@ def boundary_nodes_by_faces(n_nodes, tets):
     return np.nonzero(mask)[0].astype(np.int32)
 
 
+def boundary_faces(tets):
+    """Triangles (sorted node ids) that belong to exactly one tetrahedron."""
+    tets = np.asarray(tets, dtype=np.int64)
+    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]],
+                            tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    faces.sort(axis=1)
+    uniq, count = np.unique(faces, axis=0, return_counts=True)
+    return uniq[count == 1].astype(np.int32)
+
+
 def boundary_nodes_by_degree(n_nodes, tets):
     """Boundary nodes of a sub-mesh of a Kuhn lattice.
 

@@ -477,3 +477,142 @@ def test_degenerate_element_reported():
     xyz[t[3]] = (p0 + p1 + p2) / 3.0
     with pytest.raises(ValueError, match="degenerate"):
         oracle.OracleModel(xyz, tets, ti_materials())
+
+
+# --------------------------------------------------------------------------
+# Scheduled sources (the external heat applied at every step of Algorithm 1;
+# the heat-then-relax runs of Sec 3.1.5) and surface heat flux (Eq 4).
+# --------------------------------------------------------------------------
+def test_schedule_amplitude_values():
+    t = [1.0, 3.0, 3.0, 5.0]
+    a = [2.0, 6.0, -1.0, 0.0]
+    cases = {0.0: 2.0, 1.0: 2.0, 2.0: 4.0, 2.5: 5.0, 3.0: -1.0, 4.0: -0.5, 5.0: 0.0, 9.0: 0.0}
+    for x, v in cases.items():
+        assert oracle.schedule_amplitude(t, a, x) == pytest.approx(v, abs=1e-15), x
+    assert oracle.schedule_amplitude([2.0], [7.0], -1.0) == 7.0
+    assert oracle.schedule_amplitude([2.0], [7.0], 5.0) == 7.0
+
+
+def test_scheduled_uniform_source_closed_form():
+    """Adiabatic box, constant properties, a uniform source q0 per unit volume
+    ramped by a(t): the field stays uniform (zero row sums) and
+    T_n = T0 + dt q0 / (rho c) * sum_{k<n} a(t_k), an exact finite sum."""
+    xyz, tets, _ = jittered_box(4, 3, 3, 1e-3, seed=21)
+    mat = ti_materials(w_b=0.0)
+    m = oracle.OracleModel(xyz, tets, mat)
+    m.dt = 0.05
+    q0 = 2e6
+    Q = q0 * m.Vi
+    sched = ([0.0, 1.0, 1.0, 2.0], [0.0, 1.0, 0.5, 0.5])
+    n = 60
+    T = m.run_schedule(np.full(m.N, 37.0), n, [Q], [sched])
+    amps = [oracle.schedule_amplitude(*sched, k * m.dt) for k in range(n)]
+    # hand values of the same ramp: t/1 before 1 s, then 0.5
+    assert amps == pytest.approx([min(k * 0.05, 1.0) if k * 0.05 < 1.0 else 0.5
+                                  for k in range(n)], abs=1e-15)
+    expect = 37.0 + m.dt * q0 / (1060.0 * 3600.0) * sum(amps)
+    assert np.max(np.abs(T - expect)) <= 1e-12 * expect
+
+
+def test_two_stage_schedule_equals_two_runs():
+    xyz, tets, bnd = jittered_box(5, 4, 3, 1e-3, seed=22)
+    mat = sc.td_materials()
+    m = oracle.OracleModel(xyz, tets, mat, bnd, np.full(len(bnd), 37.0))
+    m.dt = 0.9 * m.dt_cr()
+    q = m.source_consistent([[2.5e-3, 2e-3, 1.5e-3, 1e-3, 3e7]])
+    n1, n2 = 40, 35
+    t1 = (n1 - 0.5) * m.dt  # switched off between steps n1 - 1 and n1
+    T_sched = m.run_schedule(m.initial(37.0), n1 + n2, [q], [([t1, t1], [1.0, 0.0])])
+    T_two = m.run(m.run(m.initial(37.0), n1, q), n2, None)
+    assert np.array_equal(T_sched, T_two)
+
+
+def test_flux_loads_total_and_lattice_face():
+    """On the x = 0 face of a Kuhn box every interior face node carries
+    q h^2 (six triangles of area h^2 / 2, a third each) and the loads sum to
+    q times the face area."""
+    nx, ny, nz, h = 4, 5, 3, 1e-3
+    xyz, tets = mesh.kuhn_box(nx, ny, nz, h)
+    faces = mesh.boundary_faces(tets)
+    on_x0 = np.all(xyz[faces][:, :, 0] == 0.0, axis=1)
+    q = 1.5e4
+    out = oracle.flux_loads(xyz, faces[on_x0], np.full(on_x0.sum(), q))
+    assert out.sum() == pytest.approx(q * (ny * h) * (nz * h), rel=1e-14)
+    j = np.round(xyz[:, 1] / h).astype(int)
+    k = np.round(xyz[:, 2] / h).astype(int)
+    inner = (xyz[:, 0] == 0.0) & (j > 0) & (j < ny) & (k > 0) & (k < nz)
+    assert inner.sum() == (ny - 1) * (nz - 1)
+    assert np.allclose(out[inner], q * h * h, rtol=1e-14, atol=0.0)
+    assert np.all(out[xyz[:, 0] > 0.0] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# Property tables (Eq 2; the paper's two-point tissue data of Sec 3.1.6 and
+# their generalisation to piecewise-linear tables).
+# --------------------------------------------------------------------------
+def test_two_point_tables_equal_linear_law():
+    """The paper's two-point data written as tables reproduce the clamped
+    linear law (rounding only), and the critical step is the same."""
+    xyz, tets, bnd = jittered_box(5, 4, 4, 1e-3, seed=41)
+    mat = sc.paper_table_materials()
+    lin = oracle.OracleModel(xyz, tets, mat, bnd, np.full(len(bnd), 37.0))
+    tables = {"k": ([37.0, 65.0], [0.53, 0.57]), "rho": ([37.0, 65.0], [1040.0, 1000.0]),
+              "c": ([37.0, 65.0], [3600.0, 3800.0])}
+    tab = oracle.OracleModel(xyz, tets, mat, bnd, np.full(len(bnd), 37.0), tables=tables)
+    assert tab.dt_cr() == pytest.approx(lin.dt_cr(), rel=1e-13)
+    lin.dt = tab.dt = 0.9 * lin.dt_cr()
+    q = lin.source_consistent([[2.5e-3, 2e-3, 2e-3, 1e-3, 6e7]])
+    Ta = lin.run(lin.initial(37.0), 300, q)
+    Tb = tab.run(tab.initial(37.0), 300, q)
+    assert Ta.max() > 60.0  # the run crosses the table's range
+    assert np.max(np.abs(Ta - Tb)) <= 1e-11
+
+
+def test_table_conductivity_kirchhoff_order():
+    """Piecewise-linear k(T): the long-run FED-FEM field converges at second
+    order to the Kirchhoff steady state; the linear law of the first piece
+    alone would stall at an O(1) error."""
+    L = 6e-3
+    Tk, kv = [37.0, 60.0, 90.0], [0.5, 0.65, 0.55]
+    errs = []
+    for M_ in (3, 6, 12):
+        h = L / M_
+        xyz, tets = mesh.kuhn_box(M_, 1, 1, h)
+        x = xyz[:, 0]
+        left, right = np.abs(x) < 1e-12, np.abs(x - L) < 1e-12
+        dn = np.nonzero(left | right)[0]
+        dT = np.where(left[dn], 37.0, 90.0)
+        mat = sc.Materials(rho0=1000.0, c0=4000.0, k0=0.5, T_ref=37.0, T_lo=0.0, T_hi=100.0,
+                           w_b=0.0)
+        m = oracle.OracleModel(xyz, tets, mat, dn, dT, tables={"k": (Tk, kv)})
+        m.dt = 0.9 * m.dt_cr(method="dense")
+        T = m.initial(37.0)
+        for _ in range(200):
+            Tn = m.run(T, 2000)
+            if np.max(np.abs(Tn - T)) < 1e-13:
+                T = Tn
+                break
+            T = Tn
+        ex = cf.kirchhoff_slab_table(x, L, 37.0, 90.0, Tk, kv)
+        errs.append(np.max(np.abs(T - ex)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders >= 1.8), (errs, orders)
+    # the kink of k at 60 C keeps the constant larger than for a linear k
+    assert errs[-1] < 0.05
+
+
+def test_table_window_bound_is_the_exact_extreme():
+    """k_max and (rho c)_min of tables (with rho c dipping inside a piece)
+    against dense sampling of the same functions."""
+    mat = sc.td_materials()
+    m = oracle.mat_vector(mat)
+    tables = {"k": ([10.0, 40.0, 80.0], [0.4, 0.7, 0.6]),
+              "rho": ([20.0, 90.0], [1100.0, 900.0]),
+              "c": ([0.0, 50.0, 100.0], [3000.0, 4200.0, 3300.0])}
+    kmax, rcmin = dense.material_window(m, tables)
+    Ts = np.linspace(-20.0, 130.0, 300001)
+    k = dense.prop_value(Ts, m, tables, "k")
+    rc = dense.prop_value(Ts, m, tables, "rho") * dense.prop_value(Ts, m, tables, "c")
+    assert kmax == pytest.approx(k.max(), rel=1e-12)
+    assert rcmin <= rc.min() * (1 + 1e-12)
+    assert rcmin >= rc.min() * (1 - 1e-6)
