@@ -187,7 +187,8 @@ int fedfem_set_property_tables(fedfem_handle *h, int32_t n_k, const double *T_k,
 
 /*
  * fedfem_precompute on n distinct handles at once, by `threads` host
- * threads (0: up to 16, one per core) that each take the next handle:
+ * threads (0: the environment variable FEDFEM_PRECOMPUTE_THREADS if set,
+ * else up to 16, one per core) that each take the next handle:
  * one scenario's host-side layout overlaps another's device work, each on
  * its handle's own stream.  rcs (may be NULL) receives each handle's return
  * code; the function returns the first nonzero one in handle order, else

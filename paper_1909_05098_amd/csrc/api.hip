@@ -824,8 +824,12 @@ int fedfem_precompute_many(fedfem_handle* const* handles, int32_t n, int32_t thr
             res[j] = fedfem_precompute(handles[j]);
         }
     };
-    int32_t nt = threads > 0 ? threads
-                             : (int32_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int32_t nt = threads;
+    if (nt == 0) {
+        const char* env = std::getenv("FEDFEM_PRECOMPUTE_THREADS");
+        nt = env ? std::atoi(env) : 0;
+        if (nt <= 0) nt = (int32_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    }
     nt = std::max<int32_t>(1, std::min(nt, n));
     std::vector<std::thread> pool;
     try {

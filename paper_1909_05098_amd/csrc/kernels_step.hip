@@ -36,6 +36,10 @@
 // curve; the node pass maps 256-node blocks the same way.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "internal.h"
 
 namespace fedfem {
@@ -350,11 +354,29 @@ TileArgs tile_args(const DevLayout& d) {
     return a;
 }
 
+// Dynamic LDS above 64 KiB must be allowed per kernel.  The attribute is
+// process-wide state of the kernel, so it is set once per kernel (to the
+// device's LDS limit, enough for every layout) under a lock: rewriting it on
+// every launch would race with launches of the same kernel from other host
+// threads (precompute of several handles at once).
+std::mutex g_lds_mu;
+std::set<std::pair<int, const void*>> g_lds_done;  // (device, kernel)
+
 template <typename K>
 hipError_t allow_lds(K kern, size_t lds) {
     if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void* f = reinterpret_cast<const void*>(kern);
+    int dev = 0, limit = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_lds_mu);
+    if (g_lds_done.count({dev, f})) return hipSuccess;
+    e = hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    if ((size_t)limit < lds) return hipErrorInvalidValue;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, limit);
+    if (e == hipSuccess) g_lds_done.insert({dev, f});
+    return e;
 }
 
 template <typename Real, bool COMP, bool TD, int R>
