@@ -3,7 +3,7 @@
 The committed parameters (paper_1909_05098_amd/weights/surrogate_g64.npy)
 were trained by the library's own kernels on planning-sweep seeds 0..4095;
 here they meet 64 held-out seeds (10000..10063).  FED-FEM, run batched on
-every scenario and resampled onto the 64^3 frame, is the judge.  The test
+every scenario and resampled onto the 64^3 frame, is the reference.  The test
 shows three things:
 
   * speed -- the network alone runs the scenarios at least 4x faster than
@@ -13,7 +13,7 @@ shows three things:
     closed-form prior it starts from (the network output set to zero);
   * the fallback -- with the 1/16 spot check and a 0.5 K bound, every
     scenario of a batch that fell back, and every checked scenario, carries
-    FED-FEM's own field (equal to the judge's to FP32C parity).
+    FED-FEM's own field (equal to the reference to FP32C parity).
 
 The surrogate's error is bounded below by how much FED-FEM itself moves
 between two meshes of the same scenario (a median of about 5 K on this
@@ -103,7 +103,7 @@ def test_surrogate_gain_and_fallback(scns):
     assert stats["spot_checks"] == stats["batches"]  # 16 per batch -> one check each
     fem = stats["from_fedfem"]
     assert fem.sum() >= stats["batches"]
-    # fields that came from FED-FEM in the surrogate path equal the judge's;
+    # fields that came from FED-FEM in the surrogate path equal the reference;
     # the others are the network's own predictions
     assert np.all(e_fb[fem] <= 1e-3)
     assert np.allclose(e_fb[~fem], e_net[~fem], rtol=1e-6, atol=0.0)
