@@ -629,7 +629,7 @@ int fedfem_precompute(fedfem_handle* h) {
     if ((rc = upload(h, &d.tile_elem_off, L.tile_elem_off)) ||
         (rc = upload(h, &d.tile_node_off, L.tile_node_off)) ||
         (rc = upload(h, &d.tile_nodes, L.tile_nodes)) || (rc = upload(h, &d.lconn, L.lconn)) ||
-        (rc = upload(h, &d.wpos, L.wpos)) || (rc = upload(h, &d.part_off, L.part_off)) ||
+        (rc = upload(h, &d.pidx, L.pidx)) || (rc = upload(h, &d.part_off, L.part_off)) ||
         (rc = upload(h, &h->d_ec_off, L.ec_off)) || (rc = upload(h, &h->d_ec, L.ec)) ||
         (rc = upload(h, &h->d_conn, L.conn)) || (rc = upload(h, &h->d_xyz, L.xyz)) ||
         (rc = upload(h, &h->d_nperm, L.nperm)))

@@ -203,7 +203,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
         }
         for (int64_t p = 0; p < h->d.P; p++) {
             tnodes[pb + p] = (int32_t)(L.tile_nodes[p] + no);
-            wp[pb + p] = (int32_t)(L.wpos[p] + pb);
+            wp[pb + p] = (int32_t)(L.pidx[p] + pb);
         }
         const int64_t npad = b->node_off[j + 1] - no;
         for (int64_t i = 0; i < npad; i++)
@@ -216,7 +216,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     BCHK(bupload(b, &d.tile_node_off, tno));
     BCHK(bupload(b, &d.tile_nodes, tnodes));
     BCHK(bupload(b, &d.part_off, poff));
-    BCHK(bupload(b, &d.wpos, wp));
+    BCHK(bupload(b, &d.pidx, wp));
     BCHK(bupload(b, &d.tile_elem_off, teo));
     BCHK(bupload(b, &b->tile_scen, tsc));
     BCHK(bupload(b, &b->block_scen, bsc));

@@ -19,8 +19,8 @@ namespace fedfem {
 // internal id ("tile nodes"), and each element corner stores its node's
 // position in that list (lconn, u16).  Each (tile, tile node) pair p in
 // [tile_node_off[t], tile_node_off[t+1]) produces one partial sum, stored at
-// position wpos[p] of the node-major partial array (node i owns positions
-// [part_off[i], part_off[i+1]), in ascending tile order).
+// position p (tile-major: a tile writes one contiguous run).  Node i finds its
+// partials at pidx[part_off[i] .. part_off[i+1]), in ascending tile order.
 // ---------------------------------------------------------------------------
 struct Layout {
     int64_t N = 0, E = 0, T = 0, P = 0;
@@ -34,7 +34,7 @@ struct Layout {
     std::vector<int32_t> tile_elem_off;  // [T+1]
     std::vector<int32_t> tile_node_off;  // [T+1]
     std::vector<int32_t> tile_nodes;     // [P]
-    std::vector<int32_t> wpos;           // [P] node-major position of p
+    std::vector<int32_t> pidx;           // [P] node-major list of partial slots p
     std::vector<uint16_t> lconn;         // [4E] local node id per corner
     std::vector<int32_t> part_off;       // [N+1] node -> partial positions
     std::vector<int32_t> ec_off;         // [N+1] node -> element corners
@@ -85,14 +85,14 @@ struct DevLayout {
     int32_t* tile_elem_off = nullptr;
     int32_t* tile_node_off = nullptr;
     int32_t* tile_nodes = nullptr;
-    int32_t* wpos = nullptr;
+    int32_t* pidx = nullptr;
     uint16_t* lconn = nullptr;
     int32_t* part_off = nullptr;
     void* coef = nullptr;      // [6][E] Real, off-diagonals a01 a02 a03 a12 a13 a23
     void* u = nullptr;         // [N] Real, 1/V_i, or -1 for Dirichlet nodes
     void* q = nullptr;         // [N] Real, active nodal source [W]
     void* T_[2] = {nullptr, nullptr};  // state: float2 (hi, lo) or double
-    void* partial = nullptr;   // [P] Real, node-major
+    void* partial = nullptr;   // [P] Real, tile-major
     // scheduled source patterns (fedfem_set_schedule): node i receives
     // sum_p amp[j][p] pat[p][i] on top of q in the j-th step of a graph chunk
     void* pat = nullptr;       // [n_pat][N] Real

@@ -362,7 +362,7 @@ __global__ void k_lz_scale(int64_t N, const double* __restrict__ norm, const dou
 }
 
 __global__ void k_lz_w(int64_t N, const int32_t* __restrict__ part_off,
-                       const double* __restrict__ partial,
+                       const int32_t* __restrict__ pidx, const double* __restrict__ partial,
                        const double* __restrict__ sc, const double* __restrict__ v,
                        const double* __restrict__ vprev, const double* __restrict__ beta_j,
                        double* __restrict__ w, double* __restrict__ bsum) {
@@ -371,7 +371,7 @@ __global__ void k_lz_w(int64_t N, const int32_t* __restrict__ part_off,
     double prod = 0.0;
     if (i < N) {
         double F = 0.0;
-        for (int k = part_off[i]; k < part_off[i + 1]; k++) F += partial[k];
+        for (int k = part_off[i]; k < part_off[i + 1]; k++) F += partial[pidx[k]];
         const double wi = sc[i] * F - beta_j[0] * vprev[i];
         w[i] = wi;
         prod = v[i] * wi;
@@ -533,7 +533,7 @@ hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64, double 
     const unsigned nb = blocks_for(d.N);
     hipError_t e = launch_geometry_apply(d, coef64, xs, partial, fx_scale, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lz_w, dim3(nb), dim3(kBlock), 0, s, d.N, d.part_off, partial, sc, v,
+    hipLaunchKernelGGL(k_lz_w, dim3(nb), dim3(kBlock), 0, s, d.N, d.part_off, d.pidx, partial, sc, v,
                        vprev, beta + j, w, bsum);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, alpha + j, 0);
     hipLaunchKernelGGL(k_lz_orth, dim3(nb), dim3(kBlock), 0, s, d.N, alpha + j, v, w, bsum);

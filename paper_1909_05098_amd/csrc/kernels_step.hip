@@ -19,12 +19,13 @@
 // atomics.  S is chosen per scenario so that the largest possible load maps
 // below 2^58 (see the pre-computation), leaving 5 bits of headroom for the
 // sum; loads are resolved to 2^-S, far below float precision of any load.
-// Each tile node's sum, converted back once, is written as one partial, node
-// major, so the node pass reads a node's partials contiguously.
+// Each tile node's sum, converted back once, is written as one partial at
+// its tile-node slot, so every tile writes one contiguous, coalesced run; the
+// node pass finds a node's slots through a node-major index.
 //
-// Node pass (Eq 11, 19): one thread per node adds its partials in ascending
-// tile order and applies the explicit update with lumped capacity,
-// perfusion, metabolic heat and the nodal source.  In the compensated float
+// Node pass (Eq 11, 19): one thread per node adds its partials (gathered
+// through the index) in ascending tile order and applies the explicit update
+// with lumped capacity, perfusion, metabolic heat and the nodal source.  In the compensated float
 // mode T is an interleaved (hi, lo) pair; the increment is added with an
 // error-free TwoSum and the rounding error folded into lo (Knuth's TwoSum,
 // Dekker's Fast2Sum renormalisation).  Dirichlet nodes (u <= 0) are never
@@ -139,7 +140,7 @@ struct TileArgs {
     const int32_t* tile_elem_off;
     const int32_t* tile_node_off;
     const int32_t* tile_nodes;
-    const int32_t* wpos;
+    const int32_t* pidx;
     const uint16_t* lconn;
 };
 
@@ -232,9 +233,8 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
         }
     }
     __syncthreads();
-    // 4. one partial per tile node, node-major
-    for (int j = tid; j < m; j += bs)
-        partial[a.wpos[p0 + j]] = (Real)(long long)s_acc[j] * pr.fxi;
+    // 4. one partial per tile node, tile-major: one contiguous run per tile
+    for (int j = tid; j < m; j += bs) partial[p0 + j] = (Real)(long long)s_acc[j] * pr.fxi;
 }
 
 template <typename Real, bool COMP, bool TD, int R>
@@ -271,6 +271,7 @@ struct Sched {
 
 template <typename Real, bool COMP>
 __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict__ part_off,
+                                            const int32_t* __restrict__ pidx,
                                             const Real* __restrict__ partial,
                                             const Real* __restrict__ u,
                                             const Real* __restrict__ q,
@@ -280,8 +281,26 @@ __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict
     const Real ui = u[i];
     if (!(ui > Real(0))) return;  // Dirichlet node: held at T_Gamma
     const int a = part_off[i], b = part_off[i + 1];
+    // slots four at a time: the indices first, then independent gathers,
+    // added in ascending tile order as always
     Real F = 0;
-    for (int k = a; k < b; k++) F += partial[k];
+    int k = a;
+    for (; k + 4 <= b; k += 4) {
+        const int p0 = pidx[k], p1 = pidx[k + 1], p2 = pidx[k + 2], p3 = pidx[k + 3];
+        const Real f0 = partial[p0], f1 = partial[p1], f2 = partial[p2], f3 = partial[p3];
+        F += f0;
+        F += f1;
+        F += f2;
+        F += f3;
+    }
+    if (k < b) {
+        const int n = b - k;
+        const int p0 = pidx[k], p1 = n > 1 ? pidx[k + 1] : p0, p2 = n > 2 ? pidx[k + 2] : p0;
+        const Real f0 = partial[p0], f1 = partial[p1], f2 = partial[p2];
+        F += f0;
+        if (n > 1) F += f1;
+        if (n > 2) F += f2;
+    }
     Real qi = q[i];
     for (int p = 0; p < sch.n_pat; p++) qi += sch.amp[p] * sch.pat[p * sch.N + i];
     Real hi, lo;
@@ -311,14 +330,14 @@ __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict
 template <typename Real, bool COMP>
 __global__ void __launch_bounds__(256)
 k_node_update(int64_t N, int xcd, const int32_t* __restrict__ part_off,
-              const Real* __restrict__ partial, const Real* __restrict__ u,
+              const int32_t* __restrict__ pidx, const Real* __restrict__ partial, const Real* __restrict__ u,
               const Real* __restrict__ q, const void* __restrict__ Tin, void* __restrict__ Tout,
               Props<Real> pr, int* __restrict__ flag, Sched<Real> sch) {
     const int64_t nb = (N + 255) / 256;
     const int64_t blk = xcd ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
     const int64_t i = blk * 256 + threadIdx.x;
     if (i >= N) return;
-    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flag, sch);
+    node_update<Real, COMP>(i, part_off, pidx, partial, u, q, Tin, Tout, pr, flag, sch);
 }
 
 // Batched form: 256-node blocks never straddle scenarios; the block comes
@@ -327,7 +346,8 @@ template <typename Real, bool COMP>
 __global__ void __launch_bounds__(256)
 k_node_update_batch(const int32_t* __restrict__ block_list,
                     const int32_t* __restrict__ block_scen,
-                    const int32_t* __restrict__ part_off, const Real* __restrict__ partial,
+                    const int32_t* __restrict__ part_off, const int32_t* __restrict__ pidx,
+                    const Real* __restrict__ partial,
                     const Real* __restrict__ u, const Real* __restrict__ q,
                     const void* __restrict__ Tin, void* __restrict__ Tout,
                     const Props<Real>* __restrict__ props, int* __restrict__ flags) {
@@ -335,7 +355,7 @@ k_node_update_batch(const int32_t* __restrict__ block_list,
     const int sc = block_scen[blk];
     const Props<Real> pr = props[sc];
     const int64_t i = (int64_t)blk * 256 + threadIdx.x;
-    node_update<Real, COMP>(i, part_off, partial, u, q, Tin, Tout, pr, flags + sc,
+    node_update<Real, COMP>(i, part_off, pidx, partial, u, q, Tin, Tout, pr, flags + sc,
                             Sched<Real>{nullptr, nullptr, 0, 0});
 }
 
@@ -349,7 +369,7 @@ TileArgs tile_args(const DevLayout& d) {
     a.tile_elem_off = d.tile_elem_off;
     a.tile_node_off = d.tile_node_off;
     a.tile_nodes = d.tile_nodes;
-    a.wpos = d.wpos;
+    a.pidx = d.pidx;
     a.lconn = d.lconn;
     return a;
 }
@@ -412,7 +432,7 @@ hipError_t launch_node_t(const DevLayout& d, int cur, const Props<Real>& p, int*
                     d.n_pat ? static_cast<const Real*>(d.amp) + (int64_t)j * d.n_pat : nullptr,
                     d.n_pat, d.N};
     hipLaunchKernelGGL((k_node_update<Real, COMP>), dim3((unsigned)grid), dim3(256), 0, s, d.N,
-                       d.xcd, d.part_off, static_cast<const Real*>(d.partial),
+                       d.xcd, d.part_off, d.pidx, static_cast<const Real*>(d.partial),
                        static_cast<const Real*>(d.u), static_cast<const Real*>(d.q), d.T_[cur],
                        d.T_[1 - cur], p, flag, sch);
     return hipGetLastError();
@@ -514,13 +534,13 @@ hipError_t launch_node_batch(const DevLayout& d, const BatchTables& b, int cur, 
     if (n_blocks <= 0) return hipSuccess;
     if (fp32c)
         hipLaunchKernelGGL((k_node_update_batch<float, true>), dim3(n_blocks), dim3(256), 0, s,
-                           b.block_list, b.block_scen, d.part_off,
+                           b.block_list, b.block_scen, d.part_off, d.pidx,
                            static_cast<const float*>(d.partial), static_cast<const float*>(d.u),
                            static_cast<const float*>(d.q), d.T_[cur], d.T_[1 - cur],
                            static_cast<const Props<float>*>(b.props), flags);
     else
         hipLaunchKernelGGL((k_node_update_batch<double, false>), dim3(n_blocks), dim3(256), 0,
-                           s, b.block_list, b.block_scen, d.part_off,
+                           s, b.block_list, b.block_scen, d.part_off, d.pidx,
                            static_cast<const double*>(d.partial),
                            static_cast<const double*>(d.u), static_cast<const double*>(d.q),
                            d.T_[cur], d.T_[1 - cur], static_cast<const Props<double>*>(b.props),

@@ -202,10 +202,10 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     L.part_off.assign(N + 1, 0);
     for (int64_t p = 0; p < P; p++) L.part_off[L.tile_nodes[p] + 1]++;
     for (int64_t i = 0; i < N; i++) L.part_off[i + 1] += L.part_off[i];
-    L.wpos.assign(P, 0);
+    L.pidx.assign(P, 0);
     {
         std::vector<int32_t> fill(L.part_off.begin(), L.part_off.end() - 1);
-        for (int64_t p = 0; p < P; p++) L.wpos[p] = fill[L.tile_nodes[p]]++;
+        for (int64_t p = 0; p < P; p++) L.pidx[fill[L.tile_nodes[p]]++] = (int32_t)p;
     }
     return true;
 }
