@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
         };
         bf16x8 A[4], B[NT];
         load(0, A, B);
-#pragma unroll 3
+#pragma unroll
         for (int off = 0; off < 27; off++) {
             // the next offset's fragments are in flight while this one multiplies
             bf16x8 An[4], Bn[NT];
