@@ -167,17 +167,19 @@ __global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
 // LDS-staged 3x3x3 convolution for cin % 32 == 0 and G >= 8.  A workgroup
 // owns a brick of 256 voxels of one sample (BX x BY x BZ, x fastest) and
 // walks the input channels 32 at a time: it stages the brick and its one-
-// voxel halo (32 channels, rows padded to 80 bytes) in LDS, then for each of
-// the 27 offsets every wave reads its four 16-voxel A fragments from LDS
-// (K = the 32 channels of that offset) and the weights from global memory
-// (shared by all waves, so mostly cache hits).  Each wave computes 64
-// voxels x (16 NT) output channels; blockIdx.y selects 64 output channels.
+// voxel halo in LDS as four planes of 16-byte channel groups (plane g holds
+// channels 8g..8g+7 of every halo voxel, so the 16 consecutive voxels of a
+// fragment read 256 contiguous bytes and the offset enters the address
+// linearly), then for each of the 27 offsets every wave reads its four
+// 16-voxel A fragments from LDS (K = the 32 channels of that offset) and the
+// weights from global memory (shared by all waves, so mostly cache hits).
+// Each wave computes 64 voxels x (16 NT) output channels; blockIdx.y selects
+// 64 output channels.
 constexpr int kHaloMax = 720;  // (2+2) x (8+2) x (16+2)
-constexpr int kHaloPitch = 40;  // 32 channels + 8 pad (bf16)
 
 template <int NT>
 __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, int BZ) {
-    __shared__ __align__(16) bf16 halo[kHaloMax][kHaloPitch];
+    __shared__ bf16x8 halo[4][kHaloMax];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int G = a.G;
     const int HX = BX + 2, HY = BY + 2, HZ = BZ + 2, H = HX * HY * HZ;
@@ -202,55 +204,61 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kg = (lane >> 4) * 8;
+    // weight fragments of offset `off` come from memory (L2) and are fetched
+    // two offsets ahead through a ring of three register sets; the halo
+    // fragments come from LDS one offset ahead
+    auto loadB = [&](int c0, int off, bf16x8 (&B)[NT]) {
+        const int k = off * a.cin + c0 + kg;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int co = n0 + nt * 16 + (lane & 15);
+            B[nt] = co < a.cout ? *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k)
+                                : zero8();
+        }
+    };
+    auto loadA = [&](int off, bf16x8 (&A)[4]) {
+        const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
+        const int dh = (dz * HY + dy) * HX + dx;
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+            A[mt] = halo[lane >> 4][hv[mt] + dh];
+    };
+    bf16x8 Bq[3][NT];
     for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        loadB(c0, 0, Bq[0]);
+        loadB(c0, 1, Bq[1]);
         __syncthreads();  // the previous chunk's fragments have been read
+        // 64 consecutive threads stage 16 consecutive halo voxels x 4 groups
 #pragma unroll 4
-        for (int q = t; q < H * 4; q += 256) {
-            const int h = q >> 2, part = (q & 3) * 8;
+        for (int q = t; q < ((H + 15) >> 4) * 64; q += 256) {
+            const int h = (q >> 6) * 16 + (q & 15), grp = (q >> 4) & 3;
+            if (h >= H) continue;
             const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
             const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
             bf16x8 v = zero8();
             if (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
                 const int64_t gv = ((bs * G + z) * G + y) * G + x;
-                v = *reinterpret_cast<const bf16x8*>(a.in + gv * a.ip + a.io + c0 + part);
+                v = *reinterpret_cast<const bf16x8*>(a.in + gv * a.ip + a.io + c0 + grp * 8);
             }
-            *reinterpret_cast<bf16x8*>(&halo[h][part]) = v;
+            halo[grp][h] = v;
         }
         __syncthreads();
-        // fragments of offset `off`: A from the halo, B (weights) from memory
-        auto load = [&](int off, bf16x8 (&A)[4], bf16x8 (&B)[NT]) {
-            const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
-            const int dh = (dz * HY + dy) * HX + dx;
-            const int k = off * a.cin + c0 + kg;
-#pragma unroll
-            for (int nt = 0; nt < NT; nt++) {
-                const int co = n0 + nt * 16 + (lane & 15);
-                B[nt] = co < a.cout
-                            ? *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k)
-                            : zero8();
-            }
-#pragma unroll
-            for (int mt = 0; mt < 4; mt++)
-                A[mt] = *reinterpret_cast<const bf16x8*>(&halo[hv[mt] + dh][kg]);
-        };
-        bf16x8 A[4], B[NT];
-        load(0, A, B);
+        bf16x8 A[4];
+        loadA(0, A);
 #pragma unroll
         for (int off = 0; off < 27; off++) {
-            // the next offset's fragments are in flight while this one multiplies
-            bf16x8 An[4], Bn[NT];
-            if (off + 1 < 27) load(off + 1, An, Bn);
+            if (off + 2 < 27) loadB(c0, off + 2, Bq[(off + 2) % 3]);
+            bf16x8 An[4];
+            if (off + 1 < 27) loadA(off + 1, An);
 #pragma unroll
             for (int mt = 0; mt < 4; mt++)
 #pragma unroll
                 for (int nt = 0; nt < NT; nt++)
-                    acc[mt][nt] =
-                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bq[off % 3][nt],
+                                                                          acc[mt][nt], 0, 0, 0);
             if (off + 1 < 27) {
 #pragma unroll
                 for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++) B[nt] = Bn[nt];
             }
         }
     }
