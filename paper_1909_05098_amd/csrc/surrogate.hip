@@ -345,6 +345,7 @@ template <int MT, int NT, int WM, int WN>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     constexpr int COT = 16 * MT * WM, KN = 16 * NT * WN, LP = 72;
     static_assert(WM * WN == 4, "four waves");
+    static_assert(KN <= 256 && COT <= 256, "at most one staging block of each kind per thread");
     __shared__ __align__(16) bf16 sD[COT][LP];
     __shared__ __align__(16) bf16 sX[KN][LP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -355,61 +356,76 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     const int G = a.G;
     const int64_t G3 = (int64_t)G * G * G;
     const int K = 27 * a.cin;
+    // staging blocks of this thread, the same for every chunk: the input
+    // block of k-group t / 8 (8 consecutive k never straddle an offset or K,
+    // as cin % 8 == 0) and the gradient block of channel group t / 8, both
+    // over voxel group t % 8 of the chunk
+    const int vg = t & 7;
+    const bool hasX = t < KN, hasD = t < COT;
+    const int kk = k0 + (t >> 3) * 8;
+    const bool xdata = hasX && kk < K;
+    int ci = 0, dz = 0, dy = 0, dx = 0;
+    if (xdata) {
+        const int off = kk / a.cin;
+        ci = kk - off * a.cin;
+        dz = off / 9 - 1;
+        dy = (off / 3) % 3 - 1;
+        dx = off % 3 - 1;
+    }
+    const int co = co0 + (t >> 3) * 8;
+    const bool ddata = hasD && co < a.cout;
+    // registers of one chunk's blocks; the next chunk's loads are in flight
+    // while the current chunk is multiplied
+    bf16x8 rX[8], rD[8];
+    auto fetch = [&](int64_t vc) {
+        const int64_t v0 = vc + vg * 8;
+        if (xdata) {
+            int64_t b = v0 / G3;
+            const int64_t r = v0 - b * G3;
+            int z = (int)(r / ((int64_t)G * G)), y = (int)((r / G) % G), x = (int)(r % G);
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                rX[i] = zero8();
+                const int z2 = z + dz, y2 = y + dy, x2 = x + dx;
+                if (v0 + i < ve && z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 && x2 < G) {
+                    const int64_t nv = ((b * G + z2) * G + y2) * G + x2;
+                    rX[i] = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + ci);
+                }
+                if (++x == G) {  // next voxel in x-fastest order
+                    x = 0;
+                    if (++y == G) {
+                        y = 0;
+                        if (++z == G) {
+                            z = 0;
+                            ++b;
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                rX[i] = zero8();
+                if (kk == K && v0 + i < ve) rX[i][0] = (bf16)1.0f;  // bias column
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            rD[i] = (ddata && v0 + i < ve)
+                        ? *reinterpret_cast<const bf16x8*>(a.d + (v0 + i) * a.dp + a.doff + co)
+                        : zero8();
+    };
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (vs < ve) fetch(vs);
     for (int64_t vc = vs; vc < ve; vc += 64) {
-        // input blocks: KN / 8 k-groups x 8 voxel-groups; a k-group of 8
-        // consecutive k never straddles an offset or K (cin % 8 == 0)
-        for (int blk = t; blk < KN; blk += 256) {
-            const int kg = blk >> 3, vg = blk & 7;
-            const int kk = k0 + kg * 8;
-            bf16x8 r[8];
-            if (kk < K) {
-                const int off = kk / a.cin;
-                const int ci = kk - off * a.cin;
-                const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
-#pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    const int64_t v = vc + vg * 8 + i;
-                    r[i] = zero8();
-                    if (v < ve) {
-                        const int64_t b = v / G3;
-                        const int64_t rr = v - b * G3;
-                        const int z2 = (int)(rr / ((int64_t)G * G)) + dz;
-                        const int y2 = (int)((rr / G) % G) + dy;
-                        const int x2 = (int)(rr % G) + dx;
-                        if (z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 && x2 < G) {
-                            const int64_t nv = ((b * G + z2) * G + y2) * G + x2;
-                            r[i] = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + ci);
-                        }
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 8; i++) {
-                    r[i] = zero8();
-                    if (kk == K && vc + vg * 8 + i < ve) r[i][0] = (bf16)1.0f;  // bias column
-                }
-            }
-            transpose_store8(r, &sX[kg * 8][vg * 8], LP);
-        }
-        // gradient blocks: COT / 8 channel-groups x 8 voxel-groups
-        for (int blk = t; blk < COT; blk += 256) {
-            const int cg = blk >> 3, vg = blk & 7;
-            const int co = co0 + cg * 8;
-            bf16x8 r[8];
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const int64_t v = vc + vg * 8 + i;
-                r[i] = (v < ve && co < a.cout)
-                           ? *reinterpret_cast<const bf16x8*>(a.d + v * a.dp + a.doff + co)
-                           : zero8();
-            }
-            transpose_store8(r, &sD[cg * 8][vg * 8], LP);
-        }
+        __syncthreads();  // the previous chunk's fragments have been read
+        if (hasX) transpose_store8(rX, &sX[(t >> 3) * 8][vg * 8], LP);
+        if (hasD) transpose_store8(rD, &sD[(t >> 3) * 8][vg * 8], LP);
+        if (vc + 64 < ve) fetch(vc + 64);
         __syncthreads();
 #pragma unroll
         for (int s2 = 0; s2 < 2; s2++) {
@@ -428,7 +444,6 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
                     acc[mt][nt] =
                         __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bf[nt], acc[mt][nt], 0, 0, 0);
         }
-        __syncthreads();
     }
     // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
 #pragma unroll
