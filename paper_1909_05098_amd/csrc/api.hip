@@ -626,9 +626,24 @@ int fedfem_precompute(fedfem_handle* h) {
     while (elems_per_thread(d) > 4 && d.threads < 1024) d.threads *= 2;
     d.xcd = h->opt.xcd;
     // topology
+    try {
+        pack_lconn(L);
+    } catch (const std::bad_alloc&) {
+        return set_err(h, FEDFEM_E_NOMEM, "host allocation failed");
+    }
+    d.lconn_pk = L.lconn_pk.empty() ? 0 : 1;
+    if (d.lconn_pk) {
+        uint8_t* p = nullptr;
+        if ((rc = upload(h, &p, L.lconn_pk))) return rc;
+        d.lconn = p;
+    } else {
+        uint16_t* p = nullptr;
+        if ((rc = upload(h, &p, L.lconn))) return rc;
+        d.lconn = p;
+    }
     if ((rc = upload(h, &d.tile_elem_off, L.tile_elem_off)) ||
         (rc = upload(h, &d.tile_node_off, L.tile_node_off)) ||
-        (rc = upload(h, &d.tile_nodes, L.tile_nodes)) || (rc = upload(h, &d.lconn, L.lconn)) ||
+        (rc = upload(h, &d.tile_nodes, L.tile_nodes)) ||
         (rc = upload(h, &d.pidx, L.pidx)) || (rc = upload(h, &d.part_off, L.part_off)) ||
         (rc = upload(h, &h->d_ec_off, L.ec_off)) || (rc = upload(h, &h->d_ec, L.ec)) ||
         (rc = upload(h, &h->d_conn, L.conn)) || (rc = upload(h, &h->d_xyz, L.xyz)) ||
@@ -803,6 +818,7 @@ int fedfem_precompute(fedfem_handle* h) {
     std::vector<double>().swap(L.xyz);
     std::vector<int32_t>().swap(L.conn);
     std::vector<uint16_t>().swap(L.lconn);
+    std::vector<uint8_t>().swap(L.lconn_pk);
     std::vector<int32_t>().swap(L.ec);
     return FEDFEM_OK;
 }

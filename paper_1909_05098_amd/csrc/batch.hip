@@ -231,7 +231,13 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
         *p = q;
         return e;
     };
-    BCHK(balloc(b, &d.lconn, 4 * Et));
+    // corner ids stay packed when every scenario's are; otherwise packed
+    // scenarios are expanded to u16 on the device
+    d.lconn_pk = 1;
+    for (int j = 0; j < n; j++) d.lconn_pk &= handles[j]->d.lconn_pk;
+    unsigned char* lc = nullptr;
+    BCHK(balloc(b, &lc, (d.lconn_pk ? 5 : 8) * Et));
+    d.lconn = lc;
     BCHK(ralloc(&d.coef, 6 * Et));
     BCHK(ralloc(&d.u, Nt));
     BCHK(ralloc(&d.q, Nt));
@@ -258,8 +264,17 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     for (int j = 0; j < n; j++) {
         const fedfem_handle* h = handles[j];
         const int64_t no = b->node_off[j], eo = b->elem_off[j];
-        BCHK(hipMemcpyAsync(d.lconn + 4 * eo, h->d.lconn, 4 * h->E * sizeof(uint16_t),
-                            hipMemcpyDeviceToDevice, b->stream));
+        const unsigned char* hl = static_cast<const unsigned char*>(h->d.lconn);
+        if (d.lconn_pk) {
+            BCHK(hipMemcpyAsync(lc + 4 * eo, hl, 4 * h->E, hipMemcpyDeviceToDevice, b->stream));
+            BCHK(hipMemcpyAsync(lc + 4 * Et + eo, hl + 4 * h->E, h->E, hipMemcpyDeviceToDevice,
+                                b->stream));
+        } else if (h->d.lconn_pk) {
+            BCHK(launch_lconn_unpack(hl, h->E, reinterpret_cast<uint16_t*>(lc) + 4 * eo,
+                                     b->stream));
+        } else {
+            BCHK(hipMemcpyAsync(lc + 8 * eo, hl, 8 * h->E, hipMemcpyDeviceToDevice, b->stream));
+        }
         for (int k = 0; k < 6; k++)
             BCHK(hipMemcpyAsync(static_cast<unsigned char*>(d.coef) + (k * Et + eo) * rb,
                                 static_cast<const unsigned char*>(h->d.coef) + k * h->E * rb,

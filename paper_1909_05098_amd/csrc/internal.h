@@ -36,6 +36,7 @@ struct Layout {
     std::vector<int32_t> tile_nodes;     // [P]
     std::vector<int32_t> pidx;           // [P] node-major list of partial slots p
     std::vector<uint16_t> lconn;         // [4E] local node id per corner
+    std::vector<uint8_t> lconn_pk;       // packed form of lconn (pack_lconn)
     std::vector<int32_t> part_off;       // [N+1] node -> partial positions
     std::vector<int32_t> ec_off;         // [N+1] node -> element corners
     std::vector<int32_t> ec;             // [4E] e*4+corner, ascending e
@@ -49,6 +50,14 @@ bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
 // Tile layout only (used again when tiles must shrink).
 bool build_tiles(Layout& L, int tile_elems, int max_tile_nodes,
                  std::string& err);
+
+// Tiles of at most kPackedMaxNodes nodes store their local corner ids in 10
+// bits each, 5 bytes per element instead of 8: an array of E 32-bit words
+// (ids 0, 1, 2 and the low 2 bits of id 3 at bits 0, 10, 20, 30) followed by
+// an array of E bytes (the high 8 bits of id 3).  pack_lconn fills
+// L.lconn_pk when the layout qualifies and clears it otherwise.
+constexpr int kPackedMaxNodes = 1024;
+void pack_lconn(Layout& L);
 
 // Morton (Z-order) permutation of points; returns new -> old.
 std::vector<int32_t> morton_order(const double* pts, int64_t n);
@@ -86,7 +95,8 @@ struct DevLayout {
     int32_t* tile_node_off = nullptr;
     int32_t* tile_nodes = nullptr;
     int32_t* pidx = nullptr;
-    uint16_t* lconn = nullptr;
+    void* lconn = nullptr;     // packed (lconn_pk = 1) or [4E] u16
+    int lconn_pk = 0;
     int32_t* part_off = nullptr;
     void* coef = nullptr;      // [6][E] Real, off-diagonals a01 a02 a03 a12 a13 a23
     void* u = nullptr;         // [N] Real, 1/V_i, or -1 for Dirichlet nodes
@@ -132,6 +142,9 @@ struct BatchTables {
     const int32_t* block_scen = nullptr;     // [NB]
     const void* props = nullptr;             // Props<Real>[S]
 };
+// Expand packed corner ids of E elements to [4E] u16.
+hipError_t launch_lconn_unpack(const void* packed, int64_t E, uint16_t* out,
+                               hipStream_t s);
 hipError_t launch_elem_batch(const DevLayout& d, const BatchTables& b, int cur,
                              int n_tiles, int fp32c, hipStream_t s);
 hipError_t launch_node_batch(const DevLayout& d, const BatchTables& b, int cur,

@@ -141,8 +141,25 @@ struct TileArgs {
     const int32_t* tile_node_off;
     const int32_t* tile_nodes;
     const int32_t* pidx;
-    const uint16_t* lconn;
+    const void* lconn;  // packed 10-bit ids (lconn_pk) or [4E] u16
+    int lconn_pk;
 };
+
+// The four tile-local corner ids of one element from its raw connectivity
+// record: (word, high byte) of the packed form, or two words of u16 pairs.
+__device__ __forceinline__ void corner_ids(uint2 r, bool pk, int (&n)[4]) {
+    if (pk) {
+        n[0] = (int)(r.x & 1023u);
+        n[1] = (int)((r.x >> 10) & 1023u);
+        n[2] = (int)((r.x >> 20) & 1023u);
+        n[3] = (int)((r.x >> 30) | (r.y << 2));
+    } else {
+        n[0] = (int)(r.x & 0xffffu);
+        n[1] = (int)(r.x >> 16);
+        n[2] = (int)(r.y & 0xffffu);
+        n[3] = (int)(r.y >> 16);
+    }
+}
 
 __device__ __forceinline__ long long to_fixed(float f, float scale) {
     return __float2ll_rn(f * scale);
@@ -172,14 +189,17 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
     // 1. coefficient and local-connectivity loads in flight during staging
     Real cf[R][6];
     uint2 lc[R];
-    const uint2* glc = reinterpret_cast<const uint2*>(a.lconn) + e0;
+    const bool pk = a.lconn_pk != 0;
+    const uint2* glc = static_cast<const uint2*>(a.lconn) + e0;
+    const uint32_t* gw = static_cast<const uint32_t*>(a.lconn) + e0;
+    const uint8_t* gb = static_cast<const uint8_t*>(a.lconn) + 4 * a.E + e0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int el = tid + r * bs;
         if (el < ne) {
 #pragma unroll
             for (int k = 0; k < 6; k++) cf[r][k] = coef[k * a.E + e0 + el];
-            lc[r] = glc[el];
+            lc[r] = pk ? make_uint2(gw[el], gb[el]) : glc[el];
         }
     }
     // 2. tile nodes: temperature, conductivity, zeroed accumulators
@@ -198,8 +218,8 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
     for (int r = 0; r < R; r++) {
         const int el = tid + r * bs;
         if (el < ne) {
-            const int n[4] = {(int)(lc[r].x & 0xffff), (int)(lc[r].x >> 16),
-                              (int)(lc[r].y & 0xffff), (int)(lc[r].y >> 16)};
+            int n[4];
+            corner_ids(lc[r], pk, n);
             const Real h0 = s_T[n[0]], h1 = s_T[n[1]], h2 = s_T[n[2]], h3 = s_T[n[3]];
             Real d01 = h1 - h0, d02 = h2 - h0, d03 = h3 - h0;
             Real d12 = h2 - h1, d13 = h3 - h1, d23 = h3 - h2;
@@ -371,7 +391,18 @@ TileArgs tile_args(const DevLayout& d) {
     a.tile_nodes = d.tile_nodes;
     a.pidx = d.pidx;
     a.lconn = d.lconn;
+    a.lconn_pk = d.lconn_pk;
     return a;
+}
+
+__global__ void k_lconn_unpack(const uint32_t* __restrict__ words, const uint8_t* __restrict__ high,
+                               int64_t E, ushort4* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int n[4];
+    corner_ids(make_uint2(words[e], high[e]), true, n);
+    out[e] = make_ushort4((unsigned short)n[0], (unsigned short)n[1], (unsigned short)n[2],
+                          (unsigned short)n[3]);
 }
 
 // Dynamic LDS above 64 KiB must be allowed per kernel.  The attribute is
@@ -520,6 +551,15 @@ hipError_t launch_geometry_apply(const DevLayout& d, const double* coef64, const
     p.fxs = fx_scale;
     p.fxi = 1.0 / fx_scale;
     return launch_elem_t<double, false, false>(d, coef64, p, x, partial, s);
+}
+
+hipError_t launch_lconn_unpack(const void* packed, int64_t E, uint16_t* out, hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    const uint32_t* w = static_cast<const uint32_t*>(packed);
+    const uint8_t* hb = static_cast<const uint8_t*>(packed) + 4 * E;
+    hipLaunchKernelGGL(k_lconn_unpack, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s, w, hb, E,
+                       reinterpret_cast<ushort4*>(out));
+    return hipGetLastError();
 }
 
 hipError_t launch_elem_batch(const DevLayout& d, const BatchTables& b, int cur, int n_tiles,

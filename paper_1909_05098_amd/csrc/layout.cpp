@@ -210,6 +210,24 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     return true;
 }
 
+void pack_lconn(Layout& L) {
+    std::vector<uint8_t>().swap(L.lconn_pk);
+    if (L.max_tile_nodes > kPackedMaxNodes) return;
+    const int64_t E = L.E;
+    L.lconn_pk.resize(5 * E);
+    uint8_t* words = L.lconn_pk.data();
+    uint8_t* high = words + 4 * E;
+    parallel_for(E, [&](int64_t a, int64_t b) {
+        for (int64_t e = a; e < b; e++) {
+            const uint16_t* c = &L.lconn[4 * e];
+            const uint32_t w = uint32_t(c[0]) | uint32_t(c[1]) << 10 | uint32_t(c[2]) << 20 |
+                               uint32_t(c[3] & 3) << 30;
+            std::memcpy(words + 4 * e, &w, 4);
+            high[e] = uint8_t(c[3] >> 2);
+        }
+    }, 65536);
+}
+
 bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
                   int reorder, int TE, int MN, Layout& L, std::string& err) {
     L = Layout();

@@ -31,9 +31,9 @@ def scenarios():
     return out
 
 
-def make(s, dt):
+def make(s, dt, **opt):
     h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=dt,
-                  precision=ff.FP32C)
+                  precision=ff.FP32C, **opt)
     h.precompute()
     h.set_gaussian_sources(s.sources, s.source_mode)
     return h
@@ -69,6 +69,28 @@ def test_batch_equals_single_and_oracle(scenarios):
         assert np.array_equal(h1.read_state()[0], h2.read_state()[0])
     assert np.array_equal(hb[2].read_state()[0], before)
     b.close()
+
+
+def test_batch_of_packed_and_16_bit_corner_ids(scenarios):
+    """Scenarios whose tiles exceed 1024 nodes keep 16-bit corner ids; a batch
+    mixing them with packed scenarios expands the packed ones and must still
+    equal per-handle stepping bit for bit."""
+    wide = dict(reorder=False, tile_elems=4096)
+    picks = [(scenarios[k], wide if k % 2 else {}) for k in range(4)]
+    hb = [make(s, dt, **o) for (s, _, _, _, dt), o in picks]
+    hs = [make(s, dt, **o) for (s, _, _, _, dt), o in picks]
+    nodes = [h.info()["max_tile_nodes"] for h in hb]
+    print(f"[batch] max tile nodes {nodes}", flush=True)
+    assert any(m > 1024 for m in nodes) and any(m <= 1024 for m in nodes)
+    ns = np.array([n // 2 for (_, _, _, n, _), _ in picks])
+    b = ff.Batch(hb)
+    b.run(ns)
+    for h1, h2, k in zip(hb, hs, ns):
+        h2.step(int(k))
+        assert np.array_equal(h1.read_state()[0], h2.read_state()[0])
+    b.close()
+    for h in hb + hs:
+        h.close()
 
 
 def test_batch_rejects_mixed_or_unprepared(scenarios):

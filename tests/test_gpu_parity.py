@@ -124,6 +124,28 @@ def test_td_jittered_box(prec, reorder, tile):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
+def test_wide_tiles_keep_16_bit_corner_ids(prec):
+    """Tiles of more than 1024 nodes keep 16-bit local corner ids (smaller
+    tiles use the packed 10-bit form); both forms must give the oracle's
+    temperatures."""
+    xyz, tets, bnd = jittered_box(16, 16, 8, 1e-3, seed=23)
+    mat = sc.td_materials()
+    src = np.array([[8e-3, 8e-3, 4e-3, 2e-3, 4e8]])
+    om, q, T_ref = oracle_run(xyz, tets, mat, bnd, src, sc.SOURCE_CONSISTENT, 200)
+    for reorder, tile in ((0, 4096), (1, 1024)):
+        h = gpu_handle(xyz, tets, mat, bnd, om.dt, prec, reorder=bool(reorder), tile_elems=tile)
+        wide = h.info()["max_tile_nodes"]
+        h.set_gaussian_sources(src, ff.SOURCE_CONSISTENT)
+        h.step(200)
+        err = float(np.max(np.abs(h.read_T() - T_ref)))
+        print_case(f"tile nodes {wide} prec={prec} reorder={reorder} tile={tile}", err,
+                   f"peak={T_ref.max():.2f}")
+        assert (wide > 1024) == (tile == 4096)
+        assert err <= TOL[prec]
+        h.close()
+
+
 def test_nodal_and_consistent_sources_fp64():
     xyz, tets, bnd = jittered_box(8, 8, 8, 1e-3, seed=3)
     mat = sc.td_materials()
