@@ -298,9 +298,15 @@ __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict
                                             const void* __restrict__ Tin, void* __restrict__ Tout,
                                             const Props<Real>& pr, int* __restrict__ flag,
                                             const Sched<Real>& sch) {
+    // every load that depends only on i is issued before any other, so a
+    // node waits for three rounds of memory latency: these, the slot
+    // indices, the partials
     const Real ui = u[i];
-    if (!(ui > Real(0))) return;  // Dirichlet node: held at T_Gamma
     const int a = part_off[i], b = part_off[i + 1];
+    const Real q0 = q[i];
+    Real hi, lo;
+    State<Real, COMP>::load(Tin, i, hi, lo);
+    if (!(ui > Real(0))) return;  // Dirichlet node: held at T_Gamma
     // slots four at a time: the indices first, then independent gathers,
     // added in ascending tile order as always
     Real F = 0;
@@ -321,10 +327,8 @@ __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict
         if (n > 1) F += f1;
         if (n > 2) F += f2;
     }
-    Real qi = q[i];
+    Real qi = q0;
     for (int p = 0; p < sch.n_pat; p++) qi += sch.amp[p] * sch.pat[p * sch.N + i];
-    Real hi, lo;
-    State<Real, COMP>::load(Tin, i, hi, lo);
     const Real rc = prop_rho_c(hi, pr);
     // heat flow per unit volume [W/m^3]: source and conduction per lumped
     // volume, metabolic heat, perfusion towards T_a
