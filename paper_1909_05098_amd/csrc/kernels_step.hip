@@ -289,8 +289,11 @@ struct Sched {
     int64_t N;
 };
 
-template <typename Real, bool COMP>
-__device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict__ part_off,
+// NPT nodes per thread (indices at or above N are skipped): their chains of
+// dependent loads (node data, slot indices, partials) run side by side.
+template <typename Real, bool COMP, int NPT>
+__device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
+                                            const int32_t* __restrict__ part_off,
                                             const int32_t* __restrict__ pidx,
                                             const Real* __restrict__ partial,
                                             const Real* __restrict__ u,
@@ -298,58 +301,67 @@ __device__ __forceinline__ void node_update(int64_t i, const int32_t* __restrict
                                             const void* __restrict__ Tin, void* __restrict__ Tout,
                                             const Props<Real>& pr, int* __restrict__ flag,
                                             const Sched<Real>& sch) {
-    // every load that depends only on i is issued before any other, so a
-    // node waits for three rounds of memory latency: these, the slot
-    // indices, the partials
-    const Real ui = u[i];
-    const int a = part_off[i], b = part_off[i + 1];
-    const Real q0 = q[i];
-    Real hi, lo;
-    State<Real, COMP>::load(Tin, i, hi, lo);
-    if (!(ui > Real(0))) return;  // Dirichlet node: held at T_Gamma
-    // slots four at a time: the indices first, then independent gathers,
-    // added in ascending tile order as always
-    Real F = 0;
-    int k = a;
-    for (; k + 4 <= b; k += 4) {
-        const int p0 = pidx[k], p1 = pidx[k + 1], p2 = pidx[k + 2], p3 = pidx[k + 3];
-        const Real f0 = partial[p0], f1 = partial[p1], f2 = partial[p2], f3 = partial[p3];
-        F += f0;
-        F += f1;
-        F += f2;
-        F += f3;
+    // every load that depends only on the node first, so a node waits for
+    // three rounds of memory latency: these, the slot indices, the partials
+    Real ui[NPT], q0[NPT], hi[NPT], lo[NPT];
+    int a[NPT], n[NPT];
+#pragma unroll
+    for (int v = 0; v < NPT; v++) {
+        const int64_t i = iv[v] < N ? iv[v] : 0;
+        ui[v] = u[i];
+        a[v] = part_off[i];
+        n[v] = part_off[i + 1] - a[v];
+        q0[v] = q[i];
+        State<Real, COMP>::load(Tin, i, hi[v], lo[v]);
     }
-    if (k < b) {
-        const int n = b - k;
-        const int p0 = pidx[k], p1 = n > 1 ? pidx[k + 1] : p0, p2 = n > 2 ? pidx[k + 2] : p0;
-        const Real f0 = partial[p0], f1 = partial[p1], f2 = partial[p2];
-        F += f0;
-        if (n > 1) F += f1;
-        if (n > 2) F += f2;
+    // the first four slots of every node, indices then partials
+    int pk[NPT][4];
+    Real f[NPT][4];
+#pragma unroll
+    for (int v = 0; v < NPT; v++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) pk[v][k] = k < n[v] ? pidx[a[v] + k] : -1;
+#pragma unroll
+    for (int v = 0; v < NPT; v++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) f[v][k] = pk[v][k] >= 0 ? partial[pk[v][k]] : Real(0);
+#pragma unroll
+    for (int v = 0; v < NPT; v++) {
+        // Dirichlet nodes (u <= 0) are held at T_Gamma
+        if (iv[v] >= N || !(ui[v] > Real(0))) continue;
+        // partials added in ascending tile order
+        Real F = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (k < n[v]) F += f[v][k];
+        for (int k = 4; k < n[v]; k++) F += partial[pidx[a[v] + k]];
+        const int64_t i = iv[v];
+        Real qi = q0[v];
+        for (int p = 0; p < sch.n_pat; p++) qi += sch.amp[p] * sch.pat[p * sch.N + i];
+        const Real rc = prop_rho_c(hi[v], pr);
+        // heat flow per unit volume [W/m^3]: source and conduction per lumped
+        // volume, metabolic heat, perfusion towards T_a
+        const Real R = (qi - F) * ui[v] + pr.Qm + pr.wbcb * ((pr.Ta - hi[v]) - lo[v]);
+        const Real d = pr.dt * R / rc;
+        Real nh, nl = 0;
+        if (COMP) {
+            // TwoSum(hi, d) = s + err exactly
+            const Real s = hi[v] + d;
+            const Real bp = s - hi[v];
+            const Real err = (hi[v] - (s - bp)) + (d - bp);
+            const Real l2 = lo[v] + err;
+            // Fast2Sum(s, l2): |s| >= |l2|
+            nh = s + l2;
+            nl = l2 - (nh - s);
+        } else {
+            nh = hi[v] + d;
+        }
+        State<Real, COMP>::store(Tout, i, nh, nl);
+        if (!(nh < Real(kDivergeLimit) && nh > -Real(kDivergeLimit))) *flag = 1;
     }
-    Real qi = q0;
-    for (int p = 0; p < sch.n_pat; p++) qi += sch.amp[p] * sch.pat[p * sch.N + i];
-    const Real rc = prop_rho_c(hi, pr);
-    // heat flow per unit volume [W/m^3]: source and conduction per lumped
-    // volume, metabolic heat, perfusion towards T_a
-    const Real R = (qi - F) * ui + pr.Qm + pr.wbcb * ((pr.Ta - hi) - lo);
-    const Real d = pr.dt * R / rc;
-    Real nh, nl = 0;
-    if (COMP) {
-        // TwoSum(hi, d) = s + err exactly
-        const Real s = hi + d;
-        const Real bp = s - hi;
-        const Real err = (hi - (s - bp)) + (d - bp);
-        const Real l2 = lo + err;
-        // Fast2Sum(s, l2): |s| >= |l2|
-        nh = s + l2;
-        nl = l2 - (nh - s);
-    } else {
-        nh = hi + d;
-    }
-    State<Real, COMP>::store(Tout, i, nh, nl);
-    if (!(nh < Real(kDivergeLimit) && nh > -Real(kDivergeLimit))) *flag = 1;
 }
+
+constexpr int kNodesPerThread = 2;
 
 template <typename Real, bool COMP>
 __global__ void __launch_bounds__(256)
@@ -357,11 +369,15 @@ k_node_update(int64_t N, int xcd, const int32_t* __restrict__ part_off,
               const int32_t* __restrict__ pidx, const Real* __restrict__ partial, const Real* __restrict__ u,
               const Real* __restrict__ q, const void* __restrict__ Tin, void* __restrict__ Tout,
               Props<Real> pr, int* __restrict__ flag, Sched<Real> sch) {
-    const int64_t nb = (N + 255) / 256;
+    constexpr int64_t span = 256 * kNodesPerThread;
+    const int64_t nb = (N + span - 1) / span;
     const int64_t blk = xcd ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
-    const int64_t i = blk * 256 + threadIdx.x;
-    if (i >= N) return;
-    node_update<Real, COMP>(i, part_off, pidx, partial, u, q, Tin, Tout, pr, flag, sch);
+    if (blk >= nb) return;
+    int64_t iv[kNodesPerThread];
+#pragma unroll
+    for (int v = 0; v < kNodesPerThread; v++) iv[v] = blk * span + v * 256 + threadIdx.x;
+    node_update<Real, COMP, kNodesPerThread>(iv, N, part_off, pidx, partial, u, q, Tin, Tout, pr,
+                                             flag, sch);
 }
 
 // Batched form: 256-node blocks never straddle scenarios; the block comes
@@ -378,9 +394,9 @@ k_node_update_batch(const int32_t* __restrict__ block_list,
     const int blk = block_list[blockIdx.x];
     const int sc = block_scen[blk];
     const Props<Real> pr = props[sc];
-    const int64_t i = (int64_t)blk * 256 + threadIdx.x;
-    node_update<Real, COMP>(i, part_off, pidx, partial, u, q, Tin, Tout, pr, flags + sc,
-                            Sched<Real>{nullptr, nullptr, 0, 0});
+    const int64_t iv[1] = {(int64_t)blk * 256 + threadIdx.x};
+    node_update<Real, COMP, 1>(iv, INT64_MAX, part_off, pidx, partial, u, q, Tin, Tout, pr,
+                               flags + sc, Sched<Real>{nullptr, nullptr, 0, 0});
 }
 
 TileArgs tile_args(const DevLayout& d) {
@@ -461,7 +477,7 @@ hipError_t launch_elem_t(const DevLayout& d, const Real* coef, const Props<Real>
 template <typename Real, bool COMP>
 hipError_t launch_node_t(const DevLayout& d, int cur, const Props<Real>& p, int* flag,
                          hipStream_t s, int j) {
-    const int64_t nb = (d.N + 255) / 256;
+    const int64_t nb = (d.N + 256 * kNodesPerThread - 1) / (256 * kNodesPerThread);
     const int64_t grid = d.xcd ? (nb + kXcds - 1) / kXcds * kXcds : nb;
     Sched<Real> sch{static_cast<const Real*>(d.pat),
                     d.n_pat ? static_cast<const Real*>(d.amp) + (int64_t)j * d.n_pat : nullptr,
