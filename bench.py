@@ -48,9 +48,10 @@ def kernel_sha():
     return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
 
 
-def read_traffic(n_tets):
+def read_traffic(n_tets, tile_elems, threads, xcd):
     """HBM bytes per element-kernel launch from the committed PMC summary,
-    if it was taken on the current kernel source; else None."""
+    if it was taken on the current kernel source and on this layout (tile
+    size, workgroup size, XCD remap); else None."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     text = open(PMC_SUMMARY).read()
@@ -60,7 +61,8 @@ def read_traffic(n_tets):
             return None
         if int(vals["n_tets"]) != n_tets:
             return None
-        return float(vals["traffic_bytes_per_launch"])
+        key = f"traffic_bytes_per_launch_te{tile_elems}_th{threads}_xcd{xcd}"
+        return float(vals[key]) if key in vals else None
     except (KeyError, ValueError):
         return None
 
@@ -392,6 +394,7 @@ def main():
     h.precompute()
     t_pre = time.perf_counter() - t0
     info = h.info()
+    xcd = int(tuned["xcd"]) if tuned is not None else int(bool(args.xcd))
     dt, dt_cr = h.dt()
     log(f"precompute {t_pre:.2f} s, dt={dt:.6g} dt_cr={dt_cr:.6g}, tiles="
         f"{info['n_tiles']} partials={info['n_partials']} "
@@ -420,7 +423,8 @@ def main():
     # per-kernel durations with HIP events on the handle's stream
     elem_ms, node_ms = h.time_kernels(args.kernel_steps)
     # algorithmic bytes per element-update of the stencil: six f32 coefficients
-    # and four 32-bit node ids (the layout itself stores u16 tile-local ids)
+    # and four 32-bit node ids (the layout itself stores 10- or 16-bit
+    # tile-local ids)
     elem_bytes = 40.0 * E
     node_bytes = 24.0 * N   # T hi/lo read+write, 1/V_i, source
     kern = {"elem_loads": (elem_ms, elem_bytes), "node_update": (node_ms, node_bytes)}
@@ -430,7 +434,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": read_traffic(E) if dom == "elem_loads" else None,
+                "traffic": (read_traffic(E, info["tile_elems"], info["threads"], xcd)
+                            if dom == "elem_loads" else None),
                 "algorithmic_bytes_per_launch": by, "avg_launch_ms": round(ms, 5)}
     other = [k for k in kern if k != dom][0]
     step_gbps = (elem_bytes + node_bytes) / (ms_step * 1e-3) / 1e9
@@ -454,6 +459,7 @@ def main():
                    "n_tets": E, "n_nodes": N, "dt_s": dt,
                    "precision": "f32 element loop, compensated f32 hi/lo nodal state, f64 precompute",
                    "tile_elems": info["tile_elems"], "threads": info["threads"],
+                   "xcd": xcd,
                    "autotuned": tuned is not None,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
