@@ -395,33 +395,52 @@ int lanczos(fedfem_handle* h, const double* coef64) {
     const int64_t N = h->N;
     const int maxit = h->lz_max_iter;
     double *sc, *v, *vprev, *w, *xs, *partial, *bsum, *alpha, *beta, *scal;
+    int32_t* counter = nullptr;
     int rc = 0;
     const int64_t nb = (N + 255) / 256;
     if ((rc = dalloc(h, &sc, N)) || (rc = dalloc(h, &v, N)) || (rc = dalloc(h, &vprev, N)) ||
         (rc = dalloc(h, &w, N)) || (rc = dalloc(h, &xs, N)) ||
         (rc = dalloc(h, &partial, h->d.P)) || (rc = dalloc(h, &bsum, nb)) ||
         (rc = dalloc(h, &alpha, maxit + 1)) || (rc = dalloc(h, &beta, maxit + 2)) ||
-        (rc = dalloc(h, &scal, 4)))
+        (rc = dalloc(h, &scal, 4)) || (rc = dalloc(h, &counter, 1)))
         return rc;
     HIPCHK(h, hipMemsetAsync(beta, 0, sizeof(double) * (maxit + 2), h->own_stream));
+    HIPCHK(h, launch_fill_i32(counter, 1, 0, h->own_stream));
     HIPCHK(h, launch_lanczos_start(N, h->d_Vi, h->d_isdir, sc, v, vprev, xs, bsum, scal,
                                    h->own_stream));
     std::vector<double> a(maxit + 1), b(maxit + 2);
     double theta = 0.0, prev = -1.0, last = 0.0;
     int k = 0;
+    // the host looks at the coefficients every 8 iterations (one stream
+    // synchronisation each); a breakdown (beta ~ 0: the Krylov space is
+    // exhausted) inside such a stretch ends the recurrence at its first
+    // occurrence, and the coefficients computed after it are ignored
+    constexpr int kCheck = 8;
     for (int j = 0; j < maxit; j++) {
         HIPCHK(h, launch_lanczos_iter(h->d, coef64, h->fx_scale_lz, j, sc, v, vprev, w, xs,
-                                      partial, bsum, alpha, beta, h->own_stream));
+                                      partial, bsum, counter, alpha, beta, h->own_stream));
         k = j + 1;
-        if (k < 16 || k % 16 == 0 || k == maxit) {
+        if (k % kCheck == 0 || k == maxit) {
             HIPCHK(h, hipMemcpyAsync(a.data(), alpha, sizeof(double) * k,
                                      hipMemcpyDeviceToHost, h->own_stream));
             HIPCHK(h, hipMemcpyAsync(b.data(), beta, sizeof(double) * (k + 1),
                                      hipMemcpyDeviceToHost, h->own_stream));
             HIPCHK(h, hipStreamSynchronize(h->own_stream));
-            tridiag_top(a, b, k, &theta, &last);
-            const bool breakdown = b[k] <= 1e-13 * std::max(theta, 1e-300);
-            if (breakdown || std::fabs(theta - prev) <= 1e-11 * theta) break;
+            // first breakdown in this stretch, against the largest |alpha| so far
+            // (a scale of the operator that is known before its Ritz value)
+            double scale = 1e-300;
+            for (int m = 0; m < k; m++) scale = std::max(scale, std::fabs(a[m]));
+            int kb = k;
+            for (int m = k - kCheck + 1; m <= k; m++)
+                if (m >= 1 && !(b[m] > 1e-13 * scale)) {
+                    kb = m;
+                    break;
+                }
+            tridiag_top(a, b, kb, &theta, &last);
+            if (kb < k || std::fabs(theta - prev) <= 1e-11 * theta) {
+                k = kb;
+                break;
+            }
             prev = theta;
         }
     }
@@ -429,7 +448,7 @@ int lanczos(fedfem_handle* h, const double* coef64) {
     h->lam_ritz = theta;
     h->lam_geo = theta + std::fabs(b[k] * last);
     for (void* p : {(void*)sc, (void*)v, (void*)vprev, (void*)w, (void*)xs, (void*)partial,
-                    (void*)bsum, (void*)alpha, (void*)beta, (void*)scal})
+                    (void*)bsum, (void*)alpha, (void*)beta, (void*)scal, (void*)counter})
         dfree(h, p);
     return FEDFEM_OK;
 }
@@ -833,20 +852,25 @@ int fedfem_precompute_many(fedfem_handle* const* handles, int32_t n, int32_t thr
     }
     std::vector<int> res(n, FEDFEM_OK);
     std::atomic<int32_t> next{0};
+    const int cores = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int32_t nt = threads;
+    if (nt == 0) {
+        const char* env = std::getenv("FEDFEM_PRECOMPUTE_THREADS");
+        nt = env ? std::atoi(env) : 0;
+        if (nt <= 0) nt = cores;
+    }
+    nt = std::max<int32_t>(1, std::min(nt, n));
+    // each worker's layout builds share the cores with the other workers'
+    const int inner = std::max(1, cores / nt);
     auto work = [&] {
+        const int prev = set_layout_threads(inner);
         for (;;) {
             const int32_t j = next.fetch_add(1);
             if (j >= n) break;
             res[j] = fedfem_precompute(handles[j]);
         }
+        set_layout_threads(prev);
     };
-    int32_t nt = threads;
-    if (nt == 0) {
-        const char* env = std::getenv("FEDFEM_PRECOMPUTE_THREADS");
-        nt = env ? std::atoi(env) : 0;
-        if (nt <= 0) nt = (int32_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    }
-    nt = std::max<int32_t>(1, std::min(nt, n));
     std::vector<std::thread> pool;
     try {
         for (int32_t t = 1; t < nt; t++) pool.emplace_back(work);

@@ -59,6 +59,10 @@ bool build_tiles(Layout& L, int tile_elems, int max_tile_nodes,
 constexpr int kPackedMaxNodes = 1024;
 void pack_lconn(Layout& L);
 
+// Cap the host threads of layout builds made by the calling thread (0: the
+// default, up to 16); returns the previous cap.
+int set_layout_threads(int n);
+
 // Morton (Z-order) permutation of points; returns new -> old.
 std::vector<int32_t> morton_order(const double* pts, int64_t n);
 
@@ -209,7 +213,7 @@ hipError_t launch_lanczos_start(int64_t N, const double* Vi,
 hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64,
                                double fx_scale, int j, const double* sc,
                                double* v, double* vprev, double* w, double* xs,
-                               double* partial, double* bsum, double* alpha,
-                               double* beta, hipStream_t s);
+                               double* partial, double* bsum, int* counter,
+                               double* alpha, double* beta, hipStream_t s);
 
 }  // namespace fedfem

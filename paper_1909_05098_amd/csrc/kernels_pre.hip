@@ -314,6 +314,30 @@ __device__ inline double block_sum(double v, double* sh) {
     return sh[0];
 }
 
+// Block partial s of a grid-wide sum: the last block to finish adds all
+// partials in a fixed order into out[0] (or its square root, op 1) and
+// returns the counter to zero for the next launch.
+__device__ inline void grid_sum(double s, double* __restrict__ bsum, int* __restrict__ counter,
+                                double* __restrict__ out, int op, double* sh) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = s;
+        __threadfence();
+        last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double t = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x)
+        t += __hip_atomic_load(&bsum[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t = block_sum(t, sh);
+    if (threadIdx.x == 0) {
+        out[0] = op ? sqrt(t) : t;
+        atomicExch(counter, 0);
+    }
+}
+
 __device__ inline double hash_unit(uint64_t x) {
     // splitmix64 finaliser, mapped to [-1, 1)
     x += 0x9e3779b97f4a7c15ULL;
@@ -365,7 +389,8 @@ __global__ void k_lz_w(int64_t N, const int32_t* __restrict__ part_off,
                        const int32_t* __restrict__ pidx, const double* __restrict__ partial,
                        const double* __restrict__ sc, const double* __restrict__ v,
                        const double* __restrict__ vprev, const double* __restrict__ beta_j,
-                       double* __restrict__ w, double* __restrict__ bsum) {
+                       double* __restrict__ w, double* __restrict__ bsum, int* __restrict__ counter,
+                       double* __restrict__ alpha_j) {
     __shared__ double sh[kBlock];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double prod = 0.0;
@@ -376,13 +401,13 @@ __global__ void k_lz_w(int64_t N, const int32_t* __restrict__ part_off,
         w[i] = wi;
         prod = v[i] * wi;
     }
-    const double s = block_sum(prod, sh);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+    grid_sum(block_sum(prod, sh), bsum, counter, alpha_j, 0, sh);
 }
 
 __global__ void k_lz_orth(int64_t N, const double* __restrict__ alpha_j,
                           const double* __restrict__ v, double* __restrict__ w,
-                          double* __restrict__ bsum) {
+                          double* __restrict__ bsum, int* __restrict__ counter,
+                          double* __restrict__ beta_next) {
     __shared__ double sh[kBlock];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double sq = 0.0;
@@ -391,8 +416,7 @@ __global__ void k_lz_orth(int64_t N, const double* __restrict__ alpha_j,
         w[i] = wi;
         sq = wi * wi;
     }
-    const double s = block_sum(sq, sh);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+    grid_sum(block_sum(sq, sh), bsum, counter, beta_next, 1, sh);
 }
 
 __global__ void k_lz_next(int64_t N, const double* __restrict__ beta_next,
@@ -528,17 +552,17 @@ hipError_t launch_lanczos_start(int64_t N, const double* Vi, const int32_t* is_d
 
 hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64, double fx_scale, int j,
                                const double* sc, double* v, double* vprev, double* w,
-                               double* xs, double* partial, double* bsum, double* alpha,
-                               double* beta, hipStream_t s) {
+                               double* xs, double* partial, double* bsum, int* counter,
+                               double* alpha, double* beta, hipStream_t s) {
     const unsigned nb = blocks_for(d.N);
     hipError_t e = launch_geometry_apply(d, coef64, xs, partial, fx_scale, s);
     if (e != hipSuccess) return e;
+    // alpha_j = v . w and beta_j+1 = |w - alpha_j v|, each summed by the last
+    // block of the kernel that forms the products
     hipLaunchKernelGGL(k_lz_w, dim3(nb), dim3(kBlock), 0, s, d.N, d.part_off, d.pidx, partial, sc, v,
-                       vprev, beta + j, w, bsum);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, alpha + j, 0);
-    hipLaunchKernelGGL(k_lz_orth, dim3(nb), dim3(kBlock), 0, s, d.N, alpha + j, v, w, bsum);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, beta + j + 1,
-                       1);
+                       vprev, beta + j, w, bsum, counter, alpha + j);
+    hipLaunchKernelGGL(k_lz_orth, dim3(nb), dim3(kBlock), 0, s, d.N, alpha + j, v, w, bsum,
+                       counter, beta + j + 1);
     hipLaunchKernelGGL(k_lz_next, dim3(nb), dim3(kBlock), 0, s, d.N, beta + j + 1, sc, w, v,
                        vprev, xs);
     return hipGetLastError();

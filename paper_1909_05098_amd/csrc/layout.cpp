@@ -51,11 +51,18 @@ void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& id,
     }
 }
 
-// body(a, b) over [0, n) split across up to 16 host threads; ranges of fewer
-// than `grain` items run on the calling thread
+// cap on the host threads one layout build may use (0: up to 16); set per
+// calling thread, so that builds already running side by side do not each
+// spread over every core
+thread_local int tl_layout_threads = 0;
+
+// body(a, b) over [0, n) split across up to 16 host threads (or the calling
+// thread's cap); ranges of fewer than `grain` items run on the calling thread
 template <typename F>
 void parallel_for(int64_t n, F&& body, int64_t grain = 4096) {
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    unsigned nt = tl_layout_threads > 0
+                      ? (unsigned)tl_layout_threads
+                      : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     nt = (unsigned)std::min<int64_t>(nt, std::max<int64_t>(1, n / std::max<int64_t>(1, grain)));
     if (nt <= 1) {
         body(0, n);
@@ -72,6 +79,12 @@ void parallel_for(int64_t n, F&& body, int64_t grain = 4096) {
 }
 
 }  // namespace
+
+int set_layout_threads(int n) {
+    const int old = tl_layout_threads;
+    tl_layout_threads = n < 0 ? 0 : n;
+    return old;
+}
 
 std::vector<int32_t> morton_order(const double* pts, int64_t n) {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
