@@ -174,6 +174,30 @@ def test_lambda_matches_oracle_on_jittered_mesh():
     assert abs(dt - 0.9 * dtcr) <= 1e-15 * dt
 
 
+@pytest.mark.parametrize("dims", [(2, 2, 2), (3, 2, 2), (3, 3, 3), (4, 3, 3), (5, 4, 4)])
+def test_lambda_on_few_free_nodes(dims):
+    """Boxes with 1, 2, 8, 12 and 36 free nodes: the Lanczos recurrence breaks
+    down once the Krylov space holds every free node, before, at or after a
+    point where the host reads the coefficients, and must then return the
+    exact top eigenvalue of the (dense) oracle."""
+    xyz, tets, bnd = jittered_box(*dims, 1e-3, seed=17)
+    mat = sc.td_materials()
+    om = oracle.OracleModel(xyz, tets, mat, bnd, np.full(len(bnd), 37.0))
+    lam_o = om.geometry_lambda()
+    h = gpu_handle(xyz, tets, mat, bnd, -0.9, ff.FP64)
+    inf = h.info()
+    lam_g = inf["lambda_geometry"]
+    n_free = len(xyz) - len(bnd)
+    print(f"[lambda] {dims}: {n_free} free nodes, {inf['lanczos_iterations']} iterations, "
+          f"gpu={lam_g:.12e} oracle={lam_o:.12e}", flush=True)
+    assert inf["lanczos_iterations"] <= max(n_free, 1) + 16
+    if inf["lanczos_iterations"] >= n_free:  # broke down: exact
+        assert abs(lam_g - lam_o) <= 1e-8 * lam_o
+    else:  # converged first: an upper bound
+        assert (1 - 1e-10) * lam_o <= lam_g <= (1 + 1e-6) * lam_o
+    h.close()
+
+
 def test_bitwise_determinism_and_checkpoint():
     xyz, tets, bnd = jittered_box(10, 8, 7, 1e-3, seed=4)
     mat = sc.td_materials()
