@@ -121,9 +121,12 @@ __global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
         }
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            const int co = n0 + nt * 16 + (lane & 15);
-            B[nt] = co < a.cout ? *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k)
-                                : zero8();
+            // a column past cout reads row cout - 1 instead: it only feeds
+            // output channels that are never stored, and an unconditional
+            // load keeps the prefetch distance (a masked one must be waited
+            // for where it is masked)
+            const int co = min(n0 + nt * 16 + (lane & 15), a.cout - 1);
+            B[nt] = *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k);
         }
     };
     bf16x8 A[4], B[NT];
@@ -211,9 +214,12 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
         const int k = off * a.cin + c0 + kg;
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            const int co = n0 + nt * 16 + (lane & 15);
-            B[nt] = co < a.cout ? *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k)
-                                : zero8();
+            // a column past cout reads row cout - 1 instead: it only feeds
+            // output channels that are never stored, and an unconditional
+            // load keeps the prefetch distance (a masked one must be waited
+            // for where it is masked)
+            const int co = min(n0 + nt * 16 + (lane & 15), a.cout - 1);
+            B[nt] = *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k);
         }
     };
     auto loadA = [&](int off, bf16x8 (&A)[4]) {
@@ -231,16 +237,23 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
         // 64 consecutive threads stage 16 consecutive halo voxels x 4 groups
 #pragma unroll 4
         for (int q = t; q < ((H + 15) >> 4) * 64; q += 256) {
-            const int h = (q >> 6) * 16 + (q & 15), grp = (q >> 4) & 3;
-            if (h >= H) continue;
+            // branch-free, so several loads are in flight: lanes past the
+            // halo redo its last voxel (same value, same place), and lanes
+            // outside the grid load a clamped voxel and store zeros
+            const int h = min((q >> 6) * 16 + (q & 15), H - 1), grp = (q >> 4) & 3;
             const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
             const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-            bf16x8 v = zero8();
-            if (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) {
-                const int64_t gv = ((bs * G + z) * G + y) * G + x;
-                v = *reinterpret_cast<const bf16x8*>(a.in + gv * a.ip + a.io + c0 + grp * 8);
-            }
-            halo[grp][h] = v;
+            const unsigned keep =
+                (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) ? ~0u : 0u;
+            const int xc = min(max(x, 0), G - 1), yc = min(max(y, 0), G - 1),
+                      zc = min(max(z, 0), G - 1);
+            const int64_t gv = ((bs * G + zc) * G + yc) * G + xc;
+            uint4 v = *reinterpret_cast<const uint4*>(a.in + gv * a.ip + a.io + c0 + grp * 8);
+            v.x &= keep;
+            v.y &= keep;
+            v.z &= keep;
+            v.w &= keep;
+            *reinterpret_cast<uint4*>(&halo[grp][h]) = v;
         }
         __syncthreads();
         bf16x8 A[4];
@@ -250,6 +263,9 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
             if (off + 2 < 27) loadB(c0, off + 2, Bq[(off + 2) % 3]);
             bf16x8 An[4];
             if (off + 1 < 27) loadA(off + 1, An);
+            // the prefetches stay here; the scheduler would otherwise move
+            // them next to their first use
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int mt = 0; mt < 4; mt++)
 #pragma unroll
