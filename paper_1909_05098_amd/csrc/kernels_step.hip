@@ -202,8 +202,32 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
             lc[r] = pk ? make_uint2(gw[el], gb[el]) : glc[el];
         }
     }
-    // 2. tile nodes: temperature, conductivity, zeroed accumulators
-    for (int j = tid; j < m; j += bs) {
+    // 2. tile nodes: temperature, conductivity, zeroed accumulators.  The
+    // first SJ rounds go out together, ids then temperatures (lanes past the
+    // list load its last node and store nothing), so a thread waits for two
+    // memory round trips instead of two per round.
+    constexpr int SJ = 2;
+    {
+        int gj[SJ];
+#pragma unroll
+        for (int u = 0; u < SJ; u++) gj[u] = a.tile_nodes[p0 + min(tid + u * bs, m - 1)];
+        __builtin_amdgcn_sched_barrier(0);  // all id loads before any wait
+        Real hj[SJ], lj[SJ];
+#pragma unroll
+        for (int u = 0; u < SJ; u++) State<Real, COMP>::load(Tin, gj[u], hj[u], lj[u]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < SJ; u++) {
+            const int j = tid + u * bs;
+            if (j < m) {
+                s_T[j] = hj[u];
+                if (COMP) s_Tlo[j] = lj[u];
+                if (TD) s_k[j] = prop_k(hj[u], pr);
+                s_acc[j] = 0ull;
+            }
+        }
+    }
+    for (int j = tid + SJ * bs; j < m; j += bs) {
         const int g = a.tile_nodes[p0 + j];
         Real hi, lo;
         State<Real, COMP>::load(Tin, g, hi, lo);
