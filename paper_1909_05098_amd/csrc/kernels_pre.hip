@@ -11,6 +11,8 @@ namespace fedfem {
 namespace {
 
 constexpr int kBlock = 256;
+// grids up to this many blocks finish their dot products in their last block
+constexpr unsigned kFusedSumBlocks = 256;
 
 inline unsigned blocks_for(int64_t n, int bs = kBlock) {
     return (unsigned)((n + bs - 1) / bs);
@@ -314,12 +316,18 @@ __device__ inline double block_sum(double v, double* sh) {
     return sh[0];
 }
 
-// Block partial s of a grid-wide sum: the last block to finish adds all
-// partials in a fixed order into out[0] (or its square root, op 1) and
-// returns the counter to zero for the next launch.
+// Block partial s of a grid-wide sum.  With a counter (small grids) the
+// last block to finish adds all partials in a fixed order into out[0] (or
+// its square root, op 1) and returns the counter to zero for the next
+// launch; without one (large grids, where every block's atomic on the one
+// counter would queue at L2) the partials are left for k_reduce.
 __device__ inline void grid_sum(double s, double* __restrict__ bsum, int* __restrict__ counter,
                                 double* __restrict__ out, int op, double* sh) {
     __shared__ int last;
+    if (!counter) {
+        if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+        return;
+    }
     if (threadIdx.x == 0) {
         bsum[blockIdx.x] = s;
         __threadfence();
@@ -557,12 +565,19 @@ hipError_t launch_lanczos_iter(const DevLayout& d, const double* coef64, double 
     const unsigned nb = blocks_for(d.N);
     hipError_t e = launch_geometry_apply(d, coef64, xs, partial, fx_scale, s);
     if (e != hipSuccess) return e;
-    // alpha_j = v . w and beta_j+1 = |w - alpha_j v|, each summed by the last
-    // block of the kernel that forms the products
+    // alpha_j = v . w and beta_j+1 = |w - alpha_j v|: on small grids summed
+    // by the last block of the kernel that forms the products, on large ones
+    // by a separate one-block kernel
+    int* ctr = nb <= kFusedSumBlocks ? counter : nullptr;
     hipLaunchKernelGGL(k_lz_w, dim3(nb), dim3(kBlock), 0, s, d.N, d.part_off, d.pidx, partial, sc, v,
-                       vprev, beta + j, w, bsum, counter, alpha + j);
-    hipLaunchKernelGGL(k_lz_orth, dim3(nb), dim3(kBlock), 0, s, d.N, alpha + j, v, w, bsum,
-                       counter, beta + j + 1);
+                       vprev, beta + j, w, bsum, ctr, alpha + j);
+    if (!ctr)
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, alpha + j, 0);
+    hipLaunchKernelGGL(k_lz_orth, dim3(nb), dim3(kBlock), 0, s, d.N, alpha + j, v, w, bsum, ctr,
+                       beta + j + 1);
+    if (!ctr)
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nb, beta + j + 1,
+                           1);
     hipLaunchKernelGGL(k_lz_next, dim3(nb), dim3(kBlock), 0, s, d.N, beta + j + 1, sc, w, v,
                        vprev, xs);
     return hipGetLastError();
