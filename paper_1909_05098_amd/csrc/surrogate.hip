@@ -8,7 +8,7 @@
 //   data grad the same kernel with the weights flipped in space and
 //             transposed in channels (a 3x3x3 correlation of the gradient);
 //   weight grad M = output channels, N = 27 * input channels + 1 (the
-//             bias), K = voxels: 64-voxel chunks of the gradient and of the
+//             bias), K = voxels: 128-voxel chunks of the gradient and of the
 //             gathered input are transposed in registers and staged in LDS
 //             so that each lane reads 8 consecutive voxels of one channel;
 //             partial sums per voxel split are reduced in a fixed order
@@ -331,11 +331,13 @@ hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
 // an MFMA product with the voxels as the reduction dimension.  The bias is
 // the extra column k = K of X, equal to 1 on every voxel.  A workgroup owns
 // a COT x KN tile (output channels x k) and one split of the voxels, which
-// it walks in 64-voxel chunks.  Each chunk is staged transposed in LDS
-// (channel-major rows of 64 voxels): a thread gathers an 8-voxel x
-// 8-channel block with 16-byte loads, transposes it in registers and writes
-// 8 rows of 16 bytes.  Each wave then multiplies an (MT x 16) x (NT x 16)
+// it walks in chunks of CV voxels.  Each chunk is staged transposed in LDS
+// (channel-major rows of CV voxels): a thread gathers 8-voxel x 8-channel
+// blocks with 16-byte loads, transposes them in registers and writes 8 rows
+// of 16 bytes each.  Each wave then multiplies an (MT x 16) x (NT x 16)
 // block, reusing its MT + NT fragments for MT x NT MFMAs per 32 voxels.
+// The next chunk's loads are in flight during the current chunk's
+// products, so a longer chunk hides more of their latency.
 struct WgradArgs {
     const bf16* d;  // gradient of the pre-activation output, [V][dp]
     int dp, doff, cout;
@@ -357,11 +359,14 @@ __device__ __forceinline__ void transpose_store8(const bf16x8 (&r)[8], bf16* row
     }
 }
 
-template <int MT, int NT, int WM, int WN>
+template <int MT, int NT, int WM, int WN, int CV>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
-    constexpr int COT = 16 * MT * WM, KN = 16 * NT * WN, LP = 72;
+    constexpr int COT = 16 * MT * WM, KN = 16 * NT * WN, LP = CV + 8;
+    constexpr int VG = CV / 8;                          // voxel groups per chunk
+    constexpr int XPT = (KN / 8 * VG + 255) / 256;      // input blocks per thread
+    constexpr int DPT = (COT / 8 * VG + 255) / 256;     // gradient blocks per thread
     static_assert(WM * WN == 4, "four waves");
-    static_assert(KN <= 256 && COT <= 256, "at most one staging block of each kind per thread");
+    static_assert(CV % 32 == 0, "whole MFMA k-steps per chunk");
     __shared__ __align__(16) bf16 sD[COT][LP];
     __shared__ __align__(16) bf16 sX[KN][LP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -372,64 +377,89 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     const int G = a.G;
     const int64_t G3 = (int64_t)G * G * G;
     const int K = 27 * a.cin;
-    // staging blocks of this thread, the same for every chunk: the input
-    // block of k-group t / 8 (8 consecutive k never straddle an offset or K,
-    // as cin % 8 == 0) and the gradient block of channel group t / 8, both
-    // over voxel group t % 8 of the chunk
-    const int vg = t & 7;
-    const bool hasX = t < KN, hasD = t < COT;
-    const int kk = k0 + (t >> 3) * 8;
-    const bool xdata = hasX && kk < K;
-    int ci = 0, dz = 0, dy = 0, dx = 0;
-    if (xdata) {
-        const int off = kk / a.cin;
-        ci = kk - off * a.cin;
-        dz = off / 9 - 1;
-        dy = (off / 3) % 3 - 1;
-        dx = off % 3 - 1;
+    // staging blocks of this thread, the same for every chunk: block
+    // b = t + 256 u covers k-group (or channel group) b / VG and voxel group
+    // b % VG of the chunk; 8 consecutive k never straddle an offset or K, as
+    // cin % 8 == 0
+    int xg[XPT], xvg[XPT], xci[XPT], xdz[XPT], xdy[XPT], xdx[XPT];
+    bool xon[XPT], xdat[XPT];
+#pragma unroll
+    for (int u = 0; u < XPT; u++) {
+        const int bl = t + 256 * u;
+        xon[u] = bl < KN / 8 * VG;
+        xg[u] = bl / VG;
+        xvg[u] = bl % VG;
+        const int kk = k0 + xg[u] * 8;
+        xdat[u] = xon[u] && kk < K;
+        xci[u] = xdz[u] = xdy[u] = xdx[u] = 0;
+        if (xdat[u]) {
+            const int off = kk / a.cin;
+            xci[u] = kk - off * a.cin;
+            xdz[u] = off / 9 - 1;
+            xdy[u] = (off / 3) % 3 - 1;
+            xdx[u] = off % 3 - 1;
+        }
     }
-    const int co = co0 + (t >> 3) * 8;
-    const bool ddata = hasD && co < a.cout;
+    int dg[DPT], dvg[DPT];
+    bool don[DPT], ddat[DPT];
+#pragma unroll
+    for (int u = 0; u < DPT; u++) {
+        const int bl = t + 256 * u;
+        don[u] = bl < COT / 8 * VG;
+        dg[u] = bl / VG;
+        dvg[u] = bl % VG;
+        ddat[u] = don[u] && co0 + dg[u] * 8 < a.cout;
+    }
     // registers of one chunk's blocks; the next chunk's loads are in flight
     // while the current chunk is multiplied
-    bf16x8 rX[8], rD[8];
+    bf16x8 rX[XPT][8], rD[DPT][8];
     auto fetch = [&](int64_t vc) {
-        const int64_t v0 = vc + vg * 8;
-        if (xdata) {
-            int64_t b = v0 / G3;
-            const int64_t r = v0 - b * G3;
-            int z = (int)(r / ((int64_t)G * G)), y = (int)((r / G) % G), x = (int)(r % G);
 #pragma unroll
-            for (int i = 0; i < 8; i++) {
-                rX[i] = zero8();
-                const int z2 = z + dz, y2 = y + dy, x2 = x + dx;
-                if (v0 + i < ve && z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 && x2 < G) {
-                    const int64_t nv = ((b * G + z2) * G + y2) * G + x2;
-                    rX[i] = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + ci);
-                }
-                if (++x == G) {  // next voxel in x-fastest order
-                    x = 0;
-                    if (++y == G) {
-                        y = 0;
-                        if (++z == G) {
-                            z = 0;
-                            ++b;
+        for (int u = 0; u < XPT; u++) {
+            const int64_t v0 = vc + xvg[u] * 8;
+            if (xdat[u]) {
+                int64_t b = v0 / G3;
+                const int64_t r = v0 - b * G3;
+                int z = (int)(r / ((int64_t)G * G)), y = (int)((r / G) % G), x = (int)(r % G);
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    rX[u][i] = zero8();
+                    const int z2 = z + xdz[u], y2 = y + xdy[u], x2 = x + xdx[u];
+                    if (v0 + i < ve && z2 >= 0 && z2 < G && y2 >= 0 && y2 < G && x2 >= 0 &&
+                        x2 < G) {
+                        const int64_t nv = ((b * G + z2) * G + y2) * G + x2;
+                        rX[u][i] = *reinterpret_cast<const bf16x8*>(a.in + nv * a.ip + a.io + xci[u]);
+                    }
+                    if (++x == G) {  // next voxel in x-fastest order
+                        x = 0;
+                        if (++y == G) {
+                            y = 0;
+                            if (++z == G) {
+                                z = 0;
+                                ++b;
+                            }
                         }
                     }
                 }
-            }
-        } else {
+            } else {
+                const bool bias = xon[u] && k0 + xg[u] * 8 == K;
 #pragma unroll
-            for (int i = 0; i < 8; i++) {
-                rX[i] = zero8();
-                if (kk == K && v0 + i < ve) rX[i][0] = (bf16)1.0f;  // bias column
+                for (int i = 0; i < 8; i++) {
+                    rX[u][i] = zero8();
+                    if (bias && v0 + i < ve) rX[u][i][0] = (bf16)1.0f;  // bias column
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < 8; i++)
-            rD[i] = (ddata && v0 + i < ve)
-                        ? *reinterpret_cast<const bf16x8*>(a.d + (v0 + i) * a.dp + a.doff + co)
-                        : zero8();
+        for (int u = 0; u < DPT; u++) {
+            const int64_t v0 = vc + dvg[u] * 8;
+            const int co = co0 + dg[u] * 8;
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+                rD[u][i] = (ddat[u] && v0 + i < ve)
+                               ? *reinterpret_cast<const bf16x8*>(a.d + (v0 + i) * a.dp + a.doff + co)
+                               : zero8();
+        }
     };
     f32x4 acc[MT][NT];
 #pragma unroll
@@ -437,14 +467,18 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (vs < ve) fetch(vs);
-    for (int64_t vc = vs; vc < ve; vc += 64) {
+    for (int64_t vc = vs; vc < ve; vc += CV) {
         __syncthreads();  // the previous chunk's fragments have been read
-        if (hasX) transpose_store8(rX, &sX[(t >> 3) * 8][vg * 8], LP);
-        if (hasD) transpose_store8(rD, &sD[(t >> 3) * 8][vg * 8], LP);
-        if (vc + 64 < ve) fetch(vc + 64);
+#pragma unroll
+        for (int u = 0; u < XPT; u++)
+            if (xon[u]) transpose_store8(rX[u], &sX[xg[u] * 8][xvg[u] * 8], LP);
+#pragma unroll
+        for (int u = 0; u < DPT; u++)
+            if (don[u]) transpose_store8(rD[u], &sD[dg[u] * 8][dvg[u] * 8], LP);
+        if (vc + CV < ve) fetch(vc + CV);
         __syncthreads();
 #pragma unroll
-        for (int s2 = 0; s2 < 2; s2++) {
+        for (int s2 = 0; s2 < CV / 32; s2++) {
             const int vo = s2 * 32 + (lane >> 4) * 8;
             bf16x8 A[MT], Bf[NT];
 #pragma unroll
@@ -475,28 +509,32 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
             }
 }
 
+// voxels per staged chunk of the weight gradient
+constexpr int kWgradChunk = 128;
+
 // tile shape of the weight gradient for a layer with `cout` output channels
 inline int wgrad_kn(int cout) { return cout <= 32 ? 256 : 128; }
 inline int wgrad_cot(int cout) { return cout <= 32 ? 32 : (cout <= 64 ? 64 : 128); }
 constexpr int kWgradBlocks = 1024;  // workgroups aimed at per layer
 
 // voxel split of a layer's weight gradient: ~kWgradBlocks workgroups, splits
-// of whole 64-voxel chunks; never more than kWgradBlocks / tiles splits
+// of whole chunks; never more than kWgradBlocks / tiles splits
 inline int64_t wgrad_vsplit(int64_t V, int tiles) {
     const int64_t want = std::max<int64_t>(1, (kWgradBlocks + tiles - 1) / tiles);
     const int64_t vs = (V + want - 1) / want;
-    return std::max<int64_t>(64, (vs + 63) / 64 * 64);
+    return std::max<int64_t>(kWgradChunk,
+                             (vs + kWgradChunk - 1) / kWgradChunk * kWgradChunk);
 }
 
 hipError_t launch_wgrad(const WgradArgs& w, int tiles_k, int tiles_c, int64_t splits,
                         hipStream_t s) {
     const dim3 grid((unsigned)tiles_k, (unsigned)tiles_c, (unsigned)splits);
     if (w.cout <= 32)
-        hipLaunchKernelGGL((k_wgrad<2, 4, 1, 4>), grid, dim3(256), 0, s, w);
+        hipLaunchKernelGGL((k_wgrad<2, 4, 1, 4, kWgradChunk>), grid, dim3(256), 0, s, w);
     else if (w.cout <= 64)
-        hipLaunchKernelGGL((k_wgrad<2, 4, 2, 2>), grid, dim3(256), 0, s, w);
+        hipLaunchKernelGGL((k_wgrad<2, 4, 2, 2, kWgradChunk>), grid, dim3(256), 0, s, w);
     else
-        hipLaunchKernelGGL((k_wgrad<4, 4, 2, 2>), grid, dim3(256), 0, s, w);
+        hipLaunchKernelGGL((k_wgrad<4, 4, 2, 2, kWgradChunk>), grid, dim3(256), 0, s, w);
     return hipGetLastError();
 }
 
