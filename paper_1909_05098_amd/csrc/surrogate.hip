@@ -298,8 +298,171 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
         }
 }
 
+// Double-buffered form of the LDS-staged convolution for larger grids.  A
+// workgroup of 8 waves owns a 512-voxel brick (16 x 8 x 4) and keeps two
+// halo buffers of 69 KB, so the next 32 channels are loaded while the
+// current ones are multiplied: their loads go out every third offset of the
+// offset loop, and land in the other buffer after it.  Each voxel's sum is
+// accumulated in the same order as in k_conv_lds (chunks, then offsets, one
+// MFMA over 32 channels each), so the two kernels give identical outputs.
+constexpr int kDbBX = 16, kDbBY = 8, kDbBZ = 4;
+constexpr int kDbH = (kDbBX + 2) * (kDbBY + 2) * (kDbBZ + 2);  // 1080 halo voxels
+constexpr int64_t kDbMinBlocks = 512;  // fewer bricks than this: k_conv_lds
+
+template <int NT>
+__global__ void __launch_bounds__(512) k_conv_db(ConvArgs a) {
+    constexpr int HX = kDbBX + 2, HY = kDbBY + 2, H = kDbH;
+    constexpr int SPT = ((H + 15) / 16 * 64 + 511) / 512;  // staged loads per thread
+    static_assert(SPT <= 9, "one staged load every third offset");
+    __shared__ bf16x8 halo[2][4][H];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int G = a.G;
+    const int nbx = G / kDbBX, nby = G / kDbBY, nbz = G / kDbBZ;
+    const int64_t id = blockIdx.x;
+    const int bx = (int)(id % nbx), by = (int)((id / nbx) % nby),
+              bz = (int)((id / ((int64_t)nbx * nby)) % nbz);
+    const int64_t bs = id / ((int64_t)nbx * nby * nbz);
+    const int x0 = bx * kDbBX, y0 = by * kDbBY, z0 = bz * kDbBZ;
+    const int n0 = blockIdx.y * 64;
+    // this lane's four voxels (rows lane % 16 of the wave's four M tiles)
+    int hv[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+        const int li = wave * 64 + mt * 16 + (lane & 15);
+        const int lx = li % kDbBX, ly = (li / kDbBX) % kDbBY, lz = li / (kDbBX * kDbBY);
+        hv[mt] = ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1);  // halo index of offset 0
+    }
+    // staged load u of the chunk at channel c0: 64 consecutive threads take
+    // 16 consecutive halo voxels x 4 channel groups; lanes past the halo
+    // redo its last voxel, lanes outside the grid load a clamped voxel and
+    // store zeros
+    auto stage_at = [&](int u, int& h, int& grp, unsigned& keep) -> int64_t {
+        const int q = t + u * 512;
+        h = min((q >> 6) * 16 + (q & 15), H - 1);
+        grp = (q >> 4) & 3;
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        keep = (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) ? ~0u : 0u;
+        const int xc = min(max(x, 0), G - 1), yc = min(max(y, 0), G - 1),
+                  zc = min(max(z, 0), G - 1);
+        return ((bs * G + zc) * G + yc) * G + xc;
+    };
+    auto stage_load = [&](int c0, int u) -> uint4 {
+        int h, grp;
+        unsigned keep;
+        const int64_t gv = stage_at(u, h, grp, keep);
+        return *reinterpret_cast<const uint4*>(a.in + gv * a.ip + a.io + c0 + grp * 8);
+    };
+    auto stage_store = [&](int buf, int u, uint4 v) {
+        int h, grp;
+        unsigned keep;
+        (void)stage_at(u, h, grp, keep);
+        v.x &= keep;
+        v.y &= keep;
+        v.z &= keep;
+        v.w &= keep;
+        *reinterpret_cast<uint4*>(&halo[buf][grp][h]) = v;
+    };
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kg = (lane >> 4) * 8;
+    auto loadB = [&](int c0, int off, bf16x8 (&B)[NT]) {
+        const int k = off * a.cin + c0 + kg;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            // columns past cout read row cout - 1: they only feed outputs
+            // that are never stored
+            const int co = min(n0 + nt * 16 + (lane & 15), a.cout - 1);
+            B[nt] = *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k);
+        }
+    };
+    auto loadA = [&](int buf, int off, bf16x8 (&A)[4]) {
+        const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
+        const int dh = (dz * HY + dy) * HX + dx;
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) A[mt] = halo[buf][lane >> 4][hv[mt] + dh];
+    };
+    uint4 sv[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; u++) sv[u] = stage_load(0, u);
+#pragma unroll
+    for (int u = 0; u < SPT; u++) stage_store(0, u, sv[u]);
+    __syncthreads();
+    const int nch = a.cin / 32;
+    bf16x8 Bq[3][NT];
+    for (int c = 0; c < nch; c++) {
+        const int cur = c & 1, c0 = c * 32;
+        const bool more = c + 1 < nch;
+        loadB(c0, 0, Bq[0]);
+        loadB(c0, 1, Bq[1]);
+        bf16x8 A[4];
+        loadA(cur, 0, A);
+#pragma unroll
+        for (int off = 0; off < 27; off++) {
+            if (more && off % 3 == 0 && off / 3 < SPT) sv[off / 3] = stage_load(c0 + 32, off / 3);
+            if (off + 2 < 27) loadB(c0, off + 2, Bq[(off + 2) % 3]);
+            bf16x8 An[4];
+            if (off + 1 < 27) loadA(cur, off + 1, An);
+            // the loads stay here; the scheduler would otherwise move them
+            // next to their first use
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bq[off % 3][nt],
+                                                                          acc[mt][nt], 0, 0, 0);
+            if (off + 1 < 27) {
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < SPT; u++) stage_store(cur ^ 1, u, sv[u]);
+        }
+        // the next chunk is in place, and no wave still reads this one
+        __syncthreads();
+    }
+    // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int co = n0 + nt * 16 + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int li = wave * 64 + mt * 16 + (lane >> 4) * 4 + i;
+                const int lx = li % kDbBX, ly = (li / kDbBX) % kDbBY, lz = li / (kDbBX * kDbBY);
+                const int64_t v = ((bs * G + z0 + lz) * G + y0 + ly) * G + x0 + lx;
+                float val = acc[mt][nt][i] + bias;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                a.out[v * a.op + a.oo + co] = (bf16)val;
+            }
+        }
+}
+
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
+    if (a.ks == 3 && a.cin % 32 == 0 && G >= 16 && (G & (G - 1)) == 0) {
+        // 512-voxel bricks, double-buffered, when there are enough of them
+        // and at most 32 output channels (wider tiles spill registers there)
+        const int64_t G3 = (int64_t)G * G * G;
+        const int64_t nblk = a.V / G3 * (G3 / (kDbBX * kDbBY * kDbBZ));
+        if (nblk >= kDbMinBlocks && a.cout <= 32) {
+            const dim3 grid((unsigned)nblk, 1);
+            if (a.cout <= 16)
+                hipLaunchKernelGGL(k_conv_db<1>, grid, dim3(512), 0, s, a);
+            else
+                hipLaunchKernelGGL(k_conv_db<2>, grid, dim3(512), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (a.ks == 3 && a.cin % 32 == 0 && G >= 8 && (G & (G - 1)) == 0) {
         // bricks of 256 voxels: 16 x 8 x 2, or 8 x 8 x 4 on an 8^3 grid
         const int BX = G >= 16 ? 16 : 8, BY = 8, BZ = 256 / (BX * BY);

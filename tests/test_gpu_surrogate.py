@@ -98,6 +98,28 @@ def test_forward_layers_and_network(torch_cuda):
     assert e <= 1e-2
 
 
+def test_conv_layers_on_64_grid(torch_cuda):
+    """At 64^3 the layers with at most 32 output channels run on 512-voxel
+    bricks with a double-buffered halo; each such layer, fed the GPU's own
+    input, must match the FP64 reference to BF16 rounding."""
+    torch = torch_cuda
+    G, B = 64, 1
+    rng, net, Q, x, X = setup(torch, G, B, 2)
+    Y = torch.empty((B, G, G, G), dtype=torch.float32, device="cuda")
+    net.forward(X, Y)
+    acts = {L: net.activation(L, B).astype(np.float64) for L in (0, 1, 7, 8, 9)}
+    ins = {1: acts[0], 8: np.concatenate([S.up2(acts[7]), acts[1]], -1), 9: acts[8]}
+    for L in (1, 8, 9):
+        name = S.LAYERS[L][0]
+        ref = S.relu(S.conv3(bf16(ins[L], torch), Q[name + ".w"], Q[name + ".b"]))
+        err = np.abs(acts[L] - ref)
+        tol = 2.0 ** -7 * np.abs(ref) + 1e-6 * np.abs(ref).max()
+        print(f"[surrogate] 64^3 layer {name}: max rel "
+              f"{float((err / (np.abs(ref) + 1e-12)).max()):.2e}", flush=True)
+        assert np.all(err <= tol), name
+    net.close()
+
+
 def gpu_cache(net, x, B, q):
     """Backward cache of the reference built from the GPU's own activations
     (upsampling and concatenation of BF16 values are exact; the pooled mean
