@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(512) k_conv_db(ConvArgs a) {
               bz = (int)((id / ((int64_t)nbx * nby)) % nbz);
     const int64_t bs = id / ((int64_t)nbx * nby * nbz);
     const int x0 = bx * kDbBX, y0 = by * kDbBY, z0 = bz * kDbBZ;
-    const int n0 = blockIdx.y * 64;
+    const int n0 = blockIdx.y * (16 * NT);  // this workgroup's output channels
     // this lane's four voxels (rows lane % 16 of the wave's four M tiles)
     int hv[4];
 #pragma unroll
@@ -450,16 +450,18 @@ __global__ void __launch_bounds__(512) k_conv_db(ConvArgs a) {
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
     if (a.ks == 3 && a.cin % 32 == 0 && G >= 16 && (G & (G - 1)) == 0) {
-        // 512-voxel bricks, double-buffered, when there are enough of them
-        // and at most 32 output channels (wider tiles spill registers there)
+        // 512-voxel bricks, double-buffered, when there are enough of them;
+        // at most 32 output channels per workgroup (wider tiles spill
+        // registers there), so wider layers take several
         const int64_t G3 = (int64_t)G * G * G;
         const int64_t nblk = a.V / G3 * (G3 / (kDbBX * kDbBY * kDbBZ));
-        if (nblk >= kDbMinBlocks && a.cout <= 32) {
-            const dim3 grid((unsigned)nblk, 1);
+        if (nblk >= kDbMinBlocks) {
             if (a.cout <= 16)
-                hipLaunchKernelGGL(k_conv_db<1>, grid, dim3(512), 0, s, a);
+                hipLaunchKernelGGL(k_conv_db<1>, dim3((unsigned)nblk, 1), dim3(512), 0, s, a);
             else
-                hipLaunchKernelGGL(k_conv_db<2>, grid, dim3(512), 0, s, a);
+                hipLaunchKernelGGL(k_conv_db<2>,
+                                   dim3((unsigned)nblk, (unsigned)((a.cout + 31) / 32)),
+                                   dim3(512), 0, s, a);
             return hipGetLastError();
         }
     }

@@ -431,3 +431,31 @@ def test_output_independent_of_batch_and_stream(torch_cuda):
         net.close()
     assert np.all(np.isfinite(outs[0]))
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_wide_layers_same_on_both_convolution_kernels(torch_cuda):
+    """At 32^3 a batch of 64 puts the 16^3 layers (64 output channels) on the
+    double-buffered 512-voxel-brick kernel, a batch of 8 keeps them on the
+    256-voxel one; both add each voxel's terms in the same order, so every
+    sample's output must be bit-identical."""
+    torch = torch_cuda
+    from paper_1909_05098_amd import surrogate_pipeline as pl
+    G, S = 32, 64
+    rng = np.random.default_rng(12)
+    rows = [dict(cx=c[0], cy=c[1], cz=c[2], sigma=s_, q0=q, k0=k, omega_b=w, ax=0.05, ay=0.04,
+                 az=0.035, hmesh=2e-3)
+            for c, s_, q, k, w in zip(rng.uniform(-0.02, 0.02, (S, 3)), rng.uniform(0.002, 0.006, S),
+                                      rng.uniform(5e6, 3e7, S), rng.uniform(0.45, 0.6, S),
+                                      rng.uniform(0.002, 0.02, S))]
+    smp = torch.tensor(samples_array(rows), device="cuda")
+    fr = pl.frame(G)
+    outs = []
+    for nb in (8, 64):
+        net = sg.Net(G, nb, seed=6)
+        out = torch.empty((S, G, G, G), dtype=torch.float32, device="cuda")
+        pl.predict(net, smp, PHYS, out, nb, G, fr)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        net.close()
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0], outs[1])
