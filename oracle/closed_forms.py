@@ -133,3 +133,31 @@ def kirchhoff_slab_table(x, L, T_left, T_right, Tk, kv):
 
     ua, ub = U(T_left), U(T_right)
     return np.array([U_inv(ua + (ub - ua) * xi / L) for xi in np.asarray(x)])
+
+
+def hex_box_lambda(nx, ny, nz, h):
+    """Largest eigenvalue of (sum_e A_e) v = lambda diag(V) v for one-point
+    hexahedra on a regular box of nx*ny*nz cubes of edge h, all surface nodes
+    fixed.
+
+    At the element centre the gradient of a nodal field is, in each
+    direction, the difference along that direction averaged over the four
+    parallel edges.  So the conduction form is h^3 sum_d (D_d^T D_d) (x)
+    (A^T A) (x) (A^T A) over the other two directions, with D the 1-D
+    difference (T_{j+1} - T_j)/h and A the 1-D average (T_j + T_{j+1})/2; the
+    lumped capacity is h^3 per node.  With zero boundary values the sine
+    vectors sin(p pi j / n) diagonalise D^T D (eigenvalue 4/h^2 sin^2(p pi/2n))
+    and A^T A (eigenvalue cos^2(p pi / 2n)), so the eigenvalues are
+        4/h^2 (s_x c_y c_z + c_x s_y c_z + c_x c_y s_z)
+    over all modes (p, q, r), 1 <= p < nx, 1 <= q < ny, 1 <= r < nz.
+    """
+    def sc(n):
+        th = np.arange(1, n) * np.pi / (2.0 * n)
+        return np.sin(th) ** 2, np.cos(th) ** 2
+    sx, cx = sc(nx)
+    sy, cy = sc(ny)
+    sz, cz = sc(nz)
+    lam = (sx[:, None, None] * cy[None, :, None] * cz[None, None, :]
+           + cx[:, None, None] * sy[None, :, None] * cz[None, None, :]
+           + cx[:, None, None] * cy[None, :, None] * sz[None, None, :])
+    return 4.0 / h**2 * float(lam.max())

@@ -68,6 +68,41 @@ def kuhn_box(nx, ny, nz, h, origin=(0.0, 0.0, 0.0)):
     return xyz, tets
 
 
+def hex_box(nx, ny, nz, h, origin=(0.0, 0.0, 0.0)):
+    """Box of nx*ny*nz cubes of edge h as eight-node hexahedra.
+
+    Node (i,j,k) has index i + (nx+1)*(j + (ny+1)*k) (as kuhn_box).  Each
+    hexahedron lists its bottom face (k) counter-clockwise seen from +z,
+    starting at its (i,j) corner, then the top face (k+1) in the same order.
+    Elements are ordered by (k, j, i).  Returns (xyz float64[N,3],
+    hexes int32[E,8]).
+    """
+    nx, ny, nz = int(nx), int(ny), int(nz)
+    hx, hy, hz = (h, h, h) if np.isscalar(h) else h
+    K, J, I = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                          indexing="ij")
+    xyz = np.stack([origin[0] + I.ravel() * hx, origin[1] + J.ravel() * hy,
+                    origin[2] + K.ravel() * hz], axis=1).astype(np.float64)
+    ck, cj, ci = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    corners = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0),
+               (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    hexes = np.stack([nid(ci + a, cj + b, ck + c) for a, b, c in corners], axis=1)
+    return xyz, hexes.astype(np.int32)
+
+
+def box_surface_nodes(nx, ny, nz):
+    """Node ids (index rule of kuhn_box / hex_box) on the surface of the box."""
+    K, J, I = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                          indexing="ij")
+    on = (I == 0) | (I == nx) | (J == 0) | (J == ny) | (K == 0) | (K == nz)
+    return np.nonzero(on.ravel())[0].astype(np.int32)
+
+
 def boundary_nodes_by_faces(n_nodes, tets):
     """Nodes lying on a triangle that belongs to exactly one tetrahedron."""
     tets = np.asarray(tets, dtype=np.int64)
