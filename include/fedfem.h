@@ -121,6 +121,20 @@ typedef struct {
     int32_t reserved[7];
 } fedfem_info;
 
+/*
+ * A mesh of eight-node hexahedra (Sec 2.3.3, Eq 14).  Each element lists its
+ * nodes in the order of its corners at natural coordinates (xi, eta, zeta) =
+ * (-1,-1,-1), (1,-1,-1), (1,1,-1), (-1,1,-1), (-1,-1,1), (1,-1,1), (1,1,1),
+ * (-1,1,1): one face counter-clockwise, then the opposite face in the same
+ * order.  hexes is [8 * n_hexes] node ids; the caller keeps ownership.
+ */
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;
+    int64_t n_hexes;
+    const int32_t *hexes;
+} fedfem_mesh_hex;
+
 typedef struct fedfem_handle fedfem_handle;
 
 /*
@@ -132,6 +146,24 @@ typedef struct fedfem_handle fedfem_handle;
  */
 int fedfem_create(const fedfem_mesh *mesh, const fedfem_materials *mat,
                   const fedfem_bc *bc, fedfem_handle **out);
+
+/*
+ * Create a handle on a mesh of eight-node hexahedra with one integration
+ * point (Sec 2.3.3): the element matrix is A_e = 8 |det J| B^T B with J and
+ * B at the element centre (Eq 14, 16), k_e the mean of k over the eight
+ * nodes (Eq 13), and each node receives an eighth of every element volume
+ * 8 |det J| (Sec 2.3.4).  The paper adds no hourglass control, and neither
+ * does the library: fields with zero gradient at every element centre carry
+ * no conduction load.  Validation, ownership and the rest of the API are as
+ * for fedfem_create, with these differences: the default layout is
+ * 1024-element tiles with 512 threads and up to 2048 tile nodes, threads
+ * may not exceed 512; Gaussian sources are nodal only
+ * (FEDFEM_SOURCE_CONSISTENT gives FEDFEM_E_INVALID), as are
+ * fedfem_flux_loads and fedfem_resample; batches accept tetrahedral handles
+ * only (FEDFEM_E_STATE).  fedfem_get_info reports elements in n_tets.
+ */
+int fedfem_create_hex(const fedfem_mesh_hex *mesh, const fedfem_materials *mat,
+                      const fedfem_bc *bc, fedfem_handle **out);
 
 /* Set layout options (before fedfem_precompute; FEDFEM_E_STATE after). */
 int fedfem_set_options(fedfem_handle *h, const fedfem_options *opt);

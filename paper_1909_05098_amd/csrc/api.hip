@@ -489,15 +489,17 @@ int fedfem_last_error(const fedfem_handle* h, char* buf, size_t len) {
     return FEDFEM_OK;
 }
 
-int fedfem_create(const fedfem_mesh* mesh, const fedfem_materials* mat, const fedfem_bc* bc,
-                  fedfem_handle** out) {
+namespace {
+
+// fedfem_create and fedfem_create_hex: elements of npe nodes each
+int create_handle(int64_t N, const double* xyz, int64_t E, const int32_t* conn, int npe,
+                  const fedfem_materials* mat, const fedfem_bc* bc, fedfem_handle** out) {
     if (!out) return FEDFEM_E_INVALID;
     *out = nullptr;
-    if (!mesh || !mat || !bc) return FEDFEM_E_INVALID;
-    const int64_t N = mesh->n_nodes, E = mesh->n_tets;
-    if (N < 4 || E < 1 || !mesh->xyz || !mesh->tets || N > INT32_MAX || 4 * E > INT32_MAX)
+    if (!mat || !bc) return FEDFEM_E_INVALID;
+    if (N < npe || E < 1 || !xyz || !conn || N > INT32_MAX || npe * E > INT32_MAX)
         return FEDFEM_E_INVALID;
-    if (!finite_all(mesh->xyz, 3 * N)) return FEDFEM_E_INVALID;
+    if (!finite_all(xyz, 3 * N)) return FEDFEM_E_INVALID;
     fedfem_handle* h = new (std::nothrow) fedfem_handle();
     if (!h) return FEDFEM_E_NOMEM;
     auto fail = [&](int code) {
@@ -507,10 +509,11 @@ int fedfem_create(const fedfem_mesh* mesh, const fedfem_materials* mat, const fe
     try {
         h->N = N;
         h->E = E;
-        h->xyz.assign(mesh->xyz, mesh->xyz + 3 * N);
-        h->tets.assign(mesh->tets, mesh->tets + 4 * E);
+        h->npe = npe;
+        h->xyz.assign(xyz, xyz + 3 * N);
+        h->tets.assign(conn, conn + npe * E);
         std::vector<uint8_t> used(N, 0);
-        for (int64_t s = 0; s < 4 * E; s++) {
+        for (int64_t s = 0; s < npe * E; s++) {
             const int32_t n = h->tets[s];
             if (n < 0 || n >= N) return fail(FEDFEM_E_INVALID);
             used[n] = 1;
@@ -556,23 +559,52 @@ int fedfem_create(const fedfem_mesh* mesh, const fedfem_materials* mat, const fe
     }
     h->stream = h->own_stream;
     h->opt.reorder = 1;
-    h->opt.tile_elems = 2048;
+    h->opt.tile_elems = npe == 8 ? 1024 : 2048;
     h->opt.threads = 512;
-    h->opt.max_tile_nodes = 1024;
+    h->opt.max_tile_nodes = npe == 8 ? 2048 : 1024;
     h->opt.xcd = 0;
     *out = h;
     return FEDFEM_OK;
 }
 
+}  // namespace
+
+int fedfem_create(const fedfem_mesh* mesh, const fedfem_materials* mat, const fedfem_bc* bc,
+                  fedfem_handle** out) {
+    if (!mesh) {
+        if (out) *out = nullptr;
+        return FEDFEM_E_INVALID;
+    }
+    return create_handle(mesh->n_nodes, mesh->xyz, mesh->n_tets, mesh->tets, 4, mat, bc, out);
+}
+
+int fedfem_create_hex(const fedfem_mesh_hex* mesh, const fedfem_materials* mat,
+                      const fedfem_bc* bc, fedfem_handle** out) {
+    if (!mesh) {
+        if (out) *out = nullptr;
+        return FEDFEM_E_INVALID;
+    }
+    return create_handle(mesh->n_nodes, mesh->xyz, mesh->n_hexes, mesh->hexes, 8, mat, bc, out);
+}
+
 int fedfem_set_options(fedfem_handle* h, const fedfem_options* o) {
     if (!h || !o) return FEDFEM_E_INVALID;
     if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "options are fixed after precompute");
-    const int te = o->tile_elems ? o->tile_elems : 2048;
-    const int th = o->threads ? o->threads : std::max(64, std::min(1024, te / 4));
-    const int mn = o->max_tile_nodes ? o->max_tile_nodes : (o->reorder ? te / 2 : 4 * te);
+    // hexahedra: smaller tiles and two elements per thread by default (24
+    // coefficients per element are held in registers), tiles of up to twice
+    // as many nodes as elements
+    const bool hex = h->npe == 8;
+    const int te = o->tile_elems ? o->tile_elems : (hex ? 1024 : 2048);
+    const int th = o->threads ? o->threads
+                              : std::max(64, hex ? std::min(kHexMaxThreads, te / 2)
+                                                 : std::min(1024, te / 4));
+    const int mn = o->max_tile_nodes
+                       ? o->max_tile_nodes
+                       : (o->reorder ? (hex ? 2 * te : te / 2) : h->npe * te);
     const int r = te / std::max(th, 1);
     if (te < 64 || te > 8192 || te % 64 || th < 64 || th > 1024 || th % 64 || te % th ||
-        (r != 1 && r != 2 && r != 4) || mn < 4 || mn > 4 * te ||
+        (r != 1 && r != 2 && r != 4) || mn < h->npe || mn > h->npe * te ||
+        (hex && th > kHexMaxThreads) ||
         (o->reorder != 0 && o->reorder != 1) || (o->xcd != 0 && o->xcd != 1))
         return set_err(h, FEDFEM_E_INVALID, "invalid options");
     h->opt = *o;
@@ -618,14 +650,15 @@ int fedfem_precompute(fedfem_handle* h) {
     int TE = h->opt.tile_elems;
     try {
         int MN = h->opt.max_tile_nodes;
-        if (!build_layout(h->xyz.data(), h->tets.data(), N, E, h->opt.reorder, TE, MN, L, err))
+        if (!build_layout(h->xyz.data(), h->tets.data(), h->npe, N, E, h->opt.reorder, TE, MN,
+                          L, err))
             return set_err(h, FEDFEM_E_INVALID, "%s", err.c_str());
         // shrink tiles until the widest kernel (FP64 loads) fits in LDS
         while (tile_lds_bytes(L.tile_elems, L.max_tile_nodes, 8, false, true) > lds_limit) {
             if (L.tile_elems <= 64)
                 return set_err(h, FEDFEM_E_INVALID, "tile does not fit in LDS");
             const int te2 = std::max(64, L.tile_elems / 128 * 64);
-            MN = std::min(MN, 4 * te2);
+            MN = std::min(MN, h->npe * te2);
             if (!build_tiles(L, te2, MN, err))
                 return set_err(h, FEDFEM_E_INVALID, "%s", err.c_str());
         }
@@ -640,9 +673,12 @@ int fedfem_precompute(fedfem_handle* h) {
     d.T = L.T;
     d.P = L.P;
     d.tile_elems = L.tile_elems;
+    d.npe = h->npe;
     d.max_tile_nodes = L.max_tile_nodes;
     d.threads = std::min(h->opt.threads, L.tile_elems);
-    while (elems_per_thread(d) > 4 && d.threads < 1024) d.threads *= 2;
+    const int max_threads = h->npe == 8 ? kHexMaxThreads : 1024;
+    while (elems_per_thread(d) > 4 && d.threads < max_threads) d.threads *= 2;
+    if (elems_per_thread(d) > 4) return set_err(h, FEDFEM_E_INVALID, "tiles too large for the workgroup");
     d.xcd = h->opt.xcd;
     // topology
     try {
@@ -685,12 +721,18 @@ int fedfem_precompute(fedfem_handle* h) {
     int32_t* bad = nullptr;
     int32_t* d_eperm = nullptr;
     if ((rc = upload(h, &d_eperm, L.eperm))) return rc;
-    if ((rc = dalloc(h, &coef64, 6 * E)) || (rc = dalloc(h, &h->d_vol, E)) ||
+    // coefficients per element: the six off-diagonals of A_e (tetrahedra) or
+    // the 3 x 8 scaled gradients sqrt(V_e) grad N (hexahedra)
+    const int ncoef = h->npe == 8 ? 24 : 6;
+    if ((rc = dalloc(h, &coef64, (size_t)ncoef * E)) || (rc = dalloc(h, &h->d_vol, E)) ||
         (rc = dalloc(h, &bad, 1)) || (rc = dalloc(h, &h->d_Vi, N)) ||
         (rc = dalloc(h, &h->d_flag, 4)) || (rc = dalloc(h, &h->d_stage, N)))
         return rc;
     HIPCHK(h, launch_fill_i32(bad, 1, INT32_MAX, s));
-    HIPCHK(h, launch_geometry(E, h->d_xyz, h->d_conn, d_eperm, coef64, h->d_vol, bad, s));
+    if (h->npe == 8)
+        HIPCHK(h, launch_geometry_hex(E, h->d_xyz, h->d_conn, d_eperm, coef64, h->d_vol, bad, s));
+    else
+        HIPCHK(h, launch_geometry(E, h->d_xyz, h->d_conn, d_eperm, coef64, h->d_vol, bad, s));
     int32_t hbad = 0;
     HIPCHK(h, hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
@@ -698,16 +740,20 @@ int fedfem_precompute(fedfem_handle* h) {
     dfree(h, d_eperm);
     if (hbad != INT32_MAX) {
         release_device(h);
-        return set_err(h, FEDFEM_E_DEGENERATE, "degenerate tetrahedron %d", hbad);
+        return set_err(h, FEDFEM_E_DEGENERATE, "degenerate %s %d",
+                       h->npe == 8 ? "hexahedron" : "tetrahedron", hbad);
     }
     clk.mark("geometry");
-    HIPCHK(h, launch_lump(N, h->d_ec_off, h->d_ec, h->d_vol, h->d_Vi, s));
+    HIPCHK(h, launch_lump(N, h->d_ec_off, h->d_ec, h->d_vol, h->npe, h->d_Vi, s));
     // fixed-point scales: the largest possible corner load maps below 2^58
     {
         unsigned long long* dbits = nullptr;
         if ((rc = dalloc(h, &dbits, 1))) return rc;
         HIPCHK(h, hipMemsetAsync(dbits, 0, sizeof(unsigned long long), s));
-        HIPCHK(h, launch_coef_bound(E, coef64, dbits, s));
+        if (h->npe == 8)
+            HIPCHK(h, launch_coef_bound_hex(E, coef64, dbits, s));
+        else
+            HIPCHK(h, launch_coef_bound(E, coef64, dbits, s));
         unsigned long long bits = 0;
         std::vector<double> Vi(N);
         HIPCHK(h, hipMemcpyAsync(&bits, dbits, sizeof(bits), hipMemcpyDeviceToHost, s));
@@ -742,8 +788,8 @@ int fedfem_precompute(fedfem_handle* h) {
         return r;
     };
     if (h->fp32c) {
-        if ((rc = dalloc_bytes(&d.coef, 6 * E))) return rc;
-        HIPCHK(h, launch_cast_coef(6 * E, coef64, static_cast<float*>(d.coef), s));
+        if ((rc = dalloc_bytes(&d.coef, (size_t)ncoef * E))) return rc;
+        HIPCHK(h, launch_cast_coef((int64_t)ncoef * E, coef64, static_cast<float*>(d.coef), s));
     } else {
         d.coef = coef64;
     }
@@ -977,6 +1023,8 @@ int fedfem_flux_loads(fedfem_handle* h, int64_t n_faces, const int32_t* faces, c
     int rc = check_handle(h, true);
     if (rc) return rc;
     const int64_t N = h->N;
+    if (h->npe != 4)
+        return set_err(h, FEDFEM_E_INVALID, "flux loads need a tetrahedral mesh (triangle faces)");
     if (n_faces < 0 || n_faces > INT32_MAX / 3 || !out || (n_faces > 0 && (!faces || !flux)))
         return set_err(h, FEDFEM_E_INVALID, "bad flux arguments");
     if (!finite_all(flux, n_faces)) return set_err(h, FEDFEM_E_INVALID, "non-finite flux");
@@ -1046,6 +1094,8 @@ int fedfem_set_gaussian_sources(fedfem_handle* h, int32_t n_src, const double* p
     if (n_src < 0 || n_src > 4096 || (n_src > 0 && !params) ||
         (mode != FEDFEM_SOURCE_NODAL && mode != FEDFEM_SOURCE_CONSISTENT))
         return set_err(h, FEDFEM_E_INVALID, "bad source arguments");
+    if (mode == FEDFEM_SOURCE_CONSISTENT && h->npe != 4)
+        return set_err(h, FEDFEM_E_INVALID, "consistent source quadrature needs tetrahedra");
     for (int k = 0; k < n_src; k++) {
         if (!finite_all(params + 5 * k, 5) || !(params[5 * k + 3] > 0))
             return set_err(h, FEDFEM_E_INVALID, "bad Gaussian source %d", k);
@@ -1319,9 +1369,10 @@ int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
     int rc = check_handle(h, false);
     if (rc) return rc;
     char key[128];
-    std::snprintf(key, sizeof(key), "f%d_prec%d_td%d_e%d", flags, h->mat.precision,
+    // tetrahedral keys keep their earlier form; hexahedral ones say so
+    std::snprintf(key, sizeof(key), "f%d_prec%d_td%d_e%d%s", flags, h->mat.precision,
                   (h->mat.dk_dT != 0.0 || !h->tab_t[0].empty()) ? 1 : 0,
-                  (int)std::lround(4.0 * std::log2((double)h->E)));
+                  (int)std::lround(4.0 * std::log2((double)h->E)), h->npe == 8 ? "_hex" : "");
     fedfem_options best{};
     bool found = false;
     if (cache_path) {
@@ -1347,13 +1398,16 @@ int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
         const int n_builds = batch ? 2 : 4;
         double best_ms = 1e300;
         fedfem_mesh mesh{h->N, h->xyz.data(), h->E, h->tets.data()};
+        fedfem_mesh_hex mesh_hex{h->N, h->xyz.data(), h->E, h->tets.data()};
         fedfem_bc bc{h->T0, (int64_t)h->dir_nodes.size(), h->dir_nodes.data(), h->dir_T.data(),
                      -0.5};
         for (int bi = 0; bi < n_builds; bi++) {
             const Build& bd = builds[bi];
             if (bd.te > 64 && (int64_t)bd.te > 8 * h->E) continue;  // tiny meshes
             fedfem_handle* t = nullptr;
-            if ((rc = fedfem_create(&mesh, &h->mat, &bc, &t))) return set_err(h, rc, "autotune");
+            rc = h->npe == 8 ? fedfem_create_hex(&mesh_hex, &h->mat, &bc, &t)
+                             : fedfem_create(&mesh, &h->mat, &bc, &t);
+            if (rc) return set_err(h, rc, "autotune");
             t->timing_trial = true;
             fedfem_options o{};
             o.reorder = bd.reorder;
@@ -1364,8 +1418,9 @@ int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
                 continue;  // e.g. the tile does not fit: skip the candidate
             }
             const int te = t->d.tile_elems;
-            const int ths[2] = {std::max(64, std::min(1024, te / 4)),
-                                std::max(64, std::min(1024, te / 2))};
+            const int tmax = h->npe == 8 ? kHexMaxThreads : 1024;
+            const int ths[2] = {std::max(64, std::min(tmax, te / 4)),
+                                std::max(64, std::min(tmax, te / 2))};
             for (int ti = 0; ti < (batch ? 1 : 2); ti++)
                 for (int xcd = 0; xcd < (batch ? 1 : 2); xcd++) {
                     t->d.threads = ths[ti];

@@ -14,8 +14,9 @@
 struct fedfem_handle {
     // caller inputs (deep copies)
     int64_t N = 0, E = 0;
+    int npe = 4;  // nodes per element: 4 (tetrahedra) or 8 (hexahedra)
     std::vector<double> xyz;
-    std::vector<int32_t> tets;
+    std::vector<int32_t> tets;  // [npe E] element nodes
     fedfem_materials mat{};
     bool fp32c = true;
     double T0 = 0.0;
@@ -40,9 +41,9 @@ struct fedfem_handle {
     std::vector<int32_t> host_isdir;  // internal order
     // device arrays beyond the step layout
     double* d_xyz = nullptr;      // [3N] internal order
-    int32_t* d_conn = nullptr;    // [4E]
+    int32_t* d_conn = nullptr;    // [npe E]
     int32_t* d_ec_off = nullptr;  // [N+1]
-    int32_t* d_ec = nullptr;      // [4E]
+    int32_t* d_ec = nullptr;      // [npe E]
     double* d_vol = nullptr;      // [E]
     double* d_Vi = nullptr;       // [N]
     int32_t* d_nperm = nullptr;   // [N] internal -> caller

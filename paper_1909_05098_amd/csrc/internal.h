@@ -24,28 +24,29 @@ namespace fedfem {
 // ---------------------------------------------------------------------------
 struct Layout {
     int64_t N = 0, E = 0, T = 0, P = 0;
+    int npe = 4;  // nodes per element: 4 (linear tetrahedra) or 8 (hexahedra)
     int tile_elems = 0;
     int max_tile_nodes = 0;
     std::vector<int32_t> nperm;          // internal -> caller node id
     std::vector<int32_t> ninv;           // caller -> internal node id
     std::vector<int32_t> eperm;          // internal -> caller element id
     std::vector<double> xyz;             // [3N] internal order
-    std::vector<int32_t> conn;           // [4E] internal ids, internal order
+    std::vector<int32_t> conn;           // [npe E] internal ids, internal order
     std::vector<int32_t> tile_elem_off;  // [T+1]
     std::vector<int32_t> tile_node_off;  // [T+1]
     std::vector<int32_t> tile_nodes;     // [P]
     std::vector<int32_t> pidx;           // [P] node-major list of partial slots p
-    std::vector<uint16_t> lconn;         // [4E] local node id per corner
+    std::vector<uint16_t> lconn;         // [npe E] local node id per corner
     std::vector<uint8_t> lconn_pk;       // packed form of lconn (pack_lconn)
     std::vector<int32_t> part_off;       // [N+1] node -> partial positions
     std::vector<int32_t> ec_off;         // [N+1] node -> element corners
-    std::vector<int32_t> ec;             // [4E] e*4+corner, ascending e
+    std::vector<int32_t> ec;             // [npe E] npe*e+corner, ascending e
 };
 
 // Build the layout.  Returns false with a message on failure.
-bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
-                  int reorder, int tile_elems, int max_tile_nodes, Layout& L,
-                  std::string& err);
+bool build_layout(const double* xyz, const int32_t* conn, int npe, int64_t N,
+                  int64_t E, int reorder, int tile_elems, int max_tile_nodes,
+                  Layout& L, std::string& err);
 
 // Tile layout only (used again when tiles must shrink).
 bool build_tiles(Layout& L, int tile_elems, int max_tile_nodes,
@@ -94,6 +95,7 @@ constexpr int kMaxTab = 16;  // FEDFEM_MAX_TABLE
 struct DevLayout {
     int64_t N = 0, E = 0, T = 0, P = 0;
     int tile_elems = 0, max_tile_nodes = 0, threads = 256;
+    int npe = 4;  // nodes per element: 4 (coef [6][E]) or 8 (coef [24][E])
     int xcd = 0;  // remap blocks so each XCD walks a contiguous stretch
     int32_t* tile_elem_off = nullptr;
     int32_t* tile_node_off = nullptr;
@@ -119,6 +121,9 @@ struct DevLayout {
 // ---------------------------------------------------------------------------
 size_t tile_lds_bytes(int tile_elems, int max_nodes, int real_bytes, bool comp,
                       bool td);
+// Workgroup bound of the hexahedral element kernel (24 coefficients per
+// element in registers).
+constexpr int kHexMaxThreads = 512;
 // Elements per thread of the element kernel, rounded up to 1, 2 or 4 (the
 // instantiated counts); 8 means the workgroup is too small for the tile.
 int elems_per_thread(const DevLayout& d);
@@ -170,8 +175,17 @@ hipError_t launch_coef_bound(int64_t E, const double* coef64,
 hipError_t launch_geometry(int64_t E, const double* xyz, const int32_t* conn,
                            const int32_t* eperm, double* coef64, double* vol,
                            int32_t* bad, hipStream_t s);
+// Hexahedra (Eq 14): coef64 receives W = sqrt(V_e) grad N at the element
+// centre, [24][E] (component i of corner a at row 8 i + a).
+hipError_t launch_geometry_hex(int64_t E, const double* xyz,
+                               const int32_t* conn, const int32_t* eperm,
+                               double* coef64, double* vol, int32_t* bad,
+                               hipStream_t s);
+hipError_t launch_coef_bound_hex(int64_t E, const double* coef64,
+                                 unsigned long long* out, hipStream_t s);
 hipError_t launch_lump(int64_t N, const int32_t* ec_off, const int32_t* ec,
-                       const double* vol, double* Vi, hipStream_t s);
+                       const double* vol, int npe, double* Vi,
+                       hipStream_t s);
 hipError_t launch_source_nodal(int64_t N, const double* xyz, const double* Vi,
                                int n_src, const double* src, double* q64,
                                hipStream_t s);

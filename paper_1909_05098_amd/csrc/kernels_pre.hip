@@ -78,15 +78,85 @@ __global__ void k_geometry(int64_t E, const double* __restrict__ xyz,
     }
 }
 
-// Lumped nodal volume: each element gives a quarter of its volume to each
-// of its nodes (Sec 2.3.4), summed in ascending element order.
+// Geometry of the eight-node hexahedron with one integration point at its
+// centre (Eq 14, 16).  Corner a sits at natural coordinates xi_a in
+// {-1, 1}^3 (bottom face counter-clockwise, then the top face), so at the
+// centre dN_a/dxi = xi_a / 8 and M[j][i] = dx_i/dxi_j = sum_a xi_a,j x_a,i / 8.
+// Then grad_x N_a = M^-1 grad_xi N_a and V_e = 8 |det M|.  A_e = V_e B^T B
+// has rank 3, so the element is stored as W = sqrt(V_e) grad N, 3 x 8
+// values at coef[(8 i + a) E + e] for component i of corner a, and
+// A_e[a][b] = W_a . W_b.
+__constant__ double kHexNat[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                     {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+__global__ void k_geometry_hex(int64_t E, const double* __restrict__ xyz,
+                               const int32_t* __restrict__ conn, const int32_t* __restrict__ eperm,
+                               double* __restrict__ coef, double* __restrict__ vol,
+                               int32_t* __restrict__ bad) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double p[8][3];
+    for (int c = 0; c < 8; c++) {
+        const int64_t n = conn[8 * e + c];
+        p[c][0] = xyz[3 * n];
+        p[c][1] = xyz[3 * n + 1];
+        p[c][2] = xyz[3 * n + 2];
+    }
+    double M[3][3];
+    for (int j = 0; j < 3; j++)
+        for (int i = 0; i < 3; i++) {
+            double sum = 0.0;
+            for (int a = 0; a < 8; a++) sum += kHexNat[a][j] * p[a][i];
+            M[j][i] = 0.125 * sum;
+        }
+    // cofactors: Minv = adj(M) / det
+    double C[3][3];
+    C[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    C[0][1] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    C[0][2] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    C[1][0] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+    C[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+    C[1][2] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+    C[2][0] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+    C[2][1] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+    C[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    const double det = M[0][0] * C[0][0] + M[0][1] * C[0][1] + M[0][2] * C[0][2];
+    double l2max = 0.0;
+    for (int a = 0; a < 8; a++)
+        for (int b = a + 1; b < 8; b++) {
+            const double dx = p[a][0] - p[b][0], dy = p[a][1] - p[b][1],
+                         dz = p[a][2] - p[b][2];
+            l2max = fmax(l2max, dx * dx + dy * dy + dz * dz);
+        }
+    const double lmax = sqrt(l2max);
+    if (!(fabs(det) > 1e-12 * lmax * lmax * lmax)) {
+        atomicMin(bad, eperm[e]);  // smallest caller element id
+        for (int k = 0; k < 24; k++) coef[k * E + e] = 0.0;
+        vol[e] = 0.0;
+        return;
+    }
+    const double V = 8.0 * fabs(det);
+    vol[e] = V;
+    // Minv[i][j] = C[j][i] / det; W_a = sqrt(V) Minv xi_a / 8
+    const double f = sqrt(V) * 0.125 / det;
+    for (int a = 0; a < 8; a++)
+        for (int i = 0; i < 3; i++) {
+            const double g = C[0][i] * kHexNat[a][0] + C[1][i] * kHexNat[a][1] +
+                             C[2][i] * kHexNat[a][2];
+            coef[(8 * i + a) * E + e] = f * g;
+        }
+}
+
+// Lumped nodal volume: each element gives an equal share of its volume to
+// each of its npe nodes (Sec 2.3.4), summed in ascending element order.
 __global__ void k_lump(int64_t N, const int32_t* __restrict__ off,
-                       const int32_t* __restrict__ ec, const double* __restrict__ vol,
+                       const int32_t* __restrict__ ec, const double* __restrict__ vol, int npe,
                        double* __restrict__ Vi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    const double share = 1.0 / npe;  // 1/4 or 1/8: exact
     double s = 0.0;
-    for (int k = off[i]; k < off[i + 1]; k++) s += 0.25 * vol[ec[k] >> 2];
+    for (int k = off[i]; k < off[i + 1]; k++) s += share * vol[ec[k] / npe];
     Vi[i] = s;
 }
 
@@ -209,6 +279,32 @@ __global__ void k_coef_bound(int64_t E, const double* __restrict__ coef,
         for (int k = 0; k < 6; k++) a[k] = fabs(coef[k * E + e]);
         r = fmax(fmax(a[0] + a[1] + a[2], a[0] + a[3] + a[4]),
                  fmax(a[1] + a[3] + a[5], a[2] + a[4] + a[5]));
+    }
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sh[0]));
+}
+
+// The same bound for hexahedra, with A_e[a][b] = W_a . W_b.
+__global__ void k_coef_bound_hex(int64_t E, const double* __restrict__ coef,
+                                 unsigned long long* __restrict__ out) {
+    __shared__ double sh[kBlock];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (e < E) {
+        double w[8][3];
+        for (int a = 0; a < 8; a++)
+            for (int i = 0; i < 3; i++) w[a][i] = coef[(8 * i + a) * E + e];
+        for (int a = 0; a < 8; a++) {
+            double row = 0.0;
+            for (int b = 0; b < 8; b++)
+                if (b != a) row += fabs(w[a][0] * w[b][0] + w[a][1] * w[b][1] + w[a][2] * w[b][2]);
+            r = fmax(r, row);
+        }
     }
     sh[threadIdx.x] = r;
     __syncthreads();
@@ -450,9 +546,18 @@ hipError_t launch_geometry(int64_t E, const double* xyz, const int32_t* conn,
     return hipGetLastError();
 }
 
+hipError_t launch_geometry_hex(int64_t E, const double* xyz, const int32_t* conn,
+                               const int32_t* eperm, double* coef64, double* vol, int32_t* bad,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_geometry_hex, dim3(blocks_for(E)), dim3(kBlock), 0, s, E, xyz, conn,
+                       eperm, coef64, vol, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_lump(int64_t N, const int32_t* ec_off, const int32_t* ec, const double* vol,
-                       double* Vi, hipStream_t s) {
-    hipLaunchKernelGGL(k_lump, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, ec_off, ec, vol, Vi);
+                       int npe, double* Vi, hipStream_t s) {
+    hipLaunchKernelGGL(k_lump, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, ec_off, ec, vol, npe,
+                       Vi);
     return hipGetLastError();
 }
 
@@ -492,6 +597,13 @@ hipError_t launch_face_loads(int64_t N, int64_t F, const double* xyz, const int3
 hipError_t launch_coef_bound(int64_t E, const double* coef64, unsigned long long* out,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_coef_bound, dim3(blocks_for(E)), dim3(kBlock), 0, s, E, coef64, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_bound_hex(int64_t E, const double* coef64, unsigned long long* out,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_coef_bound_hex, dim3(blocks_for(E)), dim3(kBlock), 0, s, E, coef64,
+                       out);
     return hipGetLastError();
 }
 

@@ -168,6 +168,48 @@ __device__ __forceinline__ long long to_fixed(double f, double scale) {
     return __double2ll_rn(f * scale);
 }
 
+// Tile nodes into LDS: temperature, conductivity, zeroed accumulators.  The
+// first SJ rounds go out together, ids then temperatures (lanes past the
+// list load its last node and store nothing), so a thread waits for two
+// memory round trips instead of two per round.
+template <typename Real, bool COMP, bool TD>
+__device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int m,
+                                                 const void* __restrict__ Tin,
+                                                 const Props<Real>& pr, Real* s_T, Real* s_Tlo,
+                                                 Real* s_k, unsigned long long* s_acc) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    constexpr int SJ = 2;
+    {
+        int gj[SJ];
+#pragma unroll
+        for (int u = 0; u < SJ; u++) gj[u] = a.tile_nodes[p0 + min(tid + u * bs, m - 1)];
+        __builtin_amdgcn_sched_barrier(0);  // all id loads before any wait
+        Real hj[SJ], lj[SJ];
+#pragma unroll
+        for (int u = 0; u < SJ; u++) State<Real, COMP>::load(Tin, gj[u], hj[u], lj[u]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < SJ; u++) {
+            const int j = tid + u * bs;
+            if (j < m) {
+                s_T[j] = hj[u];
+                if (COMP) s_Tlo[j] = lj[u];
+                if (TD) s_k[j] = prop_k(hj[u], pr);
+                s_acc[j] = 0ull;
+            }
+        }
+    }
+    for (int j = tid + SJ * bs; j < m; j += bs) {
+        const int g = a.tile_nodes[p0 + j];
+        Real hi, lo;
+        State<Real, COMP>::load(Tin, g, hi, lo);
+        s_T[j] = hi;
+        if (COMP) s_Tlo[j] = lo;
+        if (TD) s_k[j] = prop_k(hi, pr);
+        s_acc[j] = 0ull;
+    }
+}
+
 template <typename Real, bool COMP, bool TD, int R>
 __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
                                           const Real* __restrict__ coef,
@@ -202,40 +244,8 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
             lc[r] = pk ? make_uint2(gw[el], gb[el]) : glc[el];
         }
     }
-    // 2. tile nodes: temperature, conductivity, zeroed accumulators.  The
-    // first SJ rounds go out together, ids then temperatures (lanes past the
-    // list load its last node and store nothing), so a thread waits for two
-    // memory round trips instead of two per round.
-    constexpr int SJ = 2;
-    {
-        int gj[SJ];
-#pragma unroll
-        for (int u = 0; u < SJ; u++) gj[u] = a.tile_nodes[p0 + min(tid + u * bs, m - 1)];
-        __builtin_amdgcn_sched_barrier(0);  // all id loads before any wait
-        Real hj[SJ], lj[SJ];
-#pragma unroll
-        for (int u = 0; u < SJ; u++) State<Real, COMP>::load(Tin, gj[u], hj[u], lj[u]);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < SJ; u++) {
-            const int j = tid + u * bs;
-            if (j < m) {
-                s_T[j] = hj[u];
-                if (COMP) s_Tlo[j] = lj[u];
-                if (TD) s_k[j] = prop_k(hj[u], pr);
-                s_acc[j] = 0ull;
-            }
-        }
-    }
-    for (int j = tid + SJ * bs; j < m; j += bs) {
-        const int g = a.tile_nodes[p0 + j];
-        Real hi, lo;
-        State<Real, COMP>::load(Tin, g, hi, lo);
-        s_T[j] = hi;
-        if (COMP) s_Tlo[j] = lo;
-        if (TD) s_k[j] = prop_k(hi, pr);
-        s_acc[j] = 0ull;
-    }
+    // 2. tile nodes
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_Tlo, s_k, s_acc);
     __syncthreads();
     // 3. element loads, accumulated exactly on the fixed-point grid
 #pragma unroll
@@ -288,6 +298,104 @@ k_elem_loads(TileArgs a, const Real* __restrict__ coef, const void* __restrict__
     const int64_t t = a.xcd ? xcd_remap(blockIdx.x, a.T) : (int64_t)blockIdx.x;
     if (t >= a.T) return;
     elem_tile<Real, COMP, TD, R>(a, t, coef, Tin, partial, pr);
+}
+
+// Eight-node hexahedra with one integration point (Eq 14, 16, 17).  The
+// element is stored as W = sqrt(V_e) grad N at its centre (3 x 8, row 8 i + a
+// for component i of corner a), so that A_e = W^T W and
+//     F_e,a = k_e W_a . g,   g = sum_b W_b (T_b - T_0),
+// the differences formed as (hi_b - hi_0) + (lo_b - lo_0) (the columns of W
+// sum to zero, so T_0 drops out of g).  k_e is the mean over the eight
+// corners (Eq 13).  Tiles, staging, fixed-point assembly and partials are
+// those of the tetrahedral pass; local corner ids are 8 x u16.
+template <typename Real, bool COMP, bool TD, int R>
+__device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
+                                              const Real* __restrict__ coef,
+                                              const void* __restrict__ Tin,
+                                              Real* __restrict__ partial,
+                                              const Props<Real>& pr) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const LdsCarve c = carve(a.TE, a.maxn, sizeof(Real), COMP, TD);
+    unsigned long long* s_acc = reinterpret_cast<unsigned long long*>(lds + c.acc);
+    Real* s_T = reinterpret_cast<Real*>(lds + c.T);
+    Real* s_Tlo = reinterpret_cast<Real*>(lds + c.Tlo);
+    Real* s_k = reinterpret_cast<Real*>(lds + c.k);
+
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int64_t e0 = a.tile_elem_off[t];
+    const int ne = (int)(a.tile_elem_off[t + 1] - e0);
+    const int p0 = a.tile_node_off[t];
+    const int m = a.tile_node_off[t + 1] - p0;
+
+    // 1. coefficient and local-connectivity loads in flight during staging
+    Real w[R][24];
+    uint4 lc[R];
+    const uint4* glc = static_cast<const uint4*>(a.lconn) + e0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int el = tid + r * bs;
+        if (el < ne) {
+#pragma unroll
+            for (int k = 0; k < 24; k++) w[r][k] = coef[k * a.E + e0 + el];
+            lc[r] = glc[el];
+        }
+    }
+    // 2. tile nodes
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_Tlo, s_k, s_acc);
+    __syncthreads();
+    // 3. element loads, accumulated exactly on the fixed-point grid
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int el = tid + r * bs;
+        if (el < ne) {
+            const unsigned ww[4] = {lc[r].x, lc[r].y, lc[r].z, lc[r].w};
+            int n[8];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                n[2 * q] = (int)(ww[q] & 0xffffu);
+                n[2 * q + 1] = (int)(ww[q] >> 16);
+            }
+            const Real h0 = s_T[n[0]];
+            const Real l0 = COMP ? s_Tlo[n[0]] : Real(0);
+            Real g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+            for (int b = 1; b < 8; b++) {
+                Real d = s_T[n[b]] - h0;
+                if (COMP) d += s_Tlo[n[b]] - l0;
+                g0 += w[r][b] * d;
+                g1 += w[r][8 + b] * d;
+                g2 += w[r][16 + b] * d;
+            }
+            Real ke;
+            if (TD) {
+                Real ks = 0;
+#pragma unroll
+                for (int b = 0; b < 8; b++) ks += s_k[n[b]];
+                ke = ks * Real(0.125);
+            } else {
+                ke = pr.k0;
+            }
+            // corners in a fixed order (a lane-dependent order would index
+            // the coefficient registers at run time)
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const Real F = ke * ((w[r][q] * g0 + w[r][8 + q] * g1) + w[r][16 + q] * g2);
+                atomicAdd(&s_acc[n[q]], (unsigned long long)to_fixed(F, pr.fxs));
+            }
+        }
+    }
+    __syncthreads();
+    // 4. one partial per tile node, tile-major
+    for (int j = tid; j < m; j += bs) partial[p0 + j] = (Real)(long long)s_acc[j] * pr.fxi;
+}
+
+template <typename Real, bool COMP, bool TD, int R>
+__global__ void __launch_bounds__(kHexMaxThreads)
+k_elem_loads_hex(TileArgs a, const Real* __restrict__ coef, const void* __restrict__ Tin,
+                 Real* __restrict__ partial, Props<Real> pr) {
+    const int64_t t = a.xcd ? xcd_remap(blockIdx.x, a.T) : (int64_t)blockIdx.x;
+    if (t >= a.T) return;
+    elem_tile_hex<Real, COMP, TD, R>(a, t, coef, Tin, partial, pr);
 }
 
 // Batched form: the workgroup's tile comes from a list of active tiles and
@@ -478,7 +586,7 @@ template <typename Real, bool COMP, bool TD, int R>
 hipError_t launch_elem_r(const DevLayout& d, const Real* coef, const Props<Real>& p,
                          const void* Tin, Real* partial, hipStream_t s) {
     const size_t lds = carve(d.tile_elems, d.max_tile_nodes, sizeof(Real), COMP, TD).total;
-    auto kern = k_elem_loads<Real, COMP, TD, R>;
+    auto kern = d.npe == 8 ? k_elem_loads_hex<Real, COMP, TD, R> : k_elem_loads<Real, COMP, TD, R>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
     const int64_t grid = d.xcd ? (d.T + kXcds - 1) / kXcds * kXcds : d.T;

@@ -122,11 +122,12 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
         err = "tile_elems must be a multiple of 64 in [64, 8192]";
         return false;
     }
-    if (MN < 4 || MN > 4 * TE) {
-        err = "max_tile_nodes must lie in [4, 4 * tile_elems]";
+    if (MN < L.npe || MN > L.npe * TE) {
+        err = "max_tile_nodes must lie in [nodes per element, nodes per element * tile_elems]";
         return false;
     }
     const int64_t E = L.E, N = L.N;
+    const int npe = L.npe;
     L.tile_elems = TE;
     // greedy cut along the element order: close a tile when it holds TE
     // elements or the next element would bring it past MN distinct nodes
@@ -136,9 +137,9 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
         int32_t t = 0;
         int cnt = 0, ne = 0;
         for (int64_t e = 0; e < E; e++) {
-            const int32_t* n = &L.conn[4 * e];
+            const int32_t* n = &L.conn[(int64_t)npe * e];
             int nnew = 0;
-            for (int c = 0; c < 4; c++) {
+            for (int c = 0; c < npe; c++) {
                 bool dup = false;
                 for (int d = 0; d < c; d++) dup |= (n[d] == n[c]);
                 if (!dup && mark[n[c]] != t) nnew++;
@@ -149,13 +150,13 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
                 cnt = 0;
                 ne = 0;
                 nnew = 0;
-                for (int c = 0; c < 4; c++) {
+                for (int c = 0; c < npe; c++) {
                     bool dup = false;
                     for (int d = 0; d < c; d++) dup |= (n[d] == n[c]);
                     if (!dup) nnew++;
                 }
             }
-            for (int c = 0; c < 4; c++) mark[n[c]] = t;
+            for (int c = 0; c < npe; c++) mark[n[c]] = t;
             cnt += nnew;
             ne++;
         }
@@ -166,15 +167,15 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     // pass 1: each tile's distinct nodes in ascending id (a marker array per
     // worker finds them; only the distinct nodes are sorted) and every
     // corner's position in that list
-    std::vector<int32_t> uniq(4 * E);  // tile t's list at 4 * tile_elem_off[t]
+    std::vector<int32_t> uniq((size_t)npe * E);  // tile t's list at npe * tile_elem_off[t]
     std::vector<int32_t> ucount(T);
-    L.lconn.assign(4 * E, 0);
+    L.lconn.assign((size_t)npe * E, 0);
     parallel_for(T, [&](int64_t a, int64_t b) {
         std::vector<int32_t> loc(N, -1);
         for (int64_t t = a; t < b; t++) {
-            const int64_t e0 = L.tile_elem_off[t], nc = 4 * (L.tile_elem_off[t + 1] - e0);
-            const int32_t* c = L.conn.data() + 4 * e0;
-            int32_t* u = uniq.data() + 4 * e0;
+            const int64_t e0 = L.tile_elem_off[t], nc = npe * (L.tile_elem_off[t + 1] - e0);
+            const int32_t* c = L.conn.data() + npe * e0;
+            int32_t* u = uniq.data() + npe * e0;
             int32_t nu = 0;
             for (int64_t s2 = 0; s2 < nc; s2++)
                 if (loc[c[s2]] < 0) {
@@ -183,7 +184,7 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
                 }
             std::sort(u, u + nu);
             for (int32_t i = 0; i < nu; i++) loc[u[i]] = i;
-            for (int64_t s2 = 0; s2 < nc; s2++) L.lconn[4 * e0 + s2] = (uint16_t)loc[c[s2]];
+            for (int64_t s2 = 0; s2 < nc; s2++) L.lconn[npe * e0 + s2] = (uint16_t)loc[c[s2]];
             for (int32_t i = 0; i < nu; i++) loc[u[i]] = -1;
             ucount[t] = nu;
         }
@@ -208,7 +209,7 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     parallel_for(T, [&](int64_t a, int64_t b) {
         for (int64_t t = a; t < b; t++)
             std::memcpy(L.tile_nodes.data() + L.tile_node_off[t],
-                        uniq.data() + 4 * (int64_t)L.tile_elem_off[t],
+                        uniq.data() + npe * (int64_t)L.tile_elem_off[t],
                         sizeof(int32_t) * ucount[t]);
     }, 4);
     // node-major partial positions, ascending tile inside each node
@@ -225,7 +226,7 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
 
 void pack_lconn(Layout& L) {
     std::vector<uint8_t>().swap(L.lconn_pk);
-    if (L.max_tile_nodes > kPackedMaxNodes) return;
+    if (L.npe != 4 || L.max_tile_nodes > kPackedMaxNodes) return;
     const int64_t E = L.E;
     L.lconn_pk.resize(5 * E);
     uint8_t* words = L.lconn_pk.data();
@@ -241,12 +242,13 @@ void pack_lconn(Layout& L) {
     }, 65536);
 }
 
-bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
+bool build_layout(const double* xyz, const int32_t* conn, int npe, int64_t N, int64_t E,
                   int reorder, int TE, int MN, Layout& L, std::string& err) {
     L = Layout();
     L.N = N;
     L.E = E;
-    if (4 * E > INT32_MAX) {
+    L.npe = npe;
+    if ((int64_t)npe * E > INT32_MAX) {
         err = "mesh too large for 32-bit element-corner indices";
         return false;
     }
@@ -260,8 +262,9 @@ bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
             for (int64_t e = a; e < b; e++)
                 for (int ax = 0; ax < 3; ax++) {
                     double s = 0;
-                    for (int c = 0; c < 4; c++) s += xyz[3 * (int64_t)tets[4 * e + c] + ax];
-                    cen[3 * e + ax] = 0.25 * s;
+                    for (int c = 0; c < npe; c++)
+                        s += xyz[3 * (int64_t)conn[(int64_t)npe * e + c] + ax];
+                    cen[3 * e + ax] = s / npe;
                 }
         });
         L.eperm = morton_order(cen.data(), E);
@@ -274,18 +277,19 @@ bool build_layout(const double* xyz, const int32_t* tets, int64_t N, int64_t E,
     L.xyz.resize(3 * N);
     for (int64_t i = 0; i < N; i++)
         std::memcpy(&L.xyz[3 * i], xyz + 3 * (int64_t)L.nperm[i], 3 * sizeof(double));
-    L.conn.resize(4 * E);
+    const int64_t S = (int64_t)npe * E;  // element corners
+    L.conn.resize(S);
     for (int64_t e = 0; e < E; e++)
-        for (int c = 0; c < 4; c++)
-            L.conn[4 * e + c] = L.ninv[tets[4 * (int64_t)L.eperm[e] + c]];
-    // node -> (element, corner), ascending internal element
+        for (int c = 0; c < npe; c++)
+            L.conn[npe * e + c] = L.ninv[conn[(int64_t)npe * L.eperm[e] + c]];
+    // node -> (element, corner) as npe * e + corner, ascending internal element
     L.ec_off.assign(N + 1, 0);
-    for (int64_t s = 0; s < 4 * E; s++) L.ec_off[L.conn[s] + 1]++;
+    for (int64_t s = 0; s < S; s++) L.ec_off[L.conn[s] + 1]++;
     for (int64_t i = 0; i < N; i++) L.ec_off[i + 1] += L.ec_off[i];
-    L.ec.assign(4 * E, 0);
+    L.ec.assign(S, 0);
     {
         std::vector<int32_t> fill(L.ec_off.begin(), L.ec_off.end() - 1);
-        for (int64_t s = 0; s < 4 * E; s++) L.ec[fill[L.conn[s]]++] = (int32_t)s;
+        for (int64_t s = 0; s < S; s++) L.ec[fill[L.conn[s]]++] = (int32_t)s;
     }
     return build_tiles(L, TE, MN, err);
 }

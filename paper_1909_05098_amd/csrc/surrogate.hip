@@ -1772,7 +1772,7 @@ int fedfem_resample(fedfem_handle* h, int32_t grid, const double* frame, float* 
     if (!h || grid < 1 || grid > 1024 || !frame || !T_out || !mask_out) return FEDFEM_E_INVALID;
     if (!h->precomputed) return FEDFEM_E_NOT_PRECOMPUTED;
     if (h->broken) return FEDFEM_E_HIP;
-    if (!(frame[3] > 0)) return FEDFEM_E_INVALID;
+    if (!(frame[3] > 0) || h->npe != 4) return FEDFEM_E_INVALID;
     NCHK(hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const int64_t nv = (int64_t)grid * grid * grid;

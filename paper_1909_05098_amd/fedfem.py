@@ -78,6 +78,7 @@ _lib = None
 _P = C.c_void_p
 _SIGS = {
     "fedfem_create": (C.c_int, [_P, _P, _P, _P]),
+    "fedfem_create_hex": (C.c_int, [_P, _P, _P, _P]),
     "fedfem_set_options": (C.c_int, [_P, _P]),
     "fedfem_precompute": (C.c_int, [_P]),
     "fedfem_precompute_many": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
@@ -139,7 +140,8 @@ def _ptr(a):
 
 
 class Handle:
-    """One scenario: mesh, materials, boundary conditions, device state."""
+    """One scenario: mesh (tetrahedra, or eight-node hexahedra when `tets` has
+    8 columns), materials, boundary conditions, device state."""
 
     def __init__(self, xyz, tets, materials, T0=37.0, dir_nodes=(), dir_T=(),
                  dt=-0.9, precision=FP32C, reorder=True, tile_elems=0,
@@ -154,6 +156,8 @@ class Handle:
                                                   dn.shape))
         self.N = len(self.xyz)
         self.E = len(self.tets)
+        # (E, 4) tetrahedra or (E, 8) hexahedra (corner order of fedfem_mesh_hex)
+        self.hex = self.tets.ndim == 2 and self.tets.shape[1] == 8
         mesh = Mesh(self.N, _ptr(self.xyz), self.E, _ptr(self.tets))
         if isinstance(materials, dict):
             vals = [float(materials[f]) for f in MAT_FIELDS]
@@ -162,8 +166,9 @@ class Handle:
         mat = Materials(*vals, int(precision))
         bc = BC(float(T0), len(dn), _ptr(dn) if len(dn) else None,
                 _ptr(dT) if len(dn) else None, float(dt))
-        self._check(L.fedfem_create(C.byref(mesh), C.byref(mat), C.byref(bc),
-                                    C.byref(self._h)), "fedfem_create")
+        create = L.fedfem_create_hex if self.hex else L.fedfem_create
+        self._check(create(C.byref(mesh), C.byref(mat), C.byref(bc), C.byref(self._h)),
+                    "fedfem_create_hex" if self.hex else "fedfem_create")
         self.precision = int(precision)
         opt = Options(1 if reorder else 0, int(tile_elems), int(threads),
                       int(max_tile_nodes), 1 if xcd else 0)

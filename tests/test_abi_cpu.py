@@ -103,3 +103,20 @@ def test_product_never_imports_oracle():
     for f in ("fedfem_oracle.c", "__init__.py", "dense.py"):
         text = open(os.path.join(ROOT, "oracle", f)).read()
         assert "paper_1909_05098_amd" not in text
+
+
+@pytest.mark.parametrize("case", ["bad_id", "unused_node", "nan_xyz"])
+def test_create_hex_rejects_bad_input(case):
+    xyz, hexes = mesh.hex_box(3, 2, 2, 1e-3)
+    if case == "bad_id":
+        hexes = hexes.copy()
+        hexes[2, 7] = -1
+    elif case == "unused_node":
+        xyz = np.vstack([xyz, [[9.0, 9.0, 9.0]]])
+    elif case == "nan_xyz":
+        xyz = xyz.copy()
+        xyz[5, 2] = np.inf
+    with pytest.raises(ff.FedFemError) as ei:
+        ff.Handle(xyz, hexes, _mat(), 37.0, [0, 1], [37.0, 37.0])
+    assert ei.value.code == ff.E_INVALID
+    assert "fedfem_create_hex" in str(ei.value)

@@ -1,0 +1,192 @@
+"""GPU parity of the eight-node reduced-integration hexahedron (Sec 2.3.3,
+Eq 14, 16) with the FP64 NumPy oracle (oracle/hex.py).
+
+Tolerances as for tetrahedra: FP64 path 1e-10 K, compensated FP32 path
+1e-3 K, critical-step eigenvalue within the Lanczos bound of the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from oracle import hex as ohx
+from paper_1909_05098_amd import fedfem as ff
+from synth import mesh, scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+TOL = {ff.FP64: 1e-10, ff.FP32C: 1e-3}
+ROTATE_Z = [1, 2, 3, 0, 5, 6, 7, 4]   # same hexahedron, corners relabelled
+MIRROR = [4, 5, 6, 7, 0, 1, 2, 3]     # same hexahedron, det J < 0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+    ff.load()
+
+
+def jittered_hex_box(nx, ny, nz, h, seed, jitter=0.2):
+    xyz, hexes = mesh.hex_box(nx, ny, nz, h)
+    bnd = mesh.box_surface_nodes(nx, ny, nz)
+    rng = np.random.default_rng(seed)
+    mask = np.ones(len(xyz), bool)
+    mask[bnd] = False
+    xyz[mask] += rng.uniform(-jitter * h, jitter * h, (mask.sum(), 3))
+    return xyz, hexes, bnd
+
+
+def shuffled(xyz, hexes, bnd, seed):
+    """Random node and element numbering, and each element's corners
+    relabelled by a rotation or a mirror of the reference cube."""
+    rng = np.random.default_rng(seed)
+    n_perm = rng.permutation(len(xyz))
+    inv = np.empty_like(n_perm)
+    inv[n_perm] = np.arange(len(xyz))
+    e_perm = rng.permutation(len(hexes))
+    hx = inv[hexes[e_perm]]
+    pick = rng.integers(0, 3, len(hx))
+    hx[pick == 1] = hx[pick == 1][:, ROTATE_Z]
+    hx[pick == 2] = hx[pick == 2][:, MIRROR]
+    return xyz[n_perm], hx.astype(np.int32), np.sort(inv[bnd]).astype(np.int32)
+
+
+def oracle_model(xyz, hexes, mat, bnd, dt=None):
+    m = ohx.HexModel(xyz, hexes, oracle.mat_vector(mat), bnd, np.full(len(bnd), 37.0))
+    m.dt = 0.9 * m.dt_cr() if dt is None else dt
+    return m
+
+
+@pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
+@pytest.mark.parametrize("reorder,tile", [(1, 1024), (0, 64), (1, 128)])
+def test_hex_parity_jittered_box(prec, reorder, tile):
+    xyz, hexes, bnd = jittered_hex_box(18, 14, 10, 1e-3, seed=41)
+    xyz, hexes, bnd = shuffled(xyz, hexes, bnd, seed=3)
+    mat = sc.td_materials()
+    mat.Q_m = 3000.0
+    om = oracle_model(xyz, hexes, mat, bnd)
+    src = [[9e-3, 7e-3, 5e-3, 1.5e-3, 4e8], [4e-3, 4e-3, 3e-3, 1e-3, 2e8]]
+    q = om.source_nodal(src)
+    n = 300
+    T_ref = om.run(om.initial(37.0), n, q)
+    h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
+                  precision=prec, reorder=bool(reorder), tile_elems=tile)
+    h.precompute()
+    h.set_gaussian_sources(np.array(src), ff.SOURCE_NODAL)
+    qg = h.read_source()
+    assert np.max(np.abs(qg - q)) <= (1e-12 if prec == ff.FP64 else 1e-6) * q.max()
+    h.step(n)
+    err = float(np.max(np.abs(h.read_T() - T_ref)))
+    info = h.info()
+    print(f"[hex] prec={prec} reorder={reorder} tile={tile}: tiles={info['n_tiles']} "
+          f"max|dT|={err:.3e} K peak={T_ref.max():.2f}", flush=True)
+    assert T_ref.max() > 60.0
+    assert info["n_tiles"] >= 3
+    assert err <= TOL[prec]
+    h.close()
+
+
+def test_hex_critical_step():
+    """Lanczos on the GPU against the closed-form mode maximum (regular box)
+    and the oracle's eigenvalue (jittered box), and dt = 0.9 dt_cr."""
+    xyz, hexes = mesh.hex_box(12, 10, 9, 0.8e-3)
+    bnd = mesh.box_surface_nodes(12, 10, 9)
+    mat = sc.td_materials()
+    h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=-0.9,
+                  precision=ff.FP32C)
+    h.precompute()
+    lam = cf.hex_box_lambda(12, 10, 9, 0.8e-3)
+    lam_g = h.info()["lambda_geometry"]
+    print(f"[hex] regular box lambda gpu={lam_g:.10e} closed form={lam:.10e}", flush=True)
+    assert (1 - 1e-4) * lam <= lam_g <= (1 + 1e-3) * lam
+    dt, dtcr = h.dt()
+    assert abs(dt - 0.9 * dtcr) <= 1e-15 * dt
+    h.close()
+    xyz, hexes, bnd = jittered_hex_box(10, 9, 8, 1e-3, seed=5)
+    om = oracle_model(xyz, hexes, mat, bnd, dt=1.0)
+    lam_o = om.geometry_lambda()
+    h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=-0.9,
+                  precision=ff.FP64)
+    h.precompute()
+    lam_g = h.info()["lambda_geometry"]
+    print(f"[hex] jittered lambda gpu={lam_g:.10e} oracle={lam_o:.10e}", flush=True)
+    assert (1 - 1e-4) * lam_o <= lam_g <= (1 + 1e-3) * lam_o
+    h.close()
+
+
+@pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
+def test_hex_zero_energy_mode_is_kept(prec):
+    """Eq 14 read without hourglass control: on a regular box a checkerboard
+    field (held on the surface too) has zero gradient at every element
+    centre, so with no perfusion and no source it stays as it is."""
+    nx, ny, nz = 8, 6, 5
+    xyz, hexes = mesh.hex_box(nx, ny, nz, 1e-3)
+    K, J, I = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                          indexing="ij")
+    chk = 37.0 + 2.0 * ((-1.0) ** (I + J + K)).ravel()
+    bnd = mesh.box_surface_nodes(nx, ny, nz)
+    mat = sc.td_materials(w_b=0.0)
+    om = ohx.HexModel(xyz, hexes, oracle.mat_vector(mat), bnd, chk[bnd])
+    om.dt = 0.9 * om.dt_cr()
+    T_ref = om.run(chk.copy(), 100)
+    h = ff.Handle(xyz, hexes, mat, 37.0, bnd, chk[bnd], dt=om.dt, precision=prec)
+    h.precompute()
+    # start from the checkerboard (raw state, caller's node order)
+    T0 = chk
+    if prec == ff.FP64:
+        raw = T0.astype(np.float64).view(np.uint8)
+    else:
+        hi = T0.astype(np.float32)
+        raw = np.concatenate([hi, (T0 - hi).astype(np.float32)]).view(np.uint8)
+    h.write_state(raw, 0.0, 0)
+    h.step(100)
+    err = float(np.max(np.abs(h.read_T() - T_ref)))
+    print(f"[hex] checkerboard prec={prec}: max|dT| {err:.3e} K, oracle drift "
+          f"{float(np.max(np.abs(T_ref - chk))):.1e} K", flush=True)
+    assert np.max(np.abs(T_ref - chk)) <= 1e-12
+    assert err <= TOL[prec]
+    h.close()
+
+
+def test_hex_autotune_and_errors():
+    xyz, hexes, bnd = jittered_hex_box(16, 12, 10, 1e-3, seed=8)
+    mat = sc.td_materials()
+    om = oracle_model(xyz, hexes, mat, bnd)
+    q = om.source_nodal([[8e-3, 6e-3, 5e-3, 1.5e-3, 4e8]])
+    T_ref = om.run(om.initial(37.0), 200, q)
+    h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
+                  precision=ff.FP32C)
+    chosen = h.autotune(None)
+    assert chosen["threads"] <= 512
+    h.precompute()
+    h.set_gaussian_sources(np.array([[8e-3, 6e-3, 5e-3, 1.5e-3, 4e8]]), ff.SOURCE_NODAL)
+    h.step(200)
+    err = float(np.max(np.abs(h.read_T() - T_ref)))
+    print(f"[hex] autotuned {chosen}: max|dT| {err:.3e} K", flush=True)
+    assert err <= 1e-3
+    # what a hexahedral handle refuses
+    with pytest.raises(ff.FedFemError) as ei:
+        h.set_gaussian_sources(np.array([[8e-3, 6e-3, 5e-3, 1.5e-3, 4e8]]),
+                               ff.SOURCE_CONSISTENT)
+    assert ei.value.code == ff.E_INVALID
+    with pytest.raises(ff.FedFemError) as ei:
+        h.flux_loads(np.array([[0, 1, 2]], dtype=np.int32), [1.0])
+    assert ei.value.code == ff.E_INVALID
+    with pytest.raises(ff.FedFemError) as ei:
+        ff.Batch([h])
+    assert ei.value.code == ff.E_STATE
+    with pytest.raises(ff.FedFemError):
+        ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
+                  precision=ff.FP32C, tile_elems=2048, threads=1024)
+    h.close()
+    # a flattened hexahedron is degenerate
+    bad = xyz.copy()
+    c = hexes[len(hexes) // 2]
+    bad[c[4:]] = bad[c[:4]]
+    g = ff.Handle(bad, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=-0.9)
+    with pytest.raises(ff.FedFemError) as ei:
+        g.precompute()
+    assert ei.value.code == ff.E_DEGENERATE
+    g.close()
