@@ -18,7 +18,9 @@ Beside it: the planning sweep (256 seeded scenarios, one at a time versus one
 batched launch) and the learned surrogate on 512 held-out scenarios (FED-FEM
 one at a time and batched, the network alone, and the network with its
 FED-FEM spot check and fallback), each with scenarios/s and its error
-against FED-FEM.
+against FED-FEM; and the same ellipsoid meshed with eight-node
+reduced-integration hexahedra (element-updates/s, its element kernel's
+roofline, its parity against the oracle's stored run).
 """
 import argparse
 import hashlib
@@ -35,7 +37,9 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = ("tet-element updates/s + achieved HBM GB/s; scenarios/s plain vs "
           "batched/surrogate")
 GOLDEN3 = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
+GOLDEN_HEX = os.path.join(ROOT, "tests", "golden", "hex_ellipsoid_oracle.json")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "elem_loads_config3_pmc.txt")
+PMC_SUMMARY_HEX = os.path.join(ROOT, "profiles", "elem_loads_hex_ellipsoid_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_05098_amd", "csrc", "kernels_step.hip")
 TUNE_CACHE = os.path.join(os.environ.get("TMPDIR", "/tmp"), "fedfem_tune_cache.txt")
 
@@ -48,18 +52,18 @@ def kernel_sha():
     return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
 
 
-def read_traffic(n_tets, tile_elems, threads, xcd):
+def read_traffic(n_elems, tile_elems, threads, xcd, summary=PMC_SUMMARY, count="n_tets"):
     """HBM bytes per element-kernel launch from the committed PMC summary,
     if it was taken on the current kernel source and on this layout (tile
     size, workgroup size, XCD remap); else None."""
-    if not os.path.exists(PMC_SUMMARY):
+    if not os.path.exists(summary):
         return None
-    text = open(PMC_SUMMARY).read()
+    text = open(summary).read()
     vals = dict(re.findall(r"^(\w+)\s*=\s*(\S+)\s*$", text, flags=re.M))
     try:
         if vals.get("kernel_source_sha1") != kernel_sha():
             return None
-        if int(vals["n_tets"]) != n_tets:
+        if int(vals[count]) != n_elems:
             return None
         key = f"traffic_bytes_per_launch_te{tile_elems}_th{threads}_xcd{xcd}"
         return float(vals[key]) if key in vals else None
@@ -90,6 +94,103 @@ def cpu_baseline(scn, dt, q_params, seconds):
                        f"and dt from the initial state ({el:.1f} s timed, "
                        f"{setup:.1f} s untimed setup), OpenMP threads = "
                        f"{oracle.max_threads()}")}
+
+
+def run_hex(args):
+    """The same ellipsoid as eight-node hexahedra (2.91M elements, 2.99M
+    nodes): element-updates/s over --steps captured steps, the element
+    kernel's roofline, the result against the oracle's stored sample of the
+    same run, and the FP64 oracle timed on a few steps."""
+    import numpy as np
+    from paper_1909_05098_amd import fedfem as ff
+    from synth import scenarios as sc
+
+    t0 = time.perf_counter()
+    scn = sc.hex_ellipsoid("random", h=args.h, n_steps=args.steps)
+    log(f"hex mesh {scn.n_tets} hexahedra {scn.n_nodes} nodes ({time.perf_counter() - t0:.1f} s)")
+    golden = None
+    if os.path.exists(GOLDEN_HEX):
+        golden = json.load(open(GOLDEN_HEX))
+        if golden["n_hexes"] != scn.n_tets:
+            golden = None
+    h = ff.Handle(scn.xyz, scn.tets, scn.materials, scn.T0, scn.dir_nodes, scn.dir_T,
+                  dt=golden["dt"] if golden else -0.9, precision=ff.FP32C,
+                  reorder=(args.order == "morton"), tile_elems=args.hex_tile,
+                  threads=args.hex_threads)
+    tuned = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuned = h.autotune(TUNE_CACHE)
+        log(f"hex autotune {time.perf_counter() - t0:.2f} s -> {tuned}")
+    t0 = time.perf_counter()
+    h.precompute()
+    t_pre = time.perf_counter() - t0
+    info = h.info()
+    xcd = int(tuned["xcd"]) if tuned is not None else 0
+    dt, dt_cr = h.dt()
+    log(f"hex precompute {t_pre:.2f} s, dt={dt:.6g} dt_cr={dt_cr:.6g}, tiles={info['n_tiles']}")
+    h.set_gaussian_sources(scn.sources, ff.SOURCE_NODAL)
+    state0, _, _ = h.read_state()
+    h.prepare(args.steps)
+    if args.warmup:
+        h.step(args.warmup)
+    h.write_state(state0, 0.0, 0)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(args.steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    E, N = scn.n_tets, scn.n_nodes
+    max_err = None
+    if golden and golden["n_steps"] == args.steps:
+        T = h.read_T()
+        idx = np.asarray(golden["idx"])
+        max_err = float(np.max(np.abs(T[idx] - np.asarray(golden["T"]))))
+        log(f"hex: max|T - T_oracle| on {len(idx)} sampled nodes = {max_err:.3e} K")
+    elem_ms, node_ms = h.time_kernels(args.kernel_steps)
+    h.close()
+    # algorithmic bytes per hexahedron: 24 f32 coefficients and eight 32-bit
+    # node ids (the layout stores 16-bit tile-local ids)
+    elem_bytes = 128.0 * E
+    node_bytes = 24.0 * N
+    achieved = elem_bytes / (elem_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "elem_loads_hex", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": read_traffic(E, info["tile_elems"], info["threads"], xcd,
+                                        PMC_SUMMARY_HEX, "n_hexes"),
+                "algorithmic_bytes_per_launch": elem_bytes, "avg_launch_ms": round(elem_ms, 5)}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import hex as ohx
+        import oracle
+        t0 = time.perf_counter()
+        m = ohx.HexModel(scn.xyz, scn.tets, oracle.mat_vector(scn.materials),
+                         scn.dir_nodes, scn.dir_T, dt=dt)
+        q = m.source_nodal(scn.sources)
+        setup = time.perf_counter() - t0
+        T = m.initial(scn.T0)
+        t0 = time.perf_counter()
+        T = m.run(T, args.hex_cpu_steps, q)
+        el = time.perf_counter() - t0
+        cpu = {"value": round(E * args.hex_cpu_steps / el, 1), "unit": "element-updates/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"FP64 NumPy hexahedral oracle, {args.hex_cpu_steps} steps of the "
+                         f"same mesh from the initial state ({el:.1f} s timed, {setup:.1f} s "
+                         f"untimed setup)"}
+    return {"workload": f"ellipsoid 75x50x40 mm as eight-node reduced-integration "
+                        f"hexahedra, jittered lattice h={args.h * 1e3:g} mm, TD k(T) c(T), "
+                        f"two Gaussian sources (nodal), {args.order} order",
+            "n_hexes": E, "n_nodes": N, "steps": args.steps, "dt_s": dt,
+            "value": round(E * args.steps / t_run, 1), "unit": "element-updates/s",
+            "ms_per_step": round(t_run * 1e3 / args.steps, 5),
+            "tile_elems": info["tile_elems"], "threads": info["threads"], "xcd": xcd,
+            "roofline": roofline,
+            "node_update": {"avg_launch_ms": round(node_ms, 5),
+                            "achieved_GBps": round(node_bytes / (node_ms * 1e-3) / 1e9, 1)},
+            "max_abs_dT_vs_oracle_K": max_err, "precompute_s": round(t_pre, 3),
+            "cpu_baseline": cpu}
 
 
 def _gen_sweep_one(j):
@@ -327,6 +428,13 @@ def main():
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate leg and print its result (for profiling "
                          "its kernels); not a benchmark line")
+    ap.add_argument("--hex", type=int, default=1,
+                    help="also run the hexahedral ellipsoid (0 to skip)")
+    ap.add_argument("--hex-only", action="store_true",
+                    help="run only the hexahedral ellipsoid leg")
+    ap.add_argument("--hex-tile", type=int, default=0)
+    ap.add_argument("--hex-threads", type=int, default=0)
+    ap.add_argument("--hex-cpu-steps", type=int, default=4)
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for "
                          "counter calibration) and exit")
@@ -339,13 +447,13 @@ def main():
 
     import numpy as np
     sweep_scns = None
-    if args.sweep and not args.copy_calib_gib and not args.surrogate_only:
+    if args.sweep and not args.copy_calib_gib and not args.surrogate_only and not args.hex_only:
         t0 = time.perf_counter()
         sweep_scns = gen_sweep(range(args.sweep), min(16, os.cpu_count() or 1))
         log(f"sweep meshes: {len(sweep_scns)} scenarios "
             f"({sum(s.n_tets for s in sweep_scns)} tets, {time.perf_counter() - t0:.1f} s)")
     sur_scns = None
-    if args.surrogate and not args.copy_calib_gib:
+    if args.surrogate and not args.copy_calib_gib and not args.hex_only:
         t0 = time.perf_counter()
         sur_scns = gen_sweep(range(10000, 10000 + args.surrogate), min(16, os.cpu_count() or 1))
         log(f"surrogate held-out meshes: {len(sur_scns)} ({time.perf_counter() - t0:.1f} s)")
@@ -365,6 +473,9 @@ def main():
     if args.surrogate_only:
         print(json.dumps({"surrogate": run_surrogate(sur_scns, args.surrogate_weights)}),
               flush=True)
+        return
+    if args.hex_only:
+        print(json.dumps({"hex": run_hex(args)}), flush=True)
         return
 
     from paper_1909_05098_amd import fedfem as ff
@@ -442,6 +553,7 @@ def main():
     h.close()
     batched = run_sweep(sweep_scns, not args.no_autotune) if sweep_scns else None
     surrogate = run_surrogate(sur_scns, args.surrogate_weights) if sur_scns else None
+    hexleg = run_hex(args) if args.hex else None
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -470,6 +582,7 @@ def main():
         "precompute_s": round(t_pre, 3),
         "batched": batched,
         "surrogate": surrogate,
+        "hex": hexleg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -197,6 +197,72 @@ def jittered_ellipsoid(semi_axes, h, rng, jitter=0.2, centre=(0.0, 0.0, 0.0)):
     return xyz, tets, bnd
 
 
+# The eight corners of a lattice cube in the hexahedral node order (bottom
+# face counter-clockwise seen from +z, then the top face above it).
+HEX_CORNERS = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0),
+                        (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)], dtype=np.int64)
+
+
+def jittered_hex_ellipsoid(semi_axes, h, rng, jitter=0.2, centre=(0.0, 0.0, 0.0)):
+    """Ellipsoid filled with lattice cubes of edge h as eight-node hexahedra.
+
+    A cube is kept when its centre lies inside the ellipsoid; unused lattice
+    nodes are dropped.  A kept node is interior exactly when all eight cubes
+    around it are kept; every other node is on the boundary surface.
+    Interior nodes are moved by independent U[-jitter*h, jitter*h] offsets on
+    each axis.  Elements are ordered by cube (k, j, i).
+
+    Returns (xyz float64[N,3], hexes int32[E,8], boundary int32[B]).
+    """
+    a, b, c = (float(s) for s in semi_axes)
+    n = [int(np.ceil(s / h)) + 1 for s in (a, b, c)]
+    nx, ny, nz = 2 * n[0], 2 * n[1], 2 * n[2]
+    org = (centre[0] - n[0] * h, centre[1] - n[1] * h, centre[2] - n[2] * h)
+    ck, cj, ci = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    px = (org[0] + (ci + 0.5) * h - centre[0]) / a
+    py = (org[1] + (cj + 0.5) * h - centre[1]) / b
+    pz = (org[2] + (ck + 0.5) * h - centre[2]) / c
+    inside = (px * px + py * py + pz * pz <= 1.0).ravel()
+    cubes = np.stack([ci.ravel()[inside], cj.ravel()[inside], ck.ravel()[inside]], axis=1)
+    lat = cubes[:, None, :] + HEX_CORNERS[None]
+    gid = lat[..., 0] + (nx + 1) * (lat[..., 1] + (ny + 1) * lat[..., 2])
+    used, inv = np.unique(gid.ravel(), return_inverse=True)
+    hexes = inv.reshape(-1, 8).astype(np.int32)
+    gi = used % (nx + 1)
+    gj = (used // (nx + 1)) % (ny + 1)
+    gk = used // ((nx + 1) * (ny + 1))
+    xyz = np.stack([org[0] + gi * h, org[1] + gj * h, org[2] + gk * h],
+                   axis=1).astype(np.float64)
+    deg = np.bincount(hexes.ravel(), minlength=len(xyz))
+    bnd = np.nonzero(deg < 8)[0].astype(np.int32)
+    if jitter:
+        mask = deg == 8
+        d = rng.uniform(-jitter * h, jitter * h, size=xyz.shape)
+        xyz[mask] += d[mask]
+    return xyz, hexes, bnd
+
+
+# Corner relabellings that keep a hexahedron's topology: the four turns about
+# the bottom-top axis, each also with bottom and top exchanged.
+HEX_RELABELS = np.array([[(q + r) % 4 + 4 * f for q in range(4)]
+                         + [(q + r) % 4 + 4 * (1 - f) for q in range(4)]
+                         for f in (0, 1) for r in range(4)], dtype=np.int64)
+
+
+def shuffle_hex_mesh(xyz, hexes, marked, rng):
+    """shuffle_mesh for hexahedra: seeded node and element permutations, and
+    each element's corners relabelled by one of HEX_RELABELS."""
+    n = len(xyz)
+    node_perm = rng.permutation(n)
+    inv = np.empty(n, dtype=np.int64)
+    inv[node_perm] = np.arange(n)
+    elem_perm = rng.permutation(len(hexes))
+    hx = inv[hexes[elem_perm]]
+    pick = HEX_RELABELS[rng.integers(0, len(HEX_RELABELS), len(hx))]
+    hx = np.take_along_axis(hx, pick, axis=1).astype(np.int32)
+    return xyz[node_perm], hx, np.sort(inv[marked]).astype(np.int32), node_perm, elem_perm
+
+
 def shuffle_mesh(xyz, tets, marked, rng):
     """Apply a seeded random permutation to nodes and to elements.
 

@@ -163,6 +163,25 @@ def config3(order="random", h=0.6e-3, n_steps=1000):
                     h=h, semi_axes=ELLIPSOID_AXES)
 
 
+def hex_ellipsoid(order="random", h=0.6e-3, n_steps=1000):
+    """The 75x50x40 mm ellipsoid of config3 as eight-node hexahedra: the same
+    lattice (h = 0.6 mm), TD properties, surface held at 37 C, two seeded
+    Gaussian sources (nodal conversion), 1000 steps.  Handed over in seeded
+    random node, element and corner order."""
+    rng = seed_rng(5)
+    xyz, hexes, bnd = _mesh.jittered_hex_ellipsoid(ELLIPSOID_AXES, h, rng)
+    sigma = 4e-3
+    srcs = []
+    for _ in range(2):
+        p = _interior_point(rng, ELLIPSOID_AXES, 3 * sigma)
+        srcs.append([p[0], p[1], p[2], sigma, 2.0e7])
+    if order == "random":
+        xyz, hexes, bnd, _, _ = _mesh.shuffle_hex_mesh(xyz, hexes, bnd, seed_rng(5, 1))
+    return Scenario(f"hex_ellipsoid_h{h * 1e3:g}", xyz, hexes, td_materials(), bnd,
+                    np.full(len(bnd), 37.0), 37.0, np.array(srcs), SOURCE_NODAL, 0.0,
+                    n_steps=n_steps, h=h, semi_axes=ELLIPSOID_AXES)
+
+
 def sweep_params(j):
     """Parameters of planning-sweep scenario j (no mesh built)."""
     rng = seed_rng(4, j)

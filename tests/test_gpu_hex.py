@@ -4,6 +4,9 @@ Eq 14, 16) with the FP64 NumPy oracle (oracle/hex.py).
 Tolerances as for tetrahedra: FP64 path 1e-10 K, compensated FP32 path
 1e-3 K, critical-step eigenvalue within the Lanczos bound of the oracle's.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -190,3 +193,34 @@ def test_hex_autotune_and_errors():
         g.precompute()
     assert ei.value.code == ff.E_DEGENERATE
     g.close()
+
+
+GOLDEN_HEX = os.path.join(os.path.dirname(__file__), "golden", "hex_ellipsoid_oracle.json")
+
+
+@pytest.mark.parametrize("order", ["morton", "random"])
+def test_hex_ellipsoid_sampled_parity(order):
+    """Full size: the 2.91M-hexahedron ellipsoid, 1000 steps at the oracle's
+    own step, in the launch configuration the benchmark times (library
+    defaults), against the oracle's stored sample of 4096 nodes
+    (tests/golden/make_hex_ellipsoid.py), to 1e-3 K."""
+    g = json.load(open(GOLDEN_HEX))
+    s = sc.hex_ellipsoid("random", n_steps=g["n_steps"])
+    assert s.n_tets == g["n_hexes"] and s.n_nodes == g["n_nodes"]
+    h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T, dt=g["dt"],
+                  precision=ff.FP32C, reorder=(order == "morton"))
+    h.precompute()
+    lam = h.info()["lambda_geometry"]
+    print(f"[hex] ellipsoid lambda gpu={lam:.9e} oracle={g['lambda_geometry']:.9e}", flush=True)
+    assert (1 - 1e-4) * g["lambda_geometry"] <= lam <= (1 + 1e-3) * g["lambda_geometry"]
+    h.set_gaussian_sources(s.sources, ff.SOURCE_NODAL)
+    assert abs(h.read_source().sum() - g["source_total_W"]) <= 1e-9 * g["source_total_W"]
+    h.step(g["n_steps"])
+    T = h.read_T()
+    idx = np.asarray(g["idx"])
+    err = float(np.max(np.abs(T[idx] - np.asarray(g["T"]))))
+    print(f"[hex] ellipsoid {order}: max|dT| over {len(idx)} sampled nodes = {err:.3e} K "
+          f"(Tmax gpu {T.max():.4f}, oracle {g['T_max']:.4f})", flush=True)
+    assert err <= 1e-3
+    assert abs(T.max() - g["T_max"]) <= 1e-3
+    h.close()
