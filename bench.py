@@ -150,9 +150,10 @@ def run_hex(args):
         log(f"hex: max|T - T_oracle| on {len(idx)} sampled nodes = {max_err:.3e} K")
     elem_ms, node_ms = h.time_kernels(args.kernel_steps)
     h.close()
-    # algorithmic bytes per hexahedron: 24 f32 coefficients and eight 32-bit
-    # node ids (the layout stores 16-bit tile-local ids)
-    elem_bytes = 128.0 * E
+    # algorithmic bytes per hexahedron: the six f32 entries of its 3 x 3
+    # matrix S (A_e = Xi^T S Xi) and eight 32-bit node ids (the layout stores
+    # 16-bit tile-local ids)
+    elem_bytes = 56.0 * E
     node_bytes = 24.0 * N
     achieved = elem_bytes / (elem_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "elem_loads_hex", "achieved": round(achieved, 1),

@@ -155,9 +155,9 @@ int fedfem_create(const fedfem_mesh *mesh, const fedfem_materials *mat,
  * 8 |det J| (Sec 2.3.4).  The paper adds no hourglass control, and neither
  * does the library: fields with zero gradient at every element centre carry
  * no conduction load.  Validation, ownership and the rest of the API are as
- * for fedfem_create, with these differences: the default layout is
- * 1024-element tiles with 512 threads and up to 2048 tile nodes, threads
- * may not exceed 512; Gaussian sources are nodal only
+ * for fedfem_create, with these differences: reordered tiles may hold up
+ * to twice as many nodes as elements (default 4096 for 2048-element
+ * tiles); Gaussian sources are nodal only
  * (FEDFEM_SOURCE_CONSISTENT gives FEDFEM_E_INVALID), as are
  * fedfem_flux_loads and fedfem_resample; batches accept tetrahedral handles
  * only (FEDFEM_E_STATE).  fedfem_get_info reports elements in n_tets.

@@ -559,9 +559,9 @@ int create_handle(int64_t N, const double* xyz, int64_t E, const int32_t* conn, 
     }
     h->stream = h->own_stream;
     h->opt.reorder = 1;
-    h->opt.tile_elems = npe == 8 ? 1024 : 2048;
+    h->opt.tile_elems = 2048;
     h->opt.threads = 512;
-    h->opt.max_tile_nodes = npe == 8 ? 2048 : 1024;
+    h->opt.max_tile_nodes = npe == 8 ? 4096 : 1024;
     h->opt.xcd = 0;
     *out = h;
     return FEDFEM_OK;
@@ -590,21 +590,16 @@ int fedfem_create_hex(const fedfem_mesh_hex* mesh, const fedfem_materials* mat,
 int fedfem_set_options(fedfem_handle* h, const fedfem_options* o) {
     if (!h || !o) return FEDFEM_E_INVALID;
     if (h->precomputed) return set_err(h, FEDFEM_E_STATE, "options are fixed after precompute");
-    // hexahedra: smaller tiles and two elements per thread by default (24
-    // coefficients per element are held in registers), tiles of up to twice
-    // as many nodes as elements
+    // hexahedra: reordered tiles of up to twice as many nodes as elements
     const bool hex = h->npe == 8;
-    const int te = o->tile_elems ? o->tile_elems : (hex ? 1024 : 2048);
-    const int th = o->threads ? o->threads
-                              : std::max(64, hex ? std::min(kHexMaxThreads, te / 2)
-                                                 : std::min(1024, te / 4));
+    const int te = o->tile_elems ? o->tile_elems : 2048;
+    const int th = o->threads ? o->threads : std::max(64, std::min(1024, te / 4));
     const int mn = o->max_tile_nodes
                        ? o->max_tile_nodes
                        : (o->reorder ? (hex ? 2 * te : te / 2) : h->npe * te);
     const int r = te / std::max(th, 1);
     if (te < 64 || te > 8192 || te % 64 || th < 64 || th > 1024 || th % 64 || te % th ||
         (r != 1 && r != 2 && r != 4) || mn < h->npe || mn > h->npe * te ||
-        (hex && th > kHexMaxThreads) ||
         (o->reorder != 0 && o->reorder != 1) || (o->xcd != 0 && o->xcd != 1))
         return set_err(h, FEDFEM_E_INVALID, "invalid options");
     h->opt = *o;
@@ -676,8 +671,7 @@ int fedfem_precompute(fedfem_handle* h) {
     d.npe = h->npe;
     d.max_tile_nodes = L.max_tile_nodes;
     d.threads = std::min(h->opt.threads, L.tile_elems);
-    const int max_threads = h->npe == 8 ? kHexMaxThreads : 1024;
-    while (elems_per_thread(d) > 4 && d.threads < max_threads) d.threads *= 2;
+    while (elems_per_thread(d) > 4 && d.threads < 1024) d.threads *= 2;
     if (elems_per_thread(d) > 4) return set_err(h, FEDFEM_E_INVALID, "tiles too large for the workgroup");
     d.xcd = h->opt.xcd;
     // topology
@@ -722,8 +716,9 @@ int fedfem_precompute(fedfem_handle* h) {
     int32_t* d_eperm = nullptr;
     if ((rc = upload(h, &d_eperm, L.eperm))) return rc;
     // coefficients per element: the six off-diagonals of A_e (tetrahedra) or
-    // the 3 x 8 scaled gradients sqrt(V_e) grad N (hexahedra)
-    const int ncoef = h->npe == 8 ? 24 : 6;
+    // the six entries of the 3 x 3 matrix S with A_e[a][b] = xi_a^T S xi_b
+    // (hexahedra)
+    const int ncoef = 6;
     if ((rc = dalloc(h, &coef64, (size_t)ncoef * E)) || (rc = dalloc(h, &h->d_vol, E)) ||
         (rc = dalloc(h, &bad, 1)) || (rc = dalloc(h, &h->d_Vi, N)) ||
         (rc = dalloc(h, &h->d_flag, 4)) || (rc = dalloc(h, &h->d_stage, N)))
@@ -1418,9 +1413,8 @@ int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
                 continue;  // e.g. the tile does not fit: skip the candidate
             }
             const int te = t->d.tile_elems;
-            const int tmax = h->npe == 8 ? kHexMaxThreads : 1024;
-            const int ths[2] = {std::max(64, std::min(tmax, te / 4)),
-                                std::max(64, std::min(tmax, te / 2))};
+            const int ths[2] = {std::max(64, std::min(1024, te / 4)),
+                                std::max(64, std::min(1024, te / 2))};
             for (int ti = 0; ti < (batch ? 1 : 2); ti++)
                 for (int xcd = 0; xcd < (batch ? 1 : 2); xcd++) {
                     t->d.threads = ths[ti];

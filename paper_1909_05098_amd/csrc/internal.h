@@ -121,9 +121,6 @@ struct DevLayout {
 // ---------------------------------------------------------------------------
 size_t tile_lds_bytes(int tile_elems, int max_nodes, int real_bytes, bool comp,
                       bool td);
-// Workgroup bound of the hexahedral element kernel (24 coefficients per
-// element in registers).
-constexpr int kHexMaxThreads = 512;
 // Elements per thread of the element kernel, rounded up to 1, 2 or 4 (the
 // instantiated counts); 8 means the workgroup is too small for the tile.
 int elems_per_thread(const DevLayout& d);

@@ -82,10 +82,11 @@ __global__ void k_geometry(int64_t E, const double* __restrict__ xyz,
 // centre (Eq 14, 16).  Corner a sits at natural coordinates xi_a in
 // {-1, 1}^3 (bottom face counter-clockwise, then the top face), so at the
 // centre dN_a/dxi = xi_a / 8 and M[j][i] = dx_i/dxi_j = sum_a xi_a,j x_a,i / 8.
-// Then grad_x N_a = M^-1 grad_xi N_a and V_e = 8 |det M|.  A_e = V_e B^T B
-// has rank 3, so the element is stored as W = sqrt(V_e) grad N, 3 x 8
-// values at coef[(8 i + a) E + e] for component i of corner a, and
-// A_e[a][b] = W_a . W_b.
+// Then grad_x N_a = M^-1 grad_xi N_a and V_e = 8 |det M|.  Every corner's
+// gradient is the same 3 x 3 map applied to its xi_a, so A_e = V_e B^T B
+// factors as A_e[a][b] = xi_a^T S xi_b with S = (V_e / 64) M^-T M^-1 (3 x 3,
+// symmetric).  The element is stored as the six entries of S, at
+// coef[k E + e] in the order S00, S11, S22, S01, S02, S12.
 __constant__ double kHexNat[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
                                      {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
 
@@ -131,20 +132,25 @@ __global__ void k_geometry_hex(int64_t E, const double* __restrict__ xyz,
     const double lmax = sqrt(l2max);
     if (!(fabs(det) > 1e-12 * lmax * lmax * lmax)) {
         atomicMin(bad, eperm[e]);  // smallest caller element id
-        for (int k = 0; k < 24; k++) coef[k * E + e] = 0.0;
+        for (int k = 0; k < 6; k++) coef[k * E + e] = 0.0;
         vol[e] = 0.0;
         return;
     }
     const double V = 8.0 * fabs(det);
     vol[e] = V;
-    // Minv[i][j] = C[j][i] / det; W_a = sqrt(V) Minv xi_a / 8
-    const double f = sqrt(V) * 0.125 / det;
-    for (int a = 0; a < 8; a++)
-        for (int i = 0; i < 3; i++) {
-            const double g = C[0][i] * kHexNat[a][0] + C[1][i] * kHexNat[a][1] +
-                             C[2][i] * kHexNat[a][2];
-            coef[(8 * i + a) * E + e] = f * g;
-        }
+    // grad N_a = Minv xi_a / 8 with Minv[i][j] = C[j][i] / det, so
+    // A_ab = V grad N_a . grad N_b = xi_a^T S xi_b with the symmetric
+    //   S_jk = V / (64 det^2) sum_i C[j][i] C[k][i] = sum_i C[j][i] C[k][i] / (8 |det|)
+    const double f = 1.0 / V;
+    auto cc = [&](int j, int k) {
+        return f * (C[j][0] * C[k][0] + C[j][1] * C[k][1] + C[j][2] * C[k][2]);
+    };
+    coef[0 * E + e] = cc(0, 0);
+    coef[1 * E + e] = cc(1, 1);
+    coef[2 * E + e] = cc(2, 2);
+    coef[3 * E + e] = cc(0, 1);
+    coef[4 * E + e] = cc(0, 2);
+    coef[5 * E + e] = cc(1, 2);
 }
 
 // Lumped nodal volume: each element gives an equal share of its volume to
@@ -289,20 +295,25 @@ __global__ void k_coef_bound(int64_t E, const double* __restrict__ coef,
     if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sh[0]));
 }
 
-// The same bound for hexahedra, with A_e[a][b] = W_a . W_b.
+// The same bound for hexahedra, with A_e[a][b] = xi_a^T S xi_b.
 __global__ void k_coef_bound_hex(int64_t E, const double* __restrict__ coef,
                                  unsigned long long* __restrict__ out) {
     __shared__ double sh[kBlock];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double r = 0.0;
     if (e < E) {
-        double w[8][3];
-        for (int a = 0; a < 8; a++)
-            for (int i = 0; i < 3; i++) w[a][i] = coef[(8 * i + a) * E + e];
+        const double c[6] = {coef[e], coef[E + e], coef[2 * E + e],
+                             coef[3 * E + e], coef[4 * E + e], coef[5 * E + e]};
+        const double S[3][3] = {{c[0], c[3], c[4]}, {c[3], c[1], c[5]}, {c[4], c[5], c[2]}};
         for (int a = 0; a < 8; a++) {
+            double Sx[3];
+            for (int i = 0; i < 3; i++)
+                Sx[i] = S[i][0] * kHexNat[a][0] + S[i][1] * kHexNat[a][1] + S[i][2] * kHexNat[a][2];
             double row = 0.0;
             for (int b = 0; b < 8; b++)
-                if (b != a) row += fabs(w[a][0] * w[b][0] + w[a][1] * w[b][1] + w[a][2] * w[b][2]);
+                if (b != a)
+                    row += fabs(Sx[0] * kHexNat[b][0] + Sx[1] * kHexNat[b][1] +
+                                Sx[2] * kHexNat[b][2]);
             r = fmax(r, row);
         }
     }

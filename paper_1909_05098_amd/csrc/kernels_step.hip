@@ -301,13 +301,14 @@ k_elem_loads(TileArgs a, const Real* __restrict__ coef, const void* __restrict__
 }
 
 // Eight-node hexahedra with one integration point (Eq 14, 16, 17).  The
-// element is stored as W = sqrt(V_e) grad N at its centre (3 x 8, row 8 i + a
-// for component i of corner a), so that A_e = W^T W and
-//     F_e,a = k_e W_a . g,   g = sum_b W_b (T_b - T_0),
-// the differences formed as (hi_b - hi_0) + (lo_b - lo_0) (the columns of W
-// sum to zero, so T_0 drops out of g).  k_e is the mean over the eight
-// corners (Eq 13).  Tiles, staging, fixed-point assembly and partials are
-// those of the tetrahedral pass; local corner ids are 8 x u16.
+// element is stored as the symmetric 3 x 3 matrix S with
+// A_e[a][b] = xi_a^T S xi_b (xi_a in {-1, 1}^3, the corner's natural
+// coordinates; entries S00, S11, S22, S01, S02, S12 at coef[k E + e]), so
+//     F_e,a = k_e xi_a . (S t),   t = sum_b xi_b (T_b - T_0),
+// the differences formed as (hi_b - hi_0) + (lo_b - lo_0) (each component of
+// xi sums to zero over the corners, so T_0 drops out of t).  k_e is the mean
+// over the eight corners (Eq 13).  Tiles, staging, fixed-point assembly and
+// partials are those of the tetrahedral pass; local corner ids are 8 x u16.
 template <typename Real, bool COMP, bool TD, int R>
 __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
                                               const Real* __restrict__ coef,
@@ -328,7 +329,7 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
     const int m = a.tile_node_off[t + 1] - p0;
 
     // 1. coefficient and local-connectivity loads in flight during staging
-    Real w[R][24];
+    Real sv[R][6];
     uint4 lc[R];
     const uint4* glc = static_cast<const uint4*>(a.lconn) + e0;
 #pragma unroll
@@ -336,7 +337,7 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
         const int el = tid + r * bs;
         if (el < ne) {
 #pragma unroll
-            for (int k = 0; k < 24; k++) w[r][k] = coef[k * a.E + e0 + el];
+            for (int k = 0; k < 6; k++) sv[r][k] = coef[k * a.E + e0 + el];
             lc[r] = glc[el];
         }
     }
@@ -357,15 +358,18 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
             }
             const Real h0 = s_T[n[0]];
             const Real l0 = COMP ? s_Tlo[n[0]] : Real(0);
-            Real g0 = 0, g1 = 0, g2 = 0;
+            Real d[8];
+            d[0] = 0;
 #pragma unroll
             for (int b = 1; b < 8; b++) {
-                Real d = s_T[n[b]] - h0;
-                if (COMP) d += s_Tlo[n[b]] - l0;
-                g0 += w[r][b] * d;
-                g1 += w[r][8 + b] * d;
-                g2 += w[r][16 + b] * d;
+                d[b] = s_T[n[b]] - h0;
+                if (COMP) d[b] += s_Tlo[n[b]] - l0;
             }
+            // t = sum_b xi_b d_b, corners in the order of the natural
+            // coordinates (-,-,-), (+,-,-), (+,+,-), (-,+,-), then z = +1
+            const Real t0 = ((d[1] + d[2]) + (d[5] + d[6])) - ((d[3] + d[4]) + d[7]);
+            const Real t1 = ((d[2] + d[3]) + (d[6] + d[7])) - ((d[1] + d[4]) + d[5]);
+            const Real t2 = ((d[4] + d[5]) + (d[6] + d[7])) - ((d[1] + d[2]) + d[3]);
             Real ke;
             if (TD) {
                 Real ks = 0;
@@ -375,13 +379,16 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
             } else {
                 ke = pr.k0;
             }
-            // corners in a fixed order (a lane-dependent order would index
-            // the coefficient registers at run time)
+            const Real u0 = ke * ((sv[r][0] * t0 + sv[r][3] * t1) + sv[r][4] * t2);
+            const Real u1 = ke * ((sv[r][3] * t0 + sv[r][1] * t1) + sv[r][5] * t2);
+            const Real u2 = ke * ((sv[r][4] * t0 + sv[r][5] * t1) + sv[r][2] * t2);
+            // F_a = xi_a . u
+            const Real pp = u0 + u1, mm = u0 - u1;
+            const Real F[8] = {-pp - u2, mm - u2, pp - u2, -mm - u2,
+                               u2 - pp, mm + u2, pp + u2, u2 - mm};
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const Real F = ke * ((w[r][q] * g0 + w[r][8 + q] * g1) + w[r][16 + q] * g2);
-                atomicAdd(&s_acc[n[q]], (unsigned long long)to_fixed(F, pr.fxs));
-            }
+            for (int q = 0; q < 8; q++)
+                atomicAdd(&s_acc[n[q]], (unsigned long long)to_fixed(F[q], pr.fxs));
         }
     }
     __syncthreads();
@@ -390,7 +397,7 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
 }
 
 template <typename Real, bool COMP, bool TD, int R>
-__global__ void __launch_bounds__(kHexMaxThreads)
+__global__ void __launch_bounds__(1024)
 k_elem_loads_hex(TileArgs a, const Real* __restrict__ coef, const void* __restrict__ Tin,
                  Real* __restrict__ partial, Props<Real> pr) {
     const int64_t t = a.xcd ? xcd_remap(blockIdx.x, a.T) : (int64_t)blockIdx.x;

@@ -162,7 +162,6 @@ def test_hex_autotune_and_errors():
     h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
                   precision=ff.FP32C)
     chosen = h.autotune(None)
-    assert chosen["threads"] <= 512
     h.precompute()
     h.set_gaussian_sources(np.array([[8e-3, 6e-3, 5e-3, 1.5e-3, 4e8]]), ff.SOURCE_NODAL)
     h.step(200)
@@ -180,9 +179,10 @@ def test_hex_autotune_and_errors():
     with pytest.raises(ff.FedFemError) as ei:
         ff.Batch([h])
     assert ei.value.code == ff.E_STATE
-    with pytest.raises(ff.FedFemError):
+    with pytest.raises(ff.FedFemError) as ei:   # more tile nodes than 8 per element
         ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
-                  precision=ff.FP32C, tile_elems=2048, threads=1024)
+                  precision=ff.FP32C, tile_elems=256, max_tile_nodes=2049)
+    assert ei.value.code == ff.E_INVALID
     h.close()
     # a flattened hexahedron is degenerate
     bad = xyz.copy()
