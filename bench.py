@@ -116,7 +116,7 @@ def run_hex(args):
     h = ff.Handle(scn.xyz, scn.tets, scn.materials, scn.T0, scn.dir_nodes, scn.dir_T,
                   dt=golden["dt"] if golden else -0.9, precision=ff.FP32C,
                   reorder=(args.order == "morton"), tile_elems=args.hex_tile,
-                  threads=args.hex_threads)
+                  threads=args.hex_threads, xcd=bool(args.hex_xcd))
     tuned = None
     if not args.no_autotune:
         t0 = time.perf_counter()
@@ -126,7 +126,7 @@ def run_hex(args):
     h.precompute()
     t_pre = time.perf_counter() - t0
     info = h.info()
-    xcd = int(tuned["xcd"]) if tuned is not None else 0
+    xcd = int(tuned["xcd"]) if tuned is not None else int(bool(args.hex_xcd))
     dt, dt_cr = h.dt()
     log(f"hex precompute {t_pre:.2f} s, dt={dt:.6g} dt_cr={dt_cr:.6g}, tiles={info['n_tiles']}")
     h.set_gaussian_sources(scn.sources, ff.SOURCE_NODAL)
@@ -435,6 +435,7 @@ def main():
                     help="run only the hexahedral ellipsoid leg")
     ap.add_argument("--hex-tile", type=int, default=0)
     ap.add_argument("--hex-threads", type=int, default=0)
+    ap.add_argument("--hex-xcd", type=int, default=0)
     ap.add_argument("--hex-cpu-steps", type=int, default=4)
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (for "
