@@ -38,6 +38,7 @@ METRIC = ("tet-element updates/s + achieved HBM GB/s; scenarios/s plain vs "
           "batched/surrogate")
 GOLDEN3 = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
 GOLDEN_HEX = os.path.join(ROOT, "tests", "golden", "hex_ellipsoid_oracle.json")
+GOLDEN_DOSE = os.path.join(ROOT, "tests", "golden", "config3_dose_oracle.json")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "elem_loads_config3_pmc.txt")
 PMC_SUMMARY_HEX = os.path.join(ROOT, "profiles", "elem_loads_hex_ellipsoid_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_05098_amd", "csrc", "kernels_step.hip")
@@ -94,6 +95,47 @@ def cpu_baseline(scn, dt, q_params, seconds):
                        f"and dt from the initial state ({el:.1f} s timed, "
                        f"{setup:.1f} s untimed setup), OpenMP threads = "
                        f"{oracle.max_threads()}")}
+
+
+def run_dose(h, state0, args, E, N, ms_plain):
+    """The same config-3 run with the CEM43 thermal dose fused into the
+    nodal update: step time, the node kernel with and without it, and the
+    dose against the oracle's stored sample of the same run."""
+    import numpy as np
+    import torch
+    from paper_1909_05098_amd import fedfem as ff
+    _, node_plain = h.time_kernels(args.kernel_steps)
+    h.set_dose(ff.DOSE_CEM43)
+    h.write_state(state0, 0.0, 0)
+    h.prepare(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(args.steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    rel = None
+    if os.path.exists(GOLDEN_DOSE):
+        g = json.load(open(GOLDEN_DOSE))
+        if g["n_tets"] == E and g["n_steps"] == args.steps:
+            idx = np.asarray(g["idx"])
+            ref = np.asarray(g["dose"])
+            rel = float(np.max(np.abs(h.read_dose()[idx] - ref) / ref))
+            log(f"dose: max relative error on {len(idx)} sampled nodes = {rel:.3e}")
+    _, node_ms = h.time_kernels(args.kernel_steps)
+    h.set_dose(ff.DOSE_OFF)
+    # node pass bytes: T hi/lo read and write, u, q, and the FP64 dose read
+    # and written
+    node_bytes = 40.0 * N
+    ms_step = t_run * 1e3 / args.steps
+    return {"model": "CEM43 (Sapareto-Dewey), FP64 per node, fused into the nodal update",
+            "steps": args.steps, "ms_per_step": round(ms_step, 5),
+            "ms_per_step_without_dose": round(ms_plain, 5),
+            "value": round(E * args.steps / t_run, 1), "unit": "element-updates/s",
+            "node_update": {"avg_launch_ms": round(node_ms, 5),
+                            "avg_launch_ms_without_dose": round(node_plain, 5),
+                            "achieved_GBps": round(node_bytes / (node_ms * 1e-3) / 1e9, 1),
+                            "algorithmic_bytes_per_launch": node_bytes},
+            "max_rel_dose_error_vs_oracle": rel}
 
 
 def run_hex(args):
@@ -429,6 +471,8 @@ def main():
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate leg and print its result (for profiling "
                          "its kernels); not a benchmark line")
+    ap.add_argument("--dose", type=int, default=1,
+                    help="also time config 3 with the CEM43 dose (0 to skip)")
     ap.add_argument("--hex", type=int, default=1,
                     help="also run the hexahedral ellipsoid (0 to skip)")
     ap.add_argument("--hex-only", action="store_true",
@@ -552,6 +596,7 @@ def main():
                 "algorithmic_bytes_per_launch": by, "avg_launch_ms": round(ms, 5)}
     other = [k for k in kern if k != dom][0]
     step_gbps = (elem_bytes + node_bytes) / (ms_step * 1e-3) / 1e9
+    dose_leg = run_dose(h, state0, args, E, N, ms_step) if args.dose else None
     h.close()
     batched = run_sweep(sweep_scns, not args.no_autotune) if sweep_scns else None
     surrogate = run_surrogate(sur_scns, args.surrogate_weights) if sur_scns else None
@@ -584,6 +629,7 @@ def main():
         "precompute_s": round(t_pre, 3),
         "batched": batched,
         "surrogate": surrogate,
+        "dose": dose_leg,
         "hex": hexleg,
         "cpu_baseline": cpu,
     }

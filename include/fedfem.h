@@ -302,6 +302,38 @@ int fedfem_set_schedule(fedfem_handle *h, int32_t n_patterns,
 int fedfem_flux_loads(fedfem_handle *h, int64_t n_faces, const int32_t *faces,
                       const double *flux, double *out);
 
+/*
+ * Thermal dose accumulated at every node during the following steps.  The
+ * paper names thermal dose computation for hyperthermia treatment planning
+ * as the use of fast solutions (Sec 1) and as future work (Sec 5) without a
+ * dose model; the library offers two published ones:
+ *   FEDFEM_DOSE_CEM43      cumulative equivalent minutes at 43 C (Sapareto
+ *                          and Dewey 1984): each second at T adds
+ *                          R^(43 - T) / 60, R = 1/2 at or above 43 C and
+ *                          1/4 below (a, b ignored);
+ *   FEDFEM_DOSE_ARRHENIUS  damage integral (Henriques and Moritz 1947):
+ *                          each second adds a exp(-b / (R_gas (T + 273.15)))
+ *                          with frequency factor a > 0 [1/s], activation
+ *                          energy b >= 0 [J/mol], R_gas = 8.314462618.
+ * Step n (from t_n to t_n + dt) adds dt times the rate at the node's
+ * temperature at t_n (the explicit update, Eq 19, takes every term there);
+ * Dirichlet nodes accumulate at their held temperature.  The accumulators
+ * are FP64, fused into the nodal update, and start at zero on every call
+ * of fedfem_set_dose; FEDFEM_DOSE_OFF frees them.  The raw state
+ * (fedfem_read_state / fedfem_write_state) does not include them.  A
+ * batch refuses a handle with a dose model (FEDFEM_E_STATE).  Requires a
+ * precomputed handle; FEDFEM_E_INVALID for an unknown model or bad a, b.
+ */
+#define FEDFEM_DOSE_OFF 0
+#define FEDFEM_DOSE_CEM43 1
+#define FEDFEM_DOSE_ARRHENIUS 2
+int fedfem_set_dose(fedfem_handle *h, int32_t model, double a, double b);
+
+/* Blocking copy of the accumulated dose [n_nodes] (CEM43 minutes or the
+ * dimensionless Arrhenius integral) to host, caller node order;
+ * FEDFEM_E_STATE when no dose model is set. */
+int fedfem_read_dose(fedfem_handle *h, double *dose_out);
+
 /* Blocking copy of the nodal temperatures (hi + lo in double) to host. */
 int fedfem_read_T(fedfem_handle *h, double *T_out);
 

@@ -337,6 +337,7 @@ Props<double> props_d(const fedfem_handle* h) {
 
 hipError_t launch_one_step(fedfem_handle* h, int cur, hipStream_t s, int j) {
     const bool td = h->mat.dk_dT != 0.0 || !h->tab_t[0].empty();
+    h->d.dose_dt = h->dt;
     if (h->fp32c) return launch_step_f32c(h->d, cur, props_f(h), td, h->d_flag, s, j);
     return launch_step_f64(h->d, cur, props_d(h), td, h->d_flag, s, j);
 }
@@ -1013,6 +1014,43 @@ int fedfem_set_schedule(fedfem_handle* h, int32_t n_patterns, const double* patt
     return FEDFEM_OK;
 }
 
+int fedfem_set_dose(fedfem_handle* h, int32_t model, double a, double b) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (model == FEDFEM_DOSE_ARRHENIUS && !(a > 0 && std::isfinite(a) && b >= 0 && std::isfinite(b)))
+        return set_err(h, FEDFEM_E_INVALID, "Arrhenius dose needs A > 0 and E_a >= 0, finite");
+    if (model != FEDFEM_DOSE_OFF && model != FEDFEM_DOSE_CEM43 && model != FEDFEM_DOSE_ARRHENIUS)
+        return set_err(h, FEDFEM_E_INVALID, "unknown dose model %d", model);
+    drop_graphs(h);  // captured steps hold the dose pointer and constants
+    DevLayout& d = h->d;
+    if (model == FEDFEM_DOSE_OFF) {
+        dfree(h, d.dose);
+        d.dose = nullptr;
+        d.dose_model = 0;
+        return FEDFEM_OK;
+    }
+    if (!d.dose && (rc = dalloc(h, &d.dose, h->N))) return rc;
+    HIPCHK(h, hipMemsetAsync(d.dose, 0, sizeof(double) * h->N, h->stream));
+    d.dose_model = model;
+    // CEM43: minutes per second; Arrhenius: A and E_a / R_gas
+    d.dose_a = model == FEDFEM_DOSE_CEM43 ? 1.0 / 60.0 : a;
+    d.dose_b = model == FEDFEM_DOSE_CEM43 ? 0.0 : b / 8.314462618;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FEDFEM_OK;
+}
+
+int fedfem_read_dose(fedfem_handle* h, double* out) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!out) return FEDFEM_E_INVALID;
+    if (!h->d.dose) return set_err(h, FEDFEM_E_STATE, "no dose model is set");
+    hipStream_t s = h->stream;
+    HIPCHK(h, launch_get_source(h->N, h->d.dose, h->d_nperm, 0, h->d_stage, s));
+    HIPCHK(h, hipMemcpyAsync(out, h->d_stage, sizeof(double) * h->N, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return FEDFEM_OK;
+}
+
 int fedfem_flux_loads(fedfem_handle* h, int64_t n_faces, const int32_t* faces, const double* flux,
                       double* out) {
     int rc = check_handle(h, true);
@@ -1211,6 +1249,7 @@ int fedfem_time_kernels(fedfem_handle* h, int64_t n_steps, double* elem_ms, doub
     std::vector<hipEvent_t> ev(2 * n_steps + 1);
     for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
     const bool td = h->mat.dk_dT != 0.0 || !h->tab_t[0].empty();
+    h->d.dose_dt = h->dt;
     HIPCHK(h, launch_fill_i32(h->d_flag, 1, 0, s));
     HIPCHK(h, hipEventRecord(ev[0], s));
     for (int64_t k = 0; k < n_steps; k++) {

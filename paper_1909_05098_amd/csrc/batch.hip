@@ -123,6 +123,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
         if (!h || h->broken) return FEDFEM_E_INVALID;
         if (h->d.n_pat > 0) return FEDFEM_E_STATE;  // schedules run per handle only
         if (h->npe != 4) return FEDFEM_E_STATE;     // batches hold tetrahedral meshes
+        if (h->d.dose) return FEDFEM_E_STATE;       // and accumulate no dose
         if (!h->precomputed || !(h->dt > 0)) return FEDFEM_E_NOT_PRECOMPUTED;
         if (h->fp32c != handles[0]->fp32c || h->device != handles[0]->device)
             return FEDFEM_E_INVALID;

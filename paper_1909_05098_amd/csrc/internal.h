@@ -95,7 +95,7 @@ constexpr int kMaxTab = 16;  // FEDFEM_MAX_TABLE
 struct DevLayout {
     int64_t N = 0, E = 0, T = 0, P = 0;
     int tile_elems = 0, max_tile_nodes = 0, threads = 256;
-    int npe = 4;  // nodes per element: 4 (coef [6][E]) or 8 (coef [24][E])
+    int npe = 4;  // nodes per element: 4 or 8 (coef [6][E] either way)
     int xcd = 0;  // remap blocks so each XCD walks a contiguous stretch
     int32_t* tile_elem_off = nullptr;
     int32_t* tile_node_off = nullptr;
@@ -104,7 +104,7 @@ struct DevLayout {
     void* lconn = nullptr;     // packed (lconn_pk = 1) or [4E] u16
     int lconn_pk = 0;
     int32_t* part_off = nullptr;
-    void* coef = nullptr;      // [6][E] Real, off-diagonals a01 a02 a03 a12 a13 a23
+    void* coef = nullptr;      // [6][E] Real: a01 a02 a03 a12 a13 a23, or S (hexahedra)
     void* u = nullptr;         // [N] Real, 1/V_i, or -1 for Dirichlet nodes
     void* q = nullptr;         // [N] Real, active nodal source [W]
     void* T_[2] = {nullptr, nullptr};  // state: float2 (hi, lo) or double
@@ -114,6 +114,12 @@ struct DevLayout {
     void* pat = nullptr;       // [n_pat][N] Real
     void* amp = nullptr;       // [512][n_pat] Real, refilled before each chunk
     int n_pat = 0;
+    // thermal dose (fedfem_set_dose): every node adds dt * dose_a * f(T) at
+    // the start of each step, f the CEM43 or Arrhenius rate shape
+    double* dose = nullptr;    // [N], internal node order
+    int dose_model = 0;
+    double dose_a = 0.0, dose_b = 0.0;
+    double dose_dt = 0.0;      // the step the captured launches use
 };
 
 // ---------------------------------------------------------------------------

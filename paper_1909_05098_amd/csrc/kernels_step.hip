@@ -428,6 +428,21 @@ struct Sched {
     int64_t N;
 };
 
+// Thermal dose of one step (none when acc is null): node i adds
+// dt * a * f(T_i) with T_i its temperature at the start of the step;
+// model 1 (CEM43): f = 2^(T - 43) at or above 43 C, 4^(T - 43) below;
+// model 2 (Arrhenius): f = exp(-b / (T + 273.15)), b = E_a / R_gas.
+struct Dose {
+    double* acc;
+    int model;
+    double a, b, dt;
+};
+
+__device__ __forceinline__ double dose_rate(const Dose& dz, double T) {
+    if (dz.model == 1) return exp2(T >= 43.0 ? T - 43.0 : 2.0 * (T - 43.0)) * dz.a;
+    return exp(-dz.b / (T + 273.15)) * dz.a;
+}
+
 // NPT nodes per thread (indices at or above N are skipped): their chains of
 // dependent loads (node data, slot indices, partials) run side by side.
 template <typename Real, bool COMP, int NPT>
@@ -439,7 +454,7 @@ __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
                                             const Real* __restrict__ q,
                                             const void* __restrict__ Tin, void* __restrict__ Tout,
                                             const Props<Real>& pr, int* __restrict__ flag,
-                                            const Sched<Real>& sch) {
+                                            const Sched<Real>& sch, const Dose& dz) {
     // every load that depends only on the node first, so a node waits for
     // three rounds of memory latency: these, the slot indices, the partials
     Real ui[NPT], q0[NPT], hi[NPT], lo[NPT];
@@ -464,6 +479,13 @@ __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
     for (int v = 0; v < NPT; v++)
 #pragma unroll
         for (int k = 0; k < 4; k++) f[v][k] = pk[v][k] >= 0 ? partial[pk[v][k]] : Real(0);
+    // dose at the step's starting temperature, held nodes included
+    if (dz.acc) {
+#pragma unroll
+        for (int v = 0; v < NPT; v++)
+            if (iv[v] < N)
+                dz.acc[iv[v]] += dz.dt * dose_rate(dz, (double)hi[v] + (double)lo[v]);
+    }
 #pragma unroll
     for (int v = 0; v < NPT; v++) {
         // Dirichlet nodes (u <= 0) are held at T_Gamma
@@ -507,7 +529,7 @@ __global__ void __launch_bounds__(256)
 k_node_update(int64_t N, int xcd, const int32_t* __restrict__ part_off,
               const int32_t* __restrict__ pidx, const Real* __restrict__ partial, const Real* __restrict__ u,
               const Real* __restrict__ q, const void* __restrict__ Tin, void* __restrict__ Tout,
-              Props<Real> pr, int* __restrict__ flag, Sched<Real> sch) {
+              Props<Real> pr, int* __restrict__ flag, Sched<Real> sch, Dose dz) {
     constexpr int64_t span = 256 * kNodesPerThread;
     const int64_t nb = (N + span - 1) / span;
     const int64_t blk = xcd ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
@@ -516,7 +538,7 @@ k_node_update(int64_t N, int xcd, const int32_t* __restrict__ part_off,
 #pragma unroll
     for (int v = 0; v < kNodesPerThread; v++) iv[v] = blk * span + v * 256 + threadIdx.x;
     node_update<Real, COMP, kNodesPerThread>(iv, N, part_off, pidx, partial, u, q, Tin, Tout, pr,
-                                             flag, sch);
+                                             flag, sch, dz);
 }
 
 // Batched form: 256-node blocks never straddle scenarios; the block comes
@@ -535,7 +557,8 @@ k_node_update_batch(const int32_t* __restrict__ block_list,
     const Props<Real> pr = props[sc];
     const int64_t iv[1] = {(int64_t)blk * 256 + threadIdx.x};
     node_update<Real, COMP, 1>(iv, INT64_MAX, part_off, pidx, partial, u, q, Tin, Tout, pr,
-                               flags + sc, Sched<Real>{nullptr, nullptr, 0, 0});
+                               flags + sc, Sched<Real>{nullptr, nullptr, 0, 0},
+                               Dose{nullptr, 0, 0.0, 0.0, 0.0});
 }
 
 TileArgs tile_args(const DevLayout& d) {
@@ -624,7 +647,8 @@ hipError_t launch_node_t(const DevLayout& d, int cur, const Props<Real>& p, int*
     hipLaunchKernelGGL((k_node_update<Real, COMP>), dim3((unsigned)grid), dim3(256), 0, s, d.N,
                        d.xcd, d.part_off, d.pidx, static_cast<const Real*>(d.partial),
                        static_cast<const Real*>(d.u), static_cast<const Real*>(d.q), d.T_[cur],
-                       d.T_[1 - cur], p, flag, sch);
+                       d.T_[1 - cur], p, flag, sch,
+                       Dose{d.dose, d.dose_model, d.dose_a, d.dose_b, d.dose_dt});
     return hipGetLastError();
 }
 

@@ -18,6 +18,9 @@ FP64 = 0
 FP32C = 1
 SOURCE_NODAL = 0
 SOURCE_CONSISTENT = 1
+DOSE_OFF = 0
+DOSE_CEM43 = 1
+DOSE_ARRHENIUS = 2
 TUNE_BATCH = 1
 
 OK = 0
@@ -87,6 +90,8 @@ _SIGS = {
     "fedfem_set_property_tables": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, _P, _P,
                                              C.c_int32, _P, _P]),
     "fedfem_flux_loads": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
+    "fedfem_set_dose": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
+    "fedfem_read_dose": (C.c_int, [_P, _P]),
     "fedfem_step": (C.c_int, [_P, C.c_int64, _P]),
     "fedfem_prepare": (C.c_int, [_P, C.c_int64]),
     "fedfem_set_source": (C.c_int, [_P, _P]),
@@ -264,6 +269,18 @@ class Handle:
         out = np.empty(len(self.xyz))
         self._check(self._L.fedfem_flux_loads(self._h, len(f), _ptr(f), _ptr(q), _ptr(out)),
                     "fedfem_flux_loads")
+        return out
+
+    def set_dose(self, model, A=0.0, Ea=0.0):
+        """Start (from zero) or stop the nodal thermal dose: DOSE_CEM43, or
+        DOSE_ARRHENIUS with frequency factor A [1/s] and activation energy
+        Ea [J/mol]."""
+        self._check(self._L.fedfem_set_dose(self._h, int(model), float(A), float(Ea)),
+                    "fedfem_set_dose")
+
+    def read_dose(self):
+        out = np.empty(self.N)
+        self._check(self._L.fedfem_read_dose(self._h, _ptr(out)), "fedfem_read_dose")
         return out
 
     def read_source(self):

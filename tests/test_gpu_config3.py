@@ -53,3 +53,35 @@ def test_config3_sampled_parity(case, order):
     assert err <= 1e-3
     assert abs(T.max() - g["T_max"]) <= 1e-3
     h.close()
+
+
+GOLDEN_DOSE = os.path.join(os.path.dirname(__file__), "golden", "config3_dose_oracle.json")
+
+
+def test_config3_dose_sampled_parity(case):
+    """Full size with the CEM43 dose fused into the nodal update, in the
+    benchmark's launch configuration (Morton order, library defaults),
+    against the oracle's dose at the 4096 sampled nodes
+    (tests/golden/make_config3_dose.py).  Relative tolerance ln(4) x 1e-3:
+    the dose rate changes by at most a factor 4 per kelvin, and the
+    temperatures agree to 1e-3 K."""
+    s, g = case
+    gd = json.load(open(GOLDEN_DOSE))
+    assert gd["n_tets"] == s.n_tets and gd["dt"] == g["dt"] and gd["idx"] == g["idx"]
+    h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
+                  dt=g["dt"], precision=ff.FP32C, reorder=True)
+    h.precompute()
+    h.set_gaussian_sources(s.sources, ff.SOURCE_CONSISTENT)
+    h.set_dose(ff.DOSE_CEM43)
+    h.step(gd["n_steps"])
+    idx = np.asarray(gd["idx"])
+    T = h.read_T()
+    D = h.read_dose()[idx]
+    ref = np.asarray(gd["dose"])
+    rel = float(np.max(np.abs(D - ref) / ref))
+    print(f"[parity] config3 CEM43 dose: max relative error over {len(idx)} sampled nodes "
+          f"{rel:.3e} (dose max {ref.max():.3e} min) ; max|dT| "
+          f"{np.max(np.abs(T[idx] - np.asarray(gd['T']))):.3e} K", flush=True)
+    assert np.max(np.abs(T[idx] - np.asarray(gd["T"]))) <= 1e-3
+    assert rel <= np.log(4.0) * 1e-3
+    h.close()
