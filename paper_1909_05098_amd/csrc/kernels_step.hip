@@ -115,7 +115,8 @@ struct LdsCarve {
     size_t acc, T, Tlo, k, total;
 };
 
-// Per tile node: a 64-bit accumulator, T (hi, lo) and k(T).
+// Per tile node: a 64-bit accumulator, T (hi, lo) and k(T).  With COMP the
+// T and Tlo regions are used together as one float2 array starting at T.
 __host__ __device__ inline LdsCarve carve(int TE, int maxn, int rb, bool comp, bool td) {
     (void)TE;
     LdsCarve c;
@@ -168,6 +169,25 @@ __device__ __forceinline__ long long to_fixed(double f, double scale) {
     return __double2ll_rn(f * scale);
 }
 
+// Tile-node temperatures in LDS: FP64 T, or (FP32C) the (hi, lo) pair of a
+// node side by side, so that one 64-bit LDS read fetches both.
+template <bool COMP, typename Real>
+__device__ __forceinline__ void store_T(Real* s_T, int j, Real hi, Real lo) {
+    if constexpr (COMP) reinterpret_cast<float2*>(s_T)[j] = make_float2(hi, lo);
+    else s_T[j] = hi;
+}
+template <bool COMP, typename Real>
+__device__ __forceinline__ void load_T(const Real* s_T, int j, Real& hi, Real& lo) {
+    if constexpr (COMP) {
+        const float2 v = reinterpret_cast<const float2*>(s_T)[j];
+        hi = v.x;
+        lo = v.y;
+    } else {
+        hi = s_T[j];
+        lo = Real(0);
+    }
+}
+
 // Tile nodes into LDS: temperature, conductivity, zeroed accumulators.  The
 // first SJ rounds go out together, ids then temperatures (lanes past the
 // list load its last node and store nothing), so a thread waits for two
@@ -175,7 +195,7 @@ __device__ __forceinline__ long long to_fixed(double f, double scale) {
 template <typename Real, bool COMP, bool TD>
 __device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int m,
                                                  const void* __restrict__ Tin,
-                                                 const Props<Real>& pr, Real* s_T, Real* s_Tlo,
+                                                 const Props<Real>& pr, Real* s_T,
                                                  Real* s_k, unsigned long long* s_acc) {
     const int tid = threadIdx.x, bs = blockDim.x;
     constexpr int SJ = 2;
@@ -192,8 +212,7 @@ __device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int 
         for (int u = 0; u < SJ; u++) {
             const int j = tid + u * bs;
             if (j < m) {
-                s_T[j] = hj[u];
-                if (COMP) s_Tlo[j] = lj[u];
+                store_T<COMP>(s_T, j, hj[u], lj[u]);
                 if (TD) s_k[j] = prop_k(hj[u], pr);
                 s_acc[j] = 0ull;
             }
@@ -203,8 +222,7 @@ __device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int 
         const int g = a.tile_nodes[p0 + j];
         Real hi, lo;
         State<Real, COMP>::load(Tin, g, hi, lo);
-        s_T[j] = hi;
-        if (COMP) s_Tlo[j] = lo;
+        store_T<COMP>(s_T, j, hi, lo);
         if (TD) s_k[j] = prop_k(hi, pr);
         s_acc[j] = 0ull;
     }
@@ -219,7 +237,6 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
     const LdsCarve c = carve(a.TE, a.maxn, sizeof(Real), COMP, TD);
     unsigned long long* s_acc = reinterpret_cast<unsigned long long*>(lds + c.acc);
     Real* s_T = reinterpret_cast<Real*>(lds + c.T);
-    Real* s_Tlo = reinterpret_cast<Real*>(lds + c.Tlo);
     Real* s_k = reinterpret_cast<Real*>(lds + c.k);
 
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -245,7 +262,7 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
         }
     }
     // 2. tile nodes
-    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_Tlo, s_k, s_acc);
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_k, s_acc);
     __syncthreads();
     // 3. element loads, accumulated exactly on the fixed-point grid
 #pragma unroll
@@ -254,12 +271,14 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
         if (el < ne) {
             int n[4];
             corner_ids(lc[r], pk, n);
-            const Real h0 = s_T[n[0]], h1 = s_T[n[1]], h2 = s_T[n[2]], h3 = s_T[n[3]];
+            Real h0, h1, h2, h3, l0, l1, l2, l3;
+            load_T<COMP>(s_T, n[0], h0, l0);
+            load_T<COMP>(s_T, n[1], h1, l1);
+            load_T<COMP>(s_T, n[2], h2, l2);
+            load_T<COMP>(s_T, n[3], h3, l3);
             Real d01 = h1 - h0, d02 = h2 - h0, d03 = h3 - h0;
             Real d12 = h2 - h1, d13 = h3 - h1, d23 = h3 - h2;
             if (COMP) {
-                const Real l0 = s_Tlo[n[0]], l1 = s_Tlo[n[1]], l2 = s_Tlo[n[2]],
-                           l3 = s_Tlo[n[3]];
                 d01 += l1 - l0;
                 d02 += l2 - l0;
                 d03 += l3 - l0;
@@ -319,7 +338,6 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
     const LdsCarve c = carve(a.TE, a.maxn, sizeof(Real), COMP, TD);
     unsigned long long* s_acc = reinterpret_cast<unsigned long long*>(lds + c.acc);
     Real* s_T = reinterpret_cast<Real*>(lds + c.T);
-    Real* s_Tlo = reinterpret_cast<Real*>(lds + c.Tlo);
     Real* s_k = reinterpret_cast<Real*>(lds + c.k);
 
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -342,7 +360,7 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
         }
     }
     // 2. tile nodes
-    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_Tlo, s_k, s_acc);
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_k, s_acc);
     __syncthreads();
     // 3. element loads, accumulated exactly on the fixed-point grid
 #pragma unroll
@@ -356,14 +374,16 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
                 n[2 * q] = (int)(ww[q] & 0xffffu);
                 n[2 * q + 1] = (int)(ww[q] >> 16);
             }
-            const Real h0 = s_T[n[0]];
-            const Real l0 = COMP ? s_Tlo[n[0]] : Real(0);
+            Real h0, l0;
+            load_T<COMP>(s_T, n[0], h0, l0);
             Real d[8];
             d[0] = 0;
 #pragma unroll
             for (int b = 1; b < 8; b++) {
-                d[b] = s_T[n[b]] - h0;
-                if (COMP) d[b] += s_Tlo[n[b]] - l0;
+                Real hb, lb;
+                load_T<COMP>(s_T, n[b], hb, lb);
+                d[b] = hb - h0;
+                if (COMP) d[b] += lb - l0;
             }
             // t = sum_b xi_b d_b, corners in the order of the natural
             // coordinates (-,-,-), (+,-,-), (+,+,-), (-,+,-), then z = +1
