@@ -402,13 +402,17 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
             const Real u0 = ke * ((sv[r][0] * t0 + sv[r][3] * t1) + sv[r][4] * t2);
             const Real u1 = ke * ((sv[r][3] * t0 + sv[r][1] * t1) + sv[r][5] * t2);
             const Real u2 = ke * ((sv[r][4] * t0 + sv[r][5] * t1) + sv[r][2] * t2);
-            // F_a = xi_a . u
-            const Real pp = u0 + u1, mm = u0 - u1;
-            const Real F[8] = {-pp - u2, mm - u2, pp - u2, -mm - u2,
-                               u2 - pp, mm + u2, pp + u2, u2 - mm};
+            // F_a = xi_a . u, formed on the fixed-point grid from the three
+            // converted components: exact integer sums, so the eight corner
+            // loads of an element add up to zero exactly (|u_i| is at most
+            // max_a |F_a|, so the scale's bound holds)
+            const long long U0 = to_fixed(u0, pr.fxs), U1 = to_fixed(u1, pr.fxs),
+                            U2 = to_fixed(u2, pr.fxs);
+            const long long P = U0 + U1, M = U0 - U1;
+            const long long F[8] = {-P - U2, M - U2, P - U2, -M - U2,
+                                    U2 - P, M + U2, P + U2, U2 - M};
 #pragma unroll
-            for (int q = 0; q < 8; q++)
-                atomicAdd(&s_acc[n[q]], (unsigned long long)to_fixed(F[q], pr.fxs));
+            for (int q = 0; q < 8; q++) atomicAdd(&s_acc[n[q]], (unsigned long long)F[q]);
         }
     }
     __syncthreads();
