@@ -169,6 +169,13 @@ __device__ __forceinline__ long long to_fixed(double f, double scale) {
     return __double2ll_rn(f * scale);
 }
 
+// Per-element data is read once per step: non-temporal loads keep it from
+// displacing the node temperatures and partials in the caches.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
 // Tile-node temperatures in LDS: FP64 T, or (FP32C) the (hi, lo) pair of a
 // node side by side, so that one 64-bit LDS read fetches both.
 template <bool COMP, typename Real>
@@ -257,8 +264,14 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
         const int el = tid + r * bs;
         if (el < ne) {
 #pragma unroll
-            for (int k = 0; k < 6; k++) cf[r][k] = coef[k * a.E + e0 + el];
-            lc[r] = pk ? make_uint2(gw[el], gb[el]) : glc[el];
+            for (int k = 0; k < 6; k++) cf[r][k] = stream_load(&coef[k * a.E + e0 + el]);
+            if (pk) {
+                lc[r] = make_uint2(stream_load(&gw[el]), gb[el]);
+            } else {
+                const unsigned long long w = stream_load(
+                    reinterpret_cast<const unsigned long long*>(glc) + el);
+                lc[r] = make_uint2((unsigned)w, (unsigned)(w >> 32));
+            }
         }
     }
     // 2. tile nodes
@@ -355,7 +368,7 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
         const int el = tid + r * bs;
         if (el < ne) {
 #pragma unroll
-            for (int k = 0; k < 6; k++) sv[r][k] = coef[k * a.E + e0 + el];
+            for (int k = 0; k < 6; k++) sv[r][k] = stream_load(&coef[k * a.E + e0 + el]);
             lc[r] = glc[el];
         }
     }
