@@ -224,3 +224,53 @@ def test_hex_ellipsoid_sampled_parity(order):
     assert err <= 1e-3
     assert abs(T.max() - g["T_max"]) <= 1e-3
     h.close()
+
+
+@pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
+def test_hex_schedule_parity(prec):
+    """A heating pattern switched off part-way (two points at one time),
+    applied by the nodal update of a hexahedral handle over two calls,
+    against the oracle stepping with q_n = a(t_n) Q."""
+    xyz, hexes, bnd = jittered_hex_box(12, 10, 8, 1e-3, seed=17)
+    mat = sc.td_materials()
+    om = oracle_model(xyz, hexes, mat, bnd)
+    Q = om.source_nodal([[6e-3, 5e-3, 4e-3, 1.5e-3, 8e7]])
+    times, amps = [0.0, 200 * om.dt, 200 * om.dt], [1.0, 1.0, 0.0]
+    T = om.initial(37.0)
+    for n in range(450):
+        T = om.step(T, oracle.schedule_amplitude(times, amps, n * om.dt) * Q)
+    h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
+                  precision=prec)
+    h.precompute()
+    h.set_schedule(Q[None, :], [(times, amps)])
+    h.step(300)
+    h.step(150)
+    err = float(np.max(np.abs(h.read_T() - T)))
+    print(f"[hex] schedule prec={prec}: max|dT| {err:.3e} K", flush=True)
+    assert err <= TOL[prec]
+    h.close()
+
+
+def test_hex_two_point_tables_equal_linear_law():
+    """Tables through two points of the linear laws give the same run as
+    the laws themselves on a hexahedral handle (FP64)."""
+    xyz, hexes, bnd = jittered_hex_box(10, 9, 8, 1e-3, seed=19)
+    mat = sc.paper_table_materials()
+    two = {"k": ([37.0, 65.0], [0.53, 0.57]), "rho": ([37.0, 65.0], [1040.0, 1000.0]),
+           "c": ([37.0, 65.0], [3600.0, 3800.0])}
+    out = []
+    dt = -0.9
+    for tables in (None, two):
+        h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=dt,
+                      precision=ff.FP64)
+        if tables:
+            h.set_property_tables(tables)
+        h.precompute()
+        h.set_gaussian_sources(np.array([[5e-3, 4.5e-3, 4e-3, 1.2e-3, 1.5e8]]), ff.SOURCE_NODAL)
+        h.step(300)
+        out.append((h.read_T(), h.dt()))
+        dt = h.dt()[0]   # the same step for the table run
+        h.close()
+    assert out[0][0].max() > 60.0
+    assert abs(out[0][1][1] - out[1][1][1]) <= 1e-12 * out[0][1][1]   # same critical step
+    assert np.max(np.abs(out[0][0] - out[1][0])) <= 1e-10
