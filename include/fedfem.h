@@ -400,12 +400,18 @@ int fedfem_last_error(const fedfem_handle *h, char *buf, size_t len);
  * their pre-computed layouts once; each run takes every handle's current
  * state and active source, advances scenario j by n_steps[j] steps, and
  * writes the states back to the handles (read them with fedfem_read_T).
+ * sources may be NULL; else sources[j], when non-NULL, is a nodal heat flow
+ * [W] for scenario j (its caller's numbering) that replaces that handle's
+ * active source before the run, as the source argument of fedfem_step does
+ * (FEDFEM_E_INVALID if any is not finite; no source is replaced and no
+ * scenario advances then).
  */
 typedef struct fedfem_batch fedfem_batch;
 
 int fedfem_batch_create(fedfem_handle *const *handles, int32_t n,
                         fedfem_batch **out);
-int fedfem_batch_run(fedfem_batch *b, const int64_t *n_steps);
+int fedfem_batch_run(fedfem_batch *b, const int64_t *n_steps,
+                     const double *const *sources);
 /* Mean device time [ms] of the last fedfem_batch_run's launch sequence. */
 int fedfem_batch_last_ms(const fedfem_batch *b, double *ms);
 int fedfem_batch_destroy(fedfem_batch *b);

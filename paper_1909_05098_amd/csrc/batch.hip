@@ -7,6 +7,8 @@
 // tile and block lists and every launch covers exactly the active work.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -289,13 +291,26 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     return FEDFEM_OK;
 }
 
-int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps) {
+int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps, const double* const* sources) {
     if (!b || !n_steps) return FEDFEM_E_INVALID;
     const int S = b->S;
     for (int j = 0; j < S; j++) {
         if (n_steps[j] < 0 || n_steps[j] > 100000000) return FEDFEM_E_INVALID;
         const fedfem_handle* h = b->hs[j];
         if (h->broken || !h->precomputed || !(h->dt > 0)) return FEDFEM_E_STATE;
+    }
+    // new sources replace the handles' active ones, as in fedfem_step; all
+    // are checked before any is taken
+    if (sources) {
+        for (int j = 0; j < S; j++)
+            if (sources[j])
+                for (int64_t i = 0; i < b->hs[j]->N; i++)
+                    if (!std::isfinite(sources[j][i])) return FEDFEM_E_INVALID;
+        for (int j = 0; j < S; j++)
+            if (sources[j]) {
+                const int rc = fedfem_set_source(b->hs[j], sources[j]);
+                if (rc) return rc;
+            }
     }
     RCHK(hipSetDevice(b->device));
     DevLayout& d = b->d;

@@ -113,7 +113,7 @@ _SIGS = {
     "fedfem_strerror": (C.c_char_p, [C.c_int]),
     "fedfem_last_error": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "fedfem_batch_create": (C.c_int, [_P, C.c_int32, _P]),
-    "fedfem_batch_run": (C.c_int, [_P, _P]),
+    "fedfem_batch_run": (C.c_int, [_P, _P, _P]),
     "fedfem_batch_last_ms": (C.c_int, [_P, _P]),
     "fedfem_batch_destroy": (C.c_int, [_P]),
 }
@@ -395,10 +395,19 @@ class Batch:
             raise FedFemError(rc, "fedfem_batch_create: "
                               + L.fedfem_strerror(rc).decode())
 
-    def run(self, n_steps):
+    def run(self, n_steps, sources=None):
+        """Advance scenario j by n_steps[j]; sources[j] (optional, nodal [W])
+        replaces handle j's active source first."""
         n = np.ascontiguousarray(n_steps, dtype=np.int64)
         assert len(n) == len(self.handles)
-        rc = self._L.fedfem_batch_run(self._b, _ptr(n))
+        arr = None
+        if sources is not None:
+            assert len(sources) == len(self.handles)
+            keep = [None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+                    for q in sources]
+            arr = (C.c_void_p * len(keep))(*[None if q is None else q.ctypes.data
+                                              for q in keep])
+        rc = self._L.fedfem_batch_run(self._b, _ptr(n), arr)
         if rc != OK:
             raise FedFemError(rc, "fedfem_batch_run: "
                               + self._L.fedfem_strerror(rc).decode())

@@ -172,3 +172,39 @@ def test_recycled_device_memory_gives_identical_results(scenarios):
     assert np.array_equal(fresh[1], recycled[1])
     assert ff.release_cached_memory() > 0
     assert ff.release_cached_memory() == 0
+
+
+def test_batch_run_with_sources(scenarios):
+    """Per-scenario sources given to the batch run replace the handles'
+    active sources, as the source argument of fedfem_step does: the batch
+    equals each handle stepped alone with the same source; a None entry keeps
+    the handle's own; a non-finite source is refused before anything runs."""
+    sc3 = scenarios[:3]
+    hb = [make(s, dt) for s, _, _, _, dt in sc3]
+    hs = [make(s, dt) for s, _, _, _, dt in sc3]
+    ns = np.array([40, 25, 60])
+    rng = np.random.default_rng(7)
+    srcs = [0.5 * q + rng.uniform(0.0, 1e-3, len(q)) for _, _, q, _, _ in sc3]
+    srcs[1] = None
+    b = ff.Batch(hb)
+    before = hb[0].read_source()
+    bad = [srcs[0], None, np.full(len(sc3[2][2]), np.nan)]
+    with pytest.raises(ff.FedFemError) as ei:
+        b.run(ns, bad)
+    assert ei.value.code == ff.E_INVALID
+    assert all(h.time()[1] == 0 for h in hb)
+    assert np.array_equal(hb[0].read_source(), before)   # nothing replaced
+    b.run(ns, srcs)
+    for h1, h2, n, q in zip(hb, hs, ns, srcs):
+        h2.step(int(n), q)
+        assert np.array_equal(h1.read_state()[0], h2.read_state()[0])
+        if q is not None:
+            assert np.max(np.abs(h1.read_source() - q)) <= 1e-6 * np.max(np.abs(q))
+    # the sources stay active: a second run without them continues the same way
+    b.run(ns)
+    for h1, h2, n in zip(hb, hs, ns):
+        h2.step(int(n))
+        assert np.array_equal(h1.read_state()[0], h2.read_state()[0])
+    b.close()
+    for h in hb + hs:
+        h.close()
