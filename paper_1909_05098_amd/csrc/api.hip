@@ -1427,8 +1427,10 @@ int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
             int reorder, te;
         };
         const Build all[] = {{1, 1024}, {1, 2048}, {1, 4096}, {0, 1024}};
+        // hexahedra touch about one node per element: smaller tiles
+        const Build all_hex[] = {{1, 512}, {1, 1024}, {1, 2048}, {0, 512}};
         const Build for_batch[] = {{1, 1024}, {1, 2048}};
-        const Build* builds = batch ? for_batch : all;
+        const Build* builds = batch ? for_batch : (h->npe == 8 ? all_hex : all);
         const int n_builds = batch ? 2 : 4;
         double best_ms = 1e300;
         fedfem_mesh mesh{h->N, h->xyz.data(), h->E, h->tets.data()};
@@ -1452,10 +1454,13 @@ int fedfem_autotune(fedfem_handle* h, const char* cache_path, int32_t flags,
                 continue;  // e.g. the tile does not fit: skip the candidate
             }
             const int te = t->d.tile_elems;
-            const int ths[2] = {std::max(64, std::min(1024, te / 4)),
-                                std::max(64, std::min(1024, te / 2))};
-            for (int ti = 0; ti < (batch ? 1 : 2); ti++)
+            // 4, 2 and 1 elements per thread
+            const int ths[3] = {std::max(64, std::min(1024, te / 4)),
+                                std::max(64, std::min(1024, te / 2)),
+                                std::max(64, std::min(1024, te))};
+            for (int ti = 0; ti < (batch ? 1 : 3); ti++)
                 for (int xcd = 0; xcd < (batch ? 1 : 2); xcd++) {
+                    if (ti > 0 && ths[ti] == ths[ti - 1]) continue;  // capped at 1024
                     t->d.threads = ths[ti];
                     t->d.xcd = xcd;
                     if (elems_per_thread(t->d) > 4) continue;
