@@ -171,8 +171,9 @@ int fedfem_set_options(fedfem_handle *h, const fedfem_options *opt);
 /*
  * Autotuner: choose layout options for this handle's mesh by timing
  * candidate layouts (Morton order with 1024, 2048 and 4096-element tiles,
- * the caller's order with 1024-element tiles; each with two workgroup sizes
- * and both XCD mappings) on the GPU with HIP events, and set the fastest
+ * the caller's order with 1024-element tiles; for hexahedra 512, 1024 and
+ * 2048, and the caller's order with 512; each with 4, 2 and 1 elements per
+ * thread and both XCD mappings) on the GPU with HIP events, and set the fastest
  * (element pass + node pass per step) as the handle's options.  With
  * FEDFEM_TUNE_BATCH in flags only layouts that share one workgroup size in a
  * batch are tried (Morton order, 1024 or 2048-element tiles, 4 elements per
