@@ -373,6 +373,8 @@ int fedfem_get_info(const fedfem_handle *h, fedfem_info *info);
  * Profiling aid: advance n_steps exactly as fedfem_step does, but launch
  * each kernel separately with HIP events around it, and return the mean
  * duration [ms] of the element-load kernel and of the node-update kernel.
+ * FEDFEM_E_STATE while a source schedule is set (the amplitudes are applied
+ * per graph chunk by fedfem_step only).
  */
 int fedfem_time_kernels(fedfem_handle *h, int64_t n_steps, double *elem_ms,
                         double *node_ms);

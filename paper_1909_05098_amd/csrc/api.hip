@@ -1244,6 +1244,8 @@ int fedfem_time_kernels(fedfem_handle* h, int64_t n_steps, double* elem_ms, doub
     if (rc) return rc;
     if (n_steps <= 0 || n_steps > 10000 || !elem_ms || !node_ms)
         return set_err(h, FEDFEM_E_INVALID, "bad arguments");
+    if (h->d.n_pat > 0)
+        return set_err(h, FEDFEM_E_STATE, "kernel timing does not apply source schedules");
     if (!(h->dt > 0)) return set_err(h, FEDFEM_E_UNSTABLE, "no valid time step");
     hipStream_t s = h->stream;
     std::vector<hipEvent_t> ev(2 * n_steps + 1);

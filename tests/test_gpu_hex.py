@@ -179,6 +179,13 @@ def test_hex_autotune_and_errors():
     with pytest.raises(ff.FedFemError) as ei:
         ff.Batch([h])
     assert ei.value.code == ff.E_STATE
+    import torch
+    from paper_1909_05098_amd import surrogate as sg
+    Tg = torch.empty(8 ** 3, dtype=torch.float32, device="cuda")
+    mg = torch.empty(8 ** 3, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ff.FedFemError) as ei:   # P1 resampling is defined on tetrahedra
+        sg.resample(h, 8, [8e-3, 6e-3, 5e-3, 0.02], Tg, mg)
+    assert ei.value.code == ff.E_INVALID
     with pytest.raises(ff.FedFemError) as ei:   # more tile nodes than 8 per element
         ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
                   precision=ff.FP32C, tile_elems=256, max_tile_nodes=2049)

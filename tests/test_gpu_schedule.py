@@ -133,7 +133,11 @@ def test_batch_refuses_scheduled_handle():
     with pytest.raises(ff.FedFemError) as ei:
         ff.Batch([h])
     assert ei.value.code == ff.E_STATE
+    with pytest.raises(ff.FedFemError) as ei:   # kernel timing applies no schedule
+        h.time_kernels(3)
+    assert ei.value.code == ff.E_STATE
     h.set_schedule(None, [])
     b = ff.Batch([h])
     b.close()
+    assert min(h.time_kernels(3)) > 0
     h.close()
