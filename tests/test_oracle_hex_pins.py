@@ -188,3 +188,21 @@ def test_element_order_invariance():
     T2 = m2.run(m2.initial(37.0), 100, q)
     assert T1.max() > 40.0
     assert np.max(np.abs(T1 - T2)) <= 1e-10
+
+
+def test_one_point_matrix_factors_through_3x3():
+    """At the single integration point every corner's gradient is one 3x3
+    map applied to its natural coordinates, so A_e = Xi^T S Xi with
+    S = (V_e / 64) (J J^T)^-1 (J[j, i] = dx_i / dxi_j): six numbers per
+    element, the form the library stores.  Checked against the oracle's
+    A_e, built from B, on jittered and mirrored hexahedra; A_e has rank 3."""
+    xyz, hexes, _ = jittered_hex_box(4, 3, 3, 1e-3, seed=12)
+    hexes = hexes.copy()
+    hexes[::2] = hexes[::2][:, [4, 5, 6, 7, 0, 1, 2, 3]]
+    A, V, _ = ohx.element_matrices(xyz, hexes)
+    X = xyz[hexes]                                       # [E, 8, 3]
+    Jn = np.einsum("aj,eai->eji", ohx.NAT / 8.0, X)     # dx_i / dxi_j
+    S = V[:, None, None] / 64.0 * np.linalg.inv(Jn @ np.transpose(Jn, (0, 2, 1)))
+    A2 = np.einsum("aj,ejk,bk->eab", ohx.NAT, S, ohx.NAT)
+    assert np.max(np.abs(A2 - A)) <= 1e-12 * np.max(np.abs(A))
+    assert np.all(np.linalg.matrix_rank(A, tol=1e-9 * np.abs(A).max()) == 3)
