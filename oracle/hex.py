@@ -116,6 +116,40 @@ class HexModel:
             q += Q0 * np.exp(-r2 / (2.0 * s * s)) * self.Vi
         return q
 
+    def source_consistent(self, sources, order=4):
+        """Q_i = integral of the Gaussian density against N_i over the mesh,
+        by the order^3 tensor Gauss-Legendre rule on each element's
+        trilinear map (weights |det J(xi)|), sources given as rows
+        (x, y, z, sigma, Q0).  An element is skipped for a source when its
+        nearest point can lie no closer than 8 sigma to the centre (as for
+        tetrahedra).  Corner loads are gathered in ascending element order."""
+        g, w = np.polynomial.legendre.leggauss(order)
+        X = self.xyz[self.hexes]                                  # [E, 8, 3]
+        cen = X.mean(axis=1)
+        rad = np.sqrt(np.max(np.sum((X - cen[:, None, :]) ** 2, axis=2), axis=1))
+        acc = np.zeros((len(self.hexes), 8))
+        src = np.asarray(sources, dtype=np.float64).reshape(-1, 5)
+        for xi, wx in zip(g, w):
+            for eta, wy in zip(g, w):
+                for zeta, wz in zip(g, w):
+                    q = np.array([xi, eta, zeta])
+                    N = np.prod(1.0 + NAT * q, axis=1) / 8.0                 # [8]
+                    dN = np.empty((8, 3))
+                    for j in range(3):
+                        other = [k for k in range(3) if k != j]
+                        dN[:, j] = NAT[:, j] * np.prod(1.0 + NAT[:, other] * q[other],
+                                                       axis=1) / 8.0
+                    x = np.einsum("a,eai->ei", N, X)
+                    Jn = np.einsum("aj,eai->eji", dN, X)
+                    det = np.abs(np.linalg.det(Jn))
+                    f = np.zeros(len(X))
+                    for sx, sy, sz, sg, Q0 in src:
+                        near = np.sqrt(np.sum((cen - [sx, sy, sz]) ** 2, axis=1)) - rad
+                        r2 = np.sum((x - [sx, sy, sz]) ** 2, axis=1)
+                        f += np.where(near > 8.0 * sg, 0.0, Q0 * np.exp(-r2 / (2.0 * sg * sg)))
+                    acc += (wx * wy * wz) * (f * det)[:, None] * N[None, :]
+        return np.bincount(self.hexes.ravel(), weights=acc.ravel(), minlength=self.N)
+
     # -- time steps -------------------------------------------------------
     def initial(self, T0):
         T = np.full(self.N, float(T0))

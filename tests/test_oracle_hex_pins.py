@@ -206,3 +206,38 @@ def test_one_point_matrix_factors_through_3x3():
     A2 = np.einsum("aj,ejk,bk->eab", ohx.NAT, S, ohx.NAT)
     assert np.max(np.abs(A2 - A)) <= 1e-12 * np.max(np.abs(A))
     assert np.all(np.linalg.matrix_rank(A, tol=1e-9 * np.abs(A).max()) == 3)
+
+
+def test_consistent_source_reduces_to_lumped_for_uniform_density():
+    """On parallelepipeds (constant det J) the integral of N_a over an
+    element is V_e / 8, so a uniform density (a Gaussian far wider than the
+    mesh) gives Q_i = Q V_i, the lumped volume.  Catches a wrong shape
+    function, weight or Jacobian in the quadrature."""
+    xyz, hexes = mesh.hex_box(4, 3, 3, 1e-3)
+    Mx = np.array([[1.0, 0.2, -0.1], [0.05, 0.9, 0.15], [0.1, -0.2, 1.2]])
+    xyz = xyz @ Mx.T
+    m = ohx.HexModel(xyz, hexes, oracle.mat_vector(sc.td_materials()))
+    q = m.source_consistent([[1e-3, 1e-3, 1e-3, 1e3, 5e6]])
+    assert np.max(np.abs(q - 5e6 * m.Vi)) <= 1e-9 * np.max(5e6 * m.Vi)
+
+
+def test_consistent_source_total_power_and_relabelling():
+    """Summed over the nodes the loads integrate the density over the box
+    (N_a sum to one): for a Gaussian well inside a regular box that is the
+    product of erf terms, to the rule's error.  Relabelling the corners of
+    every element changes nothing.  Catches lost weight or an orientation-
+    dependent Jacobian."""
+    from math import erf, sqrt, pi
+    n, h = 8, 1e-3
+    xyz, hexes = mesh.hex_box(n, n, n, h)
+    c, sg, Q0 = np.array([4.1e-3, 3.8e-3, 4.3e-3]), 1.2e-3, 7e6
+    m = ohx.HexModel(xyz, hexes, oracle.mat_vector(sc.td_materials()))
+    q = m.source_consistent([[*c, sg, Q0]])
+    exact = Q0
+    for ax in range(3):
+        lo, hi = (0.0 - c[ax]) / (sqrt(2) * sg), (n * h - c[ax]) / (sqrt(2) * sg)
+        exact *= sg * sqrt(pi / 2) * (erf(hi) - erf(lo))
+    assert abs(q.sum() - exact) <= 1e-5 * exact
+    rel = hexes[:, [5, 6, 7, 4, 1, 2, 3, 0]]    # a turn with top and bottom swapped
+    m2 = ohx.HexModel(xyz, rel, oracle.mat_vector(sc.td_materials()))
+    assert np.max(np.abs(m2.source_consistent([[*c, sg, Q0]]) - q)) <= 1e-12 * q.max()
