@@ -157,10 +157,10 @@ int fedfem_create(const fedfem_mesh *mesh, const fedfem_materials *mat,
  * no conduction load.  Validation, ownership and the rest of the API are as
  * for fedfem_create, with these differences: reordered tiles may hold up
  * to twice as many nodes as elements (default 4096 for 2048-element
- * tiles); Gaussian sources are nodal only
- * (FEDFEM_SOURCE_CONSISTENT gives FEDFEM_E_INVALID), as are
- * fedfem_flux_loads and fedfem_resample; batches accept tetrahedral handles
- * only (FEDFEM_E_STATE).  fedfem_get_info reports elements in n_tets.
+ * tiles); fedfem_flux_loads and fedfem_resample give FEDFEM_E_INVALID (they
+ * are defined on triangles and tetrahedra); batches accept tetrahedral
+ * handles only (FEDFEM_E_STATE).  fedfem_get_info reports elements in
+ * n_tets.
  */
 int fedfem_create_hex(const fedfem_mesh_hex *mesh, const fedfem_materials *mat,
                       const fedfem_bc *bc, fedfem_handle **out);
@@ -260,7 +260,8 @@ int fedfem_set_source(fedfem_handle *h, const double *source);
  * at the nodes times the lumped nodal volume; FEDFEM_SOURCE_CONSISTENT
  * integrates Q_r N_i over each element with a 256-point composite rule (two
  * regular refinements, 4-point degree-2 rule per child, corners in
- * lexicographic coordinate order; elements whose bounding sphere lies beyond
+ * lexicographic coordinate order; on hexahedra the 4 x 4 x 4 Gauss-Legendre
+ * rule on the trilinear map; elements whose bounding sphere lies beyond
  * 8 sigma get nothing).  Computed on the GPU in double precision.
  */
 int fedfem_set_gaussian_sources(fedfem_handle *h, int32_t n_src,

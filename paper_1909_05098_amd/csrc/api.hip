@@ -1127,8 +1127,6 @@ int fedfem_set_gaussian_sources(fedfem_handle* h, int32_t n_src, const double* p
     if (n_src < 0 || n_src > 4096 || (n_src > 0 && !params) ||
         (mode != FEDFEM_SOURCE_NODAL && mode != FEDFEM_SOURCE_CONSISTENT))
         return set_err(h, FEDFEM_E_INVALID, "bad source arguments");
-    if (mode == FEDFEM_SOURCE_CONSISTENT && h->npe != 4)
-        return set_err(h, FEDFEM_E_INVALID, "consistent source quadrature needs tetrahedra");
     for (int k = 0; k < n_src; k++) {
         if (!finite_all(params + 5 * k, 5) || !(params[5 * k + 3] > 0))
             return set_err(h, FEDFEM_E_INVALID, "bad Gaussian source %d", k);
@@ -1142,13 +1140,17 @@ int fedfem_set_gaussian_sources(fedfem_handle* h, int32_t n_src, const double* p
         HIPCHK(h, launch_source_nodal(h->N, h->d_xyz, h->d_Vi, n_src, dsrc, h->d_stage, s));
     } else {
         double* slot = nullptr;
-        if ((rc = dalloc(h, &slot, 4 * (size_t)h->E))) {
+        if ((rc = dalloc(h, &slot, (size_t)h->npe * h->E))) {
             dfree(h, dsrc);
             return rc;
         }
-        HIPCHK(h, launch_source_consistent(h->N, h->E, h->d_xyz, h->d_conn, h->d_vol,
-                                           h->d_ec_off, h->d_ec, n_src, dsrc, h->d_qpts, slot,
-                                           h->d_stage, s));
+        if (h->npe == 8)
+            HIPCHK(h, launch_source_consistent_hex(h->N, h->E, h->d_xyz, h->d_conn, h->d_ec_off,
+                                                   h->d_ec, n_src, dsrc, slot, h->d_stage, s));
+        else
+            HIPCHK(h, launch_source_consistent(h->N, h->E, h->d_xyz, h->d_conn, h->d_vol,
+                                               h->d_ec_off, h->d_ec, n_src, dsrc, h->d_qpts,
+                                               slot, h->d_stage, s));
         HIPCHK(h, hipStreamSynchronize(s));
         dfree(h, slot);
     }

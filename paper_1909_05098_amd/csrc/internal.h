@@ -198,6 +198,11 @@ hipError_t launch_source_consistent(int64_t N, int64_t E, const double* xyz,
                                     int n_src, const double* src,
                                     const double* qpts, double* slot64,
                                     double* q64, hipStream_t s);
+// The same for eight-node hexahedra (slot holds 8 E corner loads).
+hipError_t launch_source_consistent_hex(int64_t N, int64_t E, const double* xyz,
+                                        const int32_t* conn, const int32_t* ec_off,
+                                        const int32_t* ec, int n_src, const double* src,
+                                        double* slot64, double* q64, hipStream_t s);
 hipError_t launch_cast_coef(int64_t n, const double* src, float* dst,
                             hipStream_t s);
 hipError_t launch_node_init(int64_t N, const double* Vi, const int32_t* is_dir,

@@ -186,6 +186,68 @@ __global__ void k_source_nodal(int64_t N, const double* __restrict__ xyz,
 // lexicographic coordinate order; N_c at a point is its c-th barycentric
 // coordinate.  Elements whose bounding sphere is beyond 8 sigma of a source
 // get nothing from it.
+// Consistent nodal source on hexahedra: Q_a = integral over the element of
+// the Gaussian densities times N_a, by the 4 x 4 x 4 tensor Gauss-Legendre
+// rule on the trilinear map (weight |det J(xi)| at each point).  Nodes and
+// weights of the 4-point rule are the published ones (Abramowitz and
+// Stegun, Table 25.4).  An element is skipped for a source when it lies
+// wholly beyond 8 sigma, as for tetrahedra; slot[8 e + a] receives corner a.
+__constant__ double kGL4x[4] = {-0.8611363115940525752, -0.3399810435848562648,
+                                0.3399810435848562648, 0.8611363115940525752};
+__constant__ double kGL4w[4] = {0.3478548451374538574, 0.6521451548625461426,
+                                0.6521451548625461426, 0.3478548451374538574};
+
+__global__ void k_source_elem_hex(int64_t E, const double* __restrict__ xyz,
+                                  const int32_t* __restrict__ conn, int n_src,
+                                  const double* __restrict__ src, double* __restrict__ slot) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double p[8][3];
+    double cen[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 8; c++) {
+        const int64_t n = conn[8 * e + c];
+        for (int a = 0; a < 3; a++) {
+            p[c][a] = xyz[3 * n + a];
+            cen[a] += 0.125 * p[c][a];
+        }
+    }
+    double r2 = 0.0;
+    for (int c = 0; c < 8; c++) {
+        const double dx = p[c][0] - cen[0], dy = p[c][1] - cen[1], dz = p[c][2] - cen[2];
+        r2 = fmax(r2, dx * dx + dy * dy + dz * dz);
+    }
+    const double rad = sqrt(r2);
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < n_src; k++) {
+        const double* g = src + 5 * k;
+        const double dx = cen[0] - g[0], dy = cen[1] - g[1], dz = cen[2] - g[2];
+        if (sqrt(dx * dx + dy * dy + dz * dz) - rad > 8.0 * g[3]) continue;
+        for (int qi = 0; qi < 64; qi++) {
+            const double q[3] = {kGL4x[qi & 3], kGL4x[(qi >> 2) & 3], kGL4x[qi >> 4]};
+            const double wq = kGL4w[qi & 3] * kGL4w[(qi >> 2) & 3] * kGL4w[qi >> 4];
+            double N[8], x[3] = {0.0, 0.0, 0.0}, J[3][3] = {};
+            for (int a = 0; a < 8; a++) {
+                const double f0 = 1.0 + kHexNat[a][0] * q[0], f1 = 1.0 + kHexNat[a][1] * q[1],
+                             f2 = 1.0 + kHexNat[a][2] * q[2];
+                N[a] = 0.125 * f0 * f1 * f2;
+                const double d[3] = {0.125 * kHexNat[a][0] * f1 * f2,
+                                     0.125 * kHexNat[a][1] * f0 * f2,
+                                     0.125 * kHexNat[a][2] * f0 * f1};
+                for (int i = 0; i < 3; i++) {
+                    x[i] += N[a] * p[a][i];
+                    for (int j = 0; j < 3; j++) J[j][i] += d[j] * p[a][i];
+                }
+            }
+            const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                               J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            const double f = wq * fabs(det) * gauss_at(x, g);
+            for (int a = 0; a < 8; a++) acc[a] += f * N[a];
+        }
+    }
+    for (int a = 0; a < 8; a++) slot[8 * e + a] = acc[a];
+}
+
 __global__ void k_source_elem(int64_t E, const double* __restrict__ xyz,
                               const int32_t* __restrict__ conn,
                               const double* __restrict__ vol, int n_src,
@@ -586,6 +648,19 @@ hipError_t launch_source_consistent(int64_t N, int64_t E, const double* xyz,
                                     double* q64, hipStream_t s) {
     hipLaunchKernelGGL(k_source_elem, dim3(blocks_for(E, 128)), dim3(128), 0, s, E, xyz, conn,
                        vol, n_src, src, qpts, slot64);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, ec_off, ec,
+                       slot64, q64);
+    return hipGetLastError();
+}
+
+hipError_t launch_source_consistent_hex(int64_t N, int64_t E, const double* xyz,
+                                        const int32_t* conn, const int32_t* ec_off,
+                                        const int32_t* ec, int n_src, const double* src,
+                                        double* slot64, double* q64, hipStream_t s) {
+    hipLaunchKernelGGL(k_source_elem_hex, dim3(blocks_for(E, 128)), dim3(128), 0, s, E, xyz, conn,
+                       n_src, src, slot64);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, ec_off, ec,

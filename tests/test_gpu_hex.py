@@ -170,10 +170,6 @@ def test_hex_autotune_and_errors():
     assert err <= 1e-3
     # what a hexahedral handle refuses
     with pytest.raises(ff.FedFemError) as ei:
-        h.set_gaussian_sources(np.array([[8e-3, 6e-3, 5e-3, 1.5e-3, 4e8]]),
-                               ff.SOURCE_CONSISTENT)
-    assert ei.value.code == ff.E_INVALID
-    with pytest.raises(ff.FedFemError) as ei:
         h.flux_loads(np.array([[0, 1, 2]], dtype=np.int32), [1.0])
     assert ei.value.code == ff.E_INVALID
     with pytest.raises(ff.FedFemError) as ei:
@@ -281,3 +277,31 @@ def test_hex_two_point_tables_equal_linear_law():
     assert out[0][0].max() > 60.0
     assert abs(out[0][1][1] - out[1][1][1]) <= 1e-12 * out[0][1][1]   # same critical step
     assert np.max(np.abs(out[0][0] - out[1][0])) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
+def test_hex_consistent_source_parity(prec):
+    """Gaussian sources integrated against the trilinear shape functions
+    (4 x 4 x 4 Gauss-Legendre on each element's map) on a jittered,
+    relabelled box: the nodal loads against the oracle's, then 300 steps."""
+    xyz, hexes, bnd = jittered_hex_box(14, 12, 10, 1e-3, seed=23)
+    xyz, hexes, bnd = shuffled(xyz, hexes, bnd, seed=4)
+    mat = sc.td_materials()
+    om = oracle_model(xyz, hexes, mat, bnd)
+    src = [[7e-3, 6e-3, 5e-3, 1.2e-3, 4e8], [3e-3, 9e-3, 4e-3, 0.8e-3, 2e8]]
+    q = om.source_consistent(src)
+    T_ref = om.run(om.initial(37.0), 300, q)
+    h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
+                  precision=prec, tile_elems=256)
+    h.precompute()
+    h.set_gaussian_sources(np.array(src), ff.SOURCE_CONSISTENT)
+    qg = h.read_source()
+    qerr = float(np.max(np.abs(qg - q)) / q.max())
+    h.step(300)
+    err = float(np.max(np.abs(h.read_T() - T_ref)))
+    print(f"[hex] consistent source prec={prec}: loads {qerr:.2e} relative, max|dT| "
+          f"{err:.3e} K, peak {T_ref.max():.1f} C", flush=True)
+    assert qerr <= (1e-12 if prec == ff.FP64 else 1e-6)
+    assert T_ref.max() > 60.0
+    assert err <= TOL[prec]
+    h.close()
