@@ -75,6 +75,30 @@ def assemble(n_nodes, hexes, Ae, scale=None):
     return sp.coo_matrix((Ae.ravel(), (rows, cols)), shape=(n_nodes, n_nodes)).tocsr()
 
 
+def flux_loads_quad(xyz, faces, flux):
+    """Nodal loads [W] of a surface flux q_f [W/m^2] on bilinear
+    quadrilaterals (corners in order around the face): each corner a receives
+    the integral of q_f N_a over the face, by the 2 x 2 Gauss-Legendre rule on
+    the bilinear map (area element |x_s x x_t|; exact on planar
+    parallelograms), summed in ascending face order."""
+    X = np.asarray(xyz, dtype=np.float64)[np.asarray(faces, dtype=np.int64)]   # [F, 4, 3]
+    st = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
+    g, w = np.polynomial.legendre.leggauss(2)
+    acc = np.zeros((len(X), 4))
+    for s_, ws in zip(g, w):
+        for t_, wt in zip(g, w):
+            N = (1 + st[:, 0] * s_) * (1 + st[:, 1] * t_) / 4.0
+            dNs = st[:, 0] * (1 + st[:, 1] * t_) / 4.0
+            dNt = st[:, 1] * (1 + st[:, 0] * s_) / 4.0
+            xs = np.einsum("a,fai->fi", dNs, X)
+            xt = np.einsum("a,fai->fi", dNt, X)
+            dA = np.linalg.norm(np.cross(xs, xt), axis=1)
+            acc += (ws * wt) * (np.asarray(flux, dtype=np.float64) * dA)[:, None] * N[None, :]
+    out = np.zeros(len(np.asarray(xyz)))
+    np.add.at(out, np.asarray(faces, dtype=np.int64).ravel(), acc.ravel())
+    return out
+
+
 class HexModel:
     """Element-level FED-FEM (Algorithm 1) on hexahedra, in FP64."""
 

@@ -241,3 +241,31 @@ def test_consistent_source_total_power_and_relabelling():
     rel = hexes[:, [5, 6, 7, 4, 1, 2, 3, 0]]    # a turn with top and bottom swapped
     m2 = ohx.HexModel(xyz, rel, oracle.mat_vector(sc.td_materials()))
     assert np.max(np.abs(m2.source_consistent([[*c, sg, Q0]]) - q)) <= 1e-12 * q.max()
+
+
+def test_quad_flux_loads_on_parallelograms():
+    """On a planar parallelogram each corner receives a quarter of q |f|
+    (the bilinear shape functions integrate to |f| / 4), so the loads sum
+    to q |f|, whatever the corner the list starts at and its direction; unit
+    flux on two faces of a regular box sums to their area.  Catches a wrong
+    area element, shape function or gather."""
+    xyz = np.array([[0.0, 0.0, 0.0], [2e-3, 0.5e-3, 0.0], [2.7e-3, 3.5e-3, 0.0],
+                    [0.7e-3, 3.0e-3, 0.0], [1e-3, 1e-3, 1e-3]])
+    face = np.array([[0, 1, 2, 3]])
+    area = np.linalg.norm(np.cross(xyz[1] - xyz[0], xyz[3] - xyz[0]))
+    q = ohx.flux_loads_quad(xyz, face, [3e4])
+    assert np.max(np.abs(q[:4] - 3e4 * area / 4)) <= 1e-12 * 3e4 * area and q[4] == 0.0
+    # a corner order turned and reversed gives the same loads
+    for f in ([[1, 2, 3, 0]], [[3, 2, 1, 0]]):
+        assert np.max(np.abs(ohx.flux_loads_quad(xyz, np.array(f), [3e4]) - q)) <= 1e-12 * q.max()
+    # unit flux on the six faces of a regular box: total = surface area
+    n, h = 3, 1e-3
+    bx, _ = mesh.hex_box(n, n, n, h)
+    nid = lambda i, j, k: i + (n + 1) * (j + (n + 1) * k)
+    quads = []
+    for a in range(n):
+        for b in range(n):
+            quads += [[nid(a, b, 0), nid(a + 1, b, 0), nid(a + 1, b + 1, 0), nid(a, b + 1, 0)],
+                      [nid(a, 0, b), nid(a + 1, 0, b), nid(a + 1, 0, b + 1), nid(a, 0, b + 1)]]
+    tot = ohx.flux_loads_quad(bx, np.array(quads), np.ones(len(quads))).sum()
+    assert abs(tot - 2 * (n * h) ** 2) <= 1e-15
