@@ -157,9 +157,10 @@ int fedfem_create(const fedfem_mesh *mesh, const fedfem_materials *mat,
  * no conduction load.  Validation, ownership and the rest of the API are as
  * for fedfem_create, with these differences: reordered tiles may hold up
  * to twice as many nodes as elements (default 4096 for 2048-element
- * tiles); fedfem_flux_loads and fedfem_resample give FEDFEM_E_INVALID (they
- * are defined on triangles and tetrahedra); batches accept tetrahedral
- * handles only (FEDFEM_E_STATE).  fedfem_get_info reports elements in
+ * tiles); surface flux takes quadrilateral faces (fedfem_flux_loads_quad;
+ * fedfem_flux_loads and fedfem_resample give FEDFEM_E_INVALID, being
+ * defined on triangles and tetrahedra); batches accept tetrahedral handles
+ * only (FEDFEM_E_STATE).  fedfem_get_info reports elements in
  * n_tets.
  */
 int fedfem_create_hex(const fedfem_mesh_hex *mesh, const fedfem_materials *mat,
@@ -303,6 +304,17 @@ int fedfem_set_schedule(fedfem_handle *h, int32_t n_patterns,
  */
 int fedfem_flux_loads(fedfem_handle *h, int64_t n_faces, const int32_t *faces,
                       const double *flux, double *out);
+
+/*
+ * The same on a hexahedral mesh, for bilinear quadrilaterals: faces is
+ * [4 n_faces] caller node ids, each face's corners in order around it (four
+ * distinct); corner a receives the integral of flux[f] N_a over the face,
+ * by the 2 x 2 Gauss-Legendre rule on the bilinear map (exact on planar
+ * parallelograms, where each corner gets flux[f] |f| / 4).  Sums per node
+ * in ascending face order; FEDFEM_E_INVALID on a tetrahedral handle.
+ */
+int fedfem_flux_loads_quad(fedfem_handle *h, int64_t n_faces, const int32_t *faces,
+                           const double *flux, double *out);
 
 /*
  * Thermal dose accumulated at every node during the following steps.  The

@@ -1051,33 +1051,38 @@ int fedfem_read_dose(fedfem_handle* h, double* out) {
     return FEDFEM_OK;
 }
 
-int fedfem_flux_loads(fedfem_handle* h, int64_t n_faces, const int32_t* faces, const double* flux,
-                      double* out) {
+// Surface-flux loads on faces of nv corners (3: triangles of a tetrahedral
+// mesh, 4: quadrilaterals of a hexahedral one), gathered in ascending face
+// order and returned in caller node order.
+static int flux_loads_nv(fedfem_handle* h, int nv, int64_t n_faces, const int32_t* faces,
+                         const double* flux, double* out) {
     int rc = check_handle(h, true);
     if (rc) return rc;
     const int64_t N = h->N;
-    if (h->npe != 4)
-        return set_err(h, FEDFEM_E_INVALID, "flux loads need a tetrahedral mesh (triangle faces)");
-    if (n_faces < 0 || n_faces > INT32_MAX / 3 || !out || (n_faces > 0 && (!faces || !flux)))
+    if (h->npe != (nv == 3 ? 4 : 8))
+        return set_err(h, FEDFEM_E_INVALID, nv == 3
+                           ? "triangle flux loads need a tetrahedral mesh"
+                           : "quadrilateral flux loads need a hexahedral mesh");
+    if (n_faces < 0 || n_faces > INT32_MAX / nv || !out || (n_faces > 0 && (!faces || !flux)))
         return set_err(h, FEDFEM_E_INVALID, "bad flux arguments");
     if (!finite_all(flux, n_faces)) return set_err(h, FEDFEM_E_INVALID, "non-finite flux");
-    std::vector<int32_t> fi(3 * (size_t)n_faces);
+    std::vector<int32_t> fi((size_t)nv * n_faces);
     for (int64_t f = 0; f < n_faces; f++) {
-        for (int c = 0; c < 3; c++) {
-            const int32_t v = faces[3 * f + c];
+        for (int c = 0; c < nv; c++) {
+            const int32_t v = faces[nv * f + c];
             if (v < 0 || v >= N) return set_err(h, FEDFEM_E_INVALID, "face %lld: bad node id", (long long)f);
-            fi[3 * f + c] = h->L.ninv[v];
+            fi[nv * f + c] = h->L.ninv[v];
+            for (int d = 0; d < c; d++)
+                if (faces[nv * f + d] == v)
+                    return set_err(h, FEDFEM_E_INVALID, "face %lld repeats a node", (long long)f);
         }
-        if (faces[3 * f] == faces[3 * f + 1] || faces[3 * f] == faces[3 * f + 2] ||
-            faces[3 * f + 1] == faces[3 * f + 2])
-            return set_err(h, FEDFEM_E_INVALID, "face %lld repeats a node", (long long)f);
     }
     if (n_faces == 0) {
         std::fill(out, out + N, 0.0);
         return FEDFEM_OK;
     }
-    // node -> face corners (3 f + c), ascending face order
-    std::vector<int32_t> foff(N + 1, 0), fidx(3 * (size_t)n_faces);
+    // node -> face corners (nv f + c), ascending face order
+    std::vector<int32_t> foff(N + 1, 0), fidx((size_t)nv * n_faces);
     for (size_t k = 0; k < fi.size(); k++) foff[fi[k] + 1]++;
     for (int64_t i = 0; i < N; i++) foff[i + 1] += foff[i];
     {
@@ -1090,10 +1095,10 @@ int fedfem_flux_loads(fedfem_handle* h, int64_t n_faces, const int32_t* faces, c
     double *d_flux = nullptr, *d_slot = nullptr;
     if ((rc = upload(h, &d_faces, fi)) || (rc = upload(h, &d_off, foff)) ||
         (rc = upload(h, &d_idx, fidx)) || (rc = upload(h, &d_flux, fl)) ||
-        (rc = dalloc(h, &d_slot, 3 * (size_t)n_faces)))
+        (rc = dalloc(h, &d_slot, (size_t)nv * n_faces)))
         return rc;
     HIPCHK(h, hipStreamSynchronize(h->own_stream));  // uploads ran there
-    HIPCHK(h, launch_face_loads(N, n_faces, h->d_xyz, d_faces, d_flux, d_off, d_idx, d_slot,
+    HIPCHK(h, launch_face_loads(N, n_faces, nv, h->d_xyz, d_faces, d_flux, d_off, d_idx, d_slot,
                                 h->d_stage, s));
     std::vector<double> tmp(N);
     HIPCHK(h, hipMemcpyAsync(tmp.data(), h->d_stage, sizeof(double) * N, hipMemcpyDeviceToHost, s));
@@ -1102,6 +1107,16 @@ int fedfem_flux_loads(fedfem_handle* h, int64_t n_faces, const int32_t* faces, c
     for (void* p : {(void*)d_faces, (void*)d_off, (void*)d_idx, (void*)d_flux, (void*)d_slot})
         dfree(h, p);
     return FEDFEM_OK;
+}
+
+int fedfem_flux_loads(fedfem_handle* h, int64_t n_faces, const int32_t* faces, const double* flux,
+                      double* out) {
+    return flux_loads_nv(h, 3, n_faces, faces, flux, out);
+}
+
+int fedfem_flux_loads_quad(fedfem_handle* h, int64_t n_faces, const int32_t* faces,
+                           const double* flux, double* out) {
+    return flux_loads_nv(h, 4, n_faces, faces, flux, out);
 }
 
 int fedfem_set_source(fedfem_handle* h, const double* source) {

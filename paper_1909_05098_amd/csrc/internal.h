@@ -209,11 +209,12 @@ hipError_t launch_node_init(int64_t N, const double* Vi, const int32_t* is_dir,
                             const double* dirT, double T0, int fp32c, void* u,
                             void* T0buf, void* T1buf, hipStream_t s);
 // q (Real, internal order) <- src64[nperm[i]] (caller order) or src64[i].
-// Nodal loads of a surface heat flux: per-face shares, then a fixed-order
-// gather over the node -> face-corner list (off, idx).
-hipError_t launch_face_loads(int64_t N, int64_t F, const double* xyz, const int32_t* faces,
-                             const double* flux, const int32_t* off, const int32_t* idx,
-                             double* slot, double* out, hipStream_t s);
+// Nodal loads of a surface heat flux on triangles (nv 3) or bilinear
+// quadrilaterals (nv 4): per-face corner shares, then a fixed-order gather
+// over the node -> face-corner list (off, idx).
+hipError_t launch_face_loads(int64_t N, int64_t F, int nv, const double* xyz,
+                             const int32_t* faces, const double* flux, const int32_t* off,
+                             const int32_t* idx, double* slot, double* out, hipStream_t s);
 hipError_t launch_set_source(int64_t N, const double* src64,
                              const int32_t* nperm, int fp32c, void* q,
                              hipStream_t s);

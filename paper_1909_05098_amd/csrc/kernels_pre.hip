@@ -334,6 +334,41 @@ __global__ void k_face_loads(int64_t F, const double* __restrict__ xyz,
     for (int k = 0; k < 3; k++) slot[3 * f + k] = share;
 }
 
+// The same for bilinear quadrilaterals (corners in order around the face):
+// corner a receives the integral of the flux times its bilinear shape
+// function, by the 2 x 2 Gauss-Legendre rule (nodes +-1/sqrt(3), weights 1)
+// with the area element |x_s x x_t| of the bilinear map.
+__global__ void k_face_loads_quad(int64_t F, const double* __restrict__ xyz,
+                                  const int32_t* __restrict__ faces,
+                                  const double* __restrict__ flux, double* __restrict__ slot) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double sa[4] = {-1.0, 1.0, 1.0, -1.0}, ta[4] = {-1.0, -1.0, 1.0, 1.0};
+    double p[4][3];
+    for (int c = 0; c < 4; c++)
+        for (int i = 0; i < 3; i++) p[c][i] = xyz[3 * (int64_t)faces[4 * f + c] + i];
+    const double g = 1.0 / sqrt(3.0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int qi = 0; qi < 4; qi++) {
+        const double s = (qi & 1) ? g : -g, t = (qi & 2) ? g : -g;
+        double xs[3] = {0.0, 0.0, 0.0}, xt[3] = {0.0, 0.0, 0.0}, N[4];
+        for (int c = 0; c < 4; c++) {
+            N[c] = 0.25 * (1.0 + sa[c] * s) * (1.0 + ta[c] * t);
+            const double ds = 0.25 * sa[c] * (1.0 + ta[c] * t);
+            const double dt = 0.25 * ta[c] * (1.0 + sa[c] * s);
+            for (int i = 0; i < 3; i++) {
+                xs[i] += ds * p[c][i];
+                xt[i] += dt * p[c][i];
+            }
+        }
+        const double n0 = xs[1] * xt[2] - xs[2] * xt[1], n1 = xs[2] * xt[0] - xs[0] * xt[2],
+                     n2 = xs[0] * xt[1] - xs[1] * xt[0];
+        const double dA = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        for (int c = 0; c < 4; c++) acc[c] += flux[f] * dA * N[c];
+    }
+    for (int c = 0; c < 4; c++) slot[4 * f + c] = acc[c];
+}
+
 // Largest row sum of |A_e| off the diagonal over all elements (for the
 // fixed-point scale of the element loads).  Positive doubles order like
 // their bit patterns, so an integer max over the bits is exact.
@@ -668,11 +703,15 @@ hipError_t launch_source_consistent_hex(int64_t N, int64_t E, const double* xyz,
     return hipGetLastError();
 }
 
-hipError_t launch_face_loads(int64_t N, int64_t F, const double* xyz, const int32_t* faces,
-                             const double* flux, const int32_t* off, const int32_t* idx,
-                             double* slot, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_face_loads, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, xyz, faces, flux,
-                       slot);
+hipError_t launch_face_loads(int64_t N, int64_t F, int nv, const double* xyz,
+                             const int32_t* faces, const double* flux, const int32_t* off,
+                             const int32_t* idx, double* slot, double* out, hipStream_t s) {
+    if (nv == 4)
+        hipLaunchKernelGGL(k_face_loads_quad, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, xyz,
+                           faces, flux, slot);
+    else
+        hipLaunchKernelGGL(k_face_loads, dim3(blocks_for(F)), dim3(kBlock), 0, s, F, xyz, faces,
+                           flux, slot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_slots, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, off, idx, slot,

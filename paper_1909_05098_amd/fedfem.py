@@ -90,6 +90,7 @@ _SIGS = {
     "fedfem_set_property_tables": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, _P, _P,
                                              C.c_int32, _P, _P]),
     "fedfem_flux_loads": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
+    "fedfem_flux_loads_quad": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
     "fedfem_set_dose": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
     "fedfem_read_dose": (C.c_int, [_P, _P]),
     "fedfem_step": (C.c_int, [_P, C.c_int64, _P]),
@@ -263,12 +264,15 @@ class Handle:
                                                 _ptr(am)), "fedfem_set_schedule")
 
     def flux_loads(self, faces, flux):
-        """Nodal loads [W] of surface flux `flux` [W/m^2] on triangles `faces`."""
-        f = np.ascontiguousarray(faces, dtype=np.int32).reshape(-1, 3)
+        """Nodal loads [W] of surface flux `flux` [W/m^2] on triangles (3
+        columns) or, on a hexahedral mesh, bilinear quadrilaterals (4)."""
+        f = np.ascontiguousarray(faces, dtype=np.int32)
+        nv = f.shape[1] if f.ndim == 2 else 3
+        f = f.reshape(-1, nv)
         q = np.ascontiguousarray(flux, dtype=np.float64).reshape(-1)
         out = np.empty(len(self.xyz))
-        self._check(self._L.fedfem_flux_loads(self._h, len(f), _ptr(f), _ptr(q), _ptr(out)),
-                    "fedfem_flux_loads")
+        name = "fedfem_flux_loads_quad" if nv == 4 else "fedfem_flux_loads"
+        self._check(getattr(self._L, name)(self._h, len(f), _ptr(f), _ptr(q), _ptr(out)), name)
         return out
 
     def set_dose(self, model, A=0.0, Ea=0.0):

@@ -305,3 +305,39 @@ def test_hex_consistent_source_parity(prec):
     assert T_ref.max() > 60.0
     assert err <= TOL[prec]
     h.close()
+
+
+def test_hex_quad_flux_loads():
+    """Surface flux on quadrilaterals of a hexahedral mesh against the
+    oracle's 2 x 2 rule: planar faces of the box top and warped quadrilaterals
+    through interior nodes, then a run heated by the loads."""
+    nx, ny, nz = 10, 8, 6
+    xyz, hexes, bnd = jittered_hex_box(nx, ny, nz, 1e-3, seed=29)
+    nid = lambda i, j, k: i + (nx + 1) * (j + (ny + 1) * k)
+    faces = [[nid(i, j, nz), nid(i + 1, j, nz), nid(i + 1, j + 1, nz), nid(i, j + 1, nz)]
+             for i in range(3, 7) for j in range(2, 6)]
+    faces += [[nid(i, j, 3), nid(i + 1, j, 3), nid(i + 1, j + 1, 4), nid(i, j + 1, 3)]
+              for i in range(2, 5) for j in range(2, 4)]          # warped
+    faces = np.array(faces, dtype=np.int32)
+    flux = np.linspace(2e4, 5e4, len(faces))
+    ref = ohx.flux_loads_quad(xyz, faces, flux)
+    mat = sc.td_materials()
+    om = oracle_model(xyz, hexes, mat, bnd)
+    for prec in (ff.FP64, ff.FP32C):
+        h = ff.Handle(xyz, hexes, mat, 37.0, bnd, np.full(len(bnd), 37.0), dt=om.dt,
+                      precision=prec)
+        h.precompute()
+        q = h.flux_loads(faces, flux)
+        err = float(np.max(np.abs(q - ref)) / np.max(np.abs(ref)))
+        h.set_source(q)
+        h.step(200)
+        T_ref = om.run(om.initial(37.0), 200, ref)
+        terr = float(np.max(np.abs(h.read_T() - T_ref)))
+        print(f"[hex] quad flux prec={prec}: loads {err:.2e} relative, max|dT| {terr:.3e} K",
+              flush=True)
+        assert err <= 1e-13
+        assert terr <= TOL[prec]
+        with pytest.raises(ff.FedFemError) as ei:
+            h.flux_loads(np.array([[0, 1, 2, 1]], dtype=np.int32), [1.0])   # repeated node
+        assert ei.value.code == ff.E_INVALID
+        h.close()

@@ -66,6 +66,9 @@ def test_flux_loads_match_oracle():
     with pytest.raises(ff.FedFemError):
         h.flux_loads(np.array([[0, 1, len(xyz)]]), [1.0])
     assert np.all(h.flux_loads(np.zeros((0, 3), dtype=np.int32), []) == 0.0)
+    with pytest.raises(ff.FedFemError) as ei:   # quadrilaterals belong to hexahedral meshes
+        h.flux_loads(np.array([[0, 1, 2, 3]], dtype=np.int32), [1.0])
+    assert ei.value.code == ff.E_INVALID
     h.close()
 
 
