@@ -420,7 +420,10 @@ int fedfem_last_error(const fedfem_handle *h, char *buf, size_t len);
  * [W] for scenario j (its caller's numbering) that replaces that handle's
  * active source before the run, as the source argument of fedfem_step does
  * (FEDFEM_E_INVALID if any is not finite; no source is replaced and no
- * scenario advances then).
+ * scenario advances then).  fedfem_batch_create refuses hexahedral handles
+ * and handles with a source schedule or a dose model (FEDFEM_E_STATE);
+ * fedfem_batch_run gives FEDFEM_E_STATE, advancing nothing, when a
+ * schedule or dose model was set on a member handle after creation.
  */
 typedef struct fedfem_batch fedfem_batch;
 

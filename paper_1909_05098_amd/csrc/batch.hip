@@ -298,6 +298,9 @@ int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps, const double* cons
         if (n_steps[j] < 0 || n_steps[j] > 100000000) return FEDFEM_E_INVALID;
         const fedfem_handle* h = b->hs[j];
         if (h->broken || !h->precomputed || !(h->dt > 0)) return FEDFEM_E_STATE;
+        // a schedule or dose model set after the batch was created would be
+        // ignored by the lockstep launches: refuse, as fedfem_batch_create does
+        if (h->d.n_pat > 0 || h->d.dose) return FEDFEM_E_STATE;
     }
     // new sources replace the handles' active ones, as in fedfem_step; all
     // are checked before any is taken

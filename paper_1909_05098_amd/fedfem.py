@@ -267,9 +267,13 @@ class Handle:
         """Nodal loads [W] of surface flux `flux` [W/m^2] on triangles (3
         columns) or, on a hexahedral mesh, bilinear quadrilaterals (4)."""
         f = np.ascontiguousarray(faces, dtype=np.int32)
-        nv = f.shape[1] if f.ndim == 2 else 3
-        f = f.reshape(-1, nv)
+        if f.ndim != 2 or f.shape[1] not in (3, 4):
+            raise ValueError("faces must be a 2-D array with 3 (triangles) or 4 "
+                             f"(quadrilaterals) columns, got shape {f.shape}")
+        nv = f.shape[1]
         q = np.ascontiguousarray(flux, dtype=np.float64).reshape(-1)
+        if len(q) != len(f):
+            raise ValueError(f"flux has {len(q)} entries for {len(f)} faces")
         out = np.empty(len(self.xyz))
         name = "fedfem_flux_loads_quad" if nv == 4 else "fedfem_flux_loads"
         self._check(getattr(self._L, name)(self._h, len(f), _ptr(f), _ptr(q), _ptr(out)), name)

@@ -120,3 +120,20 @@ def test_create_hex_rejects_bad_input(case):
         ff.Handle(xyz, hexes, _mat(), 37.0, [0, 1], [37.0, 37.0])
     assert ei.value.code == ff.E_INVALID
     assert "fedfem_create_hex" in str(ei.value)
+
+
+@pytest.mark.parametrize("faces, flux", [
+    (np.zeros((4, 2), np.int32), np.ones(4)),     # two columns
+    (np.zeros((4, 5), np.int32), np.ones(4)),     # five columns
+    (np.zeros(12, np.int32), np.ones(4)),         # flat array
+    (np.zeros((4, 3), np.int32), np.ones(3)),     # short flux
+    (np.zeros((4, 4), np.int32), np.ones(5)),     # long flux
+])
+def test_flux_loads_rejects_bad_shapes(faces, flux):
+    """The binding refuses face arrays that are not [F, 3] or [F, 4] and
+    flux vectors of another length before the C call (which reads F fluxes
+    and takes the face width from the entry point)."""
+    h = ff.Handle.__new__(ff.Handle)  # no device handle: the check comes first
+    h.xyz = np.zeros((8, 3))
+    with pytest.raises(ValueError):
+        h.flux_loads(faces, flux)

@@ -110,6 +110,30 @@ def test_batch_rejects_mixed_or_unprepared(scenarios):
         ff.Batch([h, h])
 
 
+def test_batch_run_refuses_schedule_or_dose_set_after_create(scenarios):
+    """A schedule or dose model set on a member after fedfem_batch_create
+    would be ignored by the lockstep launches: the run refuses it
+    (FEDFEM_E_STATE) and advances no scenario."""
+    (s0, _, _, n0, dt0), (s1, _, _, n1, dt1) = scenarios[:2]
+    h0, h1 = make(s0, dt0), make(s1, dt1)
+    b = ff.Batch([h0, h1])
+    for setter, clear in ((lambda h: h.set_schedule(np.ones((1, h.N)), [([0.0], [1.0])]),
+                           lambda h: h.set_schedule(None, [])),
+                          (lambda h: h.set_dose(ff.DOSE_CEM43),
+                           lambda h: h.set_dose(ff.DOSE_OFF))):
+        setter(h1)
+        with pytest.raises(ff.FedFemError) as ei:
+            b.run([n0, n1])
+        assert ei.value.code == ff.E_STATE
+        assert h0.time()[1] == 0 and h1.time()[1] == 0
+        clear(h1)
+    b.run([n0, n1])
+    assert h0.time()[1] == n0 and h1.time()[1] == n1
+    b.close()
+    h0.close()
+    h1.close()
+
+
 def test_precompute_many_equals_sequential_and_reports_errors(scenarios):
     """Precompute overlapped on host threads gives every handle exactly what
     its own precompute gives (critical step, then 20 steps bit for bit), and
