@@ -118,7 +118,12 @@ typedef struct {
     int64_t device_bytes;     /* device memory owned by the handle */
     double lambda_geometry;   /* top eigenvalue of (sum A_e, diag V) */
     int32_t lanczos_iterations;
-    int32_t reserved[7];
+    /* exact tile sums (Eq 11): corner loads are added as 64-bit integers
+     * in units of 2^-fixed_point_shift; the shift leaves room for the most
+     * corners one tile places on a node (max_tile_valence) */
+    int32_t max_tile_valence;
+    int32_t fixed_point_shift;
+    int32_t reserved[5];
 } fedfem_info;
 
 /*

@@ -763,10 +763,15 @@ int fedfem_precompute(fedfem_handle* h) {
             if (!h->host_isdir[i]) vmin = std::min(vmin, Vi[i]);
         double kmin, kmax, rcmin, rcmax;
         window_bounds_h(h, &kmin, &kmax, &rcmin, &rcmax);
+        // one load maps below 2^58, leaving 5 bits for the sum of up to 32
+        // loads in a tile-node accumulator; a node with more corners in one
+        // tile (an unstructured fan) lowers the scale until the whole sum
+        // stays below 2^63
+        const double fan = std::max(1.0, L.max_tile_valence / 32.0);
         // loads: k <= kmax, |T_b - T_a| <= 2e4 (both within the divergence limit)
-        h->fx_scale = fixed_scale(kmax * amax * 2.0e4);
+        h->fx_scale = fixed_scale(kmax * amax * 2.0e4 * fan);
         // Lanczos: |x| <= 1 / sqrt(min free V_i) for a unit vector
-        h->fx_scale_lz = fixed_scale(amax * 2.0 / std::sqrt(std::max(vmin, 1e-300)));
+        h->fx_scale_lz = fixed_scale(amax * 2.0 / std::sqrt(std::max(vmin, 1e-300)) * fan);
         h->a_max = amax;
     }
     // time-stepping arrays in the chosen precision
@@ -1411,6 +1416,8 @@ int fedfem_get_info(const fedfem_handle* h, fedfem_info* info) {
     info->device_bytes = h->dev_bytes;
     info->lambda_geometry = h->lam_geo;
     info->lanczos_iterations = h->lz_iters;
+    info->max_tile_valence = h->L.max_tile_valence;
+    info->fixed_point_shift = std::ilogb(h->fx_scale);
     return FEDFEM_OK;
 }
 

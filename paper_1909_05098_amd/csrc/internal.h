@@ -27,6 +27,9 @@ struct Layout {
     int npe = 4;  // nodes per element: 4 (linear tetrahedra) or 8 (hexahedra)
     int tile_elems = 0;
     int max_tile_nodes = 0;
+    // most corners of one tile on a single node: the number of loads one
+    // tile-node accumulator adds (bounds the fixed-point headroom)
+    int max_tile_valence = 0;
     std::vector<int32_t> nperm;          // internal -> caller node id
     std::vector<int32_t> ninv;           // caller -> internal node id
     std::vector<int32_t> eperm;          // internal -> caller element id

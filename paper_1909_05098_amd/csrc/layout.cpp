@@ -168,10 +168,11 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     // worker finds them; only the distinct nodes are sorted) and every
     // corner's position in that list
     std::vector<int32_t> uniq((size_t)npe * E);  // tile t's list at npe * tile_elem_off[t]
-    std::vector<int32_t> ucount(T);
+    std::vector<int32_t> ucount(T), uval(T);
     L.lconn.assign((size_t)npe * E, 0);
     parallel_for(T, [&](int64_t a, int64_t b) {
         std::vector<int32_t> loc(N, -1);
+        std::vector<int32_t> cnt;
         for (int64_t t = a; t < b; t++) {
             const int64_t e0 = L.tile_elem_off[t], nc = npe * (L.tile_elem_off[t + 1] - e0);
             const int32_t* c = L.conn.data() + npe * e0;
@@ -184,19 +185,28 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
                 }
             std::sort(u, u + nu);
             for (int32_t i = 0; i < nu; i++) loc[u[i]] = i;
-            for (int64_t s2 = 0; s2 < nc; s2++) L.lconn[npe * e0 + s2] = (uint16_t)loc[c[s2]];
+            // corners per tile node: the loads one LDS accumulator sums
+            cnt.assign(nu, 0);
+            int32_t vmax = 0;
+            for (int64_t s2 = 0; s2 < nc; s2++) {
+                L.lconn[npe * e0 + s2] = (uint16_t)loc[c[s2]];
+                vmax = std::max(vmax, ++cnt[loc[c[s2]]]);
+            }
             for (int32_t i = 0; i < nu; i++) loc[u[i]] = -1;
             ucount[t] = nu;
+            uval[t] = vmax;
         }
     }, 4);
     L.tile_node_off.assign(T + 1, 0);
     int64_t P = 0;
-    int maxn = 0;
+    int maxn = 0, maxv = 0;
     for (int64_t t = 0; t < T; t++) {
         L.tile_node_off[t] = (int32_t)P;
         P += ucount[t];
         maxn = std::max(maxn, ucount[t]);
+        maxv = std::max(maxv, uval[t]);
     }
+    L.max_tile_valence = maxv;
     if (P > INT32_MAX) {
         err = "mesh too large for 32-bit partial indices";
         return false;

@@ -66,7 +66,8 @@ class Info(C.Structure):
                 ("threads", C.c_int32), ("reorder", C.c_int32),
                 ("device_bytes", C.c_int64), ("lambda_geometry", C.c_double),
                 ("lanczos_iterations", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("max_tile_valence", C.c_int32), ("fixed_point_shift", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class FedFemError(RuntimeError):

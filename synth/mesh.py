@@ -283,3 +283,26 @@ def shuffle_mesh(xyz, tets, marked, rng):
     tets2 = np.take_along_axis(tets2, cperm, axis=1)
     marked2 = np.sort(inv[marked]).astype(np.int32)
     return xyz2, tets2, marked2, node_perm, elem_perm
+
+
+def flat_fan(m, radius, height, rng):
+    """m flat tetrahedra sharing node 0 (the origin).
+
+    Element i is (0, a_i, b_i, c_i) with its own base triangle: an
+    equilateral triangle of circumradius `radius` in the plane
+    z = -height, centred below node 0 and turned by 2 pi i / m plus a small
+    seeded angle.  The elements overlap (the list is not a conforming mesh),
+    which is allowed: each is a valid, non-degenerate tetrahedron.  With
+    height << radius node 0 sits close to every opposite face, and its m
+    corners all fall into one tile of the library's layout.  Returns
+    (xyz [1 + 3m, 3], tets [m, 4]); nodes 1.. are the base corners.
+    """
+    xyz = np.zeros((1 + 3 * m, 3))
+    tets = np.zeros((m, 4), dtype=np.int32)
+    turn = 2.0 * np.pi * np.arange(m) / m + rng.uniform(-0.05, 0.05, m)
+    for i in range(m):
+        for c in range(3):
+            a = turn[i] + 2.0 * np.pi * c / 3.0
+            xyz[1 + 3 * i + c] = (radius * np.cos(a), radius * np.sin(a), -height)
+        tets[i] = (0, 1 + 3 * i, 2 + 3 * i, 3 + 3 * i)
+    return xyz, tets
