@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfedfem.so")
-SOURCES = ["layout.cpp", "devcache.cpp", "kernels_pre.hip", "kernels_step.hip", "api.hip",
+SOURCES = ["layout.cpp", "devcache.cpp", "pool.cpp", "kernels_pre.hip", "kernels_step.hip", "api.hip",
            "batch.hip", "surrogate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_set>
@@ -898,7 +899,6 @@ int fedfem_precompute_many(fedfem_handle* const* handles, int32_t n, int32_t thr
             if (!handles[j] || !seen.insert(handles[j]).second) return FEDFEM_E_INVALID;
     }
     std::vector<int> res(n, FEDFEM_OK);
-    std::atomic<int32_t> next{0};
     const int cores = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     int32_t nt = threads;
     if (nt == 0) {
@@ -909,23 +909,7 @@ int fedfem_precompute_many(fedfem_handle* const* handles, int32_t n, int32_t thr
     nt = std::max<int32_t>(1, std::min(nt, n));
     // each worker's layout builds share the cores with the other workers'
     const int inner = std::max(1, cores / nt);
-    auto work = [&] {
-        const int prev = set_layout_threads(inner);
-        for (;;) {
-            const int32_t j = next.fetch_add(1);
-            if (j >= n) break;
-            res[j] = fedfem_precompute(handles[j]);
-        }
-        set_layout_threads(prev);
-    };
-    std::vector<std::thread> pool;
-    try {
-        for (int32_t t = 1; t < nt; t++) pool.emplace_back(work);
-    } catch (const std::system_error&) {
-        // fewer workers than asked: the remaining ones share the work
-    }
-    work();
-    for (auto& t : pool) t.join();
+    run_workers(n, nt, inner, [&](int32_t j) { res[j] = fedfem_precompute(handles[j]); });
     int first = FEDFEM_OK;
     for (int32_t j = 0; j < n; j++) {
         if (rcs) rcs[j] = res[j];

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,12 @@ void pack_lconn(Layout& L);
 // Cap the host threads of layout builds made by the calling thread (0: the
 // default, up to 16); returns the previous cap.
 int set_layout_threads(int n);
+
+// Run fn(0) .. fn(n - 1) on `threads` host workers (the caller among them)
+// that take items from one atomic counter; each worker's layout builds use
+// at most `inner` host threads (pool.cpp).
+void run_workers(int32_t n, int32_t threads, int inner,
+                 const std::function<void(int32_t)>& fn);
 
 // Morton (Z-order) permutation of points; returns new -> old.
 std::vector<int32_t> morton_order(const double* pts, int64_t n);
