@@ -39,6 +39,9 @@ METRIC = ("tet-element updates/s + achieved HBM GB/s; scenarios/s plain vs "
 GOLDEN3 = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
 GOLDEN_HEX = os.path.join(ROOT, "tests", "golden", "hex_ellipsoid_oracle.json")
 GOLDEN_DOSE = os.path.join(ROOT, "tests", "golden", "config3_dose_oracle.json")
+GOLDEN1 = os.path.join(ROOT, "tests", "golden", "config1_oracle.json")
+GOLDEN2 = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
+GOLDEN_SWEEP = os.path.join(ROOT, "tests", "golden", "sweep_oracle.json")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "elem_loads_config3_pmc.txt")
 PMC_SUMMARY_HEX = os.path.join(ROOT, "profiles", "elem_loads_hex_ellipsoid_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_05098_amd", "csrc", "kernels_step.hip")
@@ -72,29 +75,98 @@ def read_traffic(n_elems, tile_elems, threads, xcd, summary=PMC_SUMMARY, count="
         return None
 
 
-def cpu_baseline(scn, dt, q_params, seconds):
-    """The FP64 oracle as it stands, on the first steps of the same run."""
+def check_vs_golden(h, state0, golden, n_tets):
+    """Rewind the handle to its initial state, run the stored oracle run's
+    step count (untimed) and return max |T - T_oracle| over its sampled
+    nodes (every node when the record holds no sample)."""
+    import numpy as np
+    if not golden or golden.get("n_tets", golden.get("n_hexes")) != n_tets:
+        return None
+    h.write_state(state0, 0.0, 0)
+    h.step(golden["n_steps"])
+    T = h.read_T()
+    ref = np.asarray(golden["T"])
+    if "idx" in golden:
+        T = T[np.asarray(golden["idx"])]
+    return float(np.max(np.abs(T - ref)))
+
+
+def load_golden(path, key, value):
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    return g if g.get(key) == value else None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_steps(m, q, seconds, chunk=5, cap=400):
+    """Steps of the oracle model from its initial state until `seconds` have
+    passed (or `cap` steps); returns (steps, elapsed seconds)."""
+    T = m.initial(37.0)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        T = m.run(T, chunk, q)
+        steps += chunk
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= cap:
+            return steps, el
+
+
+def cpu_baseline(scn, dt, q_params, seconds, sweep_scns=None, sweep_seconds=8.0):
+    """The FP64 oracle as it stands, on the host cores: the first steps of
+    the same config-3 run on all cores (up to 16 OpenMP threads) and on one
+    thread, and, when given, whole planning-sweep scenarios (critical step,
+    source and every step, as the oracle computes them) for a bounded
+    number of seconds."""
     import oracle
+    from oracle import dense
+    from synth import scenarios as sc
     t0 = time.perf_counter()
     m = oracle.build_model(scn)
     m.dt = dt
     q = m.source(q_params, scn.source_mode)
     setup = time.perf_counter() - t0
-    T = m.initial(37.0)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        T = m.run(T, 5, q)
-        steps += 5
+    threads = oracle.max_threads()
+    steps, el = _oracle_steps(m, q, seconds)
+    m.n_threads = 1
+    steps1, el1 = _oracle_steps(m, q, seconds / 2, chunk=1, cap=100)
+    del m  # the sweep models below name their thread count (the last one set stays)
+    out = {"value": round(scn.n_tets * steps / el, 1), "unit": "element-updates/s",
+           "cores": threads, "kind": "oracle",
+           "sample": (f"FP64 oracle, {steps} steps of the same mesh, sources "
+                      f"and dt from the initial state ({el:.1f} s timed, "
+                      f"{setup:.1f} s untimed setup), OpenMP threads = {threads}"),
+           "value_1thread": round(scn.n_tets * steps1 / el1, 1),
+           "sample_1thread": f"{steps1} steps on one thread ({el1:.1f} s timed)",
+           "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
+    if sweep_scns:
+        done, upd = 0, 0.0
+        t0 = time.perf_counter()
+        for s in sweep_scns:
+            om = oracle.build_model(s, n_threads=threads)
+            dt_cr, _ = dense.critical_dt_from_lambda(om.geometry_lambda(), om.mat)
+            n, om.dt = sc.steps_for(s.t_end, dt_cr)
+            om.run(om.initial(37.0), n, om.source(s.sources, s.source_mode))
+            done += 1
+            upd += float(s.n_tets) * n
+            if time.perf_counter() - t0 >= sweep_seconds:
+                break
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 400:
-            break
-    return {"value": scn.n_tets * steps / el, "unit": "element-updates/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": (f"FP64 oracle, {steps} steps of the same mesh, sources "
-                       f"and dt from the initial state ({el:.1f} s timed, "
-                       f"{setup:.1f} s untimed setup), OpenMP threads = "
-                       f"{oracle.max_threads()}")}
+        out["sweep"] = {"scenarios_per_s": round(done / el, 3),
+                        "element_updates_per_s": round(upd / el, 1), "cores": threads,
+                        "sample": f"the first {done} planning-sweep scenarios, each from "
+                                  f"mesh to final field ({el:.1f} s)"}
+    return out
 
 
 def run_dose(h, state0, args, E, N, ms_plain):
@@ -113,15 +185,21 @@ def run_dose(h, state0, args, E, N, ms_plain):
     h.step(args.steps)
     torch.cuda.synchronize()
     t_run = time.perf_counter() - t0
-    rel = None
-    if os.path.exists(GOLDEN_DOSE):
-        g = json.load(open(GOLDEN_DOSE))
-        if g["n_tets"] == E and g["n_steps"] == args.steps:
-            idx = np.asarray(g["idx"])
-            ref = np.asarray(g["dose"])
-            rel = float(np.max(np.abs(h.read_dose()[idx] - ref) / ref))
-            log(f"dose: max relative error on {len(idx)} sampled nodes = {rel:.3e}")
     _, node_ms = h.time_kernels(args.kernel_steps)
+    # untimed: the stored oracle run's step count from the initial state,
+    # with the accumulator restarted (setting the model zeroes it)
+    rel = dT = None
+    g = load_golden(GOLDEN_DOSE, "n_tets", E)
+    if g:
+        h.write_state(state0, 0.0, 0)
+        h.set_dose(ff.DOSE_CEM43)
+        h.step(g["n_steps"])
+        idx = np.asarray(g["idx"])
+        ref = np.asarray(g["dose"])
+        rel = float(np.max(np.abs(h.read_dose()[idx] - ref) / ref))
+        dT = float(np.max(np.abs(h.read_T()[idx] - np.asarray(g["T"]))))
+        log(f"dose: max relative error on {len(idx)} sampled nodes = {rel:.3e} "
+            f"after {g['n_steps']} steps (max|dT| {dT:.3e} K)")
     h.set_dose(ff.DOSE_OFF)
     # node pass bytes: T hi/lo read and write, u, q, and the FP64 dose read
     # and written
@@ -135,7 +213,9 @@ def run_dose(h, state0, args, E, N, ms_plain):
                             "avg_launch_ms_without_dose": round(node_plain, 5),
                             "achieved_GBps": round(node_bytes / (node_ms * 1e-3) / 1e9, 1),
                             "algorithmic_bytes_per_launch": node_bytes},
-            "max_rel_dose_error_vs_oracle": rel}
+            "max_rel_dose_error_vs_oracle": rel, "max_abs_dT_vs_oracle_K": dT,
+            "oracle_check": (f"{g['n_steps']} steps from the initial state, untimed, "
+                             f"{len(g['idx'])} sampled nodes") if g else None}
 
 
 def run_hex(args):
@@ -184,13 +264,11 @@ def run_hex(args):
     torch.cuda.synchronize()
     t_run = time.perf_counter() - t0
     E, N = scn.n_tets, scn.n_nodes
-    max_err = None
-    if golden and golden["n_steps"] == args.steps:
-        T = h.read_T()
-        idx = np.asarray(golden["idx"])
-        max_err = float(np.max(np.abs(T[idx] - np.asarray(golden["T"]))))
-        log(f"hex: max|T - T_oracle| on {len(idx)} sampled nodes = {max_err:.3e} K")
     elem_ms, node_ms = h.time_kernels(args.kernel_steps)
+    max_err = check_vs_golden(h, state0, golden, E)
+    if max_err is not None:
+        log(f"hex: max|T - T_oracle| on {len(golden['idx'])} sampled nodes after "
+            f"{golden['n_steps']} steps = {max_err:.3e} K")
     h.close()
     # algorithmic bytes per hexahedron: the six f32 entries of its 3 x 3
     # matrix S (A_e = Xi^T S Xi) and eight 32-bit node ids (the layout stores
@@ -232,8 +310,110 @@ def run_hex(args):
             "roofline": roofline,
             "node_update": {"avg_launch_ms": round(node_ms, 5),
                             "achieved_GBps": round(node_bytes / (node_ms * 1e-3) / 1e9, 1)},
-            "max_abs_dT_vs_oracle_K": max_err, "precompute_s": round(t_pre, 3),
-            "cpu_baseline": cpu}
+            "max_abs_dT_vs_oracle_K": max_err,
+            "oracle_check": (f"{golden['n_steps']} steps from the initial state, untimed, "
+                             f"{len(golden['idx'])} sampled nodes") if golden else None,
+            "precompute_s": round(t_pre, 3), "cpu_baseline": cpu}
+
+
+def run_other_order(scn, golden, args):
+    """Config 3 in the order the headline did not use: with the library's
+    Morton renumbering when the headline kept the seeded random input order,
+    else the random input order as handed over (library default tiles, no
+    autotuning, since the autotuner would pick the renumbered layout).
+    --steps timed steps, kernel times by HIP events, and the stored oracle
+    run checked after rewinding."""
+    import torch
+    from paper_1909_05098_amd import fedfem as ff
+    morton = args.order != "morton"
+    h = ff.Handle(scn.xyz, scn.tets, scn.materials, scn.T0, scn.dir_nodes, scn.dir_T,
+                  dt=golden["dt"] if golden else -0.9, precision=ff.FP32C, reorder=morton)
+    t0 = time.perf_counter()
+    h.precompute()
+    t_pre = time.perf_counter() - t0
+    info = h.info()
+    h.set_gaussian_sources(scn.sources, ff.SOURCE_CONSISTENT)
+    state0, _, _ = h.read_state()
+    h.prepare(args.steps)
+    if args.warmup:
+        h.step(args.warmup)
+    h.write_state(state0, 0.0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(args.steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    elem_ms, node_ms = h.time_kernels(args.kernel_steps)
+    err = check_vs_golden(h, state0, golden, scn.n_tets)
+    h.close()
+    E, N = scn.n_tets, scn.n_nodes
+    log(f"{'morton' if morton else 'random'} order: {t_run * 1e3 / args.steps:.4f} ms/step, "
+        f"element kernel {elem_ms:.4f} ms, node pass {node_ms:.4f} ms, max|dT| {err}")
+    return {"order": "morton" if morton else "random",
+            "value": round(E * args.steps / t_run, 1), "unit": "element-updates/s",
+            "ms_per_step": round(t_run * 1e3 / args.steps, 5),
+            "tile_elems": info["tile_elems"], "threads": info["threads"],
+            "max_tile_nodes": info["max_tile_nodes"], "n_tiles": info["n_tiles"],
+            "n_partials": info["n_partials"],
+            "elem_loads": {"avg_launch_ms": round(elem_ms, 5),
+                           "achieved_GBps": round(40.0 * E / (elem_ms * 1e-3) / 1e9, 1)},
+            "node_update": {"avg_launch_ms": round(node_ms, 5),
+                            "achieved_GBps": round(24.0 * N / (node_ms * 1e-3) / 1e9, 1)},
+            "max_abs_dT_vs_oracle_K": err, "precompute_s": round(t_pre, 3)}
+
+
+def run_config12(args):
+    """Configs 1 and 2, whole runs at the oracle's own step, in FP64 and in
+    compensated FP32: element-updates/s of the captured steps and the error
+    against the oracle's stored result (every node of config 1, 4096
+    sampled nodes of config 2)."""
+    import numpy as np
+    import torch
+    from paper_1909_05098_amd import fedfem as ff
+    from synth import scenarios as sc
+    out = {}
+    for name, make, path in (("config1", sc.config1, GOLDEN1), ("config2", sc.config2, GOLDEN2)):
+        s = make()
+        g = load_golden(path, "n_tets", s.n_tets)
+        if g is None:
+            continue
+        rec = {"workload": ("1 cm cube, 10^3 Kuhn cubes, constant properties, nodal "
+                            "Gaussian source, 300 s" if name == "config1" else
+                            "ellipsoid 75x50x40 mm, jittered lattice h=1.2 mm, TD k(T) "
+                            "c(T), consistent Gaussian source, 600 s"),
+               "n_tets": s.n_tets, "n_nodes": s.n_nodes, "steps": g["n_steps"],
+               "dt_s": g["dt"]}
+        T_prec = {}
+        for prec, label in ((ff.FP64, "fp64"), (ff.FP32C, "fp32c")):
+            h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
+                          dt=g["dt"], precision=prec)
+            h.precompute()
+            h.set_gaussian_sources(s.sources, s.source_mode)
+            state0, _, _ = h.read_state()
+            h.prepare(g["n_steps"])
+            h.step(min(args.warmup, g["n_steps"]) if args.warmup else 0)
+            h.write_state(state0, 0.0, 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.step(g["n_steps"])
+            torch.cuda.synchronize()
+            t_run = time.perf_counter() - t0
+            T = h.read_T()
+            if "idx" in g:
+                T = T[np.asarray(g["idx"])]
+            T_prec[label] = T
+            err = float(np.max(np.abs(T - np.asarray(g["T"]))))
+            elem_ms, node_ms = h.time_kernels(args.kernel_steps)
+            h.close()
+            rec[label] = {"value": round(s.n_tets * g["n_steps"] / t_run, 1),
+                          "unit": "element-updates/s",
+                          "ms_per_step": round(t_run * 1e3 / g["n_steps"], 5),
+                          "elem_loads_ms": round(elem_ms, 5), "node_update_ms": round(node_ms, 5),
+                          "max_abs_dT_vs_oracle_K": err}
+            log(f"{name} {label}: {t_run * 1e3 / g['n_steps']:.4f} ms/step, max|dT| {err:.3e} K")
+        rec["max_abs_dT_fp32c_vs_fp64_K"] = float(np.max(np.abs(T_prec["fp32c"] - T_prec["fp64"])))
+        out[name] = rec
+    return out
 
 
 def _gen_sweep_one(j):
@@ -249,24 +429,40 @@ def gen_sweep(ids, workers):
         return pool.map(_gen_sweep_one, list(ids))
 
 
-def run_sweep(scns, autotune=True):
+def run_sweep(scns, autotune=True, recs=None):
     """Scenarios/s for the planning sweep: plain per-scenario use of the
     library versus one batched graph launch, on the same GPU."""
     import numpy as np
     from paper_1909_05098_amd import fedfem as ff
     from synth import scenarios as sc
 
-    def handle(s):
+    # with the oracle's stored runs of these scenarios, both legs take the
+    # oracle's own step and step count, so the results can be checked
+    # against it; otherwise each handle's own critical step
+    if recs is not None and [r["j"] for r in recs[:len(scns)]] != list(range(len(scns))):
+        recs = None
+    rec_of = (lambda i: recs[i]) if recs is not None else (lambda i: None)  # noqa: E731
+
+    def handle(i, s):
+        r = rec_of(i)
         h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
-                      dt=-0.9, precision=ff.FP32C)
+                      dt=r["dt"] if r else -0.9, precision=ff.FP32C)
         if autotune:
             h.autotune(TUNE_CACHE, for_batch=True)
         h.precompute()
         h.set_gaussian_sources(s.sources, s.source_mode)
+        if r:
+            return h, r["n_steps"]
         _, dtcr = h.dt()
         n, dt = sc.steps_for(s.t_end, dtcr)
         h.set_dt(dt)
         return h, n
+
+    def oracle_err(i, T):
+        r = rec_of(i)
+        if not r:
+            return None
+        return float(np.max(np.abs(T[np.asarray(r["idx"])] - np.asarray(r["T"]))))
 
     # tune each mesh-size class once (untimed); both legs then hit the cache
     t_tune = 0.0
@@ -282,9 +478,9 @@ def run_sweep(scns, autotune=True):
     # plain: create -> precompute -> step -> read, one scenario at a time
     plain_T, ns = [], []
     t_all = t_steps = 0.0
-    for s in scns:
+    for i, s in enumerate(scns):
         t0 = time.perf_counter()
-        h, n = handle(s)
+        h, n = handle(i, s)
         t1 = time.perf_counter()
         h.step(n)
         plain_T.append(h.read_T())
@@ -298,22 +494,31 @@ def run_sweep(scns, autotune=True):
     # captured launch sequence
     t0 = time.perf_counter()
     hs = []
-    for s in scns:
+    for i, s in enumerate(scns):
+        r = rec_of(i)
         h = ff.Handle(s.xyz, s.tets, s.materials, s.T0, s.dir_nodes, s.dir_T,
-                      dt=-0.9, precision=ff.FP32C)
+                      dt=r["dt"] if r else -0.9, precision=ff.FP32C)
         if autotune:
             h.autotune(TUNE_CACHE, for_batch=True)
         hs.append(h)
     ff.precompute_many(hs)
-    for h, s in zip(hs, scns):
+    for i, (h, s) in enumerate(zip(hs, scns)):
         h.set_gaussian_sources(s.sources, s.source_mode)
-        h.set_dt(sc.steps_for(s.t_end, h.dt()[1])[1])
+        if not rec_of(i):
+            h.set_dt(sc.steps_for(s.t_end, h.dt()[1])[1])
     t1 = time.perf_counter()
     b = ff.Batch(hs)
     t2 = time.perf_counter()
     b.run(ns)
     t3 = time.perf_counter()
-    dT = max(float(np.max(np.abs(h.read_T() - T))) for h, T in zip(hs, plain_T))
+    batched_T = [h.read_T() for h in hs]
+    dT = max(float(np.max(np.abs(Tb - T))) for Tb, T in zip(batched_T, plain_T))
+    e_b = [oracle_err(i, T) for i, T in enumerate(batched_T)]
+    e_p = [oracle_err(i, T) for i, T in enumerate(plain_T)]
+    e_b = max(e_b) if recs is not None else None
+    e_p = max(e_p) if recs is not None else None
+    if e_b is not None:
+        log(f"sweep: worst sampled max|T - T_oracle| batched {e_b:.3e} K, plain {e_p:.3e} K")
     first_graph_ms = b.last_ms()
     # steady state: the same launch sequence again (graph already captured)
     b.run(ns)
@@ -338,7 +543,11 @@ def run_sweep(scns, autotune=True):
             "autotune_s_untimed": round(t_tune, 2),
             "batched_first_run_ms": round(first_graph_ms, 3),
             "batched_element_updates_per_s": round(upd / (graph_ms * 1e-3), 1),
-            "max_abs_dT_batched_vs_plain_K": dT}
+            "max_abs_dT_batched_vs_plain_K": dT,
+            "max_abs_dT_batched_vs_oracle_K": e_b, "max_abs_dT_plain_vs_oracle_K": e_p,
+            "oracle_check": ("every scenario at the oracle's own step, its 512 hottest "
+                             "and 32 drawn nodes, worst over scenarios")
+                            if recs is not None else None}
 
 
 def forward_flops(G):
@@ -473,6 +682,12 @@ def main():
                          "its kernels); not a benchmark line")
     ap.add_argument("--dose", type=int, default=1,
                     help="also time config 3 with the CEM43 dose (0 to skip)")
+    ap.add_argument("--other-order", type=int, default=1,
+                    help="also time config 3 in the other element/node order (0 to skip)")
+    ap.add_argument("--small", type=int, default=1,
+                    help="also time configs 1 and 2 in both precisions (0 to skip)")
+    ap.add_argument("--cpu-sweep-seconds", type=float, default=8.0,
+                    help="seconds of the CPU oracle on whole sweep scenarios (0 to skip)")
     ap.add_argument("--hex", type=int, default=1,
                     help="also run the hexahedral ellipsoid (0 to skip)")
     ap.add_argument("--hex-only", action="store_true",
@@ -571,14 +786,12 @@ def main():
     E, N = scn.n_tets, scn.n_nodes
     value = E * args.steps / t_run
     ms_step = t_run * 1e3 / args.steps
-    max_err = None
-    if golden and golden["n_steps"] == args.steps:
-        T = h.read_T()
-        idx = np.asarray(golden["idx"])
-        max_err = float(np.max(np.abs(T[idx] - np.asarray(golden["T"]))))
-        log(f"max|T - T_oracle| on {len(idx)} sampled nodes = {max_err:.3e} K")
     # per-kernel durations with HIP events on the handle's stream
     elem_ms, node_ms = h.time_kernels(args.kernel_steps)
+    max_err = check_vs_golden(h, state0, golden, scn.n_tets)
+    if max_err is not None:
+        log(f"max|T - T_oracle| on {len(golden['idx'])} sampled nodes after "
+            f"{golden['n_steps']} steps = {max_err:.3e} K")
     # algorithmic bytes per element-update of the stencil: six f32 coefficients
     # and four 32-bit node ids (the layout itself stores 10- or 16-bit
     # tile-local ids)
@@ -598,14 +811,22 @@ def main():
     step_gbps = (elem_bytes + node_bytes) / (ms_step * 1e-3) / 1e9
     dose_leg = run_dose(h, state0, args, E, N, ms_step) if args.dose else None
     h.close()
-    batched = run_sweep(sweep_scns, not args.no_autotune) if sweep_scns else None
+    order_leg = run_other_order(scn, golden, args) if args.other_order else None
+    small = run_config12(args) if args.small else None
+    sweep_recs = None
+    if sweep_scns and os.path.exists(GOLDEN_SWEEP):
+        sweep_recs = json.load(open(GOLDEN_SWEEP))["scenarios"]
+        if len(sweep_recs) < len(sweep_scns):
+            sweep_recs = None
+    batched = run_sweep(sweep_scns, not args.no_autotune, sweep_recs) if sweep_scns else None
     surrogate = run_surrogate(sur_scns, args.surrogate_weights) if sur_scns else None
     hexleg = run_hex(args) if args.hex else None
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
-        cpu = cpu_baseline(scn, dt, scn.sources, args.cpu_seconds)
-        cpu["value"] = round(cpu["value"], 1)
+        cpu = cpu_baseline(scn, dt, scn.sources, args.cpu_seconds,
+                           sweep_scns if args.cpu_sweep_seconds > 0 else None,
+                           args.cpu_sweep_seconds)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "element-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -626,7 +847,12 @@ def main():
                          "achieved_GBps": round(kern[other][1] / (kern[other][0] * 1e-3) / 1e9, 1)},
         "step_GBps_algorithmic": round(step_gbps, 1),
         "max_abs_dT_vs_oracle_K": max_err,
+        "oracle_check": (f"{golden['n_steps']} steps from the initial state, untimed, "
+                         f"{len(golden['idx'])} sampled nodes (512 hottest, 3584 drawn)")
+                        if golden else None,
         "precompute_s": round(t_pre, 3),
+        "other_order": order_leg,
+        "configs_1_2": small,
         "batched": batched,
         "surrogate": surrogate,
         "dose": dose_leg,
