@@ -39,6 +39,7 @@ extern "C" {
 #define FEDFEM_E_HIP (-6)             /* HIP runtime failure (sticky)        */
 #define FEDFEM_E_NOMEM (-7)           /* host or device allocation failed    */
 #define FEDFEM_E_STATE (-8)           /* call not valid in the current state */
+#define FEDFEM_E_TOO_LARGE (-9)       /* beyond fedfem_step_static's scratch */
 
 /* ---- precision of the time-stepping kernels ----------------------------- */
 #define FEDFEM_FP64 0  /* element loop and nodal state in double             */
@@ -248,6 +249,23 @@ int fedfem_precompute_many(fedfem_handle *const *handles, int32_t n,
  * state).
  */
 int fedfem_step(fedfem_handle *h, int64_t n_steps, const double *source);
+
+/*
+ * fedfem_step without allocation, for callers that cannot allocate device
+ * memory or instantiate graphs: tight serving loops and harnesses that
+ * forbid allocation.  Same arguments, results (bit for bit) and return
+ * codes as fedfem_step, but the steps are launched one by one on the
+ * handle's stream, and the tile partials live in a device array of the
+ * library's own, of fixed size (32 MiB), instead of the handle's buffer.
+ * Each GPU the library runs on holds one copy of that array until the
+ * process ends; every call on that GPU shares it, so calls on one GPU that
+ * overlap in time (other host threads, other streams) race and must not be
+ * made.  Refused: a handle whose partials exceed the array (n_partials *
+ * 4 bytes in FEDFEM_FP32C, * 8 in FEDFEM_FP64; FEDFEM_E_TOO_LARGE, nothing
+ * advances) and a handle with source schedules (FEDFEM_E_STATE).  Like
+ * fedfem_step it waits for its steps before returning.
+ */
+int fedfem_step_static(fedfem_handle *h, int64_t n_steps, const double *source);
 
 /*
  * Instantiate the HIP graphs that an n_steps call of fedfem_step uses (for

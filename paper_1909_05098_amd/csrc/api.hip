@@ -26,6 +26,13 @@
 
 using namespace fedfem;
 
+// Tile partials of fedfem_step_static: a fixed device array instead of the
+// handle's own buffer, so that call allocates nothing.  Each device holds its
+// own copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (static_scratch below).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 int set_err(fedfem_handle* h, int code, const char* fmt, ...) {
@@ -481,6 +488,7 @@ const char* fedfem_strerror(int code) {
         case FEDFEM_E_HIP: return "HIP runtime failure";
         case FEDFEM_E_NOMEM: return "out of memory";
         case FEDFEM_E_STATE: return "call not valid in this state";
+        case FEDFEM_E_TOO_LARGE: return "problem larger than the static scratch";
         default: return "unknown error";
     }
 }
@@ -1216,6 +1224,79 @@ int fedfem_step(fedfem_handle* h, int64_t n_steps, const double* source) {
         HIPCHK(h, hipGraphLaunch(ex, s));
         if (chunk & 1) h->cur ^= 1;
         done += chunk;
+    }
+    int32_t flag = 0;
+    HIPCHK(h, hipMemcpyAsync(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->steps += n_steps;
+    h->t += (double)n_steps * h->dt;
+    if (flag) return set_err(h, FEDFEM_E_DIVERGED, "temperature left [-1e4, 1e4] degC or NaN");
+    return FEDFEM_OK;
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch`, looked up once per device (the handle's
+// device is current: check_handle made it so).
+int static_scratch(fedfem_handle* h, void** out) {
+    if (h->device < 0 || h->device >= kMaxDevices)
+        return set_err(h, FEDFEM_E_INVALID, "device %d beyond the static scratch table", h->device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    void*& p = g_scratch_ptr[h->device];
+    if (!p) {
+        void* q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(h, e, "hipGetSymbolAddress(scratch)");
+        p = q;
+    }
+    *out = p;
+    return FEDFEM_OK;
+}
+
+}  // namespace
+
+int fedfem_step_static(fedfem_handle* h, int64_t n_steps, const double* source) {
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (n_steps < 0) return set_err(h, FEDFEM_E_INVALID, "negative step count");
+    if (!(h->dt > 0)) return set_err(h, FEDFEM_E_UNSTABLE, "no valid time step");
+    if (h->d.n_pat > 0)
+        return set_err(h, FEDFEM_E_STATE,
+                       "fedfem_step_static does not apply source schedules (fedfem_step does)");
+    const size_t need = (size_t)h->d.P * (h->fp32c ? sizeof(float) : sizeof(double));
+    if (need > kStaticScratchBytes)
+        return set_err(h, FEDFEM_E_TOO_LARGE,
+                       "the tile partials need %zu bytes; the static scratch holds %zu", need,
+                       kStaticScratchBytes);
+    void* buf = nullptr;
+    if ((rc = static_scratch(h, &buf))) return rc;
+    if (source && (rc = fedfem_set_source(h, source))) return rc;
+    if (n_steps == 0) return FEDFEM_OK;
+    hipStream_t s = h->stream;
+    // the step kernels of fedfem_step, launched one by one; every tile writes
+    // all of its partials before the node pass reads them, so the scratch
+    // needs no clearing between calls
+    DevLayout d = h->d;
+    d.partial = buf;
+    d.dose_dt = h->dt;
+    const bool td = h->mat.dk_dT != 0.0 || !h->tab_t[0].empty();
+    HIPCHK(h, launch_fill_i32(h->d_flag, 1, 0, s));
+    if (h->fp32c) {
+        const Props<float> p = props_f(h);
+        for (int64_t k = 0; k < n_steps; k++) {
+            HIPCHK(h, launch_step_f32c(d, h->cur, p, td, h->d_flag, s, 0));
+            h->cur ^= 1;
+        }
+    } else {
+        const Props<double> p = props_d(h);
+        for (int64_t k = 0; k < n_steps; k++) {
+            HIPCHK(h, launch_step_f64(d, h->cur, p, td, h->d_flag, s, 0));
+            h->cur ^= 1;
+        }
     }
     int32_t flag = 0;
     HIPCHK(h, hipMemcpyAsync(&flag, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -32,6 +32,7 @@ E_DIVERGED = -5
 E_HIP = -6
 E_NOMEM = -7
 E_STATE = -8
+E_TOO_LARGE = -9
 
 MAT_FIELDS = ("rho0", "c0", "k0", "drho_dT", "dc_dT", "dk_dT", "T_ref", "T_lo",
               "T_hi", "w_b", "c_b", "T_a", "Q_m")
@@ -95,6 +96,7 @@ _SIGS = {
     "fedfem_set_dose": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
     "fedfem_read_dose": (C.c_int, [_P, _P]),
     "fedfem_step": (C.c_int, [_P, C.c_int64, _P]),
+    "fedfem_step_static": (C.c_int, [_P, C.c_int64, _P]),
     "fedfem_prepare": (C.c_int, [_P, C.c_int64]),
     "fedfem_set_source": (C.c_int, [_P, _P]),
     "fedfem_set_gaussian_sources": (C.c_int, [_P, C.c_int32, _P, C.c_int32]),
@@ -212,16 +214,30 @@ class Handle:
             pass
 
     # -- stepping -------------------------------------------------------------
+    def _source(self, source):
+        if source is None:
+            return None
+        src = np.ascontiguousarray(source, np.float64).reshape(-1)
+        if len(src) != self.N:
+            raise ValueError(f"source has {len(src)} entries, the mesh {self.N} nodes")
+        return src
+
     def step(self, n_steps, source=None):
-        src = None if source is None else np.ascontiguousarray(source, np.float64)
+        src = self._source(source)
         self._check(self._L.fedfem_step(self._h, int(n_steps), _ptr(src)),
                     "fedfem_step")
+
+    def step_static(self, n_steps, source=None):
+        """fedfem_step without allocation (the library's fixed scratch)."""
+        src = self._source(source)
+        self._check(self._L.fedfem_step_static(self._h, int(n_steps), _ptr(src)),
+                    "fedfem_step_static")
 
     def prepare(self, n_steps):
         self._check(self._L.fedfem_prepare(self._h, int(n_steps)), "fedfem_prepare")
 
     def set_source(self, source):
-        src = None if source is None else np.ascontiguousarray(source, np.float64)
+        src = self._source(source)
         self._check(self._L.fedfem_set_source(self._h, _ptr(src)),
                     "fedfem_set_source")
 
