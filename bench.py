@@ -421,12 +421,18 @@ def _gen_sweep_one(j):
     return sc.sweep_scenario(j)
 
 
-def gen_sweep(ids, workers):
+def _gen_sweep_one_v2(j):
+    from synth import scenarios as sc
+    return sc.sweep_scenario(j, mesh_variant=2)
+
+
+def gen_sweep(ids, workers, variant=1):
     """Seeded planning-sweep scenarios, built on host cores before any GPU
-    use in this process (the pool forks)."""
+    use in this process (the pool forks); variant 2 re-seeds only the
+    interior-node jitter of each mesh."""
     from multiprocessing import get_context
     with get_context("fork").Pool(workers) as pool:
-        return pool.map(_gen_sweep_one, list(ids))
+        return pool.map(_gen_sweep_one if variant == 1 else _gen_sweep_one_v2, list(ids))
 
 
 def run_sweep(scns, autotune=True, recs=None):
@@ -557,7 +563,7 @@ def forward_flops(G):
     return f + 2 * 32 * G ** 3
 
 
-def run_surrogate(scns, weights, net_batch=16, check_batch=64):
+def run_surrogate(scns, weights, net_batch=16, check_batch=64, scns_b=None):
     """Scenarios/s of FED-FEM (one at a time, batched) and of the trained
     surrogate (raw, and with the 1/16 FED-FEM spot check and fallback) on
     held-out scenarios, with each path's error against FED-FEM on the grid."""
@@ -614,6 +620,37 @@ def run_surrogate(scns, weights, net_batch=16, check_batch=64):
     e_fb = errors(out, T, M)
     log(f"surrogate leg: raw {t_raw:.3f} s, with fallback {t_fb:.2f} s, "
         f"fallback batches {stats['fallback_batches']}/{stats['batches']}")
+    # the same spot check at looser bounds
+    loose = {}
+    for tol in (1.0, 2.0):
+        t_l, st = timed(lambda: pl.infer_with_fallback(net, scns, samples, phys, out,
+                                                        batch=check_batch, grid=G, fr=fr,
+                                                        net_batch=net_batch, tol=tol))
+        e_l = errors(out, T, M)
+        loose[f"{tol:g}K"] = {"fallback_batches": st["fallback_batches"],
+                              "batches": st["batches"],
+                              "scenarios_per_s": round(S / t_l, 2),
+                              "max_abs_dT_K_median": round(float(np.median(e_l)), 3),
+                              "max_abs_dT_K_max": round(float(e_l.max()), 3)}
+        log(f"surrogate leg: spot check at {tol:g} K: fallback batches "
+            f"{st['fallback_batches']}/{st['batches']}, {S / t_l:.1f} scen/s")
+    # FED-FEM on a second mesh of every scenario (same parameters and
+    # elements, another jitter seed) against the first: how far a prediction
+    # that does not see the mesh can be expected to land
+    spread = None
+    if scns_b is not None:
+        TB, MB = field(), torch.empty_like(M)
+        pl.fem_on_grid(scns_b, TB, MB, G, fr)
+        e_sp = errors(TB, T, M)
+        spread = {"median": round(float(np.median(e_sp)), 3),
+                  "p90": round(float(np.quantile(e_sp, 0.9)), 3),
+                  "max": round(float(e_sp.max()), 3),
+                  "within_K": {f"{t:g}": round(float(np.mean(e_sp <= t)), 4)
+                               for t in (0.5, 1.0, 2.0)},
+                  "same_voxels": bool(torch.equal(M, MB))}
+        del TB, MB
+        log(f"surrogate leg: FED-FEM mesh-to-mesh spread median {spread['median']} K, "
+            f"p90 {spread['p90']} K")
     # training throughput of the same network (a fresh copy, 12 steps timed)
     tr = sg.Net(G, 8, seed=1)
     tr.set_stream(stream)
@@ -648,6 +685,10 @@ def run_surrogate(scns, weights, net_batch=16, check_batch=64):
             "batches": stats["batches"], "fedfem_runs_in_surrogate_path": stats["fedfem_runs"],
             "max_abs_dT_K": {"surrogate_raw": q(e_raw), "prior_only": q(e_prior),
                              "with_fallback": q(e_fb), "fedfem_plain_vs_batched": d_plain},
+            "surrogate_raw_within_K": {f"{t:g}": round(float(np.mean(e_raw <= t)), 4)
+                                       for t in (0.5, 1.0, 2.0)},
+            "spot_check_looser": loose,
+            "fedfem_mesh_to_mesh_max_abs_dT_K": spread,
             "forward_TFLOPs": round(ff_flops * S / t_raw / 1e12, 1),
             "forward_mfma_frac_bf16": round(ff_flops * S / t_raw / 1e12 / 2500.0, 4),
             "train_sample_steps_per_s": round(12 * 8 / t_tr, 1),
@@ -713,11 +754,13 @@ def main():
         sweep_scns = gen_sweep(range(args.sweep), min(16, os.cpu_count() or 1))
         log(f"sweep meshes: {len(sweep_scns)} scenarios "
             f"({sum(s.n_tets for s in sweep_scns)} tets, {time.perf_counter() - t0:.1f} s)")
-    sur_scns = None
+    sur_scns = sur_scns_b = None
     if args.surrogate and not args.copy_calib_gib and not args.hex_only:
         t0 = time.perf_counter()
         sur_scns = gen_sweep(range(10000, 10000 + args.surrogate), min(16, os.cpu_count() or 1))
-        log(f"surrogate held-out meshes: {len(sur_scns)} ({time.perf_counter() - t0:.1f} s)")
+        sur_scns_b = gen_sweep(range(10000, 10000 + args.surrogate),
+                               min(16, os.cpu_count() or 1), variant=2)
+        log(f"surrogate held-out meshes: {len(sur_scns)}, twice ({time.perf_counter() - t0:.1f} s)")
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -732,7 +775,8 @@ def main():
         print(json.dumps({"copy_calib_bytes_each_way": 4 * n, "launches": 3}))
         return
     if args.surrogate_only:
-        print(json.dumps({"surrogate": run_surrogate(sur_scns, args.surrogate_weights)}),
+        print(json.dumps({"surrogate": run_surrogate(sur_scns, args.surrogate_weights,
+                                                         scns_b=sur_scns_b)}),
               flush=True)
         return
     if args.hex_only:
@@ -819,7 +863,8 @@ def main():
         if len(sweep_recs) < len(sweep_scns):
             sweep_recs = None
     batched = run_sweep(sweep_scns, not args.no_autotune, sweep_recs) if sweep_scns else None
-    surrogate = run_surrogate(sur_scns, args.surrogate_weights) if sur_scns else None
+    surrogate = run_surrogate(sur_scns, args.surrogate_weights, scns_b=sur_scns_b) \
+        if sur_scns else None
     hexleg = run_hex(args) if args.hex else None
     cpu = None
     if not args.no_cpu:

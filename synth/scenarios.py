@@ -199,10 +199,14 @@ def sweep_params(j):
                 q0=q0, sigma=sigma, pos=pos, mesh_seed=mesh_seed)
 
 
-def sweep_scenario(j):
-    """Planning-sweep scenario j: seeded ellipsoid, TD properties, 300 s."""
+def sweep_scenario(j, mesh_variant=1):
+    """Planning-sweep scenario j: seeded ellipsoid, TD properties, 300 s.
+
+    mesh_variant picks the seed of the node jitter only: two variants of one
+    scenario share every parameter, the lattice, the kept elements and the
+    (unjittered) surface, and differ in where the interior nodes sit."""
     p = sweep_params(j)
-    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 4, j, 1]))
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 4, j, int(mesh_variant)]))
     xyz, tets, bnd = _mesh.jittered_ellipsoid(p["axes"], p["h"], rng)
     mat = td_materials(k0=p["k0"], w_b=p["omega_b"] * 1000.0)
     src = np.array([[p["pos"][0], p["pos"][1], p["pos"][2], p["sigma"],
