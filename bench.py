@@ -695,6 +695,54 @@ def run_surrogate(scns, weights, net_batch=16, check_batch=64, scns_b=None):
             "train_TFLOPs": round(3 * ff_flops * 12 * 8 / t_tr / 1e12, 1)}
 
 
+def run_network_only(steps, batch=8, grid=64):
+    """Only the surrogate network's kernels, for profiling them: `steps`
+    forward passes and `steps` training steps (loss, backward, Adam) at
+    `batch` samples of the held-out sweep's parameters (no FED-FEM run;
+    target zero, unit weights).  Prints the network's TFLOP/s."""
+    import numpy as np
+    import torch
+    from paper_1909_05098_amd import surrogate as sg
+    from paper_1909_05098_amd import surrogate_pipeline as pl
+    from synth import scenarios as sc
+    G = grid
+    fr = pl.frame(G)
+    rows = []
+    for j in range(10000, 10000 + batch):
+        p = sc.sweep_params(j)
+        rows.append([*p["pos"], p["sigma"], p["q0"], p["k0"], p["omega_b"], *p["axes"],
+                     p["h"], 0.0])
+    samples = torch.tensor(np.array(rows), device="cuda")
+    phys = pl.phys_of(sc.td_materials())
+    stream = torch.cuda.current_stream().cuda_stream
+    ws = pl.Workspace(batch, G)
+    sg.rasterize(G, fr, samples, phys, ws.X, ws.prior, ws.scale, stream)
+    ws.target.zero_()
+    ws.maskf.fill_(1.0)
+    net = sg.Net(G, batch, seed=3)
+    net.set_stream(stream)
+    net.forward(ws.X, ws.Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(ws.X, ws.Y)
+    torch.cuda.synchronize()
+    t_f = (time.perf_counter() - t0) / steps
+    net.loss_backward(ws.X, ws.target, ws.maskf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.loss_backward(ws.X, ws.target, ws.maskf)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    t_t = (time.perf_counter() - t0) / steps
+    net.close()
+    f = forward_flops(G) * batch
+    return {"batch": batch, "grid": G, "forward_ms": round(t_f * 1e3, 3),
+            "forward_TFLOPs": round(f / t_f / 1e12, 1),
+            "train_step_ms": round(t_t * 1e3, 3), "train_TFLOPs": round(3 * f / t_t / 1e12, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -721,6 +769,9 @@ def main():
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate leg and print its result (for profiling "
                          "its kernels); not a benchmark line")
+    ap.add_argument("--network-only", type=int, default=0,
+                    help="run only the surrogate network's forward and training kernels "
+                         "this many times each (for profiling them); not a benchmark line")
     ap.add_argument("--dose", type=int, default=1,
                     help="also time config 3 with the CEM43 dose (0 to skip)")
     ap.add_argument("--other-order", type=int, default=1,
@@ -749,13 +800,14 @@ def main():
 
     import numpy as np
     sweep_scns = None
-    if args.sweep and not args.copy_calib_gib and not args.surrogate_only and not args.hex_only:
+    if args.sweep and not (args.copy_calib_gib or args.surrogate_only or args.hex_only
+                           or args.network_only):
         t0 = time.perf_counter()
         sweep_scns = gen_sweep(range(args.sweep), min(16, os.cpu_count() or 1))
         log(f"sweep meshes: {len(sweep_scns)} scenarios "
             f"({sum(s.n_tets for s in sweep_scns)} tets, {time.perf_counter() - t0:.1f} s)")
     sur_scns = sur_scns_b = None
-    if args.surrogate and not args.copy_calib_gib and not args.hex_only:
+    if args.surrogate and not args.copy_calib_gib and not args.hex_only and not args.network_only:
         t0 = time.perf_counter()
         sur_scns = gen_sweep(range(10000, 10000 + args.surrogate), min(16, os.cpu_count() or 1))
         sur_scns_b = gen_sweep(range(10000, 10000 + args.surrogate),
@@ -773,6 +825,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_each_way": 4 * n, "launches": 3}))
+        return
+    if args.network_only:
+        print(json.dumps({"network": run_network_only(args.network_only)}), flush=True)
         return
     if args.surrogate_only:
         print(json.dumps({"surrogate": run_surrogate(sur_scns, args.surrogate_weights,
