@@ -298,148 +298,194 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
         }
 }
 
-// Double-buffered form of the LDS-staged convolution for larger grids.  A
-// workgroup of 8 waves owns a 512-voxel brick (16 x 8 x 4) and keeps two
-// halo buffers of 69 KB, so the next 32 channels are loaded while the
-// current ones are multiplied: their loads go out every third offset of the
-// offset loop, and land in the other buffer after it.  Each voxel's sum is
-// accumulated in the same order as in k_conv_lds (chunks, then offsets, one
-// MFMA over 32 channels each), so the two kernels give identical outputs.
-constexpr int kDbBX = 16, kDbBY = 8, kDbBZ = 4;
-constexpr int kDbH = (kDbBX + 2) * (kDbBY + 2) * (kDbBZ + 2);  // 1080 halo voxels
-constexpr int64_t kDbMinBlocks = 512;  // fewer bricks than this: k_conv_lds
+// LDS-staged convolution with the weights in LDS too.  A workgroup of 4
+// waves owns a brick of 16 x 4 x 4 voxels (wave w: z plane w, four 16-voxel
+// rows as its M tiles) and 32 output channels (blockIdx.y).  For each chunk
+// of 32 input channels the brick's halo (18 x 6 x 6 voxels, four planes of
+// 16-byte channel groups) is staged once, and the chunk's weights are staged
+// one dz plane of offsets at a time (9 offsets x 32 channels x 32 outputs,
+// as planes of 8-channel groups so that 16 lanes read 256 contiguous bytes)
+// into a double buffer: the next plane's (and, in the last plane, the next
+// chunk's halo) loads are in flight while the current one is multiplied.
+// Every wave thus reads both operands from LDS, and the workgroup fetches
+// each weight from memory once instead of once per wave.  78 KB of LDS, so
+// two workgroups share a CU.  Workgroups are dealt to the 8 XCDs round-robin;
+// the grid is one-dimensional and each XCD walks one contiguous stretch of
+// bricks (x fastest), all output-channel blocks of a brick in a row, so a
+// brick's halo, restaged for every channel block, and the halo it shares
+// with the previous brick are mostly found in that XCD's L2.  Each voxel's
+// sum is accumulated in the order of k_conv_lds (chunks, then offsets, one
+// MFMA over 32 channels each): the two kernels give identical outputs.
+constexpr int kWBX = 16, kWBY = 4, kWBZ = 4;
+constexpr int kWHX = kWBX + 2, kWHY = kWBY + 2;
+constexpr int kWH = (kWBX + 2) * (kWBY + 2) * (kWBZ + 2);  // 648 halo voxels
+constexpr int kWHalo = (kWH + 15) / 16 * 64;              // staged 16-byte loads
+constexpr int kWSPT = (kWHalo + 255) / 256;               // per thread: 11
+constexpr int kWWts = 9 * 4 * 32;                         // one dz plane of weights
+constexpr int kWWPT = (kWWts + 255) / 256;                // per thread: 5
 
-template <int NT>
-__global__ void __launch_bounds__(512) k_conv_db(ConvArgs a) {
-    constexpr int HX = kDbBX + 2, HY = kDbBY + 2, H = kDbH;
-    constexpr int SPT = ((H + 15) / 16 * 64 + 511) / 512;  // staged loads per thread
-    static_assert(SPT <= 9, "one staged load every third offset");
-    __shared__ bf16x8 halo[2][4][H];
+__global__ void __launch_bounds__(256) k_conv_w(ConvArgs a) {
+    __shared__ bf16x8 halo[4][kWH];
+    __shared__ bf16x8 wl[2][9][4][32];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int G = a.G;
-    const int nbx = G / kDbBX, nby = G / kDbBY, nbz = G / kDbBZ;
-    const int64_t id = blockIdx.x;
+    const int nbx = G / kWBX, nby = G / kWBY, nbz = G / kWBZ;
+    // brick count a multiple of 8 (the launcher checks): XCD blockIdx % 8
+    // takes bricks [xcd nb / 8, (xcd + 1) nb / 8)
+    const int ncb = (a.cout + 31) / 32;
+    const int64_t nb = a.V / (kWBX * kWBY * kWBZ);
+    const int64_t j = blockIdx.x / 8;
+    const int64_t id = (blockIdx.x % 8) * (nb / 8) + j / ncb;
     const int bx = (int)(id % nbx), by = (int)((id / nbx) % nby),
               bz = (int)((id / ((int64_t)nbx * nby)) % nbz);
     const int64_t bs = id / ((int64_t)nbx * nby * nbz);
-    const int x0 = bx * kDbBX, y0 = by * kDbBY, z0 = bz * kDbBZ;
-    const int n0 = blockIdx.y * (16 * NT);  // this workgroup's output channels
-    // this lane's four voxels (rows lane % 16 of the wave's four M tiles)
+    const int x0 = bx * kWBX, y0 = by * kWBY, z0 = bz * kWBZ;
+    const int n0 = (int)(j % ncb) * 32;
+    const int kg = lane >> 4, lc = lane & 15;
+    // this lane's four voxels: row mt of plane `wave`, column lc
     int hv[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; mt++) {
-        const int li = wave * 64 + mt * 16 + (lane & 15);
-        const int lx = li % kDbBX, ly = (li / kDbBX) % kDbBY, lz = li / (kDbBX * kDbBY);
-        hv[mt] = ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1);  // halo index of offset 0
-    }
-    // staged load u of the chunk at channel c0: 64 consecutive threads take
+    for (int mt = 0; mt < 4; mt++) hv[mt] = ((wave + 1) * kWHY + (mt + 1)) * kWHX + (lc + 1);
+    // halo load u of the chunk at channel c0: 64 consecutive threads take
     // 16 consecutive halo voxels x 4 channel groups; lanes past the halo
     // redo its last voxel, lanes outside the grid load a clamped voxel and
     // store zeros
-    auto stage_at = [&](int u, int& h, int& grp, unsigned& keep) -> int64_t {
-        const int q = t + u * 512;
-        h = min((q >> 6) * 16 + (q & 15), H - 1);
+    auto halo_at = [&](int u, int& h, int& grp, unsigned& keep) -> int64_t {
+        const int q = t + u * 256;
+        h = min((q >> 6) * 16 + (q & 15), kWH - 1);
         grp = (q >> 4) & 3;
-        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        const int hx = h % kWHX, hy = (h / kWHX) % kWHY, hz = h / (kWHX * kWHY);
         const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
         keep = (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) ? ~0u : 0u;
         const int xc = min(max(x, 0), G - 1), yc = min(max(y, 0), G - 1),
                   zc = min(max(z, 0), G - 1);
         return ((bs * G + zc) * G + yc) * G + xc;
     };
-    auto stage_load = [&](int c0, int u) -> uint4 {
+    auto halo_load = [&](int c0, int u) -> uint4 {
         int h, grp;
         unsigned keep;
-        const int64_t gv = stage_at(u, h, grp, keep);
+        const int64_t gv = halo_at(u, h, grp, keep);
         return *reinterpret_cast<const uint4*>(a.in + gv * a.ip + a.io + c0 + grp * 8);
     };
-    auto stage_store = [&](int buf, int u, uint4 v) {
+    auto halo_store = [&](int u, uint4 v) {
         int h, grp;
         unsigned keep;
-        (void)stage_at(u, h, grp, keep);
+        (void)halo_at(u, h, grp, keep);
         v.x &= keep;
         v.y &= keep;
         v.z &= keep;
         v.w &= keep;
-        *reinterpret_cast<uint4*>(&halo[buf][grp][h]) = v;
+        *reinterpret_cast<uint4*>(&halo[grp][h]) = v;
     };
-    f32x4 acc[4][NT];
+    // weight load u of dz plane `pl` of the chunk at c0: element r holds
+    // offset pl * 9 + r / 128, channel group (r / 32) % 4, output r % 32
+    // (columns past cout read row cout - 1: they only feed outputs that are
+    // never stored; lanes past the plane redo its last element)
+    auto wts_load = [&](int c0, int pl, int u) -> uint4 {
+        const int r = min(t + u * 256, kWWts - 1);
+        const int off = pl * 9 + r / 128, grp = (r >> 5) & 3;
+        const int co = min(n0 + (r & 31), a.cout - 1);
+        return *reinterpret_cast<const uint4*>(a.w + (int64_t)co * a.kp + off * a.cin + c0 +
+                                               grp * 8);
+    };
+    auto wts_store = [&](int buf, int u, uint4 v) {
+        const int r = min(t + u * 256, kWWts - 1);
+        *reinterpret_cast<uint4*>(&wl[buf][r / 128][(r >> 5) & 3][r & 31]) = v;
+    };
+    f32x4 acc[4][2];
 #pragma unroll
     for (int mt = 0; mt < 4; mt++)
 #pragma unroll
-        for (int nt = 0; nt < NT; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int kg = (lane >> 4) * 8;
-    auto loadB = [&](int c0, int off, bf16x8 (&B)[NT]) {
-        const int k = off * a.cin + c0 + kg;
-#pragma unroll
-        for (int nt = 0; nt < NT; nt++) {
-            // columns past cout read row cout - 1: they only feed outputs
-            // that are never stored
-            const int co = min(n0 + nt * 16 + (lane & 15), a.cout - 1);
-            B[nt] = *reinterpret_cast<const bf16x8*>(a.w + (int64_t)co * a.kp + k);
-        }
-    };
-    auto loadA = [&](int buf, int off, bf16x8 (&A)[4]) {
+        for (int nt = 0; nt < 2; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto loadA = [&](int off, bf16x8 (&A)[4]) {
         const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
-        const int dh = (dz * HY + dy) * HX + dx;
+        const int dh = (dz * kWHY + dy) * kWHX + dx;
 #pragma unroll
-        for (int mt = 0; mt < 4; mt++) A[mt] = halo[buf][lane >> 4][hv[mt] + dh];
+        for (int mt = 0; mt < 4; mt++) A[mt] = halo[kg][hv[mt] + dh];
     };
-    uint4 sv[SPT];
+    auto loadB = [&](int buf, int ol, bf16x8 (&B)[2]) {
 #pragma unroll
-    for (int u = 0; u < SPT; u++) sv[u] = stage_load(0, u);
+        for (int nt = 0; nt < 2; nt++) B[nt] = wl[buf][ol][kg][nt * 16 + lc];
+    };
+    uint4 hr[kWSPT], wr[kWWPT];
 #pragma unroll
-    for (int u = 0; u < SPT; u++) stage_store(0, u, sv[u]);
+    for (int u = 0; u < kWSPT; u++) hr[u] = halo_load(0, u);
+#pragma unroll
+    for (int u = 0; u < kWWPT; u++) wr[u] = wts_load(0, 0, u);
+#pragma unroll
+    for (int u = 0; u < kWSPT; u++) halo_store(u, hr[u]);
+#pragma unroll
+    for (int u = 0; u < kWWPT; u++) wts_store(0, u, wr[u]);
     __syncthreads();
     const int nch = a.cin / 32;
-    bf16x8 Bq[3][NT];
+    int buf = 0;
     for (int c = 0; c < nch; c++) {
-        const int cur = c & 1, c0 = c * 32;
+        const int c0 = c * 32;
         const bool more = c + 1 < nch;
-        loadB(c0, 0, Bq[0]);
-        loadB(c0, 1, Bq[1]);
-        bf16x8 A[4];
-        loadA(cur, 0, A);
+        for (int pl = 0; pl < 3; pl++) {
+            // the next plane of weights (this chunk's, or the next chunk's
+            // first) and, in the last plane, the next chunk's halo
+            const bool next_w = pl < 2 || more;
+            if (next_w) {
+                const int nc0 = pl < 2 ? c0 : c0 + 32, npl = pl < 2 ? pl + 1 : 0;
 #pragma unroll
-        for (int off = 0; off < 27; off++) {
-            if (more && off % 3 == 0 && off / 3 < SPT) sv[off / 3] = stage_load(c0 + 32, off / 3);
-            if (off + 2 < 27) loadB(c0, off + 2, Bq[(off + 2) % 3]);
-            bf16x8 An[4];
-            if (off + 1 < 27) loadA(cur, off + 1, An);
-            // the loads stay here; the scheduler would otherwise move them
-            // next to their first use
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int mt = 0; mt < 4; mt++)
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bq[off % 3][nt],
-                                                                          acc[mt][nt], 0, 0, 0);
-            if (off + 1 < 27) {
-#pragma unroll
-                for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
+                for (int u = 0; u < kWWPT; u++) wr[u] = wts_load(nc0, npl, u);
             }
-        }
-        if (more) {
+            if (pl == 2 && more) {
 #pragma unroll
-            for (int u = 0; u < SPT; u++) stage_store(cur ^ 1, u, sv[u]);
+                for (int u = 0; u < kWSPT; u++) hr[u] = halo_load(c0 + 32, u);
+            }
+            bf16x8 A[4], B[2];
+            loadA(pl * 9, A);
+            loadB(buf, 0, B);
+#pragma unroll
+            for (int ol = 0; ol < 9; ol++) {
+                bf16x8 An[4], Bn[2];
+                if (ol + 1 < 9) {
+                    loadA(pl * 9 + ol + 1, An);
+                    loadB(buf, ol + 1, Bn);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                    for (int nt = 0; nt < 2; nt++)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt],
+                                                                              acc[mt][nt], 0, 0, 0);
+                if (ol + 1 < 9) {
+#pragma unroll
+                    for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
+#pragma unroll
+                    for (int nt = 0; nt < 2; nt++) B[nt] = Bn[nt];
+                }
+            }
+            // the other weight buffer was last read in the previous plane,
+            // which every wave has finished
+            if (next_w) {
+#pragma unroll
+                for (int u = 0; u < kWWPT; u++) wts_store(buf ^ 1, u, wr[u]);
+            }
+            if (pl == 2 && more) {
+                __syncthreads();  // no wave still reads this chunk's halo
+#pragma unroll
+                for (int u = 0; u < kWSPT; u++) halo_store(u, hr[u]);
+            }
+            __syncthreads();
+            buf ^= 1;
         }
-        // the next chunk is in place, and no wave still reads this one
-        __syncthreads();
     }
     // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
 #pragma unroll
     for (int mt = 0; mt < 4; mt++)
 #pragma unroll
-        for (int nt = 0; nt < NT; nt++) {
-            const int co = n0 + nt * 16 + (lane & 15);
+        for (int nt = 0; nt < 2; nt++) {
+            const int co = n0 + nt * 16 + lc;
             if (co >= a.cout) continue;
             const float bias = a.bias ? a.bias[co] : 0.0f;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const int li = wave * 64 + mt * 16 + (lane >> 4) * 4 + i;
-                const int lx = li % kDbBX, ly = (li / kDbBX) % kDbBY, lz = li / (kDbBX * kDbBY);
-                const int64_t v = ((bs * G + z0 + lz) * G + y0 + ly) * G + x0 + lx;
+                const int lx = kg * 4 + i;  // rows of the 16-voxel M tile
+                const int64_t v = ((bs * G + z0 + wave) * G + y0 + mt) * G + x0 + lx;
                 float val = acc[mt][nt][i] + bias;
                 if (a.relu) val = fmaxf(val, 0.0f);
                 a.out[v * a.op + a.oo + co] = (bf16)val;
@@ -449,19 +495,12 @@ __global__ void __launch_bounds__(512) k_conv_db(ConvArgs a) {
 
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
-    if (a.ks == 3 && a.cin % 32 == 0 && G >= 16 && (G & (G - 1)) == 0) {
-        // 512-voxel bricks, double-buffered, when there are enough of them;
-        // at most 32 output channels per workgroup (wider tiles spill
-        // registers there), so wider layers take several
-        const int64_t G3 = (int64_t)G * G * G;
-        const int64_t nblk = a.V / G3 * (G3 / (kDbBX * kDbBY * kDbBZ));
-        if (nblk >= kDbMinBlocks) {
-            if (a.cout <= 16)
-                hipLaunchKernelGGL(k_conv_db<1>, dim3((unsigned)nblk, 1), dim3(512), 0, s, a);
-            else
-                hipLaunchKernelGGL(k_conv_db<2>,
-                                   dim3((unsigned)nblk, (unsigned)((a.cout + 31) / 32)),
-                                   dim3(512), 0, s, a);
+    if (a.ks == 3 && a.cin % 32 == 0 && G % 16 == 0) {
+        // 16 x 4 x 4 bricks; their count, B (G / 16)^3 16, is a multiple of 8
+        const int64_t nb = a.V / (kWBX * kWBY * kWBZ);
+        const int64_t ncb = (a.cout + 31) / 32;
+        if (nb % 8 == 0 && nb * ncb <= INT32_MAX) {
+            hipLaunchKernelGGL(k_conv_w, dim3((unsigned)(nb * ncb)), dim3(256), 0, s, a);
             return hipGetLastError();
         }
     }

@@ -99,9 +99,10 @@ def test_forward_layers_and_network(torch_cuda):
 
 
 def test_conv_layers_on_64_grid(torch_cuda):
-    """At 64^3 the layers with at most 32 output channels run on 512-voxel
-    bricks with a double-buffered halo; each such layer, fed the GPU's own
-    input, must match the FP64 reference to BF16 rounding."""
+    """At 64^3 the 32-output-channel layers run on 16 x 4 x 4 bricks with the
+    weights staged in LDS and the bricks striped over the XCDs; each such
+    layer, fed the GPU's own input, must match the FP64 reference to BF16
+    rounding."""
     torch = torch_cuda
     G, B = 64, 1
     rng, net, Q, x, X = setup(torch, G, B, 2)
@@ -433,11 +434,11 @@ def test_output_independent_of_batch_and_stream(torch_cuda):
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
-def test_wide_layers_same_on_both_convolution_kernels(torch_cuda):
-    """At 32^3 a batch of 64 puts the 16^3 layers (64 output channels) on the
-    double-buffered 512-voxel-brick kernel, a batch of 8 keeps them on the
-    256-voxel one; both add each voxel's terms in the same order, so every
-    sample's output must be bit-identical."""
+def test_wide_layers_same_at_batch_8_and_64(torch_cuda):
+    """At 32^3 a batch of 64 gives every layer eight times the workgroups of
+    a batch of 8 (and the XCD-striped brick order a different deal); each
+    voxel's terms are still added in the same order, so every sample's
+    output must be bit-identical."""
     torch = torch_cuda
     from paper_1909_05098_amd import surrogate_pipeline as pl
     G, S = 32, 64
