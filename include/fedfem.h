@@ -406,9 +406,12 @@ int fedfem_write_state(fedfem_handle *h, const void *buf, double t,
 int fedfem_get_info(const fedfem_handle *h, fedfem_info *info);
 
 /*
- * Profiling aid: advance n_steps exactly as fedfem_step does, but launch
- * each kernel separately with HIP events around it, and return the mean
- * duration [ms] of the element-load kernel and of the node-update kernel.
+ * Profiling aid: the mean duration [ms] of the element-load kernel and of
+ * the node-update kernel of one step, each launched n_steps times back to
+ * back between two HIP events on the handle's stream, every launch from the
+ * current state (the element pass rewrites the tile partials, the node pass
+ * the other ping-pong buffer, and a thermal dose goes to a staging buffer).
+ * The state, the clock, the step count and the dose do not change.
  * FEDFEM_E_STATE while a source schedule is set (the amplitudes are applied
  * per graph chunk by fedfem_step only).
  */

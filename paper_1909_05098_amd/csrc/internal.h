@@ -57,10 +57,14 @@ bool build_tiles(Layout& L, int tile_elems, int max_tile_nodes,
                  std::string& err);
 
 // Tiles of at most kPackedMaxNodes nodes store their local corner ids in 10
-// bits each, 5 bytes per element instead of 8: an array of E 32-bit words
-// (ids 0, 1, 2 and the low 2 bits of id 3 at bits 0, 10, 20, 30) followed by
-// an array of E bytes (the high 8 bits of id 3).  pack_lconn fills
-// L.lconn_pk when the layout qualifies and clears it otherwise.
+// bits each.  Tetrahedra: 5 bytes per element instead of 8, an array of E
+// 32-bit words (ids 0, 1, 2 and the low 2 bits of id 3 at bits 0, 10, 20,
+// 30) followed by an array of E bytes (the high 8 bits of id 3).
+// Hexahedra: 10 bytes instead of 16, an array of E 64-bit words (ids 0..5
+// at bits 0, 10, ..., 50 and the low 4 bits of id 6 at bit 60) followed by
+// an array of E 16-bit words (the high 6 bits of id 6, then id 7 at bit 6).
+// pack_lconn fills L.lconn_pk when the layout qualifies and clears it
+// otherwise.
 constexpr int kPackedMaxNodes = 1024;
 void pack_lconn(Layout& L);
 

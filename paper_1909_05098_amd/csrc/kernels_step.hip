@@ -340,7 +340,8 @@ k_elem_loads(TileArgs a, const Real* __restrict__ coef, const void* __restrict__
 // the differences formed as (hi_b - hi_0) + (lo_b - lo_0) (each component of
 // xi sums to zero over the corners, so T_0 drops out of t).  k_e is the mean
 // over the eight corners (Eq 13).  Tiles, staging, fixed-point assembly and
-// partials are those of the tetrahedral pass; local corner ids are 8 x u16.
+// partials are those of the tetrahedral pass; local corner ids are 8 x 10
+// bits (tiles of at most 1024 nodes) or 8 x u16.
 template <typename Real, bool COMP, bool TD, int R>
 __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
                                               const Real* __restrict__ coef,
@@ -359,17 +360,28 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
     const int p0 = a.tile_node_off[t];
     const int m = a.tile_node_off[t + 1] - p0;
 
-    // 1. coefficient and local-connectivity loads in flight during staging
+    // 1. coefficient and local-connectivity loads in flight during staging:
+    // eight 10-bit ids as a 64-bit word and a 16-bit word (packed), or eight
+    // u16 as one 16-byte load
     Real sv[R][6];
     uint4 lc[R];
+    const bool pk = a.lconn_pk != 0;
     const uint4* glc = static_cast<const uint4*>(a.lconn) + e0;
+    const unsigned long long* gw = static_cast<const unsigned long long*>(a.lconn) + e0;
+    const uint16_t* gh = reinterpret_cast<const uint16_t*>(
+                             static_cast<const unsigned long long*>(a.lconn) + a.E) + e0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int el = tid + r * bs;
         if (el < ne) {
 #pragma unroll
             for (int k = 0; k < 6; k++) sv[r][k] = stream_load(&coef[k * a.E + e0 + el]);
-            lc[r] = glc[el];
+            if (pk) {
+                const unsigned long long w = gw[el];
+                lc[r] = make_uint4((unsigned)w, (unsigned)(w >> 32), gh[el], 0u);
+            } else {
+                lc[r] = glc[el];
+            }
         }
     }
     // 2. tile nodes
@@ -380,12 +392,21 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
     for (int r = 0; r < R; r++) {
         const int el = tid + r * bs;
         if (el < ne) {
-            const unsigned ww[4] = {lc[r].x, lc[r].y, lc[r].z, lc[r].w};
             int n[8];
+            if (pk) {
+                const unsigned long long w =
+                    (unsigned long long)lc[r].x | ((unsigned long long)lc[r].y << 32);
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                n[2 * q] = (int)(ww[q] & 0xffffu);
-                n[2 * q + 1] = (int)(ww[q] >> 16);
+                for (int q = 0; q < 6; q++) n[q] = (int)((w >> (10 * q)) & 1023u);
+                n[6] = (int)((w >> 60) | ((lc[r].z & 63u) << 4));
+                n[7] = (int)(lc[r].z >> 6);
+            } else {
+                const unsigned ww[4] = {lc[r].x, lc[r].y, lc[r].z, lc[r].w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    n[2 * q] = (int)(ww[q] & 0xffffu);
+                    n[2 * q + 1] = (int)(ww[q] >> 16);
+                }
             }
             Real h0, l0;
             load_T<COMP>(s_T, n[0], h0, l0);

@@ -236,8 +236,25 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
 
 void pack_lconn(Layout& L) {
     std::vector<uint8_t>().swap(L.lconn_pk);
-    if (L.npe != 4 || L.max_tile_nodes > kPackedMaxNodes) return;
+    if ((L.npe != 4 && L.npe != 8) || L.max_tile_nodes > kPackedMaxNodes) return;
     const int64_t E = L.E;
+    if (L.npe == 8) {
+        L.lconn_pk.resize(10 * E);
+        uint8_t* words = L.lconn_pk.data();
+        uint8_t* high = words + 8 * E;
+        parallel_for(E, [&](int64_t a, int64_t b) {
+            for (int64_t e = a; e < b; e++) {
+                const uint16_t* c = &L.lconn[8 * e];
+                uint64_t w = 0;
+                for (int k = 0; k < 6; k++) w |= uint64_t(c[k]) << (10 * k);
+                w |= uint64_t(c[6] & 15) << 60;
+                const uint16_t hw = uint16_t((c[6] >> 4) | (c[7] << 6));
+                std::memcpy(words + 8 * e, &w, 8);
+                std::memcpy(high + 2 * e, &hw, 2);
+            }
+        }, 65536);
+        return;
+    }
     L.lconn_pk.resize(5 * E);
     uint8_t* words = L.lconn_pk.data();
     uint8_t* high = words + 4 * E;

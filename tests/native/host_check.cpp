@@ -79,6 +79,22 @@ Mesh kuhn_box(int nx, int ny, int nz, double h, uint64_t seed) {
     return m;
 }
 
+// nx * ny * nz cubes of edge h as eight-node hexahedra (bottom face
+// counter-clockwise, then the top face), interior nodes jittered as above.
+Mesh hex_box(int nx, int ny, int nz, double h, uint64_t seed) {
+    Mesh m = kuhn_box(nx, ny, nz, h, seed);
+    auto id = [&](int i, int j, int k) { return (int32_t)((k * (ny + 1) + j) * (nx + 1) + i); };
+    m.tets.clear();
+    const int cc[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
+                          {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++)
+                for (const auto& c : cc) m.tets.push_back(id(i + c[0], j + c[1], k + c[2]));
+    m.E = (int64_t)m.tets.size() / 8;
+    return m;
+}
+
 // m tetrahedra (0, a_i, b_i, c_i) sharing node 0, each with its own base
 // triangle (they overlap; the layout does not need a conforming mesh).
 Mesh fan(int m) {
@@ -151,7 +167,21 @@ bool check_layout(const Layout& L, const std::string& name) {
             if (k > L.ec_off[i] && L.ec[k - 1] >= L.ec[k]) return bad("ec order");
         }
     // packed ids decode to lconn
-    if (!L.lconn_pk.empty()) {
+    if (!L.lconn_pk.empty() && npe == 8) {
+        if ((int64_t)L.lconn_pk.size() != 10 * L.E) return bad("packed hexahedral size");
+        for (int64_t e = 0; e < L.E; e++) {
+            uint64_t w;
+            uint16_t hw;
+            std::memcpy(&w, &L.lconn_pk[8 * e], 8);
+            std::memcpy(&hw, &L.lconn_pk[8 * L.E + 2 * e], 2);
+            int ids[8];
+            for (int c = 0; c < 6; c++) ids[c] = (int)(w >> (10 * c) & 1023);
+            ids[6] = (int)(w >> 60) | (hw & 63) << 4;
+            ids[7] = hw >> 6;
+            for (int c = 0; c < 8; c++)
+                if (ids[c] != L.lconn[8 * e + c]) return bad("packed hexahedral ids");
+        }
+    } else if (!L.lconn_pk.empty()) {
         for (int64_t e = 0; e < L.E; e++) {
             uint32_t w;
             std::memcpy(&w, &L.lconn_pk[4 * e], 4);
@@ -231,6 +261,24 @@ int main() {
     }
     // an interior lattice node has 24 tetrahedra: no tile can see more
     if (kuhn_valence > 24) fail("Kuhn lattice tile valence above 24");
+    // hexahedra: packed 10-bit ids when a tile has at most 1024 nodes, u16
+    // otherwise
+    for (const int tile : {256, 512, 1024}) {
+        const Mesh hb = hex_box(22, 18, 14, 1e-3, 7);
+        Layout L;
+        std::string err;
+        if (!build_layout(hb.xyz.data(), hb.tets.data(), 8, hb.N, hb.E, 1, tile, 2 * tile, L,
+                          err)) {
+            fail("hex box: " + err);
+            continue;
+        }
+        pack_lconn(L);
+        check_layout(L, "hex box " + std::to_string(tile));
+        if (L.lconn_pk.empty() != (L.max_tile_nodes > kPackedMaxNodes))
+            fail("hex box: packed form chosen wrongly");
+        if (L.max_tile_valence > 8) fail("hex box: tile valence above 8");
+    }
+    std::printf("hexahedral layouts: ok\n");
     std::printf("serial layouts: %zu cases ok (largest tile valence %d)\n", cases.size(),
                 kuhn_valence);
     // 3. the same layouts from the worker pool, several times each, with the

@@ -327,3 +327,27 @@ def test_config2_fp32c_fp64_vs_oracle():
     print_case("config2 fp32c", e32, f"vs fp64 gpu {e32_64:.3e}")
     assert e64 <= 1e-9
     assert e32 <= 1e-3
+
+
+def test_time_kernels_leaves_state_clock_and_dose():
+    """fedfem_time_kernels times each pass from the current state without
+    advancing it: the temperatures, clock and dose are unchanged, and the
+    run continues bit for bit as if it had not been called."""
+    xyz, tets, bnd = jittered_box(9, 8, 7, 1e-3, seed=31)
+    src = np.full(len(xyz), 2e-3)
+    out = []
+    for timed in (False, True):
+        h = gpu_handle(xyz, tets, sc.td_materials(), bnd, -0.9, ff.FP32C)
+        h.set_dose(ff.DOSE_CEM43)
+        h.step(40, src)
+        if timed:
+            T0, D0, t0 = h.read_T(), h.read_dose(), h.time()
+            e_ms, n_ms = h.time_kernels(7)
+            assert e_ms > 0 and n_ms > 0
+            assert np.array_equal(h.read_T(), T0) and np.array_equal(h.read_dose(), D0)
+            assert h.time() == t0
+        h.step(30)
+        out.append((h.read_T(), h.read_dose(), h.time()))
+        h.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
