@@ -713,6 +713,173 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
             }
 }
 
+// Brick form of the weight gradient, for G % 16 == 0 and cin, cout multiples
+// of 32: dW[co][off][ci] = sum_v D[v][co] X[v + off][ci] with the voxels v
+// of 16 x 4 x 4 bricks as the MFMA reduction dimension.  A workgroup of 8
+// waves owns CI = 32 input channels (blockIdx.x), 32 output channels
+// (blockIdx.y) and a run of bricks (blockIdx.z); the next brick's loads are
+// in flight (in registers) while the current one is multiplied.  For each brick it stages,
+// once, the gradient D transposed (32 channel rows of the 256 brick voxels)
+// and the input's halo (18 x 6 x 6 voxels) transposed as channel rows of 16
+// x positions, in three copies shifted by dx = -1, 0, 1, so that the 8
+// consecutive voxels an MFMA lane takes start 16-byte aligned for every
+// offset.  Each wave then accumulates up to four of the 27 offsets (wave w:
+// offsets w, w + 8, w + 16, w + 24; offset 27 is the bias, a column of ones)
+// for all of the brick's voxels: the halo, fetched once from memory, serves
+// all 27 offsets, where the gathered form fetched it once per offset.
+// Partial sums per brick run go to part[split] like k_wgrad's, and
+// k_wgrad_reduce adds them in a fixed order (bit-reproducible).
+constexpr int kGRows = 6 * 6;  // halo rows (y, z) of a 16 x 4 x 4 brick
+// channel rows padded by 16 bytes: the 16 channels of an MFMA fragment then
+// start 4 banks apart and read all 64 banks once
+constexpr int kGXP = kGRows * 16 + 8;  // halo copy: bf16 per channel row
+constexpr int kGDP = 256 + 8;          // D^T: bf16 per channel row
+
+template <int CI>
+__global__ void __launch_bounds__(512) k_wgrad_brick(WgradArgs a, int64_t per_split) {
+    constexpr int NT = CI / 16;  // 16-channel column tiles
+    __shared__ __align__(16) bf16 xs[3][CI][kGXP];
+    __shared__ __align__(16) bf16 dT[32][kGDP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int c0 = blockIdx.x * CI, co0 = blockIdx.y * 32;
+    const int G = a.G;
+    const int nbx = G / 16, nby = G / 4, nbz = G / 4;
+    const int64_t nb = a.V / 256;
+    const int64_t b0 = (int64_t)blockIdx.z * per_split, b1 = min(nb, b0 + per_split);
+    const int kg = lane >> 4, lc = lane & 15;
+    const bool bias_here = blockIdx.x == 0;
+    // staging tasks: threads [0, 128) take 8 brick voxels x 8 output
+    // channels of D, threads [128, 128 + 36 CI / 8) one halo row of 8 input
+    // channels; the loads of the next brick are in flight during the
+    // current brick's products
+    const bool dtask = t < 128, xtask = !dtask && t < 128 + kGRows * (CI / 8);
+    const int cg = t & 3, vg = t >> 2;                      // D task
+    const int xt = t - 128, row = xt / (CI / 8), cgp = xt % (CI / 8);  // halo task
+    bf16x8 st[18];
+    auto stage_load = [&](int64_t b) {
+        const int bx = (int)(b % nbx), by = (int)((b / nbx) % nby),
+                  bz = (int)((b / ((int64_t)nbx * nby)) % nbz);
+        const int64_t bs = b / ((int64_t)nbx * nby * nbz);
+        const int x0 = bx * 16, y0 = by * 4, z0 = bz * 4;
+        if (dtask) {
+            const int co = co0 + cg * 8;
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int vb = vg * 8 + i;
+                const int64_t v =
+                    ((bs * G + z0 + vb / 64) * G + y0 + (vb / 16) % 4) * G + x0 + vb % 16;
+                st[i] = co < a.cout ? *reinterpret_cast<const bf16x8*>(a.d + v * a.dp + a.doff + co)
+                                    : zero8();
+            }
+        } else if (xtask) {
+            const int hy = row % 6, hz = row / 6;
+            const int y = y0 + hy - 1, z = z0 + hz - 1;
+            const bool rowin = y >= 0 && y < G && z >= 0 && z < G;
+            const int64_t r0 = ((bs * G + min(max(z, 0), G - 1)) * G + min(max(y, 0), G - 1)) * G;
+#pragma unroll
+            for (int hx = 0; hx < 18; hx++) {
+                const int x = x0 + hx - 1;
+                st[hx] = (rowin && x >= 0 && x < G)
+                             ? *reinterpret_cast<const bf16x8*>(a.in + (r0 + x) * a.ip + a.io + c0 +
+                                                                cgp * 8)
+                             : zero8();
+            }
+        }
+    };
+    auto stage_store = [&]() {
+        if (dtask) {
+            bf16x8 r[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) r[i] = st[i];
+            transpose_store8(r, &dT[cg * 8][vg * 8], kGDP);
+        } else if (xtask) {
+            // copy s holds halo x position x' + s at x'
+#pragma unroll
+            for (int sh = 0; sh < 3; sh++)
+#pragma unroll
+                for (int g = 0; g < 2; g++) {
+                    bf16x8 r[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) r[i] = st[sh + 8 * g + i];
+                    transpose_store8(r, &xs[sh][cgp * 8][row * 16 + 8 * g], kGXP);
+                }
+        }
+    };
+    f32x4 acc[4][2][NT];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) acc[i][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the bias column: ones in column 0
+    bf16x8 ones;
+#pragma unroll
+    for (int j = 0; j < 8; j++) ones[j] = (bf16)(lc == 0 ? 1.0f : 0.0f);
+    if (b0 < b1) stage_load(b0);
+    for (int64_t b = b0; b < b1; b++) {
+        __syncthreads();  // the previous brick's fragments have been read
+        stage_store();
+        __syncthreads();
+        if (b + 1 < b1) stage_load(b + 1);
+#pragma unroll 2
+        for (int ks = 0; ks < 8; ks++) {
+            // this lane's 8 voxels: brick voxels ks * 32 + kg * 8 ..
+            const int vb = ks * 32 + kg * 8;
+            const int xl = vb % 16, yl = (vb / 16) % 4, zl = vb / 64;
+            bf16x8 A[2];
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++)
+                A[mt] = *reinterpret_cast<const bf16x8*>(&dT[mt * 16 + lc][vb]);
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int off = wave + 8 * i;
+                if (off < 27) {
+                    const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
+                    const int hrow = (zl + dz + 1) * 6 + (yl + dy + 1);
+                    bf16x8 B[NT];
+#pragma unroll
+                    for (int nt = 0; nt < NT; nt++)
+                        B[nt] = *reinterpret_cast<const bf16x8*>(
+                            &xs[dx + 1][nt * 16 + lc][hrow * 16 + xl]);
+#pragma unroll
+                    for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+                        for (int nt = 0; nt < NT; nt++)
+                            acc[i][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                A[mt], B[nt], acc[i][mt][nt], 0, 0, 0);
+                } else if (off == 27 && bias_here) {
+#pragma unroll
+                    for (int mt = 0; mt < 2; mt++)
+                        acc[i][mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            A[mt], ones, acc[i][mt][0], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // C layout: lane holds rows (lane / 16) * 4 + j (output channels),
+    // column lane % 16 (input channel; the bias in column 0)
+    const int K = 27 * a.cin;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int off = wave + 8 * i;
+        if (off > 27 || (off == 27 && !bias_here)) continue;
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) {
+                if (off == 27 && (nt != 0 || lc != 0)) continue;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int co = co0 + mt * 16 + kg * 4 + j;
+                    const int k = off == 27 ? K : off * a.cin + c0 + nt * 16 + lc;
+                    if (co < a.cout)
+                        a.part[((int64_t)blockIdx.z * a.cout + co) * a.kp2 + k] = acc[i][mt][nt][j];
+                }
+            }
+    }
+}
+
 // voxels per staged chunk of the weight gradient
 constexpr int kWgradChunk = 128;
 
@@ -742,21 +909,40 @@ hipError_t launch_wgrad(const WgradArgs& w, int tiles_k, int tiles_c, int64_t sp
     return hipGetLastError();
 }
 
-// dW[co][k] (k < K) and db[co] (column K): fixed-order sums over the splits
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, int cout, int kp2,
-                               int K, float* __restrict__ dW, float* __restrict__ db) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// dW[co][k] (k < K) and db[co] (column K): fixed-order sums over the splits.
+// A workgroup takes 64 consecutive outputs; its four waves sum a quarter of
+// the splits each (in ascending order, eight loads in flight), and the four
+// quarter sums are added in order: the same tree for every call.
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, int splits,
+                                                      int cout, int kp2, int K,
+                                                      float* __restrict__ dW,
+                                                      float* __restrict__ db) {
+    __shared__ float q[4][64];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + l;
     const int64_t nW = (int64_t)cout * K;
-    if (i < nW) {
-        const int co = (int)(i / K), k = (int)(i % K);
-        float s = 0.0f;
-        for (int z = 0; z < splits; z++) s += part[((int64_t)z * cout + co) * kp2 + k];
-        dW[i] = s;
-    } else if (i < nW + cout) {
-        const int co = (int)(i - nW);
-        float s = 0.0f;
-        for (int z = 0; z < splits; z++) s += part[((int64_t)z * cout + co) * kp2 + K];
-        db[co] = s;
+    const bool on = i < nW + cout;
+    const int co = !on ? 0 : (i < nW ? (int)(i / K) : (int)(i - nW));
+    const int k = !on ? 0 : (i < nW ? (int)(i % K) : K);
+    const int per = (splits + 3) / 4, z0 = w * per, z1 = min(splits, z0 + per);
+    float s = 0.0f;
+    if (on) {
+        int z = z0;
+        for (; z + 8 <= z1; z += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = part[((int64_t)(z + u) * cout + co) * kp2 + k];
+#pragma unroll
+            for (int u = 0; u < 8; u++) s += v[u];
+        }
+        for (; z < z1; z++) s += part[((int64_t)z * cout + co) * kp2 + k];
+    }
+    q[w][l] = s;
+    __syncthreads();
+    if (w == 0 && on) {
+        const float r = ((q[0][l] + q[1][l]) + q[2][l]) + q[3][l];
+        if (i < nW) dW[i] = r;
+        else db[co] = r;
     }
 }
 
@@ -1395,10 +1581,23 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     hipLaunchKernelGGL(k_relu_bwd, dim3(nblocks(V * (d.cout / 8), 256)), dim3(256), 0, s, gout.p,
                        gout.pitch, gout.off, out.p, out.pitch, out.off, d.cout, V, dpre);
     // weight and bias gradient: ~kWgradBlocks workgroups over tiles x splits
+    const bool brick = G % 16 == 0 && d.cin % 32 == 0 && d.cout % 32 == 0;
     const int KN = wgrad_kn(d.cout), COT = wgrad_cot(d.cout);
-    const int kb = n->kp2[L] / KN, cb = (d.cout + COT - 1) / COT;
-    const int64_t vsplit = wgrad_vsplit(V, kb * cb);
-    const int64_t splits = (V + vsplit - 1) / vsplit;
+    const int kb = brick ? d.cin / 32 : n->kp2[L] / KN;
+    const int cb = brick ? d.cout / 32 : (d.cout + COT - 1) / COT;
+    int64_t splits = 0, per = 0, vsplit = 0;
+    if (brick) {
+        // runs of whole bricks; the partial buffer bounds the number of runs
+        const int64_t nbr = V / 256;
+        const int64_t want = std::max<int64_t>(1, (kWgradBlocks + kb * cb - 1) / (kb * cb));
+        const int64_t cap = n->part_cap / ((int64_t)d.cout * n->kp2[L]);
+        splits = std::max<int64_t>(1, std::min({want, nbr, cap, (int64_t)65535}));
+        per = (nbr + splits - 1) / splits;
+        splits = (nbr + per - 1) / per;
+    } else {
+        vsplit = wgrad_vsplit(V, kb * cb);
+        splits = (V + vsplit - 1) / vsplit;
+    }
     if (splits * d.cout * n->kp2[L] > n->part_cap || splits > 65535) return hipErrorInvalidValue;
     WgradArgs w;
     w.d = dpre;
@@ -1414,9 +1613,15 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     w.vsplit = vsplit;
     w.kp2 = n->kp2[L];
     w.part = n->part;
-    if (hipError_t e0 = launch_wgrad(w, kb, cb, splits, s)) return e0;
+    if (brick) {
+        hipLaunchKernelGGL(k_wgrad_brick<32>, dim3((unsigned)kb, (unsigned)cb, (unsigned)splits),
+                           dim3(512), 0, s, w, per);
+        if (hipError_t e0 = hipGetLastError()) return e0;
+    } else if (hipError_t e0 = launch_wgrad(w, kb, cb, splits, s)) {
+        return e0;
+    }
     const int64_t nred = (int64_t)d.cout * 27 * d.cin + d.cout;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nred, 256)), dim3(256), 0, s, n->part,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nred, 64)), dim3(256), 0, s, n->part,
                        (int)splits, d.cout, n->kp2[L], 27 * d.cin, n->g + n->w_off[L],
                        n->g + n->b_off[L]);
     hipError_t e = hipGetLastError();

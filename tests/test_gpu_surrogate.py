@@ -136,9 +136,12 @@ def gpu_cache(net, x, B, q):
     return c
 
 
-def test_loss_and_gradients(torch_cuda):
+@pytest.mark.parametrize("G,B", [(8, 2), (16, 1)])
+def test_loss_and_gradients(torch_cuda, G, B):
+    """At 8^3 every weight gradient takes the gathered kernel; at 16^3 the
+    full-resolution layers with 32-channel inputs (e1b, d1a, d1b) take the
+    brick kernel."""
     torch = torch_cuda
-    G, B = 8, 2
     rng, net, Q, x, X = setup(torch, G, B, 5)
     t = rng.normal(size=(B, G, G, G)).astype(np.float32)
     m = (rng.random((B, G, G, G)) < 0.7).astype(np.float32)
@@ -167,7 +170,18 @@ def test_loss_and_gradients(torch_cuda):
               flush=True)
     print(f"[surrogate] worst: backward-only {max(e_bwd.values()):.3e} "
           f"end-to-end {max(e_e2e.values()):.3e}", flush=True)
-    assert max(e_bwd.values()) <= GRAD_TOL
+    if G == 8:
+        assert max(e_bwd.values()) <= GRAD_TOL
+    else:
+        # the layers the brick kernel differentiates are held to GRAD_TOL;
+        # below them the gradient has passed through more BF16-stored data
+        # gradients, and where an FP32 sum (GPU) and an FP64 sum (reference)
+        # straddle a rounding boundary the stored values differ by one BF16
+        # step, which the layers below carry on: every layer is held to one
+        # BF16 rounding step, 2^-8
+        for k in ("d1b.w", "d1b.b", "d1a.w", "d1a.b", "e1b.w", "e1b.b"):
+            assert e_bwd[k] <= GRAD_TOL, k
+        assert max(e_bwd.values()) <= 2.0 ** -8
     assert max(e_e2e.values()) <= GRAD_TOL_E2E
     # bit-reproducible backward
     net.loss_backward(X, T, M)
