@@ -53,6 +53,8 @@ struct ConvArgs {
     int ip, io, cin;  // input pitch, channel offset, channels (multiple of 8)
     const bf16* w;    // [cout][kp], k = offset * cin + ci, zero beyond 27 cin
     int kp;
+    // the same weights in the brick kernel's order (k_pack_w), or null
+    const uint4* wp;
     const float* bias;  // may be null
     bf16* out;
     int op, oo, cout;   // output pitch, channel offset, channels
@@ -298,209 +300,239 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
         }
 }
 
-// LDS-staged convolution with the weights in LDS too.  A workgroup of 4
-// waves owns a brick of 16 x 4 x 4 voxels (wave w: z plane w, four 16-voxel
-// rows as its M tiles) and 32 output channels (blockIdx.y).  For each chunk
-// of 32 input channels the brick's halo (18 x 6 x 6 voxels, four planes of
-// 16-byte channel groups) is staged once, and the chunk's weights are staged
-// one dz plane of offsets at a time (9 offsets x 32 channels x 32 outputs,
-// as planes of 8-channel groups so that 16 lanes read 256 contiguous bytes)
-// into a double buffer: the next plane's (and, in the last plane, the next
-// chunk's halo) loads are in flight while the current one is multiplied.
-// Every wave thus reads both operands from LDS, and the workgroup fetches
-// each weight from memory once instead of once per wave.  78 KB of LDS, so
-// two workgroups share a CU.  Workgroups are dealt to the 8 XCDs round-robin;
-// the grid is one-dimensional and each XCD walks one contiguous stretch of
-// bricks (x fastest), all output-channel blocks of a brick in a row, so a
-// brick's halo, restaged for every channel block, and the halo it shares
-// with the previous brick are mostly found in that XCD's L2.  Each voxel's
-// sum is accumulated in the order of k_conv_lds (chunks, then offsets, one
-// MFMA over 32 channels each): the two kernels give identical outputs.
-constexpr int kWBX = 16, kWBY = 4, kWBZ = 4;
-constexpr int kWHX = kWBX + 2, kWHY = kWBY + 2;
-constexpr int kWH = (kWBX + 2) * (kWBY + 2) * (kWBZ + 2);  // 648 halo voxels
-constexpr int kWHalo = (kWH + 15) / 16 * 64;              // staged 16-byte loads
-constexpr int kWSPT = (kWHalo + 255) / 256;               // per thread: 11
-constexpr int kWWts = 9 * 4 * 32;                         // one dz plane of weights
-constexpr int kWWPT = (kWWts + 255) / 256;                // per thread: 5
+// LDS-staged convolution with a chunk's whole weight set in LDS, persistent.
+// A workgroup of 8 waves owns, in turn, a run of units: a brick of
+// 16 x 4 x 8 voxels (wave w: z plane w, its four 16-voxel rows the M tiles)
+// times a block of 32 output channels.  For each chunk of 32 input channels
+// the brick's halo (18 x 6 x 10 voxels as four planes of 16-byte channel
+// groups, 69 KB) and the chunk's weights for all 27 offsets (as planes of
+// 8-channel groups so that 16 lanes read 256 contiguous bytes, 55 KB) sit in
+// LDS; the waves run the 27 offsets without a barrier while the next item's
+// halo and, when the chunk or the output block changes, its weights are in
+// flight into registers, stored to LDS between two barriers at the item's
+// end.  A unit's outputs leave through a 4 KB LDS slot per wave, as 16-byte
+// rows of eight outputs.  Within a dz plane the offsets go in three dx groups: output row mt
+// at dy reads halo row mt + dy, so a group reads six halo rows once for all
+// three dy.  156 KB of LDS and two waves per SIMD: one workgroup per CU, 32
+// per XCD.  Workgroups are dealt to the 8 XCDs round-robin; XCD x owns the
+// bricks [x nb / 8, (x + 1) nb / 8) (x fastest) and its units in output-
+// block-major order, each workgroup a contiguous run of them, so a run
+// changes weights rarely and neighbouring bricks' halos meet in the XCD's
+// L2.  Each voxel's sum goes chunk by chunk, offsets in a fixed order, so
+// the result does not depend on the batch or the grid of workgroups.
+constexpr int kPBX = 16, kPBY = 4, kPBZ = 8;
+constexpr int kPHX = kPBX + 2, kPHY = kPBY + 2, kPHZ = kPBZ + 2;
+constexpr int kPH = kPHX * kPHY * kPHZ;        // 1080 halo voxels
+constexpr int kPHalo = (kPH + 15) / 16 * 64;   // staged 16-byte loads
+constexpr int kPSPT = (kPHalo + 511) / 512;    // per thread: 9
+constexpr int kPWts = 27 * 4 * 32;             // a chunk's weights, 16-byte elements
+constexpr int kPWPT = (kPWts + 511) / 512;     // per thread: 7
+constexpr int kPWGPerXcd = 32;
 
-__global__ void __launch_bounds__(256) k_conv_w(ConvArgs a) {
-    __shared__ bf16x8 halo[4][kWH];
-    __shared__ bf16x8 wl[2][9][4][32];
+__global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
+    __shared__ bf16x8 halo[4][kPH];
+    __shared__ bf16x8 wl[27][4][32];
+    __shared__ bf16 ep[8][64 * 32];  // per wave: its 64 voxels x 32 outputs
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int G = a.G;
-    const int nbx = G / kWBX, nby = G / kWBY, nbz = G / kWBZ;
-    // brick count a multiple of 8 (the launcher checks): XCD blockIdx % 8
-    // takes bricks [xcd nb / 8, (xcd + 1) nb / 8)
-    const int ncb = (a.cout + 31) / 32;
-    const int64_t nb = a.V / (kWBX * kWBY * kWBZ);
-    const int64_t j = blockIdx.x / 8;
-    const int64_t id = (blockIdx.x % 8) * (nb / 8) + j / ncb;
-    const int bx = (int)(id % nbx), by = (int)((id / nbx) % nby),
-              bz = (int)((id / ((int64_t)nbx * nby)) % nbz);
-    const int64_t bs = id / ((int64_t)nbx * nby * nbz);
-    const int x0 = bx * kWBX, y0 = by * kWBY, z0 = bz * kWBZ;
-    const int n0 = (int)(j % ncb) * 32;
+    const int nbx = G / kPBX, nby = G / kPBY, nbz = G / kPBZ;
+    const int ncb = (a.cout + 31) / 32, nch = a.cin / 32;
+    // bricks per XCD (the brick count is a multiple of 8) and units per XCD
+    const int bx = (int)(a.V / (kPBX * kPBY * kPBZ) / 8);
+    const int ux = bx * ncb;
+    const int xcd = (int)(blockIdx.x % 8);
+    const int u0 = (int)(blockIdx.x / 8) * per, u1 = min(ux, u0 + per);
+    if (u0 >= u1) return;
     const int kg = lane >> 4, lc = lane & 15;
-    // this lane's four voxels: row mt of plane `wave`, column lc
-    int hv[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; mt++) hv[mt] = ((wave + 1) * kWHY + (mt + 1)) * kWHX + (lc + 1);
-    // halo load u of the chunk at channel c0: 64 consecutive threads take
-    // 16 consecutive halo voxels x 4 channel groups; lanes past the halo
+    struct Unit {
+        int x0, y0, z0, bs, cb;
+    };
+    auto unit = [&](int u) -> Unit {
+        const int cb = u / bx, id = xcd * bx + u % bx;
+        Unit w;
+        w.x0 = __builtin_amdgcn_readfirstlane((id % nbx) * kPBX);
+        w.y0 = __builtin_amdgcn_readfirstlane(((id / nbx) % nby) * kPBY);
+        w.z0 = __builtin_amdgcn_readfirstlane(((id / (nbx * nby)) % nbz) * kPBZ);
+        w.bs = __builtin_amdgcn_readfirstlane(id / (nbx * nby * nbz));
+        w.cb = __builtin_amdgcn_readfirstlane(cb);
+        return w;
+    };
+    // halo load u of a brick's chunk at channel c0: 64 consecutive threads
+    // take 16 consecutive halo voxels x 4 channel groups; lanes past the halo
     // redo its last voxel, lanes outside the grid load a clamped voxel and
     // store zeros
-    auto halo_at = [&](int u, int& h, int& grp, unsigned& keep) -> int64_t {
-        const int q = t + u * 256;
-        h = min((q >> 6) * 16 + (q & 15), kWH - 1);
+    auto halo_at = [&](const Unit& w, int u, int& h, int& grp, unsigned& keep) -> int64_t {
+        const int q = t + u * 512;
+        h = min((q >> 6) * 16 + (q & 15), kPH - 1);
         grp = (q >> 4) & 3;
-        const int hx = h % kWHX, hy = (h / kWHX) % kWHY, hz = h / (kWHX * kWHY);
-        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        const int hx = h % kPHX, hy = (h / kPHX) % kPHY, hz = h / (kPHX * kPHY);
+        const int x = w.x0 + hx - 1, y = w.y0 + hy - 1, z = w.z0 + hz - 1;
         keep = (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) ? ~0u : 0u;
         const int xc = min(max(x, 0), G - 1), yc = min(max(y, 0), G - 1),
                   zc = min(max(z, 0), G - 1);
-        return ((bs * G + zc) * G + yc) * G + xc;
+        return (((int64_t)w.bs * G + zc) * G + yc) * G + xc;
     };
-    auto halo_load = [&](int c0, int u) -> uint4 {
+    auto halo_load = [&](const Unit& w, int c, int u) -> uint4 {
         int h, grp;
         unsigned keep;
-        const int64_t gv = halo_at(u, h, grp, keep);
-        return *reinterpret_cast<const uint4*>(a.in + gv * a.ip + a.io + c0 + grp * 8);
+        const int64_t gv = halo_at(w, u, h, grp, keep);
+        return *reinterpret_cast<const uint4*>(a.in + gv * a.ip + a.io + c * 32 + grp * 8);
     };
-    auto halo_store = [&](int u, uint4 v) {
+    auto halo_store = [&](const Unit& w, int u, uint4 v) {
         int h, grp;
         unsigned keep;
-        (void)halo_at(u, h, grp, keep);
+        (void)halo_at(w, u, h, grp, keep);
         v.x &= keep;
         v.y &= keep;
         v.z &= keep;
         v.w &= keep;
         *reinterpret_cast<uint4*>(&halo[grp][h]) = v;
     };
-    // weight load u of dz plane `pl` of the chunk at c0: element r holds
-    // offset pl * 9 + r / 128, channel group (r / 32) % 4, output r % 32
-    // (columns past cout read row cout - 1: they only feed outputs that are
-    // never stored; lanes past the plane redo its last element)
-    auto wts_load = [&](int c0, int pl, int u) -> uint4 {
-        const int r = min(t + u * 256, kWWts - 1);
-        const int off = pl * 9 + r / 128, grp = (r >> 5) & 3;
-        const int co = min(n0 + (r & 31), a.cout - 1);
-        return *reinterpret_cast<const uint4*>(a.w + (int64_t)co * a.kp + off * a.cin + c0 +
-                                               grp * 8);
+    // weight load u of chunk c for output block cb: element r of the chunk's
+    // 27 x 4 x 32 run in the brick order holds offset r / 128, channel group
+    // (r / 32) % 4, output cb 32 + r % 32 (lanes past the run redo its last
+    // element)
+    auto wts_load = [&](int cb, int c, int u) -> uint4 {
+        const int r = min(t + u * 512, kPWts - 1);
+        return a.wp[(int64_t)(cb * nch + c) * kPWts + r];
     };
-    auto wts_store = [&](int buf, int u, uint4 v) {
-        const int r = min(t + u * 256, kWWts - 1);
-        *reinterpret_cast<uint4*>(&wl[buf][r / 128][(r >> 5) & 3][r & 31]) = v;
+    auto wts_store = [&](int u, uint4 v) {
+        const int r = min(t + u * 512, kPWts - 1);
+        *reinterpret_cast<uint4*>(&wl[r / 128][(r >> 5) & 3][r & 31]) = v;
     };
-    f32x4 acc[4][2];
+    // this lane's halo row 0 (output row -1, column lc) of its plane
+    const int hv0 = (wave + 1) * kPHY * kPHX + lc + 1;
+    // halo rows -1 .. 4 of this lane's plane shifted by (dz, dx) = (pl - 1,
+    // dx - 1): row r serves output row mt at dy index r - mt
+    auto loadA6 = [&](int g, bf16x8 (&A)[6]) {
+        const int dh = (g / 3 - 1) * kPHY * kPHX + g % 3 - 1;
 #pragma unroll
-    for (int mt = 0; mt < 4; mt++)
-#pragma unroll
-        for (int nt = 0; nt < 2; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    auto loadA = [&](int off, bf16x8 (&A)[4]) {
-        const int dz = off / 9 - 1, dy = (off / 3) % 3 - 1, dx = off % 3 - 1;
-        const int dh = (dz * kWHY + dy) * kWHX + dx;
-#pragma unroll
-        for (int mt = 0; mt < 4; mt++) A[mt] = halo[kg][hv[mt] + dh];
+        for (int r = 0; r < 6; r++) A[r] = halo[kg][hv0 + r * kPHX + dh];
     };
-    auto loadB = [&](int buf, int ol, bf16x8 (&B)[2]) {
+    auto loadB = [&](int off, bf16x8 (&B)[2]) {
 #pragma unroll
-        for (int nt = 0; nt < 2; nt++) B[nt] = wl[buf][ol][kg][nt * 16 + lc];
+        for (int nt = 0; nt < 2; nt++) B[nt] = wl[off][kg][nt * 16 + lc];
     };
-    uint4 hr[kWSPT], wr[kWWPT];
+    uint4 hr[kPSPT], wr[kPWPT];
+    {
+        const Unit w = unit(u0);
 #pragma unroll
-    for (int u = 0; u < kWSPT; u++) hr[u] = halo_load(0, u);
+        for (int u = 0; u < kPSPT; u++) hr[u] = halo_load(w, 0, u);
 #pragma unroll
-    for (int u = 0; u < kWWPT; u++) wr[u] = wts_load(0, 0, u);
+        for (int u = 0; u < kPWPT; u++) wr[u] = wts_load(w.cb, 0, u);
 #pragma unroll
-    for (int u = 0; u < kWSPT; u++) halo_store(u, hr[u]);
+        for (int u = 0; u < kPSPT; u++) halo_store(w, u, hr[u]);
 #pragma unroll
-    for (int u = 0; u < kWWPT; u++) wts_store(0, u, wr[u]);
-    __syncthreads();
-    const int nch = a.cin / 32;
-    int buf = 0;
-    for (int c = 0; c < nch; c++) {
-        const int c0 = c * 32;
-        const bool more = c + 1 < nch;
-        for (int pl = 0; pl < 3; pl++) {
-            // the next plane of weights (this chunk's, or the next chunk's
-            // first) and, in the last plane, the next chunk's halo
-            const bool next_w = pl < 2 || more;
-            if (next_w) {
-                const int nc0 = pl < 2 ? c0 : c0 + 32, npl = pl < 2 ? pl + 1 : 0;
-#pragma unroll
-                for (int u = 0; u < kWWPT; u++) wr[u] = wts_load(nc0, npl, u);
-            }
-            if (pl == 2 && more) {
-#pragma unroll
-                for (int u = 0; u < kWSPT; u++) hr[u] = halo_load(c0 + 32, u);
-            }
-            bf16x8 A[4], B[2];
-            loadA(pl * 9, A);
-            loadB(buf, 0, B);
-#pragma unroll
-            for (int ol = 0; ol < 9; ol++) {
-                bf16x8 An[4], Bn[2];
-                if (ol + 1 < 9) {
-                    loadA(pl * 9 + ol + 1, An);
-                    loadB(buf, ol + 1, Bn);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int mt = 0; mt < 4; mt++)
-#pragma unroll
-                    for (int nt = 0; nt < 2; nt++)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt],
-                                                                              acc[mt][nt], 0, 0, 0);
-                if (ol + 1 < 9) {
-#pragma unroll
-                    for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
-#pragma unroll
-                    for (int nt = 0; nt < 2; nt++) B[nt] = Bn[nt];
-                }
-            }
-            // the other weight buffer was last read in the previous plane,
-            // which every wave has finished
-            if (next_w) {
-#pragma unroll
-                for (int u = 0; u < kWWPT; u++) wts_store(buf ^ 1, u, wr[u]);
-            }
-            if (pl == 2 && more) {
-                __syncthreads();  // no wave still reads this chunk's halo
-#pragma unroll
-                for (int u = 0; u < kWSPT; u++) halo_store(u, hr[u]);
-            }
-            __syncthreads();
-            buf ^= 1;
-        }
+        for (int u = 0; u < kPWPT; u++) wts_store(u, wr[u]);
     }
-    // C layout: lane holds rows (lane / 16) * 4 + i, column lane % 16
+    __syncthreads();
+    for (int un = u0; un < u1; un++) {
+        const Unit w = unit(un);
+        const Unit wn = unit(min(un + 1, u1 - 1));
+        f32x4 acc[4][2];
 #pragma unroll
-    for (int mt = 0; mt < 4; mt++)
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < nch; c++) {
+            // the next item: this unit's next chunk, or the next unit's first
+            const bool more = c + 1 < nch, next = more || un + 1 < u1;
+            const Unit& wx = more ? w : wn;
+            const int cx = more ? c + 1 : 0;
+            const bool new_w = next && (nch > 1 || wx.cb != w.cb);
+            if (next) {
+#pragma unroll
+                for (int u = 0; u < kPSPT; u++) hr[u] = halo_load(wx, cx, u);
+            }
+            if (new_w) {
+#pragma unroll
+                for (int u = 0; u < kPWPT; u++) wr[u] = wts_load(wx.cb, cx, u);
+            }
+            // 27 steps: nine (dz, dx) groups of three dy offsets, offset
+            // (dz, dy, dx) being weight row (dz + 1) 9 + (dy + 1) 3 + dx + 1;
+            // a group's six halo rows are read one group ahead, the weights
+            // two steps ahead
+            auto step_off = [](int st) { return st / 9 * 9 + st % 3 * 3 + st / 3 % 3; };
+            bf16x8 A[6], Bq[3][2];
+            loadA6(0, A);
+            loadB(step_off(0), Bq[0]);
+            loadB(step_off(1), Bq[1]);
+#pragma unroll
+            for (int g = 0; g < 9; g++) {
+                bf16x8 An[6];
+#pragma unroll
+                for (int dy = 0; dy < 3; dy++) {
+                    const int st = g * 3 + dy;
+                    if (st + 2 < 27) loadB(step_off(st + 2), Bq[(st + 2) % 3]);
+                    if (dy == 0 && g < 8) loadA6(g + 1, An);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                        for (int nt = 0; nt < 2; nt++)
+                            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                A[mt + dy], Bq[st % 3][nt], acc[mt][nt], 0, 0, 0);
+                }
+                if (g < 8) {
+#pragma unroll
+                    for (int r = 0; r < 6; r++) A[r] = An[r];
+                }
+            }
+            if (next) {
+                __syncthreads();  // no wave still reads this item's halo or weights
+#pragma unroll
+                for (int u = 0; u < kPSPT; u++) halo_store(wx, u, hr[u]);
+                if (new_w) {
+#pragma unroll
+                    for (int u = 0; u < kPWPT; u++) wts_store(u, wr[u]);
+                }
+                __syncthreads();
+            }
+        }
+        // epilogue through this wave's LDS slot: C layout (lane holds rows
+        // (lane / 16) 4 + i, column lane % 16) to voxel-major rows of 32
+        // outputs, then 16-byte stores of eight outputs each
+        bf16* ew = &ep[wave][0];
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
-            const int co = n0 + nt * 16 + lc;
-            if (co >= a.cout) continue;
-            const float bias = a.bias ? a.bias[co] : 0.0f;
+            const int col = nt * 16 + lc, co = w.cb * 32 + col;
+            const float bias = a.bias && co < a.cout ? a.bias[co] : 0.0f;
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int lx = kg * 4 + i;  // rows of the 16-voxel M tile
-                const int64_t v = ((bs * G + z0 + wave) * G + y0 + mt) * G + x0 + lx;
-                float val = acc[mt][nt][i] + bias;
-                if (a.relu) val = fmaxf(val, 0.0f);
-                a.out[v * a.op + a.oo + co] = (bf16)val;
-            }
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    float val = acc[mt][nt][i] + bias;
+                    if (a.relu) val = fmaxf(val, 0.0f);
+                    ew[(mt * 16 + kg * 4 + i) * 32 + col] = (bf16)val;
+                }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int p = 0; p < 4; p++) {
+            const int idx = p * 64 + lane, m = idx >> 2, part = idx & 3;
+            const int co = w.cb * 32 + part * 8;
+            if (co >= a.cout) continue;  // cout is a multiple of 8
+            const uint4 v = *reinterpret_cast<const uint4*>(&ew[m * 32 + part * 8]);
+            const int64_t vox =
+                (((int64_t)w.bs * G + w.z0 + wave) * G + w.y0 + (m >> 4)) * G + w.x0 + (m & 15);
+            *reinterpret_cast<uint4*>(a.out + vox * a.op + a.oo + co) = v;
+        }
+    }
 }
 
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
-    if (a.ks == 3 && a.cin % 32 == 0 && G % 16 == 0) {
-        // 16 x 4 x 4 bricks; their count, B (G / 16)^3 16, is a multiple of 8
-        const int64_t nb = a.V / (kWBX * kWBY * kWBZ);
-        const int64_t ncb = (a.cout + 31) / 32;
-        if (nb % 8 == 0 && nb * ncb <= INT32_MAX) {
-            hipLaunchKernelGGL(k_conv_w, dim3((unsigned)(nb * ncb)), dim3(256), 0, s, a);
+    if (a.ks == 3 && a.cin % 32 == 0 && G % 16 == 0 && a.wp && a.cout % 8 == 0 &&
+        a.op % 8 == 0 && a.oo % 8 == 0) {
+        // 16 x 4 x 8 bricks; their count, B G^3 / 512, is a multiple of 8
+        const int64_t nb = a.V / (kPBX * kPBY * kPBZ);
+        const int64_t ux = nb / 8 * ((a.cout + 31) / 32);
+        if (nb % 8 == 0 && ux <= INT32_MAX) {
+            const int64_t wgs = std::min<int64_t>(ux, kPWGPerXcd);
+            const int per = (int)((ux + wgs - 1) / wgs);
+            hipLaunchKernelGGL(k_conv_p, dim3((unsigned)(8 * wgs)), dim3(512), 0, s, a, per);
             return hipGetLastError();
         }
     }
@@ -1185,6 +1217,37 @@ __global__ void k_pack(const float* __restrict__ master, int cin, int cout, int 
     }
 }
 
+// The weights in the brick convolution's order: for each block of 32 outputs
+// cb, chunk of 32 inputs c, offset off and input group grp, the 32 outputs'
+// eight channels in a row (16 bytes each), so that one dz plane of a chunk
+// (9 offsets) is one contiguous run: element
+//   ((((cb nch + c) 27 + off) 4 + grp) 32 + n) 8 + e
+// holds output cb 32 + n, input c 32 + grp 8 + e (zero past the outputs).
+// With `flip` the copy is of the data-gradient convolution: inputs are the
+// layer's outputs, outputs its inputs, offsets mirrored.
+__global__ void k_pack_w(const float* __restrict__ master, int cin, int cout, int flip,
+                         bf16* __restrict__ wp) {
+    const int ci_n = flip ? cout : cin, co_n = flip ? cin : cout;
+    const int nch = ci_n / 32, ncb = (co_n + 31) / 32;
+    const int64_t n_el = (int64_t)ncb * nch * 27 * 1024;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_el) return;
+    const int e = (int)(i % 8), n = (int)((i / 8) % 32), grp = (int)((i / 256) % 4);
+    const int off = (int)((i / 1024) % 27);
+    const int64_t cc = i / (1024 * 27);
+    const int c = (int)(cc % nch), cb = (int)(cc / nch);
+    const int ci = c * 32 + grp * 8 + e, co = cb * 32 + n;
+    float val = 0.0f;
+    if (co < co_n)
+        val = flip ? master[((int64_t)ci * 27 + (26 - off)) * cin + co]
+                   : master[((int64_t)co * 27 + off) * cin + ci];
+    wp[i] = (bf16)val;
+}
+
+int64_t packed_w_count(int cin_conv, int cout_conv) {
+    return (int64_t)((cout_conv + 31) / 32) * (cin_conv / 32) * 27 * 1024;
+}
+
 __device__ inline uint64_t mix64(uint64_t x) {
     x += 0x9e3779b97f4a7c15ULL;
     x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -1489,6 +1552,9 @@ struct fedsur_net {
     int kp[FEDSUR_LAYERS], kpt[FEDSUR_LAYERS], kp2[FEDSUR_LAYERS];
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // FP32 master etc.
     bf16 *W[FEDSUR_LAYERS], *Wt[FEDSUR_LAYERS];
+    // brick-order copies for the 32-channel convolution (null if the layer's
+    // input, resp. output, channels are not a multiple of 32)
+    bf16 *Wp[FEDSUR_LAYERS], *Wtp[FEDSUR_LAYERS];
     // activations
     bf16 *e1a, *cat1, *p1, *e2a, *cat2, *p2, *e3a, *e3b, *d2a, *d2b, *d1a, *d1b;
     float* y = nullptr;
@@ -1557,6 +1623,7 @@ hipError_t run_conv(fedsur_net* n, int L, const bf16* x, int B) {
     a.cin = kLayers[L].cin;
     a.w = n->W[L];
     a.kp = n->kp[L];
+    a.wp = reinterpret_cast<const uint4*>(n->Wp[L]);
     a.bias = n->p + n->b_off[L];
     a.out = out.p;
     a.op = out.pitch;
@@ -1633,6 +1700,7 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     a.cin = d.cout;
     a.w = n->Wt[L];
     a.kp = n->kpt[L];
+    a.wp = reinterpret_cast<const uint4*>(n->Wtp[L]);
     a.bias = nullptr;
     a.out = dx->p;
     a.op = dx->pitch;
@@ -1652,6 +1720,14 @@ hipError_t pack_all(fedsur_net* n) {
         hipLaunchKernelGGL(k_pack, dim3(nblocks(tot, 256)), dim3(256), 0, n->stream,
                            n->p + n->w_off[L], d.cin, d.cout, n->kp[L], n->kpt[L], n->W[L],
                            n->Wt[L]);
+        if (n->Wp[L])
+            hipLaunchKernelGGL(k_pack_w, dim3(nblocks(packed_w_count(d.cin, d.cout), 256)),
+                               dim3(256), 0, n->stream, n->p + n->w_off[L], d.cin, d.cout, 0,
+                               n->Wp[L]);
+        if (n->Wtp[L])
+            hipLaunchKernelGGL(k_pack_w, dim3(nblocks(packed_w_count(d.cout, d.cin), 256)),
+                               dim3(256), 0, n->stream, n->p + n->w_off[L], d.cin, d.cout, 1,
+                               n->Wtp[L]);
     }
     return hipGetLastError();
 }
@@ -1799,6 +1875,11 @@ int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed, fedsur_net** o
         const LayerDef& d = kLayers[L];
         ok = nalloc(n, &n->W[L], (size_t)d.cout * n->kp[L]) == hipSuccess &&
              nalloc(n, &n->Wt[L], (size_t)d.cin * n->kpt[L]) == hipSuccess;
+        n->Wp[L] = n->Wtp[L] = nullptr;
+        if (ok && d.cin % 32 == 0)
+            ok = nalloc(n, &n->Wp[L], (size_t)packed_w_count(d.cin, d.cout)) == hipSuccess;
+        if (ok && d.cout % 32 == 0)
+            ok = nalloc(n, &n->Wtp[L], (size_t)packed_w_count(d.cout, d.cin)) == hipSuccess;
     }
     ok = ok && nalloc(n, &n->e1a, V0 * 32) == hipSuccess &&
          nalloc(n, &n->cat1, V0 * 96) == hipSuccess && nalloc(n, &n->p1, V1 * 32) == hipSuccess &&
