@@ -522,8 +522,203 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
     }
 }
 
+// The first layer (8 input channels) on the same bricks and schedule: one
+// 32-wide MFMA step takes four offsets x 8 channels (lane group kg holds
+// offset 4 s + kg), 7 steps for the 27 offsets, the 28th a zero weight row
+// (its A lanes read offset 26, a finite value).  Halo 17 KB, weights 14 KB.
+constexpr int kP8Steps = 7;
+constexpr int kP8Wts = kP8Steps * 4 * 32;     // 16-byte weight elements per block
+constexpr int kP8SPT = (kPH + 511) / 512;     // halo loads per thread: 3
+constexpr int kP8WPT = (kP8Wts + 511) / 512;  // weight loads per thread: 2
+
+__global__ void __launch_bounds__(512) k_conv_p8(ConvArgs a, int per) {
+    __shared__ bf16x8 halo[kPH];
+    __shared__ bf16x8 wl[kP8Steps][4][32];
+    __shared__ bf16 ep[8][64 * 32];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int G = a.G;
+    const int nbx = G / kPBX, nby = G / kPBY, nbz = G / kPBZ;
+    const int ncb = (a.cout + 31) / 32;
+    const int bx = (int)(a.V / (kPBX * kPBY * kPBZ) / 8);
+    const int ux = bx * ncb;
+    const int xcd = (int)(blockIdx.x % 8);
+    const int u0 = (int)(blockIdx.x / 8) * per, u1 = min(ux, u0 + per);
+    if (u0 >= u1) return;
+    const int kg = lane >> 4, lc = lane & 15;
+    struct Unit {
+        int x0, y0, z0, bs, cb;
+    };
+    auto unit = [&](int u) -> Unit {
+        const int cb = u / bx, id = xcd * bx + u % bx;
+        Unit w;
+        w.x0 = __builtin_amdgcn_readfirstlane((id % nbx) * kPBX);
+        w.y0 = __builtin_amdgcn_readfirstlane(((id / nbx) % nby) * kPBY);
+        w.z0 = __builtin_amdgcn_readfirstlane(((id / (nbx * nby)) % nbz) * kPBZ);
+        w.bs = __builtin_amdgcn_readfirstlane(id / (nbx * nby * nbz));
+        w.cb = __builtin_amdgcn_readfirstlane(cb);
+        return w;
+    };
+    // halo voxel q = t + 512 u (the last ones redone); outside the grid a
+    // clamped voxel is loaded and zeros stored
+    auto halo_at = [&](const Unit& w, int u, int& h, unsigned& keep) -> int64_t {
+        h = min(t + u * 512, kPH - 1);
+        const int hx = h % kPHX, hy = (h / kPHX) % kPHY, hz = h / (kPHX * kPHY);
+        const int x = w.x0 + hx - 1, y = w.y0 + hy - 1, z = w.z0 + hz - 1;
+        keep = (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) ? ~0u : 0u;
+        const int xc = min(max(x, 0), G - 1), yc = min(max(y, 0), G - 1),
+                  zc = min(max(z, 0), G - 1);
+        return (((int64_t)w.bs * G + zc) * G + yc) * G + xc;
+    };
+    auto halo_load = [&](const Unit& w, int u) -> uint4 {
+        int h;
+        unsigned keep;
+        const int64_t gv = halo_at(w, u, h, keep);
+        return *reinterpret_cast<const uint4*>(a.in + gv * a.ip + a.io);
+    };
+    auto halo_store = [&](const Unit& w, int u, uint4 v) {
+        int h;
+        unsigned keep;
+        (void)halo_at(w, u, h, keep);
+        v.x &= keep;
+        v.y &= keep;
+        v.z &= keep;
+        v.w &= keep;
+        *reinterpret_cast<uint4*>(&halo[h]) = v;
+    };
+    // weight element r of block cb: step r / 128, lane group (r / 32) % 4,
+    // output cb 32 + r % 32
+    auto wts_load = [&](int cb, int u) -> uint4 {
+        const int r = min(t + u * 512, kP8Wts - 1);
+        return a.wp[(int64_t)cb * kP8Wts + r];
+    };
+    auto wts_store = [&](int u, uint4 v) {
+        const int r = min(t + u * 512, kP8Wts - 1);
+        *reinterpret_cast<uint4*>(&wl[r / 128][(r >> 5) & 3][r & 31]) = v;
+    };
+    // this lane's halo index of step s, row mt: its voxel (lc, mt, wave)
+    // shifted by offset min(4 s + kg, 26)
+    const int hv0 = ((wave + 1) * kPHY + 1) * kPHX + lc + 1;
+    auto loadA = [&](int s, bf16x8 (&A)[4]) {
+        const int off = min(4 * s + kg, 26);
+        const int dh = ((off / 9 - 1) * kPHY + (off / 3) % 3 - 1) * kPHX + off % 3 - 1;
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) A[mt] = halo[hv0 + mt * kPHX + dh];
+    };
+    auto loadB = [&](int s, bf16x8 (&B)[2]) {
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) B[nt] = wl[s][kg][nt * 16 + lc];
+    };
+    uint4 hr[kP8SPT], wr[kP8WPT];
+    {
+        const Unit w = unit(u0);
+#pragma unroll
+        for (int u = 0; u < kP8SPT; u++) hr[u] = halo_load(w, u);
+#pragma unroll
+        for (int u = 0; u < kP8WPT; u++) wr[u] = wts_load(w.cb, u);
+#pragma unroll
+        for (int u = 0; u < kP8SPT; u++) halo_store(w, u, hr[u]);
+#pragma unroll
+        for (int u = 0; u < kP8WPT; u++) wts_store(u, wr[u]);
+    }
+    __syncthreads();
+    for (int un = u0; un < u1; un++) {
+        const Unit w = unit(un);
+        const bool next = un + 1 < u1;
+        const Unit wn = unit(next ? un + 1 : un);
+        const bool new_w = next && wn.cb != w.cb;
+        if (next) {
+#pragma unroll
+            for (int u = 0; u < kP8SPT; u++) hr[u] = halo_load(wn, u);
+        }
+        if (new_w) {
+#pragma unroll
+            for (int u = 0; u < kP8WPT; u++) wr[u] = wts_load(wn.cb, u);
+        }
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 A[4], B[2];
+        loadA(0, A);
+        loadB(0, B);
+#pragma unroll
+        for (int st = 0; st < kP8Steps; st++) {
+            bf16x8 An[4], Bn[2];
+            if (st + 1 < kP8Steps) {
+                loadA(st + 1, An);
+                loadB(st + 1, Bn);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int nt = 0; nt < 2; nt++)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt],
+                                                                          acc[mt][nt], 0, 0, 0);
+            if (st + 1 < kP8Steps) {
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
+#pragma unroll
+                for (int nt = 0; nt < 2; nt++) B[nt] = Bn[nt];
+            }
+        }
+        if (next) {
+            __syncthreads();  // no wave still reads this unit's halo or weights
+#pragma unroll
+            for (int u = 0; u < kP8SPT; u++) halo_store(wn, u, hr[u]);
+            if (new_w) {
+#pragma unroll
+                for (int u = 0; u < kP8WPT; u++) wts_store(u, wr[u]);
+            }
+            __syncthreads();
+        }
+        // epilogue through this wave's LDS slot, as in k_conv_p
+        bf16* ew = &ep[wave][0];
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+            const int col = nt * 16 + lc, co = w.cb * 32 + col;
+            const float bias = a.bias && co < a.cout ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    float val = acc[mt][nt][i] + bias;
+                    if (a.relu) val = fmaxf(val, 0.0f);
+                    ew[(mt * 16 + kg * 4 + i) * 32 + col] = (bf16)val;
+                }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int p = 0; p < 4; p++) {
+            const int idx = p * 64 + lane, m = idx >> 2, part = idx & 3;
+            const int co = w.cb * 32 + part * 8;
+            if (co >= a.cout) continue;
+            const uint4 v = *reinterpret_cast<const uint4*>(&ew[m * 32 + part * 8]);
+            const int64_t vox =
+                (((int64_t)w.bs * G + w.z0 + wave) * G + w.y0 + (m >> 4)) * G + w.x0 + (m & 15);
+            *reinterpret_cast<uint4*>(a.out + vox * a.op + a.oo + co) = v;
+        }
+    }
+}
+
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
+    if (a.ks == 3 && a.cin == 8 && G % 16 == 0 && a.wp && a.cout % 8 == 0 && a.op % 8 == 0 &&
+        a.oo % 8 == 0 && a.ip % 8 == 0 && a.io % 8 == 0) {
+        // the first layer on the same bricks
+        const int64_t nb = a.V / (kPBX * kPBY * kPBZ);
+        const int64_t ux = nb / 8 * ((a.cout + 31) / 32);
+        if (nb % 8 == 0 && ux <= INT32_MAX) {
+            // 64 KB of LDS: two workgroups per CU
+            const int64_t wgs = std::min<int64_t>(ux, 2 * kPWGPerXcd);
+            const int per = (int)((ux + wgs - 1) / wgs);
+            hipLaunchKernelGGL(k_conv_p8, dim3((unsigned)(8 * wgs)), dim3(512), 0, s, a, per);
+            return hipGetLastError();
+        }
+    }
     if (a.ks == 3 && a.cin % 32 == 0 && G % 16 == 0 && a.wp && a.cout % 8 == 0 &&
         a.op % 8 == 0 && a.oo % 8 == 0) {
         // 16 x 4 x 8 bricks; their count, B G^3 / 512, is a multiple of 8
@@ -1244,7 +1439,21 @@ __global__ void k_pack_w(const float* __restrict__ master, int cin, int cout, in
     wp[i] = (bf16)val;
 }
 
+// The first layer's copy (8 input channels) in k_conv_p8's order: element
+//   (((cb 7 + s) 4 + kg) 32 + n) 8 + e
+// holds output cb 32 + n, offset 4 s + kg (zero from 27 on), input e.
+__global__ void k_pack_w8(const float* __restrict__ master, int cout, bf16* __restrict__ wp) {
+    const int ncb = (cout + 31) / 32;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)ncb * 7 * 1024) return;
+    const int e = (int)(i % 8), n = (int)((i / 8) % 32), kg = (int)((i / 256) % 4);
+    const int st = (int)((i / 1024) % 7), cb = (int)(i / (1024 * 7));
+    const int off = 4 * st + kg, co = cb * 32 + n;
+    wp[i] = (bf16)(off < 27 && co < cout ? master[((int64_t)co * 27 + off) * 8 + e] : 0.0f);
+}
+
 int64_t packed_w_count(int cin_conv, int cout_conv) {
+    if (cin_conv == 8) return (int64_t)((cout_conv + 31) / 32) * 7 * 1024;
     return (int64_t)((cout_conv + 31) / 32) * (cin_conv / 32) * 27 * 1024;
 }
 
@@ -1552,8 +1761,9 @@ struct fedsur_net {
     int kp[FEDSUR_LAYERS], kpt[FEDSUR_LAYERS], kp2[FEDSUR_LAYERS];
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // FP32 master etc.
     bf16 *W[FEDSUR_LAYERS], *Wt[FEDSUR_LAYERS];
-    // brick-order copies for the 32-channel convolution (null if the layer's
-    // input, resp. output, channels are not a multiple of 32)
+    // brick-order copies for the brick convolutions (null if the layer's
+    // input, resp. output, channels are neither 8 nor a multiple of 32, resp.
+    // not a multiple of 32)
     bf16 *Wp[FEDSUR_LAYERS], *Wtp[FEDSUR_LAYERS];
     // activations
     bf16 *e1a, *cat1, *p1, *e2a, *cat2, *p2, *e3a, *e3b, *d2a, *d2b, *d1a, *d1b;
@@ -1720,7 +1930,10 @@ hipError_t pack_all(fedsur_net* n) {
         hipLaunchKernelGGL(k_pack, dim3(nblocks(tot, 256)), dim3(256), 0, n->stream,
                            n->p + n->w_off[L], d.cin, d.cout, n->kp[L], n->kpt[L], n->W[L],
                            n->Wt[L]);
-        if (n->Wp[L])
+        if (n->Wp[L] && d.cin == 8)
+            hipLaunchKernelGGL(k_pack_w8, dim3(nblocks(packed_w_count(d.cin, d.cout), 256)),
+                               dim3(256), 0, n->stream, n->p + n->w_off[L], d.cout, n->Wp[L]);
+        else if (n->Wp[L])
             hipLaunchKernelGGL(k_pack_w, dim3(nblocks(packed_w_count(d.cin, d.cout), 256)),
                                dim3(256), 0, n->stream, n->p + n->w_off[L], d.cin, d.cout, 0,
                                n->Wp[L]);
@@ -1876,7 +2089,7 @@ int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed, fedsur_net** o
         ok = nalloc(n, &n->W[L], (size_t)d.cout * n->kp[L]) == hipSuccess &&
              nalloc(n, &n->Wt[L], (size_t)d.cin * n->kpt[L]) == hipSuccess;
         n->Wp[L] = n->Wtp[L] = nullptr;
-        if (ok && d.cin % 32 == 0)
+        if (ok && (d.cin % 32 == 0 || d.cin == 8))
             ok = nalloc(n, &n->Wp[L], (size_t)packed_w_count(d.cin, d.cout)) == hipSuccess;
         if (ok && d.cout % 32 == 0)
             ok = nalloc(n, &n->Wtp[L], (size_t)packed_w_count(d.cout, d.cin)) == hipSuccess;
