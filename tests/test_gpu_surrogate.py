@@ -99,23 +99,25 @@ def test_forward_layers_and_network(torch_cuda):
 
 
 def test_conv_layers_on_64_grid(torch_cuda):
-    """At 64^3 the 32-output-channel layers run on 16 x 4 x 4 bricks with the
-    weights staged in LDS and the bricks striped over the XCDs; each such
-    layer, fed the GPU's own input, must match the FP64 reference to BF16
-    rounding."""
+    """At 64^3 every layer (64^3, 32^3 and 16^3 levels) runs on the
+    persistent brick kernels: 16 x 4 x 8 voxels per unit, a chunk's weights
+    in LDS, the bricks striped over the XCDs, and the first layer (8 input
+    channels) with four offsets per MFMA step.  Each layer, fed the GPU's own
+    input, must match the FP64 reference to BF16 rounding."""
     torch = torch_cuda
     G, B = 64, 1
     rng, net, Q, x, X = setup(torch, G, B, 2)
     Y = torch.empty((B, G, G, G), dtype=torch.float32, device="cuda")
     net.forward(X, Y)
-    acts = {L: net.activation(L, B).astype(np.float64) for L in (0, 1, 7, 8, 9)}
-    ins = {1: acts[0], 8: np.concatenate([S.up2(acts[7]), acts[1]], -1), 9: acts[8]}
-    for L in (1, 8, 9):
-        name = S.LAYERS[L][0]
+    acts = [net.activation(L, B).astype(np.float64) for L in range(10)]
+    ins = {0: x, 1: acts[0], 2: S.pool2(acts[1]), 3: acts[2], 4: S.pool2(acts[3]),
+           5: acts[4], 6: np.concatenate([S.up2(acts[5]), acts[3]], -1), 7: acts[6],
+           8: np.concatenate([S.up2(acts[7]), acts[1]], -1), 9: acts[8]}
+    for L, (name, _, _) in enumerate(S.LAYERS):
         ref = S.relu(S.conv3(bf16(ins[L], torch), Q[name + ".w"], Q[name + ".b"]))
         err = np.abs(acts[L] - ref)
         tol = 2.0 ** -7 * np.abs(ref) + 1e-6 * np.abs(ref).max()
-        print(f"[surrogate] 64^3 layer {name}: max rel "
+        print(f"[surrogate] 64^3 network, layer {name}: max rel "
               f"{float((err / (np.abs(ref) + 1e-12)).max()):.2e}", flush=True)
         assert np.all(err <= tol), name
     net.close()
