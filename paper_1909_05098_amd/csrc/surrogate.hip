@@ -1540,18 +1540,46 @@ __device__ double prior_rise(double r2, const RasterSample& p, const RasterPhys&
     return p.q0 / rc * sum;
 }
 
+// Term j (piece j / 8, point j % 8) of the same quadrature, split into what
+// depends on the sample only: the term is c exp(-a r2) with
+//   c = Q0 / (rho c) (half w) exp(-m tau) g^(3/2),  a = 1 / (2 s).
+__device__ void prior_term(int j, const RasterSample& p, const RasterPhys& ph, double& c,
+                           double& a) {
+    const double rc = ph.rho0 * ph.c0;
+    const double alpha = p.k0 / rc, m = p.omega_b * ph.rhob_cb / rc, s0 = p.sigma * p.sigma;
+    const int seg = j >> 3, k = j & 7;
+    const double hi = ph.t_heat / 128.0 * (double)(1 << seg), lo = seg == 0 ? 0.0 : 0.5 * hi;
+    const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+    const double tau = mid + (k < 4 ? -half * kGLx[k] : half * kGLx[k - 4]);
+    const double sv = s0 + 2.0 * alpha * tau;
+    const double g = s0 / sv;
+    c = p.q0 / rc * half * kGLw[k & 3] * exp(-m * tau) * g * sqrt(g);
+    a = 0.5 / sv;
+}
+
 __global__ void k_prior_scale(int B, const RasterSample* __restrict__ smp, RasterPhys ph,
                               float* __restrict__ scale) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < B) scale[b] = (float)prior_rise(0.0, smp[b], ph);
 }
 
-__global__ void k_rasterize(int G, double fx, double fy, double fz, double h, int B,
-                            const RasterSample* __restrict__ smp, RasterPhys ph,
-                            const float* __restrict__ scale, bf16* __restrict__ x,
-                            float* __restrict__ prior) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_rasterize(int G, double fx, double fy, double fz,
+                                                    double h, int B,
+                                                    const RasterSample* __restrict__ smp,
+                                                    RasterPhys ph,
+                                                    const float* __restrict__ scale,
+                                                    bf16* __restrict__ x,
+                                                    float* __restrict__ prior) {
+    // the prior's 64 quadrature terms of the block's first sample, once per
+    // block; a voxel of another sample (a block straddling two) takes the
+    // quadrature directly
+    __shared__ double tc[64], ta[64];
     const int64_t G3 = (int64_t)G * G * G;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t b0 = i0 / G3;
+    if (threadIdx.x < 64) prior_term(threadIdx.x, smp[b0], ph, tc[threadIdx.x], ta[threadIdx.x]);
+    __syncthreads();
+    const int64_t i = i0 + threadIdx.x;
     if (i >= (int64_t)B * G3) return;
     const int64_t b = i / G3;
     const int64_t r = i - b * G3;
@@ -1568,7 +1596,17 @@ __global__ void k_rasterize(int G, double fx, double fy, double fz, double h, in
                  ez = (vz - fz - half) / p.az;
     const float mk = (ex * ex + ey * ey + ez * ez <= 1.0) ? 1.0f : 0.0f;
     const double r2 = (vx - p.cx) * (vx - p.cx) + (vy - p.cy) * (vy - p.cy) + (vz - p.cz) * (vz - p.cz);
-    const double pr = prior_rise(r2, p, ph);
+    double pr;
+    if (b == b0) {
+        // FP32 exponentials: a term's error stays below 1e-7 of its c (the
+        // argument x = a r2 rounded to FP32 moves it by at most x e^-x 2^-24,
+        // expf adds its own ulp), and the terms are summed in FP64
+        pr = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < 64; j++) pr += tc[j] * (double)expf((float)(-ta[j] * r2));
+    } else {
+        pr = prior_rise(r2, p, ph);
+    }
     const float P = scale[b];
     bf16x8 o;
     o[0] = (bf16)(float)q;
