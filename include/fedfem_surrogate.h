@@ -33,10 +33,11 @@ extern "C" {
 typedef struct fedsur_net fedsur_net;
 
 /*
- * Create a network for grid size G (a multiple of 4, at least 4) and up to
- * batch_max samples per call, with He-initialised weights from a seeded
- * counter-based generator.  Allocates all activation, gradient and
- * optimiser buffers on the current device.
+ * Create a network for grid size G (a multiple of 4, from 4 to 256) and up
+ * to batch_max samples per call (1 to 4096, with batch_max G^3 below 2^31),
+ * with He-initialised weights from a seeded counter-based generator.
+ * Allocates all activation, gradient and optimiser buffers on the current
+ * device.  FEDFEM_E_INVALID for sizes outside these bounds.
  */
 int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed,
                   fedsur_net **out);

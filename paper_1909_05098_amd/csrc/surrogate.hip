@@ -1193,64 +1193,89 @@ __global__ void k_relu_bwd(const bf16* __restrict__ g, int gp, int go, const bf1
 }
 
 // out (contiguous, grid G/2) = mean of the 2x2x2 children of in (grid G)
+// Coarse voxel u = ((b H + Z) H + Y) H + X of a 2 x 2 x 2 level pair (fine
+// edge G = 2 H), in 32-bit arithmetic (the launchers keep B G^3 C / 8 below
+// 2^31); `v0` is its first fine voxel, the others at + dz G^2 + dy G + dx.
+struct Coarse {
+    uint32_t u, v0;
+};
+__device__ inline Coarse coarse_of(uint32_t u, int G) {
+    const uint32_t H = (uint32_t)G / 2;
+    const uint32_t u2 = u / H, X = u - u2 * H;
+    const uint32_t u3 = u2 / H, Y = u2 - u3 * H;
+    const uint32_t b = u3 / H, Z = u3 - b * H;
+    return {u, ((b * (uint32_t)G + 2 * Z) * (uint32_t)G + 2 * Y) * (uint32_t)G + 2 * X};
+}
+__device__ inline uint32_t child(uint32_t v0, int d, int G) {
+    return v0 + (uint32_t)(d >> 2) * (uint32_t)G * (uint32_t)G + (uint32_t)((d >> 1) & 1) * (uint32_t)G +
+           (uint32_t)(d & 1);
+}
+
 __global__ void k_pool_fwd(const bf16* __restrict__ in, int ip, int io, int C, int G, int B,
                            bf16* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int H = G / 2, c8 = C / 8;
     const int64_t n = (int64_t)B * H * H * H * c8;
     if (i >= n) return;
-    const int c = (int)(i % c8) * 8;
-    int64_t u = i / c8;
-    const int X = (int)(u % H), Y = (int)((u / H) % H), Z = (int)((u / ((int64_t)H * H)) % H);
-    const int64_t b = u / ((int64_t)H * H * H);
-    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int d = 0; d < 8; d++) {
-        const int64_t v = ((b * G + 2 * Z + (d >> 2)) * G + 2 * Y + ((d >> 1) & 1)) * G + 2 * X + (d & 1);
-        const bf16x8 x = *reinterpret_cast<const bf16x8*>(in + v * ip + io + c);
+    const uint32_t i32 = (uint32_t)i;
+    const int c = (int)(i32 % (uint32_t)c8) * 8;
+    const Coarse q = coarse_of(i32 / (uint32_t)c8, G);
+    bf16x8 x[8];
 #pragma unroll
-        for (int j = 0; j < 8; j++) s[j] += (float)x[j];
-    }
+    for (int d = 0; d < 8; d++)
+        x[d] = *reinterpret_cast<const bf16x8*>(in + (int64_t)child(q.v0, d, G) * ip + io + c);
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 8; d++)
+#pragma unroll
+        for (int j = 0; j < 8; j++) s[j] += (float)x[d][j];
     bf16x8 o;
 #pragma unroll
     for (int j = 0; j < 8; j++) o[j] = (bf16)(s[j] * 0.125f);
-    *reinterpret_cast<bf16x8*>(out + u * C + c) = o;
+    *reinterpret_cast<bf16x8*>(out + (int64_t)q.u * C + c) = o;
 }
 
 // out[v][c] (contiguous, grid G) = a[v][c] + gp[parent(v)][c] / 8
+// one thread per coarse voxel and 8 channels: out = a + g / 8 at its children
 __global__ void k_pool_bwd_add(const bf16* __restrict__ a, int ap, int ao,
                                const bf16* __restrict__ gpar, int C, int G, int B,
                                bf16* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c8 = C / 8, H = G / 2;
-    const int64_t n = (int64_t)B * G * G * G * c8;
+    const int64_t n = (int64_t)B * H * H * H * c8;
     if (i >= n) return;
-    const int c = (int)(i % c8) * 8;
-    const int64_t v = i / c8;
-    const int x = (int)(v % G), y = (int)((v / G) % G), z = (int)((v / ((int64_t)G * G)) % G);
-    const int64_t b = v / ((int64_t)G * G * G);
-    const int64_t u = ((b * H + z / 2) * H + y / 2) * H + x / 2;
-    const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + v * ap + ao + c);
-    const bf16x8 gv = *reinterpret_cast<const bf16x8*>(gpar + u * C + c);
-    bf16x8 o;
+    const uint32_t i32 = (uint32_t)i;
+    const int c = (int)(i32 % (uint32_t)c8) * 8;
+    const Coarse q = coarse_of(i32 / (uint32_t)c8, G);
+    const bf16x8 gv = *reinterpret_cast<const bf16x8*>(gpar + (int64_t)q.u * C + c);
+    bf16x8 av[8];
 #pragma unroll
-    for (int j = 0; j < 8; j++) o[j] = (bf16)((float)av[j] + 0.125f * (float)gv[j]);
-    *reinterpret_cast<bf16x8*>(out + v * C + c) = o;
+    for (int d = 0; d < 8; d++)
+        av[d] = *reinterpret_cast<const bf16x8*>(a + (int64_t)child(q.v0, d, G) * ap + ao + c);
+#pragma unroll
+    for (int d = 0; d < 8; d++) {
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; j++) o[j] = (bf16)((float)av[d][j] + 0.125f * (float)gv[j]);
+        *reinterpret_cast<bf16x8*>(out + (int64_t)child(q.v0, d, G) * C + c) = o;
+    }
 }
 
 // out[v][oo + c] (grid G) = in[parent(v)][c] (contiguous, grid G/2)
+// one thread per coarse voxel and 8 channels: its value to the 8 children
 __global__ void k_up_fwd(const bf16* __restrict__ in, int C, int G, int B, bf16* __restrict__ out,
                          int op, int oo) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c8 = C / 8, H = G / 2;
-    const int64_t n = (int64_t)B * G * G * G * c8;
+    const int64_t n = (int64_t)B * H * H * H * c8;
     if (i >= n) return;
-    const int c = (int)(i % c8) * 8;
-    const int64_t v = i / c8;
-    const int x = (int)(v % G), y = (int)((v / G) % G), z = (int)((v / ((int64_t)G * G)) % G);
-    const int64_t b = v / ((int64_t)G * G * G);
-    const int64_t u = ((b * H + z / 2) * H + y / 2) * H + x / 2;
-    *reinterpret_cast<bf16x8*>(out + v * op + oo + c) =
-        *reinterpret_cast<const bf16x8*>(in + u * C + c);
+    const uint32_t i32 = (uint32_t)i;
+    const int c = (int)(i32 % (uint32_t)c8) * 8;
+    const Coarse q = coarse_of(i32 / (uint32_t)c8, G);
+    const bf16x8 x = *reinterpret_cast<const bf16x8*>(in + (int64_t)q.u * C + c);
+#pragma unroll
+    for (int d = 0; d < 8; d++)
+        *reinterpret_cast<bf16x8*>(out + (int64_t)child(q.v0, d, G) * op + oo + c) = x;
 }
 
 // out[u][c] (contiguous, grid G/2) = sum of g over the 2x2x2 children of u
@@ -1260,21 +1285,22 @@ __global__ void k_up_bwd(const bf16* __restrict__ g, int gp, int go, int C, int 
     const int H = G / 2, c8 = C / 8;
     const int64_t n = (int64_t)B * H * H * H * c8;
     if (i >= n) return;
-    const int c = (int)(i % c8) * 8;
-    const int64_t u = i / c8;
-    const int X = (int)(u % H), Y = (int)((u / H) % H), Z = (int)((u / ((int64_t)H * H)) % H);
-    const int64_t b = u / ((int64_t)H * H * H);
-    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int d = 0; d < 8; d++) {
-        const int64_t v = ((b * G + 2 * Z + (d >> 2)) * G + 2 * Y + ((d >> 1) & 1)) * G + 2 * X + (d & 1);
-        const bf16x8 x = *reinterpret_cast<const bf16x8*>(g + v * gp + go + c);
+    const uint32_t i32 = (uint32_t)i;
+    const int c = (int)(i32 % (uint32_t)c8) * 8;
+    const Coarse q = coarse_of(i32 / (uint32_t)c8, G);
+    bf16x8 x[8];
 #pragma unroll
-        for (int j = 0; j < 8; j++) s[j] += (float)x[j];
-    }
+    for (int d = 0; d < 8; d++)
+        x[d] = *reinterpret_cast<const bf16x8*>(g + (int64_t)child(q.v0, d, G) * gp + go + c);
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 8; d++)
+#pragma unroll
+        for (int j = 0; j < 8; j++) s[j] += (float)x[d][j];
     bf16x8 o;
 #pragma unroll
     for (int j = 0; j < 8; j++) o[j] = (bf16)s[j];
-    *reinterpret_cast<bf16x8*>(out + u * C + c) = o;
+    *reinterpret_cast<bf16x8*>(out + (int64_t)q.u * C + c) = o;
 }
 
 // y[v] = sum_c w[c] d[v][c] + b (32 channels)
@@ -2003,10 +2029,10 @@ hipError_t forward_impl(fedsur_net* n, int B, const bf16* x, float* y) {
     hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 2, B) * 8, 256)), dim3(256), 0, s, n->cat2,
                        192, 128, 64, G / 2, B, n->p2);
     if ((e = run_conv(n, E3A, x, B)) || (e = run_conv(n, E3B, x, B))) return e;
-    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 1, B) * 16, 256)), dim3(256), 0, s, n->e3b,
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 2, B) * 16, 256)), dim3(256), 0, s, n->e3b,
                        128, G / 2, B, n->cat2, 192, 0);
     if ((e = run_conv(n, D2A, x, B)) || (e = run_conv(n, D2B, x, B))) return e;
-    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 0, B) * 8, 256)), dim3(256), 0, s, n->d2b,
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 1, B) * 8, 256)), dim3(256), 0, s, n->d2b,
                        64, G, B, n->cat1, 96, 0);
     if ((e = run_conv(n, D1A, x, B)) || (e = run_conv(n, D1B, x, B))) return e;
     hipLaunchKernelGGL(k_head_fwd, dim3(nblocks(vox(n, 0, B), 256)), dim3(256), 0, s, n->d1b,
@@ -2047,13 +2073,13 @@ hipError_t backward_impl(fedsur_net* n, int B, const bf16* x) {
     if ((e = conv_backward(n, E3B, x, B, gA2, n->gB2, &gA2))) return e;
     if ((e = conv_backward(n, E3A, x, B, gA2, n->gB2, &gp2))) return e;
     // g(e2b) = gcat2[:, 128:192] + pool backward of g(p2), into gA1
-    hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V1 * 8, 256)), dim3(256), 0, s, n->gcat2, 192,
+    hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V2 * 8, 256)), dim3(256), 0, s, n->gcat2, 192,
                        128, n->gp2, 64, G / 2, B, n->gA1);
     const View gp1{n->gp1, 32, 0, 32, 1};
     if ((e = conv_backward(n, E2B, x, B, gA1, n->gB1, &gA1))) return e;
     if ((e = conv_backward(n, E2A, x, B, gA1, n->gB1, &gp1))) return e;
     // g(e1b) = gcat1[:, 64:96] + pool backward of g(p1), into gA0
-    hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V0 * 4, 256)), dim3(256), 0, s, n->gcat1, 96,
+    hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V1 * 4, 256)), dim3(256), 0, s, n->gcat1, 96,
                        64, n->gp1, 32, G, B, n->gA0);
     if ((e = conv_backward(n, E1B, x, B, gA0, n->gB0, &gA0))) return e;
     if ((e = conv_backward(n, E1A, x, B, gA0, n->gB0, nullptr))) return e;
@@ -2081,7 +2107,8 @@ void destroy_net(fedsur_net* n) {
 extern "C" {
 
 int fedsur_create(int32_t grid, int32_t batch_max, uint64_t seed, fedsur_net** out) {
-    if (!out || grid < 4 || grid % 4 || grid > 256 || batch_max < 1 || batch_max > 4096)
+    if (!out || grid < 4 || grid % 4 || grid > 256 || batch_max < 1 || batch_max > 4096 ||
+        (int64_t)batch_max * grid * grid * grid >= (int64_t(1) << 31))
         return FEDFEM_E_INVALID;
     *out = nullptr;
     fedsur_net* n = new (std::nothrow) fedsur_net();

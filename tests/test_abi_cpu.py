@@ -137,3 +137,16 @@ def test_flux_loads_rejects_bad_shapes(faces, flux):
     h.xyz = np.zeros((8, 3))
     with pytest.raises(ValueError):
         h.flux_loads(faces, flux)
+
+
+@pytest.mark.parametrize("grid,batch", [(0, 1), (6, 1), (260, 1), (64, 0), (64, 4097),
+                                        (256, 128)])
+def test_network_create_rejects_bad_sizes(grid, batch):
+    """fedsur_create checks its sizes before any device work: the grid a
+    multiple of 4 in [4, 256], the batch in [1, 4096] and batch G^3 below
+    2^31 (the 2 x 2 x 2 kernels index voxels in 32 bits)."""
+    from paper_1909_05098_amd import surrogate as sg
+    L = sg.lib()
+    out = C.c_void_p()
+    assert L.fedsur_create(grid, batch, C.c_uint64(0), C.byref(out)) == ff.E_INVALID
+    assert not out.value
