@@ -55,6 +55,11 @@ struct ConvArgs {
     int kp;
     // the same weights in the brick kernel's order (k_pack_w), or null
     const uint4* wp;
+    // input channels [0, upc) taken from `up` at half resolution (a 2 x 2 x 2
+    // upsampling read in place: voxel v reads its parent), pitch upp, offset
+    // upo; upc = 0: none (only the brick kernels take upc > 0)
+    const bf16* up = nullptr;
+    int upp = 0, upo = 0, upc = 0;
     const float* bias;  // may be null
     bf16* out;
     int op, oo, cout;   // output pitch, channel offset, channels
@@ -361,27 +366,35 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
     // take 16 consecutive halo voxels x 4 channel groups; lanes past the halo
     // redo its last voxel, lanes outside the grid load a clamped voxel and
     // store zeros
-    auto halo_at = [&](const Unit& w, int u, int& h, int& grp, unsigned& keep) -> int64_t {
+    auto halo_at = [&](const Unit& w, int u, int& h, int& grp, unsigned& keep, int& xc, int& yc,
+                       int& zc) {
         const int q = t + u * 512;
         h = min((q >> 6) * 16 + (q & 15), kPH - 1);
         grp = (q >> 4) & 3;
         const int hx = h % kPHX, hy = (h / kPHX) % kPHY, hz = h / (kPHX * kPHY);
         const int x = w.x0 + hx - 1, y = w.y0 + hy - 1, z = w.z0 + hz - 1;
         keep = (x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G) ? ~0u : 0u;
-        const int xc = min(max(x, 0), G - 1), yc = min(max(y, 0), G - 1),
-                  zc = min(max(z, 0), G - 1);
-        return (((int64_t)w.bs * G + zc) * G + yc) * G + xc;
+        xc = min(max(x, 0), G - 1);
+        yc = min(max(y, 0), G - 1);
+        zc = min(max(z, 0), G - 1);
     };
     auto halo_load = [&](const Unit& w, int c, int u) -> uint4 {
-        int h, grp;
+        int h, grp, xc, yc, zc;
         unsigned keep;
-        const int64_t gv = halo_at(w, u, h, grp, keep);
+        halo_at(w, u, h, grp, keep, xc, yc, zc);
+        if (c * 32 < a.upc) {
+            // an upsampled channel chunk: the parent voxel
+            const int Gh = G >> 1;
+            const int64_t pv = (((int64_t)w.bs * Gh + (zc >> 1)) * Gh + (yc >> 1)) * Gh + (xc >> 1);
+            return *reinterpret_cast<const uint4*>(a.up + pv * a.upp + a.upo + c * 32 + grp * 8);
+        }
+        const int64_t gv = (((int64_t)w.bs * G + zc) * G + yc) * G + xc;
         return *reinterpret_cast<const uint4*>(a.in + gv * a.ip + a.io + c * 32 + grp * 8);
     };
     auto halo_store = [&](const Unit& w, int u, uint4 v) {
-        int h, grp;
+        int h, grp, xc, yc, zc;
         unsigned keep;
-        (void)halo_at(w, u, h, grp, keep);
+        halo_at(w, u, h, grp, keep, xc, yc, zc);
         v.x &= keep;
         v.y &= keep;
         v.z &= keep;
@@ -706,6 +719,8 @@ __global__ void __launch_bounds__(512) k_conv_p8(ConvArgs a, int per) {
 
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
+    if (a.upc && !(a.ks == 3 && a.cin % 32 == 0 && a.upc % 32 == 0 && G % 16 == 0 && a.wp))
+        return hipErrorInvalidValue;  // only the brick kernel reads upsampled channels
     if (a.ks == 3 && a.cin == 8 && G % 16 == 0 && a.wp && a.cout % 8 == 0 && a.op % 8 == 0 &&
         a.oo % 8 == 0 && a.ip % 8 == 0 && a.io % 8 == 0) {
         // the first layer on the same bricks
@@ -731,6 +746,7 @@ hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
             return hipGetLastError();
         }
     }
+    if (a.upc) return hipErrorInvalidValue;
     if (a.ks == 3 && a.cin % 32 == 0 && G >= 8 && (G & (G - 1)) == 0) {
         // bricks of 256 voxels: 16 x 8 x 2, or 8 x 8 x 4 on an 8^3 grid
         const int BX = G >= 16 ? 16 : 8, BY = 8, BZ = 256 / (BX * BY);
@@ -774,6 +790,8 @@ struct WgradArgs {
     int dp, doff, cout;
     const bf16* in;  // convolution input
     int ip, io, cin;
+    const bf16* up = nullptr;  // input channels [0, upc) at half resolution, as in ConvArgs
+    int upp = 0, upo = 0, upc = 0;
     int G;
     int64_t V, vsplit;
     int kp2;      // k extent of the partial buffer (multiple of KN, > 27 cin)
@@ -1003,13 +1021,19 @@ __global__ void __launch_bounds__(512) k_wgrad_brick(WgradArgs a, int64_t per_sp
             const int y = y0 + hy - 1, z = z0 + hz - 1;
             const bool rowin = y >= 0 && y < G && z >= 0 && z < G;
             const int64_t r0 = ((bs * G + min(max(z, 0), G - 1)) * G + min(max(y, 0), G - 1)) * G;
+            // the row's parent row at half resolution (upsampled channel chunks)
+            const int Gh = G >> 1;
+            const int64_t pr0 =
+                ((bs * Gh + (min(max(z, 0), G - 1) >> 1)) * Gh + (min(max(y, 0), G - 1) >> 1)) * Gh;
 #pragma unroll
             for (int hx = 0; hx < 18; hx++) {
                 const int x = x0 + hx - 1;
-                st[hx] = (rowin && x >= 0 && x < G)
-                             ? *reinterpret_cast<const bf16x8*>(a.in + (r0 + x) * a.ip + a.io + c0 +
-                                                                cgp * 8)
-                             : zero8();
+                const bf16* src =
+                    c0 < a.upc
+                        ? a.up + ((pr0 + (x >> 1)) * a.upp + a.upo + c0 + cgp * 8)
+                        : a.in + ((r0 + x) * a.ip + a.io + c0 + cgp * 8);
+                st[hx] = (rowin && x >= 0 && x < G) ? *reinterpret_cast<const bf16x8*>(src)
+                                                    : zero8();
             }
         }
     };
@@ -1888,6 +1912,21 @@ View in_view(fedsur_net* n, int L, const bf16* x) {
     }
 }
 
+// D2A's and D1A's leading input channels are the upsampled output of the
+// level below (e3b: 128, d2b: 64).  On grids of 16k the brick kernels read
+// them at the parent voxel instead of from a written copy in cat2 / cat1.
+struct UpSrc {
+    const bf16* p;
+    int pitch, c;
+};
+UpSrc up_source(const fedsur_net* n, int L) {
+    const int G = n->G >> kLayers[L].lvl;
+    if (G % 16) return {nullptr, 0, 0};
+    if (L == D2A) return {n->e3b, 128, 128};
+    if (L == D1A) return {n->d2b, 64, 64};
+    return {nullptr, 0, 0};
+}
+
 hipError_t run_conv(fedsur_net* n, int L, const bf16* x, int B) {
     const View in = in_view(n, L, x), out = out_view(n, L);
     ConvArgs a;
@@ -1898,6 +1937,11 @@ hipError_t run_conv(fedsur_net* n, int L, const bf16* x, int B) {
     a.w = n->W[L];
     a.kp = n->kp[L];
     a.wp = reinterpret_cast<const uint4*>(n->Wp[L]);
+    const UpSrc u = up_source(n, L);
+    a.up = u.p;
+    a.upp = u.pitch;
+    a.upo = 0;
+    a.upc = u.c;
     a.bias = n->p + n->b_off[L];
     a.out = out.p;
     a.op = out.pitch;
@@ -1949,6 +1993,12 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     w.ip = in.pitch;
     w.io = in.off;
     w.cin = d.cin;
+    const UpSrc u = up_source(n, L);
+    if (u.c && !brick) return hipErrorInvalidValue;
+    w.up = u.p;
+    w.upp = u.pitch;
+    w.upo = 0;
+    w.upc = u.c;
     w.G = G;
     w.V = V;
     w.vsplit = vsplit;
@@ -2029,11 +2079,13 @@ hipError_t forward_impl(fedsur_net* n, int B, const bf16* x, float* y) {
     hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 2, B) * 8, 256)), dim3(256), 0, s, n->cat2,
                        192, 128, 64, G / 2, B, n->p2);
     if ((e = run_conv(n, E3A, x, B)) || (e = run_conv(n, E3B, x, B))) return e;
-    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 2, B) * 16, 256)), dim3(256), 0, s, n->e3b,
-                       128, G / 2, B, n->cat2, 192, 0);
+    if (!up_source(n, D2A).c)
+        hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 2, B) * 16, 256)), dim3(256), 0, s,
+                           n->e3b, 128, G / 2, B, n->cat2, 192, 0);
     if ((e = run_conv(n, D2A, x, B)) || (e = run_conv(n, D2B, x, B))) return e;
-    hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 1, B) * 8, 256)), dim3(256), 0, s, n->d2b,
-                       64, G, B, n->cat1, 96, 0);
+    if (!up_source(n, D1A).c)
+        hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 1, B) * 8, 256)), dim3(256), 0, s,
+                           n->d2b, 64, G, B, n->cat1, 96, 0);
     if ((e = run_conv(n, D1A, x, B)) || (e = run_conv(n, D1B, x, B))) return e;
     hipLaunchKernelGGL(k_head_fwd, dim3(nblocks(vox(n, 0, B), 256)), dim3(256), 0, s, n->d1b,
                        n->p + n->head_off, vox(n, 0, B), y);
