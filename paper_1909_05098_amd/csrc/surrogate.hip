@@ -60,6 +60,10 @@ struct ConvArgs {
     // upo; upc = 0: none (only the brick kernels take upc > 0)
     const bf16* up = nullptr;
     int upp = 0, upo = 0, upc = 0;
+    // also the 2 x 2 x 2 mean of the output, [V / 8][pp] (only the brick
+    // kernel), or null
+    bf16* pool = nullptr;
+    int pp = 0;
     const float* bias;  // may be null
     bf16* out;
     int op, oo, cout;   // output pitch, channel offset, channels
@@ -316,7 +320,8 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
 // halo and, when the chunk or the output block changes, its weights are in
 // flight into registers, stored to LDS between two barriers at the item's
 // end.  A unit's outputs leave through a 4 KB LDS slot per wave, as 16-byte
-// rows of eight outputs.  Within a dz plane the offsets go in three dx groups: output row mt
+// rows of eight outputs, and, for a layer whose output is pooled, their
+// 2 x 2 x 2 means too (read from the slots after one more barrier).  Within a dz plane the offsets go in three dx groups: output row mt
 // at dy reads halo row mt + dy, so a group reads six halo rows once for all
 // three dy.  156 KB of LDS and two waves per SIMD: one workgroup per CU, 32
 // per XCD.  Workgroups are dealt to the 8 XCDs round-robin; XCD x owns the
@@ -337,7 +342,7 @@ constexpr int kPWGPerXcd = 32;
 __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
     __shared__ bf16x8 halo[4][kPH];
     __shared__ bf16x8 wl[27][4][32];
-    __shared__ bf16 ep[8][64 * 32];  // per wave: its 64 voxels x 32 outputs
+    __shared__ __align__(16) bf16 ep[8][64 * 32];  // per wave: its 64 voxels x 32 outputs
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int G = a.G;
     const int nbx = G / kPBX, nby = G / kPBY, nbz = G / kPBZ;
@@ -505,6 +510,7 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
         // epilogue through this wave's LDS slot: C layout (lane holds rows
         // (lane / 16) 4 + i, column lane % 16) to voxel-major rows of 32
         // outputs, then 16-byte stores of eight outputs each
+        if (a.pool) __syncthreads();  // the previous unit's means have been read
         bf16* ew = &ep[wave][0];
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
@@ -532,6 +538,33 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
                 (((int64_t)w.bs * G + w.z0 + wave) * G + w.y0 + (m >> 4)) * G + w.x0 + (m & 15);
             *reinterpret_cast<uint4*>(a.out + vox * a.op + a.oo + co) = v;
         }
+        if (a.pool) {
+            // the brick's 8 x 2 x 4 means over 2 x 2 x 2 voxels from the
+            // slots of waves 2p and 2p + 1: wave p < 4 takes coarse plane p,
+            // lane: coarse voxel lane / 4 (x fastest), channel group lane % 4;
+            // summed in the order dz, dy, dx like k_pool_fwd
+            __syncthreads();
+            if (wave < 4) {
+                const int cv = lane >> 2, grp = lane & 3, cx = cv & 7, cy = cv >> 3;
+                const int co = w.cb * 32 + grp * 8;
+                float sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int d = 0; d < 8; d++) {
+                    const int m = (2 * cy + ((d >> 1) & 1)) * 16 + 2 * cx + (d & 1);
+                    const bf16x8 v =
+                        *reinterpret_cast<const bf16x8*>(&ep[2 * wave + (d >> 2)][m * 32 + grp * 8]);
+#pragma unroll
+                    for (int e = 0; e < 8; e++) sum[e] += (float)v[e];
+                }
+                bf16x8 o;
+#pragma unroll
+                for (int e = 0; e < 8; e++) o[e] = (bf16)(sum[e] * 0.125f);
+                const int Gh = G >> 1;
+                const int64_t pv = (((int64_t)w.bs * Gh + (w.z0 >> 1) + wave) * Gh + (w.y0 >> 1) + cy) *
+                                       Gh + (w.x0 >> 1) + cx;
+                if (co < a.cout) *reinterpret_cast<bf16x8*>(a.pool + pv * a.pp + co) = o;
+            }
+        }
     }
 }
 
@@ -547,7 +580,7 @@ constexpr int kP8WPT = (kP8Wts + 511) / 512;  // weight loads per thread: 2
 __global__ void __launch_bounds__(512) k_conv_p8(ConvArgs a, int per) {
     __shared__ bf16x8 halo[kPH];
     __shared__ bf16x8 wl[kP8Steps][4][32];
-    __shared__ bf16 ep[8][64 * 32];
+    __shared__ __align__(16) bf16 ep[8][64 * 32];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int G = a.G;
     const int nbx = G / kPBX, nby = G / kPBY, nbz = G / kPBZ;
@@ -719,8 +752,9 @@ __global__ void __launch_bounds__(512) k_conv_p8(ConvArgs a, int per) {
 
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
-    if (a.upc && !(a.ks == 3 && a.cin % 32 == 0 && a.upc % 32 == 0 && G % 16 == 0 && a.wp))
-        return hipErrorInvalidValue;  // only the brick kernel reads upsampled channels
+    if ((a.upc || a.pool) && !(a.ks == 3 && a.cin % 32 == 0 && a.upc % 32 == 0 && G % 16 == 0 &&
+                               a.wp && a.pp % 8 == 0))
+        return hipErrorInvalidValue;  // only the brick kernel reads upsampled channels and pools
     if (a.ks == 3 && a.cin == 8 && G % 16 == 0 && a.wp && a.cout % 8 == 0 && a.op % 8 == 0 &&
         a.oo % 8 == 0 && a.ip % 8 == 0 && a.io % 8 == 0) {
         // the first layer on the same bricks
@@ -746,7 +780,7 @@ hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
             return hipGetLastError();
         }
     }
-    if (a.upc) return hipErrorInvalidValue;
+    if (a.upc || a.pool) return hipErrorInvalidValue;
     if (a.ks == 3 && a.cin % 32 == 0 && G >= 8 && (G & (G - 1)) == 0) {
         // bricks of 256 voxels: 16 x 8 x 2, or 8 x 8 x 4 on an 8^3 grid
         const int BX = G >= 16 ? 16 : 8, BY = 8, BZ = 256 / (BX * BY);
@@ -1020,20 +1054,23 @@ __global__ void __launch_bounds__(512) k_wgrad_brick(WgradArgs a, int64_t per_sp
             const int hy = row % 6, hz = row / 6;
             const int y = y0 + hy - 1, z = z0 + hz - 1;
             const bool rowin = y >= 0 && y < G && z >= 0 && z < G;
-            const int64_t r0 = ((bs * G + min(max(z, 0), G - 1)) * G + min(max(y, 0), G - 1)) * G;
-            // the row's parent row at half resolution (upsampled channel chunks)
+            const int zc = min(max(z, 0), G - 1), yc = min(max(y, 0), G - 1);
+            // the row's first voxel and x stride; an upsampled channel chunk
+            // reads the parent row at half resolution (x / 2)
+            const bool upc = c0 < a.upc;
             const int Gh = G >> 1;
-            const int64_t pr0 =
-                ((bs * Gh + (min(max(z, 0), G - 1) >> 1)) * Gh + (min(max(y, 0), G - 1) >> 1)) * Gh;
+            const bf16* row_p =
+                upc ? a.up + (((bs * Gh + (zc >> 1)) * Gh + (yc >> 1)) * Gh) * a.upp + a.upo + c0 +
+                          cgp * 8
+                    : a.in + (((bs * G + zc) * G + yc) * G) * a.ip + a.io + c0 + cgp * 8;
+            const int xs = upc ? 1 : 0;
+            const int64_t pitch = upc ? a.upp : a.ip;
 #pragma unroll
             for (int hx = 0; hx < 18; hx++) {
                 const int x = x0 + hx - 1;
-                const bf16* src =
-                    c0 < a.upc
-                        ? a.up + ((pr0 + (x >> 1)) * a.upp + a.upo + c0 + cgp * 8)
-                        : a.in + ((r0 + x) * a.ip + a.io + c0 + cgp * 8);
-                st[hx] = (rowin && x >= 0 && x < G) ? *reinterpret_cast<const bf16x8*>(src)
-                                                    : zero8();
+                st[hx] = (rowin && x >= 0 && x < G)
+                             ? *reinterpret_cast<const bf16x8*>(row_p + (int64_t)(x >> xs) * pitch)
+                             : zero8();
             }
         }
     };
@@ -1927,6 +1964,17 @@ UpSrc up_source(const fedsur_net* n, int L) {
     return {nullptr, 0, 0};
 }
 
+// E1B's and E2B's outputs are pooled for the level below (p1: 32, p2: 64
+// channels); on grids of 16k the brick kernel writes the means itself.
+bf16* pool_target(const fedsur_net* n, int L, int& pitch) {
+    const int G = n->G >> kLayers[L].lvl;
+    pitch = 0;
+    if (G % 16) return nullptr;
+    if (L == E1B) return pitch = 32, n->p1;
+    if (L == E2B) return pitch = 64, n->p2;
+    return nullptr;
+}
+
 hipError_t run_conv(fedsur_net* n, int L, const bf16* x, int B) {
     const View in = in_view(n, L, x), out = out_view(n, L);
     ConvArgs a;
@@ -1942,6 +1990,7 @@ hipError_t run_conv(fedsur_net* n, int L, const bf16* x, int B) {
     a.upp = u.pitch;
     a.upo = 0;
     a.upc = u.c;
+    a.pool = pool_target(n, L, a.pp);
     a.bias = n->p + n->b_off[L];
     a.out = out.p;
     a.op = out.pitch;
@@ -2073,11 +2122,14 @@ hipError_t forward_impl(fedsur_net* n, int B, const bf16* x, float* y) {
     const int G = n->G;
     hipError_t e;
     if ((e = run_conv(n, E1A, x, B)) || (e = run_conv(n, E1B, x, B))) return e;
-    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 1, B) * 4, 256)), dim3(256), 0, s, n->cat1,
-                       96, 64, 32, G, B, n->p1);
+    int pp;
+    if (!pool_target(n, E1B, pp))
+        hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 1, B) * 4, 256)), dim3(256), 0, s,
+                           n->cat1, 96, 64, 32, G, B, n->p1);
     if ((e = run_conv(n, E2A, x, B)) || (e = run_conv(n, E2B, x, B))) return e;
-    hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 2, B) * 8, 256)), dim3(256), 0, s, n->cat2,
-                       192, 128, 64, G / 2, B, n->p2);
+    if (!pool_target(n, E2B, pp))
+        hipLaunchKernelGGL(k_pool_fwd, dim3(nblocks(vox(n, 2, B) * 8, 256)), dim3(256), 0, s,
+                           n->cat2, 192, 128, 64, G / 2, B, n->p2);
     if ((e = run_conv(n, E3A, x, B)) || (e = run_conv(n, E3B, x, B))) return e;
     if (!up_source(n, D2A).c)
         hipLaunchKernelGGL(k_up_fwd, dim3(nblocks(vox(n, 2, B) * 16, 256)), dim3(256), 0, s,
