@@ -510,7 +510,10 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
         // epilogue through this wave's LDS slot: C layout (lane holds rows
         // (lane / 16) 4 + i, column lane % 16) to voxel-major rows of 32
         // outputs, then 16-byte stores of eight outputs each
-        if (a.pool) __syncthreads();  // the previous unit's means have been read
+        // the previous unit's means must have been read before the slots are
+        // rewritten: a barrier of this unit's items orders that, except for a
+        // last unit of one chunk, which has none
+        if (a.pool && un > u0 && un + 1 == u1 && nch == 1) __syncthreads();
         bf16* ew = &ep[wave][0];
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
