@@ -952,6 +952,11 @@ def main():
     batched = run_sweep(sweep_scns, not args.no_autotune, sweep_recs) if sweep_scns else None
     surrogate = run_surrogate(sur_scns, args.surrogate_weights, scns_b=sur_scns_b) \
         if sur_scns else None
+    if surrogate is not None:
+        # the network alone at batch 8 (20 forward passes, 20 training steps):
+        # its kernels' rate without the rasteriser, decoder and resampler
+        surrogate["network_batch8"] = run_network_only(20)
+        log(f"surrogate network alone at batch 8: {surrogate['network_batch8']}")
     hexleg = run_hex(args) if args.hex else None
     cpu = None
     if not args.no_cpu:
