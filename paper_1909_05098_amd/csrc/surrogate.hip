@@ -1031,13 +1031,15 @@ __global__ void __launch_bounds__(512) k_wgrad_brick(WgradArgs a, int64_t per_sp
     const int kg = lane >> 4, lc = lane & 15;
     const bool bias_here = blockIdx.x == 0;
     // staging tasks: threads [0, 128) take 8 brick voxels x 8 output
-    // channels of D, threads [128, 128 + 36 CI / 8) one halo row of 8 input
-    // channels; the loads of the next brick are in flight during the
+    // channels of D, threads [128, 128 + 72 CI / 8) half a halo row (x
+    // positions 8 g .. 8 g + 9 of its 18) of 8 input channels, for all three
+    // shifted copies; the loads of the next brick are in flight during the
     // current brick's products
-    const bool dtask = t < 128, xtask = !dtask && t < 128 + kGRows * (CI / 8);
-    const int cg = t & 3, vg = t >> 2;                      // D task
-    const int xt = t - 128, row = xt / (CI / 8), cgp = xt % (CI / 8);  // halo task
-    bf16x8 st[18];
+    const bool dtask = t < 128, xtask = !dtask && t < 128 + 2 * kGRows * (CI / 8);
+    const int cg = t & 3, vg = t >> 2;  // D task
+    const int xt = t - 128, row = xt / (2 * (CI / 8)), cgp = xt % (CI / 8),
+              gx = (xt / (CI / 8)) & 1;  // halo task
+    bf16x8 st[10];
     auto stage_load = [&](int64_t b) {
         const int bx = (int)(b % nbx), by = (int)((b / nbx) % nby),
                   bz = (int)((b / ((int64_t)nbx * nby)) % nbz);
@@ -1069,11 +1071,11 @@ __global__ void __launch_bounds__(512) k_wgrad_brick(WgradArgs a, int64_t per_sp
             const int xs = upc ? 1 : 0;
             const int64_t pitch = upc ? a.upp : a.ip;
 #pragma unroll
-            for (int hx = 0; hx < 18; hx++) {
-                const int x = x0 + hx - 1;
-                st[hx] = (rowin && x >= 0 && x < G)
-                             ? *reinterpret_cast<const bf16x8*>(row_p + (int64_t)(x >> xs) * pitch)
-                             : zero8();
+            for (int e = 0; e < 10; e++) {
+                const int x = x0 + gx * 8 + e - 1;
+                st[e] = (rowin && x >= 0 && x < G)
+                            ? *reinterpret_cast<const bf16x8*>(row_p + (int64_t)(x >> xs) * pitch)
+                            : zero8();
             }
         }
     };
@@ -1084,16 +1086,15 @@ __global__ void __launch_bounds__(512) k_wgrad_brick(WgradArgs a, int64_t per_sp
             for (int i = 0; i < 8; i++) r[i] = st[i];
             transpose_store8(r, &dT[cg * 8][vg * 8], kGDP);
         } else if (xtask) {
-            // copy s holds halo x position x' + s at x'
+            // copy s holds halo x position x' + s at x' (this task: x' in
+            // [8 gx, 8 gx + 8), positions 8 gx + s .. held in st[s ..])
 #pragma unroll
-            for (int sh = 0; sh < 3; sh++)
+            for (int sh = 0; sh < 3; sh++) {
+                bf16x8 r[8];
 #pragma unroll
-                for (int g = 0; g < 2; g++) {
-                    bf16x8 r[8];
-#pragma unroll
-                    for (int i = 0; i < 8; i++) r[i] = st[sh + 8 * g + i];
-                    transpose_store8(r, &xs[sh][cgp * 8][row * 16 + 8 * g], kGXP);
-                }
+                for (int i = 0; i < 8; i++) r[i] = st[sh + i];
+                transpose_store8(r, &xs[sh][cgp * 8][row * 16 + 8 * gx], kGXP);
+            }
         }
     };
     f32x4 acc[4][2][NT];
