@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int BX, int BY, in
 // flight into registers, stored to LDS between two barriers at the item's
 // end.  A unit's outputs leave through a 4 KB LDS slot per wave, as 16-byte
 // rows of eight outputs, and, for a layer whose output is pooled, their
-// 2 x 2 x 2 means too (read from the slots after one more barrier).  Within a dz plane the offsets go in three dx groups: output row mt
+// 2 x 2 x 2 means too (read from the slots at the next item's end barrier).  Within a dz plane the offsets go in three dx groups: output row mt
 // at dy reads halo row mt + dy, so a group reads six halo rows once for all
 // three dy.  156 KB of LDS and two waves per SIMD: one workgroup per CU, 32
 // per XCD.  Workgroups are dealt to the 8 XCDs round-robin; XCD x owns the
@@ -444,6 +444,36 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
         for (int u = 0; u < kPWPT; u++) wts_store(u, wr[u]);
     }
     __syncthreads();
+    // the 2 x 2 x 2 means of unit w's outputs, from the epilogue slots of
+    // waves 2p and 2p + 1: wave p < 4 takes coarse plane p, lane: coarse voxel
+    // lane / 4 (x fastest), channel group lane % 4; summed in the order dz,
+    // dy, dx like k_pool_fwd.  Run by the waves after a barrier that follows
+    // the unit's epilogue, before any slot is rewritten.
+    auto pool_means = [&](const Unit& w) {
+        if (wave >= 4) return;
+        const int cv = lane >> 2, grp = lane & 3, cx = cv & 7, cy = cv >> 3;
+        const int co = w.cb * 32 + grp * 8;
+        float sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
+            const int m = (2 * cy + ((d >> 1) & 1)) * 16 + 2 * cx + (d & 1);
+            const bf16x8 v =
+                *reinterpret_cast<const bf16x8*>(&ep[2 * wave + (d >> 2)][m * 32 + grp * 8]);
+#pragma unroll
+            for (int e = 0; e < 8; e++) sum[e] += (float)v[e];
+        }
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; e++) o[e] = (bf16)(sum[e] * 0.125f);
+        const int Gh = G >> 1;
+        const int64_t pv =
+            (((int64_t)w.bs * Gh + (w.z0 >> 1) + wave) * Gh + (w.y0 >> 1) + cy) * Gh + (w.x0 >> 1) + cx;
+        if (co < a.cout) *reinterpret_cast<bf16x8*>(a.pool + pv * a.pp + co) = o;
+    };
+    // a unit whose means are still to be written: they are formed at the
+    // next barrier pair (the next item's end), after its epilogue
+    bool pend = false;
+    Unit wpend = unit(u0);
     for (int un = u0; un < u1; un++) {
         const Unit w = unit(un);
         const Unit wn = unit(min(un + 1, u1 - 1));
@@ -498,6 +528,10 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
             }
             if (next) {
                 __syncthreads();  // no wave still reads this item's halo or weights
+                if (pend) {
+                    pool_means(wpend);
+                    pend = false;
+                }
 #pragma unroll
                 for (int u = 0; u < kPSPT; u++) halo_store(wx, u, hr[u]);
                 if (new_w) {
@@ -510,10 +544,14 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
         // epilogue through this wave's LDS slot: C layout (lane holds rows
         // (lane / 16) 4 + i, column lane % 16) to voxel-major rows of 32
         // outputs, then 16-byte stores of eight outputs each
-        // the previous unit's means must have been read before the slots are
-        // rewritten: a barrier of this unit's items orders that, except for a
-        // last unit of one chunk, which has none
-        if (a.pool && un > u0 && un + 1 == u1 && nch == 1) __syncthreads();
+        // means still pending (no barrier pair since their epilogue): form
+        // them now, between two barriers, before the slots are rewritten
+        if (pend) {
+            __syncthreads();
+            pool_means(wpend);
+            pend = false;
+            __syncthreads();
+        }
         bf16* ew = &ep[wave][0];
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
@@ -542,45 +580,29 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
             *reinterpret_cast<uint4*>(a.out + vox * a.op + a.oo + co) = v;
         }
         if (a.pool) {
-            // the brick's 8 x 2 x 4 means over 2 x 2 x 2 voxels from the
-            // slots of waves 2p and 2p + 1: wave p < 4 takes coarse plane p,
-            // lane: coarse voxel lane / 4 (x fastest), channel group lane % 4;
-            // summed in the order dz, dy, dx like k_pool_fwd
-            __syncthreads();
-            if (wave < 4) {
-                const int cv = lane >> 2, grp = lane & 3, cx = cv & 7, cy = cv >> 3;
-                const int co = w.cb * 32 + grp * 8;
-                float sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-                for (int d = 0; d < 8; d++) {
-                    const int m = (2 * cy + ((d >> 1) & 1)) * 16 + 2 * cx + (d & 1);
-                    const bf16x8 v =
-                        *reinterpret_cast<const bf16x8*>(&ep[2 * wave + (d >> 2)][m * 32 + grp * 8]);
-#pragma unroll
-                    for (int e = 0; e < 8; e++) sum[e] += (float)v[e];
-                }
-                bf16x8 o;
-#pragma unroll
-                for (int e = 0; e < 8; e++) o[e] = (bf16)(sum[e] * 0.125f);
-                const int Gh = G >> 1;
-                const int64_t pv = (((int64_t)w.bs * Gh + (w.z0 >> 1) + wave) * Gh + (w.y0 >> 1) + cy) *
-                                       Gh + (w.x0 >> 1) + cx;
-                if (co < a.cout) *reinterpret_cast<bf16x8*>(a.pool + pv * a.pp + co) = o;
-            }
+            pend = true;
+            wpend = w;
         }
+    }
+    if (pend) {
+        __syncthreads();
+        pool_means(wpend);
     }
 }
 
 // The first layer (8 input channels) on the same bricks and schedule: one
 // 32-wide MFMA step takes four offsets x 8 channels (lane group kg holds
 // offset 4 s + kg), 7 steps for the 27 offsets, the 28th a zero weight row
-// (its A lanes read offset 26, a finite value).  Halo 17 KB, weights 14 KB.
+// (its A lanes read offset 26, a finite value).  Halo 17 KB, weights 14 KB,
+// at most 128 registers: two workgroups (16 waves) share a CU, whose other
+// workgroup's waves cover a step's LDS latency.
 constexpr int kP8Steps = 7;
 constexpr int kP8Wts = kP8Steps * 4 * 32;     // 16-byte weight elements per block
 constexpr int kP8SPT = (kPH + 511) / 512;     // halo loads per thread: 3
 constexpr int kP8WPT = (kP8Wts + 511) / 512;  // weight loads per thread: 2
 
-__global__ void __launch_bounds__(512) k_conv_p8(ConvArgs a, int per) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_conv_p8(ConvArgs a, int per) {
     __shared__ bf16x8 halo[kPH];
     __shared__ bf16x8 wl[kP8Steps][4][32];
     __shared__ __align__(16) bf16 ep[8][64 * 32];
@@ -688,29 +710,17 @@ __global__ void __launch_bounds__(512) k_conv_p8(ConvArgs a, int per) {
         for (int mt = 0; mt < 4; mt++)
 #pragma unroll
             for (int nt = 0; nt < 2; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        bf16x8 A[4], B[2];
-        loadA(0, A);
-        loadB(0, B);
 #pragma unroll
         for (int st = 0; st < kP8Steps; st++) {
-            bf16x8 An[4], Bn[2];
-            if (st + 1 < kP8Steps) {
-                loadA(st + 1, An);
-                loadB(st + 1, Bn);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            bf16x8 A[4], B[2];
+            loadA(st, A);
+            loadB(st, B);
 #pragma unroll
             for (int mt = 0; mt < 4; mt++)
 #pragma unroll
                 for (int nt = 0; nt < 2; nt++)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt],
                                                                           acc[mt][nt], 0, 0, 0);
-            if (st + 1 < kP8Steps) {
-#pragma unroll
-                for (int mt = 0; mt < 4; mt++) A[mt] = An[mt];
-#pragma unroll
-                for (int nt = 0; nt < 2; nt++) B[nt] = Bn[nt];
-            }
         }
         if (next) {
             __syncthreads();  // no wave still reads this unit's halo or weights
