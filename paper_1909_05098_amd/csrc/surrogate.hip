@@ -1189,6 +1189,8 @@ constexpr int kWgradChunk = 128;
 inline int wgrad_kn(int cout) { return cout <= 32 ? 256 : 128; }
 inline int wgrad_cot(int cout) { return cout <= 32 ? 32 : (cout <= 64 ? 64 : 128); }
 constexpr int kWgradBlocks = 1024;  // workgroups aimed at per layer
+// the brick form runs one workgroup per CU (128 KB of LDS): one wave of them
+constexpr int kWgradBrickBlocks = 256;
 
 // voxel split of a layer's weight gradient: ~kWgradBlocks workgroups, splits
 // of whole chunks; never more than kWgradBlocks / tiles splits
@@ -1432,12 +1434,21 @@ __global__ void __launch_bounds__(256) k_head_bwd(const float* __restrict__ dy,
 #pragma unroll
         for (int c = 0; c < 32; c++) x[c] = 0.0f;
     }
-    for (int c = 0; c < 32; c++) {
-        const float s = block_sum256(dv * x[c], sh);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 33 + c] = s;
+    // the block's 33 sums (dy x per channel, and dy): a butterfly within
+    // each wave, then the four waves' sums in order (fixed, so the result is
+    // reproducible)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 33; c++) {
+        float v = c < 32 ? dv * x[c] : dv;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) sh[wave * 33 + c] = v;
     }
-    const float s = block_sum256(dv, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 33 + 32] = s;
+    __syncthreads();
+    if (threadIdx.x < 33)
+        part[(int64_t)blockIdx.x * 33 + threadIdx.x] =
+            ((sh[threadIdx.x] + sh[33 + threadIdx.x]) + sh[66 + threadIdx.x]) + sh[99 + threadIdx.x];
 }
 
 // out[j] = sum_b part[b][j]: one workgroup per column j, each thread summing
@@ -2028,7 +2039,8 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     hipStream_t s = n->stream;
     hipLaunchKernelGGL(k_relu_bwd, dim3(nblocks(V * (d.cout / 8), 256)), dim3(256), 0, s, gout.p,
                        gout.pitch, gout.off, out.p, out.pitch, out.off, d.cout, V, dpre);
-    // weight and bias gradient: ~kWgradBlocks workgroups over tiles x splits
+    // weight and bias gradient: ~kWgradBlocks (brick form: kWgradBrickBlocks)
+    // workgroups over tiles x splits
     const bool brick = G % 16 == 0 && d.cin % 32 == 0 && d.cout % 32 == 0;
     const int KN = wgrad_kn(d.cout), COT = wgrad_cot(d.cout);
     const int kb = brick ? d.cin / 32 : n->kp2[L] / KN;
@@ -2037,7 +2049,8 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     if (brick) {
         // runs of whole bricks; the partial buffer bounds the number of runs
         const int64_t nbr = V / 256;
-        const int64_t want = std::max<int64_t>(1, (kWgradBlocks + kb * cb - 1) / (kb * cb));
+        const int64_t want =
+            std::max<int64_t>(1, (kWgradBrickBlocks + kb * cb - 1) / (kb * cb));
         const int64_t cap = n->part_cap / ((int64_t)d.cout * n->kp2[L]);
         splits = std::max<int64_t>(1, std::min({want, nbr, cap, (int64_t)65535}));
         per = (nbr + splits - 1) / splits;
