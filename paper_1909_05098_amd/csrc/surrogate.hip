@@ -4,18 +4,23 @@
 // accumulation):
 //   forward   M = voxels, N = output channels, K = 27 * input channels
 //             (offset-major, channel-minor), each lane loading 8 consecutive
-//             input channels of one voxel (16 bytes, channels-last);
-//   data grad the same kernel with the weights flipped in space and
+//             input channels of one voxel (16 bytes, channels-last); on
+//             grids of 16k a persistent brick kernel (k_conv_p, k_conv_p8)
+//             with the halo and a chunk's weights in LDS, which also writes
+//             the pooled means of its output and reads upsampled input
+//             channels at their parent voxel; gathered kernels otherwise;
+//   data grad the same kernels with the weights flipped in space and
 //             transposed in channels (a 3x3x3 correlation of the gradient);
 //   weight grad M = output channels, N = 27 * input channels + 1 (the
-//             bias), K = voxels: 128-voxel chunks of the gradient and of the
-//             gathered input are transposed in registers and staged in LDS
-//             so that each lane reads 8 consecutive voxels of one channel;
-//             partial sums per voxel split are reduced in a fixed order
-//             (bit-reproducible).
+//             bias), K = voxels: bricks (or 128-voxel chunks) of the
+//             gradient and of the input are transposed in registers and
+//             staged in LDS so that each lane reads 8 consecutive voxels of
+//             one channel; partial sums per voxel split are reduced in a
+//             fixed order (bit-reproducible).
 // The remaining kernels are memory-bound elementwise passes: ReLU backward,
-// pooling, upsampling, the 1x1x1 head, the masked loss, Adam, weight
-// packing, input rasterisation and the resampling of FED-FEM fields.
+// pooling, upsampling (on small grids), the 1x1x1 head, the masked loss,
+// Adam, weight packing, input rasterisation and the resampling of FED-FEM
+// fields.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
