@@ -2054,8 +2054,8 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     if (brick) {
         // runs of whole bricks; the partial buffer bounds the number of runs
         const int64_t nbr = V / 256;
-        const int64_t want =
-            std::max<int64_t>(1, (kWgradBrickBlocks + kb * cb - 1) / (kb * cb));
+        // at most one workgroup per CU in all (a second round would run alone)
+        const int64_t want = std::max<int64_t>(1, kWgradBrickBlocks / (kb * cb));
         const int64_t cap = n->part_cap / ((int64_t)d.cout * n->kp2[L]);
         splits = std::max<int64_t>(1, std::min({want, nbr, cap, (int64_t)65535}));
         per = (nbr + splits - 1) / splits;
