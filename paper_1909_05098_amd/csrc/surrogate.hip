@@ -69,6 +69,11 @@ struct ConvArgs {
     // kernel), or null
     bf16* pool = nullptr;
     int pp = 0;
+    // output element kept only where mk (a ReLU's output, pitch mkp, offset
+    // mko) is positive: the backward of that ReLU applied to the stored BF16
+    // value (only the brick kernel), or null
+    const bf16* mk = nullptr;
+    int mkp = 0, mko = 0;
     const float* bias;  // may be null
     bf16* out;
     int op, oo, cout;   // output pitch, channel offset, channels
@@ -579,10 +584,16 @@ __global__ void __launch_bounds__(512) k_conv_p(ConvArgs a, int per) {
             const int idx = p * 64 + lane, m = idx >> 2, part = idx & 3;
             const int co = w.cb * 32 + part * 8;
             if (co >= a.cout) continue;  // cout is a multiple of 8
-            const uint4 v = *reinterpret_cast<const uint4*>(&ew[m * 32 + part * 8]);
+            bf16x8 v = *reinterpret_cast<const bf16x8*>(&ew[m * 32 + part * 8]);
             const int64_t vox =
                 (((int64_t)w.bs * G + w.z0 + wave) * G + w.y0 + (m >> 4)) * G + w.x0 + (m & 15);
-            *reinterpret_cast<uint4*>(a.out + vox * a.op + a.oo + co) = v;
+            if (a.mk) {
+                const bf16x8 y = *reinterpret_cast<const bf16x8*>(a.mk + vox * a.mkp + a.mko + co);
+#pragma unroll
+                for (int e = 0; e < 8; e++)
+                    if (!((float)y[e] > 0.0f)) v[e] = (bf16)0.0f;
+            }
+            *reinterpret_cast<bf16x8*>(a.out + vox * a.op + a.oo + co) = v;
         }
         if (a.pool) {
             pend = true;
@@ -770,9 +781,11 @@ k_conv_p8(ConvArgs a, int per) {
 
 hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
     const int G = a.G;
-    if ((a.upc || a.pool) && !(a.ks == 3 && a.cin % 32 == 0 && a.upc % 32 == 0 && G % 16 == 0 &&
-                               a.wp && a.pp % 8 == 0))
-        return hipErrorInvalidValue;  // only the brick kernel reads upsampled channels and pools
+    if ((a.upc || a.pool || a.mk) &&
+        !(a.ks == 3 && a.cin % 32 == 0 && a.upc % 32 == 0 && G % 16 == 0 && a.wp &&
+          a.pp % 8 == 0 && a.mkp % 8 == 0 && a.mko % 8 == 0))
+        return hipErrorInvalidValue;  // only the brick kernel reads upsampled channels, pools
+                                      // and masks
     if (a.ks == 3 && a.cin == 8 && G % 16 == 0 && a.wp && a.cout % 8 == 0 && a.op % 8 == 0 &&
         a.oo % 8 == 0 && a.ip % 8 == 0 && a.io % 8 == 0) {
         // the first layer on the same bricks
@@ -798,7 +811,7 @@ hipError_t conv_fwd(const ConvArgs& a, hipStream_t s) {
             return hipGetLastError();
         }
     }
-    if (a.upc || a.pool) return hipErrorInvalidValue;
+    if (a.upc || a.pool || a.mk) return hipErrorInvalidValue;
     if (a.ks == 3 && a.cin % 32 == 0 && G >= 8 && (G & (G - 1)) == 0) {
         // bricks of 256 voxels: 16 x 8 x 2, or 8 x 8 x 4 on an 8^3 grid
         const int BX = G >= 16 ? 16 : 8, BY = 8, BZ = 256 / (BX * BY);
@@ -1318,9 +1331,11 @@ __global__ void k_pool_fwd(const bf16* __restrict__ in, int ip, int io, int C, i
 }
 
 // out[v][c] (contiguous, grid G) = a[v][c] + gp[parent(v)][c] / 8
-// one thread per coarse voxel and 8 channels: out = a + g / 8 at its children
+// one thread per coarse voxel and 8 channels: out = a + g / 8 at its
+// children, then through the ReLU whose output is y (kept where y > 0)
 __global__ void k_pool_bwd_add(const bf16* __restrict__ a, int ap, int ao,
                                const bf16* __restrict__ gpar, int C, int G, int B,
+                               const bf16* __restrict__ y, int yp, int yo,
                                bf16* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c8 = C / 8, H = G / 2;
@@ -1330,15 +1345,21 @@ __global__ void k_pool_bwd_add(const bf16* __restrict__ a, int ap, int ao,
     const int c = (int)(i32 % (uint32_t)c8) * 8;
     const Coarse q = coarse_of(i32 / (uint32_t)c8, G);
     const bf16x8 gv = *reinterpret_cast<const bf16x8*>(gpar + (int64_t)q.u * C + c);
-    bf16x8 av[8];
+    bf16x8 av[8], yv[8];
 #pragma unroll
-    for (int d = 0; d < 8; d++)
-        av[d] = *reinterpret_cast<const bf16x8*>(a + (int64_t)child(q.v0, d, G) * ap + ao + c);
+    for (int d = 0; d < 8; d++) {
+        const int64_t v = child(q.v0, d, G);
+        av[d] = *reinterpret_cast<const bf16x8*>(a + v * ap + ao + c);
+        yv[d] = *reinterpret_cast<const bf16x8*>(y + v * yp + yo + c);
+    }
 #pragma unroll
     for (int d = 0; d < 8; d++) {
         bf16x8 o;
 #pragma unroll
-        for (int j = 0; j < 8; j++) o[j] = (bf16)((float)av[d][j] + 0.125f * (float)gv[j]);
+        for (int j = 0; j < 8; j++) {
+            const bf16 gsum = (bf16)((float)av[d][j] + 0.125f * (float)gv[j]);
+            o[j] = (float)yv[d][j] > 0.0f ? gsum : (bf16)0.0f;
+        }
         *reinterpret_cast<bf16x8*>(out + (int64_t)child(q.v0, d, G) * C + c) = o;
     }
 }
@@ -1361,8 +1382,10 @@ __global__ void k_up_fwd(const bf16* __restrict__ in, int C, int G, int B, bf16*
 }
 
 // out[u][c] (contiguous, grid G/2) = sum of g over the 2x2x2 children of u
+// one thread per coarse voxel and 8 channels: the sum over its children,
+// then through the ReLU whose output is y (kept where y > 0)
 __global__ void k_up_bwd(const bf16* __restrict__ g, int gp, int go, int C, int G, int B,
-                         bf16* __restrict__ out) {
+                         const bf16* __restrict__ y, int yp, int yo, bf16* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int H = G / 2, c8 = C / 8;
     const int64_t n = (int64_t)B * H * H * H * c8;
@@ -1379,9 +1402,10 @@ __global__ void k_up_bwd(const bf16* __restrict__ g, int gp, int go, int C, int 
     for (int d = 0; d < 8; d++)
 #pragma unroll
         for (int j = 0; j < 8; j++) s[j] += (float)x[d][j];
+    const bf16x8 yv = *reinterpret_cast<const bf16x8*>(y + (int64_t)q.u * yp + yo + c);
     bf16x8 o;
 #pragma unroll
-    for (int j = 0; j < 8; j++) o[j] = (bf16)s[j];
+    for (int j = 0; j < 8; j++) o[j] = (float)yv[j] > 0.0f ? (bf16)s[j] : (bf16)0.0f;
     *reinterpret_cast<bf16x8*>(out + (int64_t)q.u * C + c) = o;
 }
 
@@ -1431,7 +1455,8 @@ __global__ void __launch_bounds__(256) k_head_bwd(const float* __restrict__ dy,
 #pragma unroll
             for (int j = 0; j < 8; j++) {
                 x[c8 * 8 + j] = (float)xv[j];
-                o[j] = (bf16)(dv * w[c8 * 8 + j]);
+                // through d1b's ReLU: kept where its output is positive
+                o[j] = x[c8 * 8 + j] > 0.0f ? (bf16)(dv * w[c8 * 8 + j]) : (bf16)0.0f;
             }
             *reinterpret_cast<bf16x8*>(g + v * 32 + c8 * 8) = o;
         }
@@ -2033,17 +2058,18 @@ hipError_t run_conv(fedsur_net* n, int L, const bf16* x, int B) {
     return conv_fwd(a, n->stream);
 }
 
-// pre-activation gradient of layer L into dpre (contiguous [V][cout]),
-// then weight/bias gradients, then (if dx) the input gradient into dx
-hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View& gout,
-                         bf16* dpre, const View* dx) {
+// weight/bias gradients of layer L from its pre-activation gradient dpre
+// (contiguous [V][cout], the producer having applied L's ReLU), then (if dx)
+// the gradient of its input into dx, passed through the ReLU whose output is
+// dxmask when one is given (the layer below): fused into the brick kernel's
+// epilogue, or an in-place pass after the gathered kernels
+hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const bf16* dpre,
+                         const View* dx, const View* dxmask) {
     const LayerDef& d = kLayers[L];
-    const View out = out_view(n, L), in = in_view(n, L, x);
+    const View in = in_view(n, L, x);
     const int64_t V = vox(n, d.lvl, B);
     const int G = n->G >> d.lvl;
     hipStream_t s = n->stream;
-    hipLaunchKernelGGL(k_relu_bwd, dim3(nblocks(V * (d.cout / 8), 256)), dim3(256), 0, s, gout.p,
-                       gout.pitch, gout.off, out.p, out.pitch, out.off, d.cout, V, dpre);
     // weight and bias gradient: ~kWgradBlocks (brick form: kWgradBrickBlocks)
     // workgroups over tiles x splits
     const bool brick = G % 16 == 0 && d.cin % 32 == 0 && d.cout % 32 == 0;
@@ -2115,7 +2141,21 @@ hipError_t conv_backward(fedsur_net* n, int L, const bf16* x, int B, const View&
     a.ks = 3;
     a.relu = 0;
     a.V = V;
-    return conv_fwd(a, s);
+    const bool fuse_mask = dxmask && G % 16 == 0 && d.cout % 32 == 0 && a.wp;
+    if (fuse_mask) {
+        a.mk = dxmask->p;
+        a.mkp = dxmask->pitch;
+        a.mko = dxmask->off;
+    }
+    if (hipError_t e1 = conv_fwd(a, s)) return e1;
+    if (dxmask && !fuse_mask) {
+        if (dx->pitch != d.cin || dx->off) return hipErrorInvalidValue;
+        // dx is contiguous here ([V][cin]); each element is read, then written
+        hipLaunchKernelGGL(k_relu_bwd, dim3(nblocks(V * (d.cin / 8), 256)), dim3(256), 0, s,
+                           dx->p, dx->pitch, dx->off, dxmask->p, dxmask->pitch, dxmask->off,
+                           d.cin, V, dx->p);
+    }
+    return hipGetLastError();
 }
 
 hipError_t pack_all(fedsur_net* n) {
@@ -2182,44 +2222,49 @@ hipError_t backward_impl(fedsur_net* n, int B, const bf16* x) {
     const int G = n->G;
     const int64_t V0 = vox(n, 0, B), V1 = vox(n, 1, B), V2 = vox(n, 2, B);
     hipError_t e;
-    // head: dL/d(d1b) into gA0 [V0][32], head weight/bias partials
+    // Every gradient handed to conv_backward is pre-activation: its producer
+    // (the head, a 2 x 2 x 2 pass or the layer above's data gradient) applies
+    // the layer's ReLU.  Pre-activation gradients alternate between the gA*
+    // and gB* buffers of each level.
+    // head: dL/d(d1b) through d1b's ReLU into gA0 [V0][32], head partials
     const int64_t nb = (V0 + 255) / 256;
     if (nb * 33 > n->part_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)nb), dim3(256), 0, s, n->dy, n->d1b,
                        n->p + n->head_off, V0, n->gA0, n->part);
     hipLaunchKernelGGL(k_colreduce, dim3(33), dim3(256), 0, s, n->part, nb, 33, n->g + n->head_off);
-    // d1b, d1a (input: cat1 -> gcat1)
-    const View gA0{n->gA0, 32, 0, 32, 0}, gB0{n->gB0, 32, 0, 32, 0};
-    const View gc1{n->gcat1, 96, 0, 96, 0};
-    // pre-activation gradients go to gB0 / gA0 alternately (contiguous [V][32])
-    if ((e = conv_backward(n, D1B, x, B, gA0, n->gB0, &gA0))) return e;
-    if ((e = conv_backward(n, D1A, x, B, gA0, n->gB0, &gc1))) return e;
-    // upsample backward: channels [0, 64) of gcat1 -> g(d2b) in gA1 [V1][64]
+    const View gB0{n->gB0, 32, 0, 32, 0}, gB1{n->gB1, 64, 0, 64, 1};
+    const View gB2{n->gB2, 128, 0, 128, 2};
+    const View gc1{n->gcat1, 96, 0, 96, 0}, gc2{n->gcat2, 192, 0, 192, 1};
+    const View gp1{n->gp1, 32, 0, 32, 1}, gp2{n->gp2, 64, 0, 64, 2};
+    const View o_d1a = out_view(n, D1A), o_d2a = out_view(n, D2A), o_e3a = out_view(n, E3A);
+    const View o_e2a = out_view(n, E2A), o_e1a = out_view(n, E1A);
+    const View o_d2b = out_view(n, D2B), o_e3b = out_view(n, E3B);
+    const View o_e2b = out_view(n, E2B), o_e1b = out_view(n, E1B);
+    // d1b (input d1a, through d1a's ReLU -> gB0), d1a (input cat1 -> gcat1)
+    if ((e = conv_backward(n, D1B, x, B, n->gA0, &gB0, &o_d1a))) return e;
+    if ((e = conv_backward(n, D1A, x, B, n->gB0, &gc1, nullptr))) return e;
+    // upsample backward: channels [0, 64) of gcat1, through d2b's ReLU -> gA1
     hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(V1 * 8, 256)), dim3(256), 0, s, n->gcat1, 96, 0, 64,
-                       G, B, n->gA1);
-    const View gA1{n->gA1, 64, 0, 64, 1};
-    const View gc2{n->gcat2, 192, 0, 192, 1};
-    if ((e = conv_backward(n, D2B, x, B, gA1, n->gB1, &gA1))) return e;
-    if ((e = conv_backward(n, D2A, x, B, gA1, n->gB1, &gc2))) return e;
-    // channels [0, 128) of gcat2 -> g(e3b) in gA2 [V2][128]
+                       G, B, o_d2b.p, o_d2b.pitch, o_d2b.off, n->gA1);
+    if ((e = conv_backward(n, D2B, x, B, n->gA1, &gB1, &o_d2a))) return e;
+    if ((e = conv_backward(n, D2A, x, B, n->gB1, &gc2, nullptr))) return e;
+    // channels [0, 128) of gcat2, through e3b's ReLU -> gA2 [V2][128]
     hipLaunchKernelGGL(k_up_bwd, dim3(nblocks(V2 * 16, 256)), dim3(256), 0, s, n->gcat2, 192, 0,
-                       128, G / 2, B, n->gA2);
-    const View gA2{n->gA2, 128, 0, 128, 2};
-    const View gp2{n->gp2, 64, 0, 64, 2};
-    if ((e = conv_backward(n, E3B, x, B, gA2, n->gB2, &gA2))) return e;
-    if ((e = conv_backward(n, E3A, x, B, gA2, n->gB2, &gp2))) return e;
-    // g(e2b) = gcat2[:, 128:192] + pool backward of g(p2), into gA1
+                       128, G / 2, B, o_e3b.p, o_e3b.pitch, o_e3b.off, n->gA2);
+    if ((e = conv_backward(n, E3B, x, B, n->gA2, &gB2, &o_e3a))) return e;
+    if ((e = conv_backward(n, E3A, x, B, n->gB2, &gp2, nullptr))) return e;
+    // g(e2b) = gcat2[:, 128:192] + pool backward of g(p2), through e2b's ReLU
+    // -> gA1
     hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V2 * 8, 256)), dim3(256), 0, s, n->gcat2, 192,
-                       128, n->gp2, 64, G / 2, B, n->gA1);
-    const View gp1{n->gp1, 32, 0, 32, 1};
-    if ((e = conv_backward(n, E2B, x, B, gA1, n->gB1, &gA1))) return e;
-    if ((e = conv_backward(n, E2A, x, B, gA1, n->gB1, &gp1))) return e;
-    // g(e1b) = gcat1[:, 64:96] + pool backward of g(p1), into gA0
+                       128, n->gp2, 64, G / 2, B, o_e2b.p, o_e2b.pitch, o_e2b.off, n->gA1);
+    if ((e = conv_backward(n, E2B, x, B, n->gA1, &gB1, &o_e2a))) return e;
+    if ((e = conv_backward(n, E2A, x, B, n->gB1, &gp1, nullptr))) return e;
+    // g(e1b) = gcat1[:, 64:96] + pool backward of g(p1), through e1b's ReLU
+    // -> gA0
     hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblocks(V1 * 4, 256)), dim3(256), 0, s, n->gcat1, 96,
-                       64, n->gp1, 32, G, B, n->gA0);
-    if ((e = conv_backward(n, E1B, x, B, gA0, n->gB0, &gA0))) return e;
-    if ((e = conv_backward(n, E1A, x, B, gA0, n->gB0, nullptr))) return e;
-    (void)gB0;
+                       64, n->gp1, 32, G, B, o_e1b.p, o_e1b.pitch, o_e1b.off, n->gA0);
+    if ((e = conv_backward(n, E1B, x, B, n->gA0, &gB0, &o_e1a))) return e;
+    if ((e = conv_backward(n, E1A, x, B, n->gB0, nullptr, nullptr))) return e;
     return hipGetLastError();
 }
 
