@@ -138,11 +138,13 @@ def gpu_cache(net, x, B, q):
     return c
 
 
-@pytest.mark.parametrize("G,B", [(8, 2), (16, 1)])
+@pytest.mark.parametrize("G,B", [(8, 2), (16, 1), (32, 1)])
 def test_loss_and_gradients(torch_cuda, G, B):
     """At 8^3 every weight gradient takes the gathered kernel; at 16^3 the
     full-resolution layers with 32-channel inputs (e1b, d1a, d1b) take the
-    brick kernel."""
+    brick kernel; at 32^3 the 16^3 level too (e2a, e2b, d2a, d2b: d2a's
+    upsampled input read in place, the data gradients passed through the
+    next layer's ReLU in the convolution's epilogue)."""
     torch = torch_cuda
     rng, net, Q, x, X = setup(torch, G, B, 5)
     t = rng.normal(size=(B, G, G, G)).astype(np.float32)
