@@ -124,7 +124,11 @@ typedef struct {
      * corners one tile places on a node (max_tile_valence) */
     int32_t max_tile_valence;
     int32_t fixed_point_shift;
-    int32_t reserved[5];
+    /* nodes that a single tile touches (reordered tetrahedral layouts; 0
+     * otherwise): the nodal update reads their one tile sum at the node's
+     * own index */
+    int32_t n_single_tile_nodes;
+    int32_t reserved[4];
 } fedfem_info;
 
 /*

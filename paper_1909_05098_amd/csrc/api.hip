@@ -677,6 +677,7 @@ int fedfem_precompute(fedfem_handle* h) {
     d.E = E;
     d.T = L.T;
     d.P = L.P;
+    d.n_int = L.n_int;
     d.tile_elems = L.tile_elems;
     d.npe = h->npe;
     d.max_tile_nodes = L.max_tile_nodes;
@@ -703,6 +704,7 @@ int fedfem_precompute(fedfem_handle* h) {
     if ((rc = upload(h, &d.tile_elem_off, L.tile_elem_off)) ||
         (rc = upload(h, &d.tile_node_off, L.tile_node_off)) ||
         (rc = upload(h, &d.tile_nodes, L.tile_nodes)) ||
+        (rc = upload(h, &d.tile_part, L.tile_part)) ||
         (rc = upload(h, &d.pidx, L.pidx)) || (rc = upload(h, &d.part_off, L.part_off)) ||
         (rc = upload(h, &h->d_ec_off, L.ec_off)) || (rc = upload(h, &h->d_ec, L.ec)) ||
         (rc = upload(h, &h->d_conn, L.conn)) || (rc = upload(h, &h->d_xyz, L.xyz)) ||
@@ -1476,6 +1478,7 @@ int fedfem_get_info(const fedfem_handle* h, fedfem_info* info) {
     info->lanczos_iterations = h->lz_iters;
     info->max_tile_valence = h->L.max_tile_valence;
     info->fixed_point_shift = std::ilogb(h->fx_scale);
+    info->n_single_tile_nodes = (int32_t)h->d.n_int;
     return FEDFEM_OK;
 }
 

@@ -194,7 +194,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     }
     // integer tables on the host
     std::vector<int32_t> tno(Tt + 1), tnodes(Pt), poff(Nt + 1, 0), wp(Pt), teo(Tt + 1), tsc(Tt),
-        bsc(Nt / 256);
+        bsc(Nt / 256), tpart(4 * Tt);
     for (int j = 0; j < n; j++) {
         const fedfem_handle* h = handles[j];
         const Layout& L = h->L;
@@ -204,6 +204,14 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
             tno[to + t] = (int32_t)(L.tile_node_off[t] + pb);
             teo[to + t] = (int32_t)(eo + L.tile_elem_off[t]);
             tsc[to + t] = j;
+            // single-tile node ids shift with the nodes, positions with the
+            // partials
+            const int32_t* tp = &L.tile_part[4 * t];
+            int32_t* bt = &tpart[4 * (to + t)];
+            bt[0] = (int32_t)(tp[0] + pb);
+            bt[1] = tp[1];
+            bt[2] = (int32_t)(tp[2] + pb);
+            bt[3] = (int32_t)(tp[3] + no);
         }
         for (int64_t p = 0; p < h->d.P; p++) {
             tnodes[pb + p] = (int32_t)(L.tile_nodes[p] + no);
@@ -219,6 +227,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     poff[Nt] = (int32_t)Pt;
     BCHK(bupload(b, &d.tile_node_off, tno));
     BCHK(bupload(b, &d.tile_nodes, tnodes));
+    BCHK(bupload(b, &d.tile_part, tpart));
     BCHK(bupload(b, &d.part_off, poff));
     BCHK(bupload(b, &d.pidx, wp));
     BCHK(bupload(b, &d.tile_elem_off, teo));

@@ -15,17 +15,30 @@ namespace fedfem {
 //
 // Internal numbering: nodes and elements optionally follow a Morton curve.
 // Elements are cut into tiles of consecutive elements, each holding at most
-// `tile_elems` elements and touching at most `max_tile_nodes` distinct nodes.
+// `tile_elems` elements and touching at most `max_tile_nodes` distinct nodes;
+// reordered tetrahedral layouts then deal each tile's elements out so that
+// neighbouring positions hold elements from separate parts of the tile.
 // For every tile the distinct nodes it touches are listed in ascending
 // internal id ("tile nodes"), and each element corner stores its node's
-// position in that list (lconn, u16).  Each (tile, tile node) pair p in
-// [tile_node_off[t], tile_node_off[t+1]) produces one partial sum, stored at
-// position p (tile-major: a tile writes one contiguous run).  Node i finds its
-// partials at pidx[part_off[i] .. part_off[i+1]), in ascending tile order.
+// position in that list (lconn, u16).  Each (tile, tile node) pair in
+// [tile_node_off[t], tile_node_off[t+1]) produces one partial sum.
+// Reordered tetrahedral layouts number the nodes that a single tile touches
+// first (ids [0, n_int), grouped by tile): such a node's partial sits at its
+// own index.  The other tile nodes' partials follow at [n_int, P), tile-major
+// (each tile writes one contiguous run).  tile_part[4t .. 4t+3] =
+// (pi, ni, ps, n0): tile t's list starts with its ni single-tile nodes, ids
+// n0 .. n0 + ni - 1, and list position j writes position pi + j if j < ni,
+// else ps + j (pi = n0 here; batched copies shift ids and positions apart).
+// Otherwise n_int = 0, ni = 0 and ps = tile_node_off[t].  Node i
+// finds its partials at pidx[part_off[i] .. part_off[i+1]), in ascending tile
+// order.
 // ---------------------------------------------------------------------------
 struct Layout {
     int64_t N = 0, E = 0, T = 0, P = 0;
+    int64_t n_int = 0;  // nodes of a single tile: ids [0, n_int)
     int npe = 4;  // nodes per element: 4 (linear tetrahedra) or 8 (hexahedra)
+    int reorder = 0;
+    int spread = 0;  // elements dealt out inside each tile (see spread_tiles)
     int tile_elems = 0;
     int max_tile_nodes = 0;
     // most corners of one tile on a single node: the number of loads one
@@ -39,7 +52,8 @@ struct Layout {
     std::vector<int32_t> tile_elem_off;  // [T+1]
     std::vector<int32_t> tile_node_off;  // [T+1]
     std::vector<int32_t> tile_nodes;     // [P]
-    std::vector<int32_t> pidx;           // [P] node-major list of partial slots p
+    std::vector<int32_t> tile_part;      // [4T] (pi, ni, ps, n0) per tile
+    std::vector<int32_t> pidx;           // [P] node-major list of partial positions
     std::vector<uint16_t> lconn;         // [npe E] local node id per corner
     std::vector<uint8_t> lconn_pk;       // packed form of lconn (pack_lconn)
     std::vector<int32_t> part_off;       // [N+1] node -> partial positions
@@ -114,6 +128,8 @@ struct DevLayout {
     int32_t* tile_elem_off = nullptr;
     int32_t* tile_node_off = nullptr;
     int32_t* tile_nodes = nullptr;
+    int32_t* tile_part = nullptr;  // [4T] (pi, ni, ps, n0), see Layout
+    int64_t n_int = 0;             // nodes [0, n_int) read their partial at their index
     int32_t* pidx = nullptr;
     void* lconn = nullptr;     // packed (lconn_pk = 1) or [4E] u16
     int lconn_pk = 0;
@@ -122,7 +138,7 @@ struct DevLayout {
     void* u = nullptr;         // [N] Real, 1/V_i, or -1 for Dirichlet nodes
     void* q = nullptr;         // [N] Real, active nodal source [W]
     void* T_[2] = {nullptr, nullptr};  // state: float2 (hi, lo) or double
-    void* partial = nullptr;   // [P] Real, tile-major
+    void* partial = nullptr;   // [P] Real, positions as Layout describes
     // scheduled source patterns (fedfem_set_schedule): node i receives
     // sum_p amp[j][p] pat[p][i] on top of q in the j-th step of a graph chunk
     void* pat = nullptr;       // [n_pat][N] Real

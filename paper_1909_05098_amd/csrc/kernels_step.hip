@@ -141,7 +141,7 @@ struct TileArgs {
     const int32_t* tile_elem_off;
     const int32_t* tile_node_off;
     const int32_t* tile_nodes;
-    const int32_t* pidx;
+    const int4* tile_part;  // per tile: its single-tile nodes and where its partials go
     const void* lconn;  // packed 10-bit ids (lconn_pk) or [4E] u16
     int lconn_pk;
 };
@@ -195,12 +195,28 @@ __device__ __forceinline__ void load_T(const Real* s_T, int j, Real& hi, Real& l
     }
 }
 
+// A tile's list starts with its ni single-tile nodes, ids n0 .. n0 + ni - 1;
+// list position j writes its partial to pi + j when j < ni, else ps + j.
+struct TilePart {
+    int pi, ni, ps, n0;
+    __device__ __forceinline__ int pos(int j) const { return j < ni ? pi + j : ps + j; }
+    __device__ __forceinline__ int node(const TileArgs& a, int p0, int j) const {
+        return j < ni ? n0 + j : a.tile_nodes[p0 + j];
+    }
+};
+__device__ __forceinline__ TilePart tile_part(const TileArgs& a, int64_t t) {
+    const int4 v = a.tile_part[t];
+    return TilePart{v.x, v.y, v.z, v.w};
+}
+
 // Tile nodes into LDS: temperature, conductivity, zeroed accumulators.  The
 // first SJ rounds go out together, ids then temperatures (lanes past the
 // list load its last node and store nothing), so a thread waits for two
-// memory round trips instead of two per round.
+// memory round trips instead of two per round.  Single-tile nodes need no id
+// load: theirs follow from the list position.
 template <typename Real, bool COMP, bool TD>
 __device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int m,
+                                                 const TilePart& tp,
                                                  const void* __restrict__ Tin,
                                                  const Props<Real>& pr, Real* s_T,
                                                  Real* s_k, unsigned long long* s_acc) {
@@ -209,7 +225,7 @@ __device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int 
     {
         int gj[SJ];
 #pragma unroll
-        for (int u = 0; u < SJ; u++) gj[u] = a.tile_nodes[p0 + min(tid + u * bs, m - 1)];
+        for (int u = 0; u < SJ; u++) gj[u] = tp.node(a, p0, min(tid + u * bs, m - 1));
         __builtin_amdgcn_sched_barrier(0);  // all id loads before any wait
         Real hj[SJ], lj[SJ];
 #pragma unroll
@@ -226,7 +242,7 @@ __device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int 
         }
     }
     for (int j = tid + SJ * bs; j < m; j += bs) {
-        const int g = a.tile_nodes[p0 + j];
+        const int g = tp.node(a, p0, j);
         Real hi, lo;
         State<Real, COMP>::load(Tin, g, hi, lo);
         store_T<COMP>(s_T, j, hi, lo);
@@ -251,6 +267,7 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
     const int ne = (int)(a.tile_elem_off[t + 1] - e0);
     const int p0 = a.tile_node_off[t];
     const int m = a.tile_node_off[t + 1] - p0;
+    const TilePart tp = tile_part(a, t);
 
     // 1. coefficient and local-connectivity loads in flight during staging
     Real cf[R][6];
@@ -275,7 +292,7 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
         }
     }
     // 2. tile nodes
-    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_k, s_acc);
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, tp, Tin, pr, s_T, s_k, s_acc);
     __syncthreads();
     // 3. element loads, accumulated exactly on the fixed-point grid
 #pragma unroll
@@ -319,8 +336,9 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
         }
     }
     __syncthreads();
-    // 4. one partial per tile node, tile-major: one contiguous run per tile
-    for (int j = tid; j < m; j += bs) partial[p0 + j] = (Real)(long long)s_acc[j] * pr.fxi;
+    // 4. one partial per tile node: the single-tile nodes' at their own
+    // index, the others' in the tile's run of the tile-major part
+    for (int j = tid; j < m; j += bs) partial[tp.pos(j)] = (Real)(long long)s_acc[j] * pr.fxi;
 }
 
 template <typename Real, bool COMP, bool TD, int R>
@@ -359,6 +377,8 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
     const int ne = (int)(a.tile_elem_off[t + 1] - e0);
     const int p0 = a.tile_node_off[t];
     const int m = a.tile_node_off[t + 1] - p0;
+    // hexahedral layouts keep tile-major positions for every tile node
+    const TilePart tp{0, 0, p0, 0};
 
     // 1. coefficient and local-connectivity loads in flight during staging:
     // eight 10-bit ids as a 64-bit word and a 16-bit word (packed), or eight
@@ -385,7 +405,7 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
         }
     }
     // 2. tile nodes
-    stage_tile_nodes<Real, COMP, TD>(a, p0, m, Tin, pr, s_T, s_k, s_acc);
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, tp, Tin, pr, s_T, s_k, s_acc);
     __syncthreads();
     // 3. element loads, accumulated exactly on the fixed-point grid
 #pragma unroll
@@ -450,8 +470,8 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
         }
     }
     __syncthreads();
-    // 4. one partial per tile node, tile-major
-    for (int j = tid; j < m; j += bs) partial[p0 + j] = (Real)(long long)s_acc[j] * pr.fxi;
+    // 4. one partial per tile node, placed as in the tetrahedral pass
+    for (int j = tid; j < m; j += bs) partial[tp.pos(j)] = (Real)(long long)s_acc[j] * pr.fxi;
 }
 
 template <typename Real, bool COMP, bool TD, int R>
@@ -503,8 +523,10 @@ __device__ __forceinline__ double dose_rate(const Dose& dz, double T) {
 
 // NPT nodes per thread (indices at or above N are skipped): their chains of
 // dependent loads (node data, slot indices, partials) run side by side.
+// Nodes below n_int are single-tile nodes: their one partial sits at their
+// own index and is loaded with the node's own data.
 template <typename Real, bool COMP, int NPT>
-__device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
+__device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N, int64_t n_int,
                                             const int32_t* __restrict__ part_off,
                                             const int32_t* __restrict__ pidx,
                                             const Real* __restrict__ partial,
@@ -515,18 +537,31 @@ __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
                                             const Sched<Real>& sch, const Dose& dz) {
     // every load that depends only on the node first, so a node waits for
     // three rounds of memory latency: these, the slot indices, the partials
-    Real ui[NPT], q0[NPT], hi[NPT], lo[NPT];
+    // (one round for single-tile nodes, whose slot lists are not read).  The
+    // loads go out unconditionally, so that none waits on a branch: a node
+    // reads the slot offsets or the partial at index 0 where it needs none
+    // (one shared cache line per wave).
+    Real ui[NPT], q0[NPT], hi[NPT], lo[NPT], fs[NPT];
     int a[NPT], n[NPT];
 #pragma unroll
     for (int v = 0; v < NPT; v++) {
         const int64_t i = iv[v] < N ? iv[v] : 0;
+        const bool single = i < n_int;
         ui[v] = u[i];
-        a[v] = part_off[i];
-        n[v] = part_off[i + 1] - a[v];
+        const int64_t io = single ? 0 : i;
+        a[v] = part_off[io];
+        n[v] = part_off[io + 1];
+        fs[v] = partial[single ? i : 0];
         q0[v] = q[i];
         State<Real, COMP>::load(Tin, i, hi[v], lo[v]);
     }
-    // the first four slots of every node, indices then partials
+#pragma unroll
+    for (int v = 0; v < NPT; v++) {
+        const bool single = (iv[v] < N ? iv[v] : 0) < n_int;
+        n[v] = single ? 0 : n[v] - a[v];
+        if (!single) fs[v] = Real(0);
+    }
+    // the first four slots of every other node, indices then partials
     int pk[NPT][4];
     Real f[NPT][4];
 #pragma unroll
@@ -549,7 +584,7 @@ __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
         // Dirichlet nodes (u <= 0) are held at T_Gamma
         if (iv[v] >= N || !(ui[v] > Real(0))) continue;
         // partials added in ascending tile order
-        Real F = 0;
+        Real F = fs[v];
 #pragma unroll
         for (int k = 0; k < 4; k++)
             if (k < n[v]) F += f[v][k];
@@ -582,21 +617,35 @@ __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
 
 constexpr int kNodesPerThread = 2;
 
+// With the XCD remap, blocks wholly below n_int (single-tile nodes only) and
+// the others are remapped separately, so that every XCD gets its share of
+// each kind.
 template <typename Real, bool COMP>
 __global__ void __launch_bounds__(256)
-k_node_update(int64_t N, int xcd, const int32_t* __restrict__ part_off,
+k_node_update(int64_t N, int64_t n_int, int xcd, const int32_t* __restrict__ part_off,
               const int32_t* __restrict__ pidx, const Real* __restrict__ partial, const Real* __restrict__ u,
               const Real* __restrict__ q, const void* __restrict__ Tin, void* __restrict__ Tout,
               Props<Real> pr, int* __restrict__ flag, Sched<Real> sch, Dose dz) {
     constexpr int64_t span = 256 * kNodesPerThread;
     const int64_t nb = (N + span - 1) / span;
-    const int64_t blk = xcd ? xcd_remap(blockIdx.x, nb) : (int64_t)blockIdx.x;
+    int64_t blk = blockIdx.x;
+    if (xcd) {
+        const int64_t nbf = n_int / span, gf = (nbf + kXcds - 1) / kXcds * kXcds;
+        if (blk < gf) {
+            blk = xcd_remap(blk, nbf);
+            if (blk >= nbf) return;
+        } else {
+            blk = xcd_remap(blk - gf, nb - nbf);
+            if (blk >= nb - nbf) return;
+            blk += nbf;
+        }
+    }
     if (blk >= nb) return;
     int64_t iv[kNodesPerThread];
 #pragma unroll
     for (int v = 0; v < kNodesPerThread; v++) iv[v] = blk * span + v * 256 + threadIdx.x;
-    node_update<Real, COMP, kNodesPerThread>(iv, N, part_off, pidx, partial, u, q, Tin, Tout, pr,
-                                             flag, sch, dz);
+    node_update<Real, COMP, kNodesPerThread>(iv, N, n_int, part_off, pidx, partial, u, q, Tin,
+                                             Tout, pr, flag, sch, dz);
 }
 
 // Batched form: 256-node blocks never straddle scenarios; the block comes
@@ -614,7 +663,7 @@ k_node_update_batch(const int32_t* __restrict__ block_list,
     const int sc = block_scen[blk];
     const Props<Real> pr = props[sc];
     const int64_t iv[1] = {(int64_t)blk * 256 + threadIdx.x};
-    node_update<Real, COMP, 1>(iv, INT64_MAX, part_off, pidx, partial, u, q, Tin, Tout, pr,
+    node_update<Real, COMP, 1>(iv, INT64_MAX, 0, part_off, pidx, partial, u, q, Tin, Tout, pr,
                                flags + sc, Sched<Real>{nullptr, nullptr, 0, 0},
                                Dose{nullptr, 0, 0.0, 0.0, 0.0});
 }
@@ -629,7 +678,7 @@ TileArgs tile_args(const DevLayout& d) {
     a.tile_elem_off = d.tile_elem_off;
     a.tile_node_off = d.tile_node_off;
     a.tile_nodes = d.tile_nodes;
-    a.pidx = d.pidx;
+    a.tile_part = reinterpret_cast<const int4*>(d.tile_part);
     a.lconn = d.lconn;
     a.lconn_pk = d.lconn_pk;
     return a;
@@ -674,6 +723,7 @@ template <typename Real, bool COMP, bool TD, int R>
 hipError_t launch_elem_r(const DevLayout& d, const Real* coef, const Props<Real>& p,
                          const void* Tin, Real* partial, hipStream_t s) {
     const size_t lds = carve(d.tile_elems, d.max_tile_nodes, sizeof(Real), COMP, TD).total;
+    if (d.npe == 8 && d.n_int != 0) return hipErrorInvalidValue;  // tile-major hexahedra only
     auto kern = d.npe == 8 ? k_elem_loads_hex<Real, COMP, TD, R> : k_elem_loads<Real, COMP, TD, R>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
@@ -697,13 +747,16 @@ hipError_t launch_elem_t(const DevLayout& d, const Real* coef, const Props<Real>
 template <typename Real, bool COMP>
 hipError_t launch_node_t(const DevLayout& d, int cur, const Props<Real>& p, int* flag,
                          hipStream_t s, int j) {
-    const int64_t nb = (d.N + 256 * kNodesPerThread - 1) / (256 * kNodesPerThread);
-    const int64_t grid = d.xcd ? (nb + kXcds - 1) / kXcds * kXcds : nb;
+    constexpr int64_t span = 256 * kNodesPerThread;
+    const int64_t nb = (d.N + span - 1) / span, nbf = d.n_int / span;
+    const int64_t grid = d.xcd ? (nbf + kXcds - 1) / kXcds * kXcds +
+                                     (nb - nbf + kXcds - 1) / kXcds * kXcds
+                               : nb;
     Sched<Real> sch{static_cast<const Real*>(d.pat),
                     d.n_pat ? static_cast<const Real*>(d.amp) + (int64_t)j * d.n_pat : nullptr,
                     d.n_pat, d.N};
     hipLaunchKernelGGL((k_node_update<Real, COMP>), dim3((unsigned)grid), dim3(256), 0, s, d.N,
-                       d.xcd, d.part_off, d.pidx, static_cast<const Real*>(d.partial),
+                       d.n_int, d.xcd, d.part_off, d.pidx, static_cast<const Real*>(d.partial),
                        static_cast<const Real*>(d.u), static_cast<const Real*>(d.q), d.T_[cur],
                        d.T_[1 - cur], p, flag, sch,
                        Dose{d.dose, d.dose_model, d.dose_a, d.dose_b, d.dose_dt});

@@ -117,6 +117,149 @@ std::vector<int32_t> morton_order(const double* pts, int64_t n) {
     return id;
 }
 
+namespace {
+
+// node -> (element, corner) as npe * e + corner, ascending internal element
+void node_corners(Layout& L) {
+    const int64_t N = L.N, S = (int64_t)L.npe * L.E;
+    L.ec_off.assign(N + 1, 0);
+    for (int64_t s = 0; s < S; s++) L.ec_off[L.conn[s] + 1]++;
+    for (int64_t i = 0; i < N; i++) L.ec_off[i + 1] += L.ec_off[i];
+    L.ec.assign(S, 0);
+    std::vector<int32_t> fill(L.ec_off.begin(), L.ec_off.end() - 1);
+    for (int64_t s = 0; s < S; s++) L.ec[fill[L.conn[s]]++] = (int32_t)s;
+}
+
+// Interior-first numbering (reordered tetrahedral layouts).  A node that a
+// single tile touches gets its whole load from that tile, so its partial can
+// sit at the node's own index and the node pass reads it with no slot lookup.
+// Hexahedral layouts keep the curve numbering: there the new order of the
+// tile lists cost the element pass more than the node pass gained.  Nodes are renumbered in
+// the order the tiles first reach them, single-tile nodes first: tile t's
+// single-tile nodes take the ids [int_off[t], int_off[t+1]) in the order of
+// its list, the shared nodes follow from n_int on, and nodes of no element
+// come last.  Each tile's list is sorted again, which puts its single-tile
+// nodes first, and the corners' local ids follow the new order.
+void interior_first(Layout& L) {
+    const int64_t N = L.N, T = L.T, P = L.P;
+    const int npe = L.npe;
+    std::vector<int32_t> ntile(N, 0);
+    for (int64_t p = 0; p < P; p++) ntile[L.tile_nodes[p]]++;
+    std::vector<int32_t> nmap(N, -1);
+    int32_t next = 0;
+    for (int64_t p = 0; p < P; p++)
+        if (ntile[L.tile_nodes[p]] == 1) nmap[L.tile_nodes[p]] = next++;
+    L.n_int = next;
+    for (int64_t p = 0; p < P; p++)
+        if (nmap[L.tile_nodes[p]] < 0) nmap[L.tile_nodes[p]] = next++;
+    for (int64_t i = 0; i < N; i++)
+        if (nmap[i] < 0) nmap[i] = next++;
+    std::vector<int32_t>().swap(ntile);
+    // tile lists in ascending new id, corner ids remapped
+    parallel_for(T, [&](int64_t a, int64_t b) {
+        std::vector<std::pair<int32_t, int32_t>> key;
+        std::vector<uint16_t> to;
+        for (int64_t t = a; t < b; t++) {
+            const int64_t p0 = L.tile_node_off[t], m = L.tile_node_off[t + 1] - p0;
+            key.resize(m);
+            for (int64_t j = 0; j < m; j++) key[j] = {nmap[L.tile_nodes[p0 + j]], (int32_t)j};
+            std::sort(key.begin(), key.end());
+            to.resize(m);
+            for (int64_t j = 0; j < m; j++) {
+                L.tile_nodes[p0 + j] = key[j].first;
+                to[key[j].second] = (uint16_t)j;
+            }
+            const int64_t s0 = (int64_t)npe * L.tile_elem_off[t],
+                          s1 = (int64_t)npe * L.tile_elem_off[t + 1];
+            for (int64_t s2 = s0; s2 < s1; s2++) L.lconn[s2] = to[L.lconn[s2]];
+        }
+    }, 4);
+    parallel_for((int64_t)npe * L.E, [&](int64_t a, int64_t b) {
+        for (int64_t s2 = a; s2 < b; s2++) L.conn[s2] = nmap[L.conn[s2]];
+    }, 65536);
+    std::vector<int32_t> nperm(N);
+    std::vector<double> xyz(3 * N);
+    for (int64_t i = 0; i < N; i++) {
+        nperm[nmap[i]] = L.nperm[i];
+        std::memcpy(&xyz[3 * (int64_t)nmap[i]], &L.xyz[3 * i], 3 * sizeof(double));
+    }
+    L.nperm.swap(nperm);
+    L.xyz.swap(xyz);
+    for (int64_t i = 0; i < N; i++) L.ninv[L.nperm[i]] = (int32_t)i;
+}
+
+// Where each tile writes its partials and where each node finds them.  Tile
+// t's list starts with its ni single-tile nodes (ids n0 .. n0 + ni - 1),
+// whose partials go to the positions of the same numbers; the rest of the
+// list goes tile-major after all single-tile nodes, at ps + j for list
+// position j.  tile_part holds (n0, ni, ps, n0) per tile.  pidx[part_off[i]
+// .. part_off[i+1]) lists node i's positions in ascending tile order.
+void slot_positions(Layout& L) {
+    const int64_t N = L.N, T = L.T, P = L.P;
+    L.tile_part.assign(4 * T, 0);
+    int64_t ib = 0;
+    for (int64_t t = 0; t < T; t++) {
+        const int64_t p0 = L.tile_node_off[t], p1 = L.tile_node_off[t + 1];
+        int64_t ni = 0;
+        while (p0 + ni < p1 && L.tile_nodes[p0 + ni] < L.n_int) ni++;
+        L.tile_part[4 * t] = (int32_t)ib;
+        L.tile_part[4 * t + 1] = (int32_t)ni;
+        L.tile_part[4 * t + 2] = (int32_t)(L.n_int + (p0 - ib) - ni);
+        L.tile_part[4 * t + 3] = (int32_t)ib;
+        ib += ni;
+    }
+    L.part_off.assign(N + 1, 0);
+    for (int64_t p = 0; p < P; p++) L.part_off[L.tile_nodes[p] + 1]++;
+    for (int64_t i = 0; i < N; i++) L.part_off[i + 1] += L.part_off[i];
+    L.pidx.assign(P, 0);
+    std::vector<int32_t> fill(L.part_off.begin(), L.part_off.end() - 1);
+    for (int64_t t = 0; t < T; t++) {
+        const int64_t p0 = L.tile_node_off[t], m = L.tile_node_off[t + 1] - p0;
+        const int32_t* tp = &L.tile_part[4 * t];
+        for (int64_t j = 0; j < m; j++)
+            L.pidx[fill[L.tile_nodes[p0 + j]]++] = (int32_t)(j < tp[1] ? tp[0] + j : tp[2] + j);
+    }
+}
+
+// Element order inside each tile (reordered tetrahedral layouts).  The curve
+// order puts neighbouring elements next to each other, so the 64 lanes of one
+// accumulation step would hit the same few tile nodes in local memory.  The
+// tile's elements are dealt out instead: with ch = ceil(ne / 64), curve
+// position l * ch + k moves to the k-th group of 64, lane l, so one step's
+// lanes take elements from 64 separate stretches of the tile.  The tile's
+// element set, and so its node list, stays the same; sums on the fixed-point
+// grid are exact, so the loads do not depend on this order.  undo = true
+// restores the curve order of the tiles in L.tile_elem_off.  Hexahedra keep
+// the curve order: there one step adds the same corner of 64 neighbouring
+// elements, which are distinct nodes spread evenly over the banks, and
+// dealing them out would only scatter the banks.
+void spread_tiles(Layout& L, bool undo) {
+    const int npe = L.npe;
+    parallel_for(L.T, [&](int64_t a, int64_t b) {
+        std::vector<int32_t> conn, eperm;
+        for (int64_t t = a; t < b; t++) {
+            const int64_t e0 = L.tile_elem_off[t], ne = L.tile_elem_off[t + 1] - e0;
+            const int64_t ch = (ne + 63) / 64;
+            conn.assign(L.conn.begin() + npe * e0, L.conn.begin() + npe * (e0 + ne));
+            eperm.assign(L.eperm.begin() + e0, L.eperm.begin() + e0 + ne);
+            int64_t i = 0;
+            for (int64_t k = 0; k < ch; k++)
+                for (int64_t l = 0; l < 64; l++) {
+                    const int64_t o = l * ch + k;
+                    if (o >= ne) continue;
+                    // curve position o <-> spread position i
+                    const int64_t from = undo ? i : o, to = undo ? o : i;
+                    for (int c = 0; c < npe; c++)
+                        L.conn[npe * (e0 + to) + c] = conn[npe * from + c];
+                    L.eperm[e0 + to] = eperm[from];
+                    i++;
+                }
+        }
+    }, 16);
+}
+
+}  // namespace
+
 bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     if (TE < 64 || TE > 8192 || TE % 64) {
         err = "tile_elems must be a multiple of 64 in [64, 8192]";
@@ -128,6 +271,10 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     }
     const int64_t E = L.E, N = L.N;
     const int npe = L.npe;
+    if (L.spread) {
+        spread_tiles(L, true);
+        L.spread = 0;
+    }
     L.tile_elems = TE;
     // greedy cut along the element order: close a tile when it holds TE
     // elements or the next element would bring it past MN distinct nodes
@@ -164,6 +311,10 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
     }
     const int64_t T = (int64_t)L.tile_elem_off.size() - 1;
     L.T = T;
+    if (L.reorder && npe == 4) {
+        spread_tiles(L, false);
+        L.spread = 1;
+    }
     // pass 1: each tile's distinct nodes in ascending id (a marker array per
     // worker finds them; only the distinct nodes are sorted) and every
     // corner's position in that list
@@ -222,15 +373,10 @@ bool build_tiles(Layout& L, int TE, int MN, std::string& err) {
                         uniq.data() + npe * (int64_t)L.tile_elem_off[t],
                         sizeof(int32_t) * ucount[t]);
     }, 4);
-    // node-major partial positions, ascending tile inside each node
-    L.part_off.assign(N + 1, 0);
-    for (int64_t p = 0; p < P; p++) L.part_off[L.tile_nodes[p] + 1]++;
-    for (int64_t i = 0; i < N; i++) L.part_off[i + 1] += L.part_off[i];
-    L.pidx.assign(P, 0);
-    {
-        std::vector<int32_t> fill(L.part_off.begin(), L.part_off.end() - 1);
-        for (int64_t p = 0; p < P; p++) L.pidx[fill[L.tile_nodes[p]]++] = (int32_t)p;
-    }
+    if (L.reorder && npe == 4) interior_first(L);
+    else L.n_int = 0;
+    slot_positions(L);
+    node_corners(L);
     return true;
 }
 
@@ -275,6 +421,7 @@ bool build_layout(const double* xyz, const int32_t* conn, int npe, int64_t N, in
     L.N = N;
     L.E = E;
     L.npe = npe;
+    L.reorder = reorder;
     if ((int64_t)npe * E > INT32_MAX) {
         err = "mesh too large for 32-bit element-corner indices";
         return false;
@@ -309,15 +456,6 @@ bool build_layout(const double* xyz, const int32_t* conn, int npe, int64_t N, in
     for (int64_t e = 0; e < E; e++)
         for (int c = 0; c < npe; c++)
             L.conn[npe * e + c] = L.ninv[conn[(int64_t)npe * L.eperm[e] + c]];
-    // node -> (element, corner) as npe * e + corner, ascending internal element
-    L.ec_off.assign(N + 1, 0);
-    for (int64_t s = 0; s < S; s++) L.ec_off[L.conn[s] + 1]++;
-    for (int64_t i = 0; i < N; i++) L.ec_off[i + 1] += L.ec_off[i];
-    L.ec.assign(S, 0);
-    {
-        std::vector<int32_t> fill(L.ec_off.begin(), L.ec_off.end() - 1);
-        for (int64_t s = 0; s < S; s++) L.ec[fill[L.conn[s]]++] = (int32_t)s;
-    }
     return build_tiles(L, TE, MN, err);
 }
 

@@ -68,7 +68,7 @@ class Info(C.Structure):
                 ("device_bytes", C.c_int64), ("lambda_geometry", C.c_double),
                 ("lanczos_iterations", C.c_int32),
                 ("max_tile_valence", C.c_int32), ("fixed_point_shift", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("n_single_tile_nodes", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class FedFemError(RuntimeError):

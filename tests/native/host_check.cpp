@@ -150,16 +150,50 @@ bool check_layout(const Layout& L, const std::string& name) {
     }
     if (maxn != L.max_tile_nodes) return bad("max_tile_nodes");
     if (maxv != L.max_tile_valence) return bad("max_tile_valence");
-    // node-major partial list: a permutation, each node's slots ascending
-    std::vector<char> seen(L.P, 0);
-    for (int64_t i = 0; i < L.N; i++)
+    // partial positions: tile t's list starts with its single-tile nodes,
+    // numbered consecutively from the running count; positions cover [0, P)
+    // once, single-tile nodes at their own index
+    // reordered tetrahedral layouts number single-tile nodes first
+    const bool single_first = L.reorder && npe == 4;
+    if (L.n_int < 0 || L.n_int > L.N || (!single_first && L.n_int != 0)) return bad("n_int");
+    if ((int64_t)L.tile_part.size() != 4 * L.T) return bad("tile_part size");
+    std::vector<int32_t> ntile(L.N, 0), at(L.P, -1);
+    for (int64_t p = 0; p < L.P; p++) ntile[L.tile_nodes[p]]++;
+    int64_t ib = 0;
+    for (int64_t t = 0; t < L.T; t++) {
+        const int64_t n0 = L.tile_node_off[t], m = L.tile_node_off[t + 1] - n0;
+        const int32_t* tp = &L.tile_part[4 * t];
+        if (tp[0] != ib || tp[3] != ib || tp[1] < 0 || tp[1] > m) return bad("tile_part");
+        for (int64_t j = 0; j < m; j++) {
+            const int32_t i = L.tile_nodes[n0 + j];
+            if ((j < tp[1]) != (i < L.n_int)) return bad("single-tile nodes not first");
+            if (j < tp[1] && i != tp[0] + j) return bad("single-tile ids not consecutive");
+            if ((i < L.n_int) != (ntile[i] == 1 && single_first)) return bad("n_int split");
+            const int64_t pos = j < tp[1] ? tp[0] + j : (int64_t)tp[2] + j;
+            if (j >= tp[1] && pos < L.n_int) return bad("shared position in the single range");
+            if (pos < 0 || pos >= L.P || at[pos] >= 0) return bad("positions not a permutation");
+            at[pos] = i;
+        }
+        ib += tp[1];
+    }
+    if (ib != L.n_int) return bad("single-tile count");
+    // node-major partial list: each node's positions, ascending tile order
+    for (int64_t i = 0; i < L.N; i++) {
+        if (i < L.n_int &&
+            (L.part_off[i + 1] - L.part_off[i] != 1 || L.pidx[L.part_off[i]] != i))
+            return bad("single-tile node not at its index");
+        if (L.part_off[i + 1] - L.part_off[i] != ntile[i]) return bad("part_off count");
         for (int64_t k = L.part_off[i]; k < L.part_off[i + 1]; k++) {
             const int32_t p = L.pidx[k];
-            if (p < 0 || p >= L.P || seen[p]) return bad("pidx not a permutation");
-            seen[p] = 1;
-            if (L.tile_nodes[p] != i) return bad("pidx names another node");
+            if (p < 0 || p >= L.P) return bad("pidx out of range");
+            if (at[p] != i) return bad("pidx names another node");
             if (k > L.part_off[i] && L.pidx[k - 1] >= p) return bad("pidx not ascending");
         }
+    }
+    // caller <-> internal node ids are inverse permutations
+    for (int64_t i = 0; i < L.N; i++)
+        if (L.nperm[i] < 0 || L.nperm[i] >= L.N || L.ninv[L.nperm[i]] != i)
+            return bad("nperm / ninv");
     // node -> element corners, ascending element
     for (int64_t i = 0; i < L.N; i++)
         for (int64_t k = L.ec_off[i]; k < L.ec_off[i + 1]; k++) {
@@ -206,7 +240,26 @@ bool same_layout(const Layout& a, const Layout& b) {
            a.eperm == b.eperm && a.conn == b.conn && a.tile_elem_off == b.tile_elem_off &&
            a.tile_node_off == b.tile_node_off && a.tile_nodes == b.tile_nodes &&
            a.pidx == b.pidx && a.lconn == b.lconn && a.lconn_pk == b.lconn_pk &&
-           a.part_off == b.part_off && a.ec == b.ec;
+           a.part_off == b.part_off && a.ec == b.ec && a.n_int == b.n_int &&
+           a.tile_part == b.tile_part && a.xyz == b.xyz;
+}
+
+// The internal mesh is the caller's under the node and element permutations.
+bool same_mesh(const Layout& L, const Mesh& m, const std::string& name) {
+    const int npe = L.npe;
+    for (int64_t e = 0; e < L.E; e++)
+        for (int c = 0; c < npe; c++)
+            if (L.conn[npe * e + c] != L.ninv[m.tets[npe * (int64_t)L.eperm[e] + c]]) {
+                fail(name + ": internal connectivity");
+                return false;
+            }
+    for (int64_t i = 0; i < L.N; i++)
+        for (int a = 0; a < 3; a++)
+            if (L.xyz[3 * i + a] != m.xyz[3 * (int64_t)L.nperm[i] + a]) {
+                fail(name + ": internal coordinates");
+                return false;
+            }
+    return true;
 }
 
 bool build(const Mesh& m, const Case& c, Layout& L, const std::string& name) {
@@ -217,7 +270,7 @@ bool build(const Mesh& m, const Case& c, Layout& L, const std::string& name) {
         return false;
     }
     pack_lconn(L);
-    return true;
+    return same_mesh(L, m, name);
 }
 
 }  // namespace
@@ -261,6 +314,21 @@ int main() {
     }
     // an interior lattice node has 24 tetrahedra: no tile can see more
     if (kuhn_valence > 24) fail("Kuhn lattice tile valence above 24");
+    // tiles cut again on a built layout (the shrink path) renumber on top
+    // of the first numbering
+    for (const size_t k : {size_t(1), size_t(3), size_t(2)}) {
+        Layout L = ref[k];
+        std::string err;
+        const std::string name = "rebuilt box " + std::to_string(k);
+        if (!build_tiles(L, 128, 64, err)) {
+            fail(name + ": " + err);
+            continue;
+        }
+        pack_lconn(L);
+        if (check_layout(L, name) && same_mesh(L, meshes[k], name) && L.reorder &&
+            L.n_int == 0)
+            fail(name + ": no single-tile nodes");
+    }
     // hexahedra: packed 10-bit ids when a tile has at most 1024 nodes, u16
     // otherwise
     for (const int tile : {256, 512, 1024}) {
@@ -274,6 +342,7 @@ int main() {
         }
         pack_lconn(L);
         check_layout(L, "hex box " + std::to_string(tile));
+        same_mesh(L, hb, "hex box " + std::to_string(tile));
         if (L.lconn_pk.empty() != (L.max_tile_nodes > kPackedMaxNodes))
             fail("hex box: packed form chosen wrongly");
         if (L.max_tile_valence > 8) fail("hex box: tile valence above 8");

@@ -125,6 +125,34 @@ def test_td_jittered_box(prec, reorder, tile):
 
 
 @pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_single_tile_nodes_and_xcd_remap(prec, xcd):
+    """Reordered layouts number the nodes of a single tile first and read
+    their one tile sum at the node's own index (Eq 11 with one term); the
+    nodal update takes whole 512-node blocks of them in one load round, with
+    or without the XCD remap of its blocks.  The box is large enough for
+    several such blocks and a mixed one."""
+    xyz, tets, bnd = jittered_box(30, 24, 20, 1e-3, seed=33)
+    xyz, tets, bnd, _, _ = mesh.shuffle_mesh(xyz, tets, bnd, np.random.default_rng(9))
+    mat = sc.td_materials()
+    src = np.array([[12e-3, 10e-3, 8e-3, 3e-3, 5e6], [22e-3, 14e-3, 12e-3, 2e-3, 4e6]])
+    om, q, T_ref = oracle_run(xyz, tets, mat, bnd, src, sc.SOURCE_CONSISTENT, 200)
+    h = gpu_handle(xyz, tets, mat, bnd, om.dt, prec, reorder=True, tile_elems=2048,
+                   xcd=bool(xcd))
+    info = h.info()
+    n_single = info["n_single_tile_nodes"]
+    assert 3 * 512 <= n_single < len(xyz)
+    h.set_gaussian_sources(src, ff.SOURCE_CONSISTENT)
+    h.step(200)
+    T = h.read_T()
+    err = np.max(np.abs(T - T_ref))
+    print_case(f"single-tile nodes prec={prec} xcd={xcd}", err,
+               f"single={n_single}/{len(xyz)} tiles={info['n_tiles']}")
+    assert T_ref.max() > 60.0
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
 def test_wide_tiles_keep_16_bit_corner_ids(prec):
     """Tiles of more than 1024 nodes keep 16-bit local corner ids (smaller
     tiles use the packed 10-bit form); both forms must give the oracle's
