@@ -2,6 +2,7 @@
 // node lists, and the node -> partial / node -> element-corner lists.  Integer
 // topology only; all floating-point pre-computation runs on the GPU.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -415,6 +416,59 @@ void pack_lconn(Layout& L) {
     }, 65536);
 }
 
+// Corner relabelling of reordered hexahedral layouts.  Corner a of an
+// eight-node element sits at natural coordinates xi_a in {-1, 1}^3 (bit 0 of
+// kHexCorner[a] is xi, bit 1 eta, bit 2 zeta; set = +1).  A symmetry of the
+// reference cube (an axis permutation with sign flips) relabels the corners
+// without changing the element: with one integration point at the centre the
+// element matrix depends on |det J| and the node set only.  Each element is
+// relabelled so that its local axes g_j = sum_a xi_a,j x_a point along +x,
+// +y, +z as far as the 48 symmetries allow.  On a lattice-like mesh the same
+// corner of neighbouring elements is then a different node, so one
+// accumulation step of the element pass (one corner of 64 elements) does
+// not add to the same tile node twice.
+constexpr int kHexCorner[8] = {0, 1, 3, 2, 4, 5, 7, 6};
+
+void orient_hexahedra(Layout& L) {
+    int corner_of[8];  // natural-coordinate bits -> corner index
+    for (int a = 0; a < 8; a++) corner_of[kHexCorner[a]] = a;
+    static const int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    parallel_for(L.E, [&](int64_t a0, int64_t b0) {
+        for (int64_t e = a0; e < b0; e++) {
+            int32_t* c = &L.conn[8 * e];
+            double g[3][3] = {};  // g[j] = sum_a xi_a,j x_a
+            for (int a = 0; a < 8; a++)
+                for (int j = 0; j < 3; j++) {
+                    const double s = (kHexCorner[a] >> j & 1) ? 1.0 : -1.0;
+                    for (int k = 0; k < 3; k++) g[j][k] += s * L.xyz[3 * (int64_t)c[a] + k];
+                }
+            // new axis k is old axis perm[k] with sign sg[k]
+            int best = 0;
+            double best_v = -1.0;
+            for (int p = 0; p < 6; p++) {
+                double v = 0.0;
+                for (int k = 0; k < 3; k++) v += std::fabs(g[kPerm[p][k]][k]);
+                if (v > best_v) {
+                    best_v = v;
+                    best = p;
+                }
+            }
+            int32_t old[8];
+            std::memcpy(old, c, sizeof old);
+            for (int a = 0; a < 8; a++) {
+                int bits = 0;  // old natural coordinates of new corner a
+                for (int k = 0; k < 3; k++) {
+                    const int j = kPerm[best][k];
+                    const bool plus = (kHexCorner[a] >> k & 1) != 0;
+                    const bool flip = g[j][k] < 0.0;
+                    if (plus != flip) bits |= 1 << j;
+                }
+                c[a] = old[corner_of[bits]];
+            }
+        }
+    }, 16384);
+}
+
 bool build_layout(const double* xyz, const int32_t* conn, int npe, int64_t N, int64_t E,
                   int reorder, int TE, int MN, Layout& L, std::string& err) {
     L = Layout();
@@ -456,6 +510,7 @@ bool build_layout(const double* xyz, const int32_t* conn, int npe, int64_t N, in
     for (int64_t e = 0; e < E; e++)
         for (int c = 0; c < npe; c++)
             L.conn[npe * e + c] = L.ninv[conn[(int64_t)npe * L.eperm[e] + c]];
+    if (reorder && npe == 8) orient_hexahedra(L);
     return build_tiles(L, TE, MN, err);
 }
 

@@ -87,10 +87,27 @@ Mesh hex_box(int nx, int ny, int nz, double h, uint64_t seed) {
     m.tets.clear();
     const int cc[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
                           {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+    // each element's corners relabelled by one of the 48 symmetries of the
+    // cube (axis permutation and sign flips), so that layouts see every
+    // orientation
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int bits[8] = {0, 1, 3, 2, 4, 5, 7, 6};
+    int corner_of[8];
+    for (int a = 0; a < 8; a++) corner_of[bits[a]] = a;
+    uint64_t r = seed * 0x9E3779B97F4A7C15ULL + 1;
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
-            for (int i = 0; i < nx; i++)
-                for (const auto& c : cc) m.tets.push_back(id(i + c[0], j + c[1], k + c[2]));
+            for (int i = 0; i < nx; i++) {
+                r = r * 6364136223846793005ULL + 1442695040888963407ULL;
+                const int p = (int)((r >> 33) % 6), fl = (int)((r >> 40) & 7);
+                for (int a = 0; a < 8; a++) {
+                    int b = 0;
+                    for (int q = 0; q < 3; q++)
+                        if (((bits[a] >> q) ^ (fl >> q)) & 1) b |= 1 << perm[p][q];
+                    const int* c = cc[corner_of[b]];
+                    m.tets.push_back(id(i + c[0], j + c[1], k + c[2]));
+                }
+            }
     m.E = (int64_t)m.tets.size() / 8;
     return m;
 }
@@ -244,15 +261,58 @@ bool same_layout(const Layout& a, const Layout& b) {
            a.tile_part == b.tile_part && a.xyz == b.xyz;
 }
 
+// Natural-coordinate bits of hexahedral corner a (bit 0 xi, 1 eta, 2 zeta).
+constexpr int kCornerBits[8] = {0, 1, 3, 2, 4, 5, 7, 6};
+
 // The internal mesh is the caller's under the node and element permutations.
+// Reordered hexahedra may also have their corners relabelled by a symmetry
+// of the reference cube, which must then leave every local axis pointing
+// along the positive global axis it is nearest to.
 bool same_mesh(const Layout& L, const Mesh& m, const std::string& name) {
     const int npe = L.npe;
-    for (int64_t e = 0; e < L.E; e++)
-        for (int c = 0; c < npe; c++)
-            if (L.conn[npe * e + c] != L.ninv[m.tets[npe * (int64_t)L.eperm[e] + c]]) {
-                fail(name + ": internal connectivity");
+    const bool relabel = npe == 8 && L.reorder;
+    for (int64_t e = 0; e < L.E; e++) {
+        const int32_t* ci = &L.conn[npe * e];
+        const int32_t* cc = &m.tets[npe * (int64_t)L.eperm[e]];
+        if (!relabel) {
+            for (int c = 0; c < npe; c++)
+                if (ci[c] != L.ninv[cc[c]]) {
+                    fail(name + ": internal connectivity");
+                    return false;
+                }
+            continue;
+        }
+        // internal corner a holds caller corner from[a]; cube edges (corners
+        // one coordinate apart) must stay edges
+        int from[8];
+        for (int a = 0; a < 8; a++) {
+            from[a] = -1;
+            for (int b = 0; b < 8; b++)
+                if (ci[a] == L.ninv[cc[b]]) from[a] = b;
+            if (from[a] < 0) {
+                fail(name + ": hexahedron lost a corner");
                 return false;
             }
+        }
+        for (int a = 0; a < 8; a++)
+            for (int b = 0; b < 8; b++) {
+                const int da = __builtin_popcount(kCornerBits[a] ^ kCornerBits[b]);
+                const int db = __builtin_popcount(kCornerBits[from[a]] ^ kCornerBits[from[b]]);
+                if (da != db) {
+                    fail(name + ": corner relabelling is no cube symmetry");
+                    return false;
+                }
+            }
+        for (int k = 0; k < 3; k++) {
+            double g = 0.0;  // component k of local axis k
+            for (int a = 0; a < 8; a++)
+                g += ((kCornerBits[a] >> k & 1) ? 1.0 : -1.0) * L.xyz[3 * (int64_t)ci[a] + k];
+            if (!(g > 0.0)) {
+                fail(name + ": hexahedron not oriented along the axes");
+                return false;
+            }
+        }
+    }
     for (int64_t i = 0; i < L.N; i++)
         for (int a = 0; a < 3; a++)
             if (L.xyz[3 * i + a] != m.xyz[3 * (int64_t)L.nperm[i] + a]) {
