@@ -34,6 +34,7 @@ struct fedfem_batch {
     std::vector<int32_t> tile_count, block_count;
     int32_t *tile_list = nullptr, *tile_scen = nullptr;
     int32_t *block_list = nullptr, *block_scen = nullptr, *flags = nullptr;
+    int32_t* scen_single = nullptr;  // [2S], see BatchTables
     void* props = nullptr;
     std::vector<std::pair<void*, size_t>> allocs;  // device blocks and their sizes
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -194,7 +195,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     }
     // integer tables on the host
     std::vector<int32_t> tno(Tt + 1), tnodes(Pt), poff(Nt + 1, 0), wp(Pt), teo(Tt + 1), tsc(Tt),
-        bsc(Nt / 256), tpart(4 * Tt);
+        bsc(Nt / 256), tpart(4 * Tt), ssingle(2 * n);
     for (int j = 0; j < n; j++) {
         const fedfem_handle* h = handles[j];
         const Layout& L = h->L;
@@ -221,6 +222,8 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
         for (int64_t i = 0; i < npad; i++)
             poff[no + i] = (int32_t)((i < h->N ? L.part_off[i] : L.part_off[h->N]) + pb);
         for (int64_t k = no / 256; k < b->node_off[j + 1] / 256; k++) bsc[k] = j;
+        ssingle[2 * j] = (int32_t)(no + L.n_int);
+        ssingle[2 * j + 1] = (int32_t)(pb - no);
     }
     tno[Tt] = (int32_t)Pt;
     teo[Tt] = (int32_t)Et;
@@ -233,6 +236,7 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     BCHK(bupload(b, &d.tile_elem_off, teo));
     BCHK(bupload(b, &b->tile_scen, tsc));
     BCHK(bupload(b, &b->block_scen, bsc));
+    BCHK(bupload(b, &b->scen_single, ssingle));
     BCHK(balloc(b, &b->tile_list, Tt));
     BCHK(balloc(b, &b->block_list, Nt / 256));
     BCHK(balloc(b, &b->flags, n));
@@ -387,6 +391,7 @@ int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps, const double* cons
         tb.block_list = b->block_list;
         tb.block_scen = b->block_scen;
         tb.props = b->props;
+        tb.scen_single = reinterpret_cast<const int2*>(b->scen_single);
         RCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
         int r = S;  // number of active scenarios (prefix of ord)
         hipError_t err = hipSuccess;

@@ -183,6 +183,10 @@ struct BatchTables {
     const int32_t* block_list = nullptr;     // [NB]
     const int32_t* block_scen = nullptr;     // [NB]
     const void* props = nullptr;             // Props<Real>[S]
+    // per scenario: (node_off + n_int, pbase - node_off): its nodes below the
+    // first number are single-tile nodes, whose partial sits at the node's
+    // index plus the second
+    const int2* scen_single = nullptr;       // [S]
 };
 // Expand packed corner ids of E elements to [4E] u16.
 hipError_t launch_lconn_unpack(const void* packed, int64_t E, uint16_t* out,

@@ -524,9 +524,11 @@ __device__ __forceinline__ double dose_rate(const Dose& dz, double T) {
 // NPT nodes per thread (indices at or above N are skipped): their chains of
 // dependent loads (node data, slot indices, partials) run side by side.
 // Nodes below n_int are single-tile nodes: their one partial sits at their
-// own index and is loaded with the node's own data.
+// own index plus pshift (0 but in batched copies) and is loaded with the
+// node's own data.
 template <typename Real, bool COMP, int NPT>
 __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N, int64_t n_int,
+                                            int64_t pshift,
                                             const int32_t* __restrict__ part_off,
                                             const int32_t* __restrict__ pidx,
                                             const Real* __restrict__ partial,
@@ -551,7 +553,7 @@ __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
         const int64_t io = single ? 0 : i;
         a[v] = part_off[io];
         n[v] = part_off[io + 1];
-        fs[v] = partial[single ? i : 0];
+        fs[v] = partial[single ? i + pshift : 0];
         q0[v] = q[i];
         State<Real, COMP>::load(Tin, i, hi[v], lo[v]);
     }
@@ -644,12 +646,13 @@ k_node_update(int64_t N, int64_t n_int, int xcd, const int32_t* __restrict__ par
     int64_t iv[kNodesPerThread];
 #pragma unroll
     for (int v = 0; v < kNodesPerThread; v++) iv[v] = blk * span + v * 256 + threadIdx.x;
-    node_update<Real, COMP, kNodesPerThread>(iv, N, n_int, part_off, pidx, partial, u, q, Tin,
+    node_update<Real, COMP, kNodesPerThread>(iv, N, n_int, 0, part_off, pidx, partial, u, q, Tin,
                                              Tout, pr, flag, sch, dz);
 }
 
 // Batched form: 256-node blocks never straddle scenarios; the block comes
-// from a list of active blocks and its material from the block's scenario.
+// from a list of active blocks, its material and where its single-tile nodes
+// end from the block's scenario.
 template <typename Real, bool COMP>
 __global__ void __launch_bounds__(256)
 k_node_update_batch(const int32_t* __restrict__ block_list,
@@ -658,13 +661,15 @@ k_node_update_batch(const int32_t* __restrict__ block_list,
                     const Real* __restrict__ partial,
                     const Real* __restrict__ u, const Real* __restrict__ q,
                     const void* __restrict__ Tin, void* __restrict__ Tout,
-                    const Props<Real>* __restrict__ props, int* __restrict__ flags) {
+                    const Props<Real>* __restrict__ props,
+                    const int2* __restrict__ scen_single, int* __restrict__ flags) {
     const int blk = block_list[blockIdx.x];
     const int sc = block_scen[blk];
     const Props<Real> pr = props[sc];
+    const int2 ss = scen_single[sc];
     const int64_t iv[1] = {(int64_t)blk * 256 + threadIdx.x};
-    node_update<Real, COMP, 1>(iv, INT64_MAX, 0, part_off, pidx, partial, u, q, Tin, Tout, pr,
-                               flags + sc, Sched<Real>{nullptr, nullptr, 0, 0},
+    node_update<Real, COMP, 1>(iv, INT64_MAX, ss.x, ss.y, part_off, pidx, partial, u, q, Tin,
+                               Tout, pr, flags + sc, Sched<Real>{nullptr, nullptr, 0, 0},
                                Dose{nullptr, 0, 0.0, 0.0, 0.0});
 }
 
@@ -871,14 +876,14 @@ hipError_t launch_node_batch(const DevLayout& d, const BatchTables& b, int cur, 
                            b.block_list, b.block_scen, d.part_off, d.pidx,
                            static_cast<const float*>(d.partial), static_cast<const float*>(d.u),
                            static_cast<const float*>(d.q), d.T_[cur], d.T_[1 - cur],
-                           static_cast<const Props<float>*>(b.props), flags);
+                           static_cast<const Props<float>*>(b.props), b.scen_single, flags);
     else
         hipLaunchKernelGGL((k_node_update_batch<double, false>), dim3(n_blocks), dim3(256), 0,
                            s, b.block_list, b.block_scen, d.part_off, d.pidx,
                            static_cast<const double*>(d.partial),
                            static_cast<const double*>(d.u), static_cast<const double*>(d.q),
                            d.T_[cur], d.T_[1 - cur], static_cast<const Props<double>*>(b.props),
-                           flags);
+                           b.scen_single, flags);
     return hipGetLastError();
 }
 
