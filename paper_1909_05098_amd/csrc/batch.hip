@@ -23,6 +23,10 @@
 
 using namespace fedfem;
 
+namespace fedfem {
+constexpr int kChains = 2;  // independent lockstep chains in a batched run
+}
+
 struct fedfem_batch {
     std::vector<fedfem_handle*> hs;
     int S = 0;
@@ -39,6 +43,10 @@ struct fedfem_batch {
     std::vector<std::pair<void*, size_t>> allocs;  // device blocks and their sizes
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // the other chains' capture streams, and the events that fork them from
+    // cap and join them back
+    hipStream_t chain[kChains - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kChains - 1] = {};
     double last_ms = 0.0;
 };
 
@@ -72,6 +80,11 @@ void destroy_batch(fedfem_batch* b) {
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int c = 0; c < kChains - 1; c++) {
+        if (b->chain[c]) (void)hipStreamDestroy(b->chain[c]);
+        if (b->ev_join[c]) (void)hipEventDestroy(b->ev_join[c]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     delete b;
 }
 
@@ -142,6 +155,11 @@ int fedfem_batch_create(fedfem_handle* const* handles, int32_t n, fedfem_batch**
     BCHK(hipSetDevice(b->device));
     BCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     BCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    BCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    for (int c = 0; c < kChains - 1; c++) {
+        BCHK(hipStreamCreateWithFlags(&b->chain[c], hipStreamNonBlocking));
+        BCHK(hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming));
+    }
     BCHK(hipEventCreate(&b->ev0));
     BCHK(hipEventCreate(&b->ev1));
     // offsets
@@ -331,20 +349,43 @@ int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps, const double* cons
     RCHK(hipSetDevice(b->device));
     DevLayout& d = b->d;
     const size_t rb = b->fp32c ? 4 : 8;
-    // longest first: active scenarios form a prefix
+    // Two independent lockstep chains, each over half of the scenarios (by
+    // element-steps), so that one chain's node pass and the tail of each
+    // launch overlap the other chain's work.  Within a chain, longest first:
+    // the active scenarios form a prefix of its lists.
     std::vector<int> ord(S);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(),
                      [&](int x, int y) { return n_steps[x] > n_steps[y]; });
+    std::vector<int> grp[kChains];
+    {
+        int64_t work[kChains] = {};
+        for (int r = 0; r < S; r++) {
+            const int j = ord[r];
+            int g = 0;
+            for (int c = 1; c < kChains; c++)
+                if (work[c] < work[g]) g = c;
+            grp[g].push_back(j);
+            work[g] += (b->elem_off[j + 1] - b->elem_off[j]) * std::max<int64_t>(1, n_steps[j]);
+        }
+    }
     std::vector<int32_t> tl, bl;
-    std::vector<int64_t> tcum(S + 1, 0), bcum(S + 1, 0);
-    for (int r = 0; r < S; r++) {
-        const int j = ord[r];
-        for (int64_t t = b->tile_off[j]; t < b->tile_off[j + 1]; t++) tl.push_back((int32_t)t);
-        for (int64_t k = b->node_off[j] / 256; k < b->node_off[j + 1] / 256; k++)
-            bl.push_back((int32_t)k);
-        tcum[r + 1] = (int64_t)tl.size();
-        bcum[r + 1] = (int64_t)bl.size();
+    std::vector<int64_t> tcum[kChains], bcum[kChains];
+    int64_t tbase[kChains], bbase[kChains];
+    for (int g = 0; g < kChains; g++) {
+        tbase[g] = (int64_t)tl.size();
+        bbase[g] = (int64_t)bl.size();
+        tcum[g].assign(grp[g].size() + 1, 0);
+        bcum[g].assign(grp[g].size() + 1, 0);
+        for (size_t r = 0; r < grp[g].size(); r++) {
+            const int j = grp[g][r];
+            for (int64_t t = b->tile_off[j]; t < b->tile_off[j + 1]; t++)
+                tl.push_back((int32_t)t);
+            for (int64_t k = b->node_off[j] / 256; k < b->node_off[j + 1] / 256; k++)
+                bl.push_back((int32_t)k);
+            tcum[g][r + 1] = (int64_t)tl.size() - tbase[g];
+            bcum[g][r + 1] = (int64_t)bl.size() - bbase[g];
+        }
     }
     RCHK(hipMemcpyAsync(b->tile_list, tl.data(), tl.size() * 4, hipMemcpyHostToDevice,
                         b->stream));
@@ -385,23 +426,42 @@ int fedfem_batch_run(fedfem_batch* b, const int64_t* n_steps, const double* cons
             for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
             b->graphs.clear();
         }
-        BatchTables tb;
-        tb.tile_list = b->tile_list;
-        tb.tile_scen = b->tile_scen;
-        tb.block_list = b->block_list;
-        tb.block_scen = b->block_scen;
-        tb.props = b->props;
-        tb.scen_single = reinterpret_cast<const int2*>(b->scen_single);
         RCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        int r = S;  // number of active scenarios (prefix of ord)
-        hipError_t err = hipSuccess;
-        for (int64_t k = 0; k < nmax && err == hipSuccess; k++) {
-            while (r > 0 && n_steps[ord[r - 1]] <= k) r--;
-            const int cur = (int)(k & 1);
-            err = launch_elem_batch(d, tb, cur, (int)tcum[r], b->fp32c, b->cap);
-            if (err == hipSuccess)
-                err = launch_node_batch(d, tb, cur, (int)bcum[r], b->fp32c, b->flags, b->cap);
+        hipError_t err = hipEventRecord(b->ev_fork, b->cap);
+        bool forked[kChains] = {};
+        for (int g = 1; g < kChains && err == hipSuccess; g++)
+            if (!grp[g].empty()) {
+                err = hipStreamWaitEvent(b->chain[g - 1], b->ev_fork, 0);
+                forked[g] = err == hipSuccess;
+            }
+        for (int g = 0; g < kChains && err == hipSuccess; g++) {
+            if (grp[g].empty()) continue;
+            hipStream_t cs = g == 0 ? b->cap : b->chain[g - 1];
+            BatchTables tb;
+            tb.tile_list = b->tile_list + tbase[g];
+            tb.tile_scen = b->tile_scen;
+            tb.block_list = b->block_list + bbase[g];
+            tb.block_scen = b->block_scen;
+            tb.props = b->props;
+            tb.scen_single = reinterpret_cast<const int2*>(b->scen_single);
+            int r = (int)grp[g].size();  // active scenarios of the chain
+            const int64_t kmax = n_steps[grp[g][0]];
+            for (int64_t k = 0; k < kmax && err == hipSuccess; k++) {
+                while (r > 0 && n_steps[grp[g][r - 1]] <= k) r--;
+                const int cur = (int)(k & 1);
+                err = launch_elem_batch(d, tb, cur, (int)tcum[g][r], b->fp32c, cs);
+                if (err == hipSuccess)
+                    err = launch_node_batch(d, tb, cur, (int)bcum[g][r], b->fp32c, b->flags, cs);
+            }
         }
+        // join every forked chain, also after an error, so that the capture
+        // ends cleanly
+        for (int g = 1; g < kChains; g++)
+            if (forked[g]) {
+                hipError_t ej = hipEventRecord(b->ev_join[g - 1], b->chain[g - 1]);
+                if (ej == hipSuccess) ej = hipStreamWaitEvent(b->cap, b->ev_join[g - 1], 0);
+                if (err == hipSuccess) err = ej;
+            }
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->cap, &g);
         if (err != hipSuccess || e2 != hipSuccess) {
