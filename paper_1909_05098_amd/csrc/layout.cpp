@@ -1,6 +1,9 @@
 // Host-side mesh layout: Morton renumbering, element tiles with their local
-// node lists, and the node -> partial / node -> element-corner lists.  Integer
-// topology only; all floating-point pre-computation runs on the GPU.
+// node lists, single-tile-first node numbering and the element order inside
+// tetrahedral tiles, the hexahedra's corner relabelling, and the node ->
+// partial / node -> element-corner lists.  Integer topology (plus the corner
+// coordinates that orient hexahedra); all floating-point pre-computation
+// runs on the GPU.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
