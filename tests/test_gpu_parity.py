@@ -152,6 +152,28 @@ def test_single_tile_nodes_and_xcd_remap(prec, xcd):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_one_tile_mesh_has_only_single_tile_nodes(xcd):
+    """A mesh that fits one tile: every node is a single-tile node (the
+    partial of each at its own index, no slot list read), including the
+    last, partly filled block of the nodal update."""
+    xyz, tets, bnd = jittered_box(7, 6, 5, 1e-3, seed=41)
+    xyz, tets, bnd, _, _ = mesh.shuffle_mesh(xyz, tets, bnd, np.random.default_rng(3))
+    mat = sc.td_materials()
+    src = np.array([[3e-3, 3e-3, 2.5e-3, 1.5e-3, 2e7]])
+    om, q, T_ref = oracle_run(xyz, tets, mat, bnd, src, sc.SOURCE_CONSISTENT, 150)
+    h = gpu_handle(xyz, tets, mat, bnd, om.dt, ff.FP64, reorder=True, tile_elems=2048,
+                   xcd=bool(xcd))
+    info = h.info()
+    assert info["n_tiles"] == 1 and info["n_single_tile_nodes"] == len(xyz)
+    h.set_gaussian_sources(src, ff.SOURCE_CONSISTENT)
+    h.step(150)
+    err = np.max(np.abs(h.read_T() - T_ref))
+    print_case(f"one-tile mesh xcd={xcd}", err, f"nodes={len(xyz)} peak={T_ref.max():.2f}")
+    assert T_ref.max() > 45.0
+    assert err <= TOL[ff.FP64]
+
+
 @pytest.mark.parametrize("prec", [ff.FP64, ff.FP32C])
 def test_wide_tiles_keep_16_bit_corner_ids(prec):
     """Tiles of more than 1024 nodes keep 16-bit local corner ids (smaller
