@@ -200,8 +200,11 @@ __device__ __forceinline__ void load_T(const Real* s_T, int j, Real& hi, Real& l
 struct TilePart {
     int pi, ni, ps, n0;
     __device__ __forceinline__ int pos(int j) const { return j < ni ? pi + j : ps + j; }
+    // the id is loaded either way (a select, not a branch, so that the load
+    // does not make the compiler wait for every load before it)
     __device__ __forceinline__ int node(const TileArgs& a, int p0, int j) const {
-        return j < ni ? n0 + j : a.tile_nodes[p0 + j];
+        const int g = a.tile_nodes[p0 + j];
+        return j < ni ? n0 + j : g;
     }
 };
 __device__ __forceinline__ TilePart tile_part(const TileArgs& a, int64_t t) {
@@ -210,23 +213,38 @@ __device__ __forceinline__ TilePart tile_part(const TileArgs& a, int64_t t) {
 }
 
 // Tile nodes into LDS: temperature, conductivity, zeroed accumulators.  The
-// first SJ rounds go out together, ids then temperatures (lanes past the
-// list load its last node and store nothing), so a thread waits for two
-// memory round trips instead of two per round.  Single-tile nodes need no id
-// load: theirs follow from the list position.
+// first SJ rounds go out together, list entries (stage_ids) then
+// temperatures (lanes past the list load its last node and store nothing),
+// so a thread waits for two memory round trips instead of two per round.
+// Single-tile nodes' ids follow from the list position.
+constexpr int kStageRounds = 2;
+
+// The raw list entries of the first rounds.  The tetrahedral pass issues
+// them before its element loads, so that the temperature loads wait for
+// these alone.
+__device__ __forceinline__ void stage_ids(const TileArgs& a, int p0, int m,
+                                          int (&graw)[kStageRounds]) {
+#pragma unroll
+    for (int u = 0; u < kStageRounds; u++)
+        graw[u] = a.tile_nodes[p0 + min((int)threadIdx.x + u * (int)blockDim.x, m - 1)];
+}
+
 template <typename Real, bool COMP, bool TD>
 __device__ __forceinline__ void stage_tile_nodes(const TileArgs& a, int p0, int m,
                                                  const TilePart& tp,
+                                                 const int (&graw)[kStageRounds],
                                                  const void* __restrict__ Tin,
                                                  const Props<Real>& pr, Real* s_T,
                                                  Real* s_k, unsigned long long* s_acc) {
     const int tid = threadIdx.x, bs = blockDim.x;
-    constexpr int SJ = 2;
+    constexpr int SJ = kStageRounds;
     {
         int gj[SJ];
 #pragma unroll
-        for (int u = 0; u < SJ; u++) gj[u] = tp.node(a, p0, min(tid + u * bs, m - 1));
-        __builtin_amdgcn_sched_barrier(0);  // all id loads before any wait
+        for (int u = 0; u < SJ; u++) {
+            const int j = min(tid + u * bs, m - 1);
+            gj[u] = j < tp.ni ? tp.n0 + j : graw[u];
+        }
         Real hj[SJ], lj[SJ];
 #pragma unroll
         for (int u = 0; u < SJ; u++) State<Real, COMP>::load(Tin, gj[u], hj[u], lj[u]);
@@ -269,6 +287,10 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
     const int m = a.tile_node_off[t + 1] - p0;
     const TilePart tp = tile_part(a, t);
 
+    // 0. the first rounds' tile-node list entries
+    int graw[kStageRounds];
+    stage_ids(a, p0, m, graw);
+    __builtin_amdgcn_sched_barrier(0);
     // 1. coefficient and local-connectivity loads in flight during staging
     Real cf[R][6];
     uint2 lc[R];
@@ -276,23 +298,24 @@ __device__ __forceinline__ void elem_tile(const TileArgs& a, int64_t t,
     const uint2* glc = static_cast<const uint2*>(a.lconn) + e0;
     const uint32_t* gw = static_cast<const uint32_t*>(a.lconn) + e0;
     const uint8_t* gb = static_cast<const uint8_t*>(a.lconn) + 4 * a.E + e0;
+    // (lanes past the tile reload its last element: straight-line loads, so
+    // that the staging below waits for the list entries only)
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int el = tid + r * bs;
-        if (el < ne) {
+        const int el = min(tid + r * bs, ne - 1);
 #pragma unroll
-            for (int k = 0; k < 6; k++) cf[r][k] = stream_load(&coef[k * a.E + e0 + el]);
-            if (pk) {
-                lc[r] = make_uint2(stream_load(&gw[el]), gb[el]);
-            } else {
-                const unsigned long long w = stream_load(
-                    reinterpret_cast<const unsigned long long*>(glc) + el);
-                lc[r] = make_uint2((unsigned)w, (unsigned)(w >> 32));
-            }
+        for (int k = 0; k < 6; k++) cf[r][k] = stream_load(&coef[k * a.E + e0 + el]);
+        if (pk) {
+            lc[r] = make_uint2(stream_load(&gw[el]), gb[el]);
+        } else {
+            const unsigned long long w = stream_load(
+                reinterpret_cast<const unsigned long long*>(glc) + el);
+            lc[r] = make_uint2((unsigned)w, (unsigned)(w >> 32));
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
     // 2. tile nodes
-    stage_tile_nodes<Real, COMP, TD>(a, p0, m, tp, Tin, pr, s_T, s_k, s_acc);
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, tp, graw, Tin, pr, s_T, s_k, s_acc);
     __syncthreads();
     // 3. element loads, accumulated exactly on the fixed-point grid
 #pragma unroll
@@ -405,7 +428,10 @@ __device__ __forceinline__ void elem_tile_hex(const TileArgs& a, int64_t t,
         }
     }
     // 2. tile nodes
-    stage_tile_nodes<Real, COMP, TD>(a, p0, m, tp, Tin, pr, s_T, s_k, s_acc);
+    int graw[kStageRounds];
+    stage_ids(a, p0, m, graw);
+    __builtin_amdgcn_sched_barrier(0);  // all list loads before any wait
+    stage_tile_nodes<Real, COMP, TD>(a, p0, m, tp, graw, Tin, pr, s_T, s_k, s_acc);
     __syncthreads();
     // 3. element loads, accumulated exactly on the fixed-point grid
 #pragma unroll
@@ -617,7 +643,7 @@ __device__ __forceinline__ void node_update(const int64_t (&iv)[NPT], int64_t N,
     }
 }
 
-constexpr int kNodesPerThread = 2;
+constexpr int kNodesPerThread = 1;
 
 // With the XCD remap, blocks wholly below n_int (single-tile nodes only) and
 // the others are remapped separately, so that every XCD gets its share of
